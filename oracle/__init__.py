@@ -1,0 +1,26 @@
+"""CPU FP64 oracle for the cone-beam operators and the algorithms built on them.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the package smoke check and the benchmark's CPU-baseline
+leg are the only callers.  The product path never imports this package, and this package never
+imports the product (it shares only the seeded input generators, which hold none of the method's
+arithmetic).
+
+Operators (plain C in ``ct_oracle.c``, loaded with ctypes):
+  siddon_fwd / siddon_rays         ray-driven exact intersection projector (Siddon 1985, Section 2.1)
+  siddon_adj / siddon_adj_voxels   its exact transpose (scatter of the same traversal)
+  interp_fwd / interp_rays         trilinear-interpolated projector (Chou 2011, Section 2.1)
+  bp / bp_voxels                   voxel-driven backprojection, FDK or pseudo-matched weights
+                                   (Jia 2011, Section 2.2)
+Algorithms (``algos.py``, numpy over the operators): CGLS, SART, TV steepest descent.
+"""
+from .core import (Geometry, W_FDK, W_PM, bp, bp_coverage, bp_transpose, bp_voxels, get_threads,
+                   interp_fwd, interp_ray, interp_rays, ray_endpoints, set_threads, siddon_adj,
+                   siddon_adj_voxels, siddon_fwd, siddon_ray, siddon_rays, load)
+from .algos import cgls, sart, tv_grad, tv_value, tv_steps
+
+__all__ = [
+    "Geometry", "W_FDK", "W_PM", "bp", "bp_coverage", "bp_transpose", "bp_voxels", "get_threads",
+    "interp_fwd", "interp_ray", "interp_rays", "ray_endpoints", "set_threads", "siddon_adj",
+    "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "load", "cgls", "sart",
+    "tv_grad", "tv_value", "tv_steps",
+]

@@ -1,0 +1,127 @@
+"""Oracle versions of the iterative algorithms that call the projection operators (test
+infrastructure only), in FP64 numpy.  Each follows the published method step by step.
+
+Operators are passed in as callables so the same code runs on the matrix-free oracle operators
+and on dense matrices built from them (used by the pins).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import core
+
+
+def _dot(a, b):
+    return float(np.dot(np.ravel(a), np.ravel(b)))
+
+
+def cgls(A, At, b, niter, x0=None):
+    """Conjugate gradient least squares (Bjorck), the algorithm used for the coffee-bean scan
+    (Section 3.2): minimises ||A x - b|| over Krylov spaces of A^T A.
+
+    Returns (x, resid) where resid[k] = sqrt(rho_k) from the recurrence rho_{k+1} = rho_k - alpha
+    gamma_k (which uses <r_k, A p_k> = gamma_k); resid has niter+1 entries and repeats its last
+    value if the iteration stops early (A p = 0).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(At(b)) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A(x)
+    s = At(r)
+    p = s.copy()
+    gamma = _dot(s, s)
+    rho = _dot(r, r)
+    resid = [np.sqrt(max(rho, 0.0))]
+    for _ in range(niter):
+        q = A(p)
+        delta = _dot(q, q)
+        if delta == 0.0:
+            break
+        alpha = gamma / delta
+        x = x + alpha * p
+        r = r - alpha * q
+        rho = rho - alpha * gamma
+        resid.append(np.sqrt(max(rho, 0.0)))
+        s = At(r)
+        gamma_new = _dot(s, s)
+        beta = gamma_new / gamma
+        gamma = gamma_new
+        p = s + beta * p
+    while len(resid) < niter + 1:
+        resid.append(resid[-1])
+    return x, np.array(resid)
+
+
+# SART thresholds (the paper gives no SART parameters; these are our readings):
+#   a ray's weight 1/(A_t 1)_p is used only when its chord through the grid exceeds 1e-2 of the
+#   smallest voxel size (shorter chords graze a corner and are dropped);
+#   a voxel is updated only where the backprojected ones (B_t 1)_j exceed 1e-6.
+SART_RAY_FRACTION = 1e-2
+SART_VOXEL_MIN = 1e-6
+
+
+def sart(geo: core.Geometry, angles, b, niter, lam=1.0, x0=None):
+    """SART (Andersen & Kak 1984; the OS-SART family of Section 3.2 with one angle per block).
+
+    For each sweep, for each angle t in natural order:
+        W_p = 1/(A_t 1)_p,  V_j = (B_t 1)_j,  x += lam * B_t(W * (b_t - A_t x)) / V
+    with A the Siddon projector and B the FDK-weighted voxel backprojector.
+    """
+    angles = np.asarray(angles, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(geo.vol_shape) if x0 is None else np.array(x0, dtype=np.float64)
+    ones_vol = np.ones(geo.vol_shape)
+    dmin = min(geo.dVoxel)
+    ones_proj = np.ones((1,) + b.shape[1:])
+    for _ in range(niter):
+        for t in range(len(angles)):
+            th = angles[t:t + 1]
+            chord = core.siddon_fwd(geo, th, ones_vol)[0]
+            W = np.where(chord > SART_RAY_FRACTION * dmin, 1.0 / np.where(chord > 0, chord, 1.0), 0.0)
+            r = W * (b[t] - core.siddon_fwd(geo, th, x)[0])
+            num = core.bp(geo, th, r[None], core.W_FDK)
+            V = core.bp(geo, th, ones_proj, core.W_FDK)
+            upd = np.where(V > SART_VOXEL_MIN, num / np.where(V > 0, V, 1.0), 0.0)
+            x = x + lam * upd
+    return x
+
+
+def tv_grad(x, eps=1e-8):
+    """Gradient of TV_eps(x) = sum_j sqrt(|D x_j|^2 + eps) with forward differences on a unit grid
+    and zero difference at the last index of each axis (Neumann boundary)."""
+    x = np.asarray(x, dtype=np.float64)
+    d = [np.zeros_like(x) for _ in range(3)]
+    # axes: 2 = x (fastest), 1 = y, 0 = z
+    d[0][:, :, :-1] = x[:, :, 1:] - x[:, :, :-1]
+    d[1][:, :-1, :] = x[:, 1:, :] - x[:, :-1, :]
+    d[2][:-1, :, :] = x[1:, :, :] - x[:-1, :, :]
+    n = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + eps)
+    g = -(d[0] + d[1] + d[2]) / n
+    g[:, :, 1:] += (d[0] / n)[:, :, :-1]
+    g[:, 1:, :] += (d[1] / n)[:, :-1, :]
+    g[1:, :, :] += (d[2] / n)[:-1, :, :]
+    return g
+
+
+def tv_value(x, eps=1e-8):
+    x = np.asarray(x, dtype=np.float64)
+    dx = np.zeros_like(x)
+    dy = np.zeros_like(x)
+    dz = np.zeros_like(x)
+    dx[:, :, :-1] = x[:, :, 1:] - x[:, :, :-1]
+    dy[:, :-1, :] = x[:, 1:, :] - x[:, :-1, :]
+    dz[:-1, :, :] = x[1:, :, :] - x[:-1, :, :]
+    return float(np.sum(np.sqrt(dx * dx + dy * dy + dz * dz + eps)))
+
+
+def tv_steps(x, nsteps, lam, eps=1e-8):
+    """Steepest descent on TV (Section 2.3, gradient-descent form): the step length is
+    alpha = lam * ||x_in||_2, fixed for the block, and every step moves by alpha along -g/||g||_2
+    (the norm of the update is needed at every iteration)."""
+    x = np.array(x, dtype=np.float64)
+    alpha = lam * float(np.linalg.norm(x.ravel()))
+    for _ in range(nsteps):
+        g = tv_grad(x, eps)
+        ng = float(np.linalg.norm(g.ravel()))
+        if ng > 0.0:
+            x = x - alpha * g / ng
+    return x
