@@ -1,0 +1,210 @@
+/*
+ * ct.h - C ABI of the MI355X cone-beam CT operator library (libct.so).
+ *
+ * The library implements the computational core of iterative cone-beam CT reconstruction as
+ * organised in Biguri et al., "Arbitrarily large iterative tomographic reconstruction on
+ * multiple GPUs using the TIGRE toolbox": the linear model A x = b + e of Section 2, Eq. (1)
+ * (A holds the intersection lengths of X-ray paths with image elements), its forward projection
+ * A x (Section 2.1), backprojection A^T b (Section 2.2), the out-of-core splitting of the image
+ * into axial slabs and of the projections into angle chunks (Algorithms 1 and 2), the iterative
+ * algorithms that call them (CGLS and SART, Section 3.2) and the TV steepest-descent regulariser
+ * (Section 2.3).
+ *
+ * Conventions (all entry points):
+ *  - Units are millimetres and radians.  The orbit is circular about the z axis: for angle t the
+ *    source sits at DSO (cos t, sin t, 0), the detector centre at -(DSD - DSO)(cos t, sin t, 0),
+ *    with detector axes e_u = (-sin t, cos t, 0) and e_v = (0, 0, 1).  Pixel (a, b) has its centre
+ *    at u_a = (a - (Nu-1)/2) du + offU, v_b = (b - (Nv-1)/2) dv + offV along those axes; one ray
+ *    per pixel runs from the source to that centre.
+ *  - Voxel (i, j, k) has its centre at offOrigin + ((i-(Nx-1)/2) dx, (j-(Ny-1)/2) dy,
+ *    (k-(Nz-1)/2) dz).  The volume is stored vol[k][j][i] (x fastest); projections are stored
+ *    proj[angle][b][a] (u fastest).  Arrays are dense, with no padding.
+ *  - Every function returns a ct_status: CT_OK (0) or a negative error code, and never throws or
+ *    aborts across the ABI.  ct_last_error() returns a message for the calling thread's last
+ *    failure.  Argument and geometry validation happen before anything is written; outputs are
+ *    untouched after a validation error and unspecified after CT_ERR_HIP.
+ *  - Device pointers are HIP device allocations (e.g. torch tensor data_ptr()) on the current
+ *    HIP device.  `stream` is a hipStream_t (NULL = the default stream).  Resident calls are
+ *    stream-ordered and return after enqueueing; *_host calls are synchronous.
+ *  - The caller owns every input and output array.  A plan owns only its per-angle geometry
+ *    table (host and device copies); ct_plan_destroy releases it.
+ *  - A plan may be used by one host thread at a time.  Distinct plans are independent.
+ *  - All kernels are deterministic: identical inputs give bitwise identical outputs, whatever
+ *    else runs on the device.
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CT_OK = 0,
+    CT_ERR_ARG = -1,      /* bad argument (null pointer, bad range, unknown enum) */
+    CT_ERR_GEOMETRY = -2, /* geometry fails validation (see ct_plan_create) */
+    CT_ERR_DTYPE = -3,    /* unsupported storage type or pairing */
+    CT_ERR_OOM = -4,      /* device or pinned-host allocation failed */
+    CT_ERR_CAP = -5,      /* device memory cap too small for one slice plus buffers */
+    CT_ERR_HIP = -6,      /* a HIP runtime call failed */
+    CT_ERR_STATE = -7     /* object in an unusable state */
+} ct_status;
+
+/* Storage type of a volume or projection array.  Arithmetic is always FP32 (accumulation along
+ * every ray and over every voxel's angles); CGLS inner products and norms are FP64. */
+typedef enum { CT_F32 = 0, CT_F16 = 1, CT_BF16 = 2 } ct_dtype;
+
+/* Forward projectors (Section 2.1). */
+typedef enum {
+    CT_SIDDON = 0, /* exact ray/voxel intersection lengths (Siddon 1985) */
+    CT_INTERP = 1  /* line integral of the trilinear interpolant, sampled every
+                      accuracy * min(dVoxel) mm on a lattice anchored at the source (Chou 2011) */
+} ct_projector;
+
+/* Backprojectors (Section 2.2). */
+typedef enum {
+    CT_BP_FDK = 0,            /* voxel-driven, bilinear, weight (DSO / L)^2, L = voxel depth
+                                 along the central ray */
+    CT_BP_PSEUDO_MATCHED = 1, /* voxel-driven, bilinear, weight (dx dy dz)/(du dv) DSD^2 |SX| / L^3,
+                                 the ray-tube density that approximates the transpose of Siddon */
+    CT_BP_ADJOINT = 2         /* the exact transpose of CT_SIDDON */
+} ct_backprojector;
+
+/* Scanner and grid description (Section 2 / Section 3.2 scanner distances). */
+typedef struct {
+    double DSO;             /* source to rotation axis, > 0 */
+    double DSD;             /* source to detector plane, > DSO */
+    int64_t nVoxel[3];      /* Nx, Ny, Nz, each > 0 */
+    double dVoxel[3];       /* voxel size, each > 0 */
+    double offOrigin[3];    /* volume centre relative to the rotation axis origin */
+    int64_t nDetector[2];   /* Nu, Nv, each > 0 */
+    double dDetector[2];    /* pixel size, each > 0 */
+    double offDetector[2];  /* detector centre offset along e_u, e_v */
+    double accuracy;        /* CT_INTERP sample spacing / min(dVoxel), in (0, 1]; 0 means 0.5 */
+} ct_geometry;
+
+typedef struct ct_plan ct_plan;
+
+/* Validate the geometry and build the per-angle table (host FP64).  Validation: DSD > DSO > 0,
+ * all sizes and spacings > 0, n_angles > 0, every angle finite, and every corner of the volume
+ * box strictly inside the source orbit (x^2 + y^2 < DSO^2), so that every voxel lies in front of
+ * the source at every angle.  `angles` (host, n_angles doubles) is copied.  No device work is
+ * done here; the device copy of the table is made on first use on each device.
+ * Errors: CT_ERR_ARG (null pointers, n_angles <= 0), CT_ERR_GEOMETRY. */
+ct_status ct_plan_create(const ct_geometry *geometry, const double *angles, int64_t n_angles,
+                         ct_plan **out);
+/* Release the plan.  All work that uses it must have completed (device copies are released in
+ * stream order, without host synchronisation). */
+void ct_plan_destroy(ct_plan *plan);
+/* Copy of the validated geometry (accuracy resolved) and the angle count. */
+ct_status ct_plan_info(const ct_plan *plan, ct_geometry *geometry, int64_t *n_angles);
+
+/* Forward projection proj = A vol (or proj += A vol when accumulate != 0) for the angles
+ * [angle_begin, angle_end) of the plan (Section 2.1; one thread per detector pixel).
+ * d_vol: device, Nz*Ny*Nx elements of vol_dtype.  d_proj: device, (angle_end - angle_begin)
+ * projections of Nv*Nu elements of proj_dtype; projection 0 of d_proj is angle angle_begin.
+ * Errors: CT_ERR_ARG (null pointers, empty or out-of-range angle range), CT_ERR_DTYPE, CT_ERR_HIP. */
+ct_status ct_forward(ct_plan *plan, ct_projector projector, const void *d_vol, ct_dtype vol_dtype,
+                     void *d_proj, ct_dtype proj_dtype, int accumulate, int64_t angle_begin,
+                     int64_t angle_end, void *stream);
+
+/* Backprojection vol = B proj (or vol += B proj) over the angles [angle_begin, angle_end)
+ * (Section 2.2; one thread per voxel column segment, loops over angles).  Layouts and errors as
+ * ct_forward, with the roles of the arrays swapped. */
+ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const void *d_proj,
+                         ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype, int accumulate,
+                         int64_t angle_begin, int64_t angle_end, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Out-of-core operators: the image and projections live in host memory and the device holds at
+ * most `device_cap_bytes` of working buffers (Algorithm 1 for the forward, Algorithm 2 for the
+ * backprojection).  The image is split into equal axial slabs, as large as the cap allows, and
+ * the projections into chunks of angles; copies run on side streams overlapped with kernels;
+ * partial projections from earlier slabs are accumulated inside the projection kernel.
+ * Host arrays may be pageable (staged through a pinned ring) or pinned (copied directly).
+ * Errors: CT_ERR_ARG, CT_ERR_DTYPE, CT_ERR_CAP (cap below one slice plus buffers), CT_ERR_OOM,
+ * CT_ERR_HIP.  Stats may be NULL. */
+typedef struct {
+    int32_t n_slabs;        /* image splits N_sp */
+    int32_t slab_slices;    /* slices per slab (last slab may be shorter) */
+    int32_t chunk_angles;   /* angles per projection chunk */
+    int32_t n_chunks;       /* chunks per slab */
+    double bytes_h2d;       /* host to device bytes moved */
+    double bytes_d2h;       /* device to host bytes moved */
+    double t_total_s;       /* wall time of the call */
+    double t_compute_s;     /* time the compute stream was busy (kernels, incl. overlapped copies) */
+    double t_stage_s;       /* host time spent copying between caller memory and pinned staging */
+    double t_other_mem_s;   /* allocation, freeing and copies not overlapped with kernels */
+} ct_ooc_stats;
+
+/* Pure host planner used by the *_host calls: slab height and chunk size for a cap.
+ * direction: 0 = forward (3 projection chunk buffers), 1 = backprojection (2 buffers).
+ * Errors: CT_ERR_ARG, CT_ERR_DTYPE, CT_ERR_CAP. */
+ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
+                      ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out);
+
+ct_status ct_forward_host(ct_plan *plan, ct_projector projector, const void *h_vol, ct_dtype vol_dtype,
+                          void *h_proj, ct_dtype proj_dtype, uint64_t device_cap_bytes,
+                          ct_ooc_stats *stats);
+ct_status ct_backproject_host(ct_plan *plan, ct_backprojector backprojector, const void *h_proj,
+                              ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
+                              uint64_t device_cap_bytes, ct_ooc_stats *stats);
+
+/* ---------------------------------------------------------------------------------------------
+ * Device-resident algorithms.  Each runs entirely on `stream` without host synchronisation
+ * (scalars stay in device memory).  `d_workspace` is optional: when NULL the library allocates
+ * stream-ordered scratch (hipMallocAsync) and frees it on the same stream; otherwise it must
+ * hold at least the number of bytes reported by the matching *_workspace_bytes call and must
+ * not be used concurrently by another call. */
+
+/* CGLS (Bjorck) with A = CT_SIDDON and A^T = CT_BP_ADJOINT over all plan angles: from the
+ * initial d_x, minimises ||A x - b||.  Volume-shaped vectors (x, p, s) are stored in vol_dtype and
+ * projection-shaped ones (r, q) in proj_dtype; inner products, step sizes and the residual-norm
+ * recurrence rho_{k+1} = rho_k - alpha_k gamma_k are FP64.  d_resid (device, niter+1 doubles, may
+ * be NULL) receives sqrt(rho_k); if A p = 0 the iteration stops and the last value repeats.
+ * d_b: device projections (all angles).  d_x: device volume, in: x0, out: result. */
+ct_status ct_cgls_workspace_bytes(const ct_plan *plan, ct_dtype vol_dtype, ct_dtype proj_dtype,
+                                  uint64_t *bytes);
+ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype,
+                  int32_t niter, double *d_resid, void *d_workspace, void *stream);
+
+/* SART (Andersen and Kak; Section 3.2 uses its ordered-subset form) with A = CT_SIDDON and
+ * B = CT_BP_FDK, one angle per update (block must be 1), angles in natural order, relaxation
+ * lambda:  x += lambda B_t(W (b_t - A_t x)) / V  with W = 1/(A_t 1) for rays whose chord through
+ * the grid exceeds 1e-2 min(dVoxel) (others weigh 0) and V = B_t 1, voxels with V <= 1e-6 left
+ * unchanged.  d_b and d_x as ct_cgls; FP32 storage only. */
+ct_status ct_sart_workspace_bytes(const ct_plan *plan, uint64_t *bytes);
+ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, double lambda,
+                  int32_t block, void *d_workspace, void *stream);
+
+/* TV steepest descent (Section 2.3, gradient-descent form): nsteps steps of
+ * x <- x - alpha g / ||g||_2, g = grad TV_eps(x) with forward differences on a unit grid and zero
+ * difference at the last index of each axis, TV_eps(x) = sum_j sqrt(|D x_j|^2 + eps), and
+ * alpha = lambda ||x_in||_2 fixed for the call.  Norms are FP64.  d_x: device volume (FP32) of
+ * the geometry's nVoxel shape. */
+ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes);
+ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, double lambda,
+                      double eps, void *d_workspace, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Small device utilities used by the algorithms, exported for callers that compose their own. */
+
+/* out[0] = sum_i a[i] * b[i] in FP64 with a fixed reduction order (bitwise repeatable).
+ * a, b: device arrays of n elements of dtype; out: device double. */
+ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out,
+                 void *stream);
+/* Storage conversion: dst[i] = (dst_dtype) src[i] (round to nearest even). */
+ct_status ct_convert(const void *d_src, ct_dtype src_dtype, void *d_dst, ct_dtype dst_dtype, int64_t n,
+                     void *stream);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char *ct_last_error(void);
+/* Library version string. */
+const char *ct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CT_H */

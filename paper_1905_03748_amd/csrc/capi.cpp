@@ -1,0 +1,272 @@
+// C ABI entry points, geometry validation, per-angle tables and error reporting.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ct_internal.hpp"
+
+namespace ct {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ct_status fail(ct_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+ct_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return CT_ERR_OOM;
+    return CT_ERR_HIP;
+}
+
+size_t dtype_size(ct_dtype t) { return t == CT_F32 ? 4 : 2; }
+bool dtype_ok(int t) { return t == CT_F32 || t == CT_F16 || t == CT_BF16; }
+
+static ct_status validate(const ct_geometry &g) {
+    if (!(g.DSO > 0) || !(g.DSD > g.DSO) || !std::isfinite(g.DSD))
+        return fail(CT_ERR_GEOMETRY, "geometry: need DSD > DSO > 0");
+    for (int a = 0; a < 3; ++a) {
+        if (g.nVoxel[a] <= 0 || !(g.dVoxel[a] > 0) || !std::isfinite(g.dVoxel[a]) ||
+            !std::isfinite(g.offOrigin[a]))
+            return fail(CT_ERR_GEOMETRY, "geometry: voxel counts and sizes must be positive and finite");
+    }
+    for (int a = 0; a < 2; ++a) {
+        if (g.nDetector[a] <= 0 || !(g.dDetector[a] > 0) || !std::isfinite(g.dDetector[a]) ||
+            !std::isfinite(g.offDetector[a]))
+            return fail(CT_ERR_GEOMETRY, "geometry: detector counts and sizes must be positive and finite");
+    }
+    if (g.nVoxel[0] > (1 << 24) || g.nVoxel[1] > (1 << 24) || g.nVoxel[2] > (1 << 24) ||
+        g.nDetector[0] > (1 << 24) || g.nDetector[1] > (1 << 24))
+        return fail(CT_ERR_GEOMETRY, "geometry: a dimension exceeds 2^24");
+    if (!(g.accuracy >= 0.0 && g.accuracy <= 1.0))
+        return fail(CT_ERR_GEOMETRY, "geometry: accuracy must be in (0, 1] (0 selects 0.5)");
+    double r2 = 0;
+    for (int sx = -1; sx <= 1; sx += 2)
+        for (int sy = -1; sy <= 1; sy += 2) {
+            double x = g.offOrigin[0] + sx * g.nVoxel[0] * g.dVoxel[0] / 2.0;
+            double y = g.offOrigin[1] + sy * g.nVoxel[1] * g.dVoxel[1] / 2.0;
+            r2 = std::fmax(r2, x * x + y * y);
+        }
+    if (!(r2 < g.DSO * g.DSO))
+        return fail(CT_ERR_GEOMETRY, "geometry: the volume box must lie strictly inside the source orbit");
+    return CT_OK;
+}
+
+static AngleGeo angle_geo(const ct_geometry &g, double th) {
+    AngleGeo t;
+    std::memset(&t, 0, sizeof(t));
+    t.c = std::cos(th);
+    t.s = std::sin(th);
+    const double Smm[3] = {g.DSO * t.c, g.DSO * t.s, 0.0};
+    for (int a = 0; a < 3; ++a)
+        t.S[a] = (Smm[a] - g.offOrigin[a]) / g.dVoxel[a] + (g.nVoxel[a] - 1) / 2.0;
+    // detector centre minus source = -DSD (cos, sin, 0)
+    t.Dc[0] = -g.DSD * t.c / g.dVoxel[0];
+    t.Dc[1] = -g.DSD * t.s / g.dVoxel[1];
+    t.Dc[2] = 0.0;
+    t.eu[0] = -t.s / g.dVoxel[0];
+    t.eu[1] = t.c / g.dVoxel[1];
+    t.eu[2] = 0.0;
+    return t;
+}
+
+ct_status plan_device_table(ct_plan *p, hipStream_t st, const AngleGeo **out) {
+    int dev = 0;
+    CT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->dtab.find(dev);
+    if (it == p->dtab.end()) {
+        ct_plan::DevTab t{nullptr, nullptr};
+        const size_t bytes = sizeof(AngleGeo) * p->tab.size();
+        CT_HIP(hipMallocAsync((void **)&t.ptr, bytes, st));
+        hipError_t e = hipMemcpyAsync(t.ptr, p->tab.data(), bytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(t.ready, st);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(t.ptr, st);
+            if (t.ready) (void)hipEventDestroy(t.ready);
+            return hip_fail(e, "angle table upload");
+        }
+        it = p->dtab.emplace(dev, t).first;
+    } else {
+        CT_HIP(hipStreamWaitEvent(st, it->second.ready, 0));
+    }
+    *out = it->second.ptr;
+    return CT_OK;
+}
+
+}  // namespace ct
+
+using namespace ct;
+
+extern "C" {
+
+const char *ct_last_error(void) { return g_last_error.c_str(); }
+
+const char *ct_version(void) { return "ct-mi355x 0.1 (gfx950)"; }
+
+ct_status ct_plan_create(const ct_geometry *geometry, const double *angles, int64_t n_angles,
+                         ct_plan **out) {
+    if (!geometry || !angles || !out) return fail(CT_ERR_ARG, "ct_plan_create: null pointer");
+    if (n_angles <= 0) return fail(CT_ERR_ARG, "ct_plan_create: n_angles must be positive");
+    ct_geometry g = *geometry;
+    if (g.accuracy == 0.0) g.accuracy = 0.5;
+    ct_status st = validate(g);
+    if (st != CT_OK) return st;
+    for (int64_t i = 0; i < n_angles; ++i)
+        if (!std::isfinite(angles[i])) return fail(CT_ERR_GEOMETRY, "ct_plan_create: non-finite angle");
+    ct_plan *p = new (std::nothrow) ct_plan();
+    if (!p) return fail(CT_ERR_OOM, "ct_plan_create: host allocation failed");
+    p->g = g;
+    p->angles.assign(angles, angles + n_angles);
+    p->tab.resize(n_angles);
+    for (int64_t i = 0; i < n_angles; ++i) p->tab[i] = angle_geo(g, angles[i]);
+    *out = p;
+    return CT_OK;
+}
+
+void ct_plan_destroy(ct_plan *plan) {
+    if (!plan) return;
+    int cur = 0;
+    bool have = hipGetDevice(&cur) == hipSuccess;
+    for (auto &kv : plan->dtab) {
+        if (hipSetDevice(kv.first) != hipSuccess) continue;
+        // stream-ordered release: the caller has finished all work that uses the plan
+        (void)hipFreeAsync(kv.second.ptr, nullptr);
+        (void)hipEventDestroy(kv.second.ready);
+    }
+    if (have && !plan->dtab.empty()) (void)hipSetDevice(cur);
+    delete plan;
+}
+
+ct_status ct_plan_info(const ct_plan *plan, ct_geometry *geometry, int64_t *n_angles) {
+    if (!plan) return fail(CT_ERR_ARG, "ct_plan_info: null plan");
+    if (geometry) *geometry = plan->g;
+    if (n_angles) *n_angles = (int64_t)plan->angles.size();
+    return CT_OK;
+}
+
+static ct_status check_range(const ct_plan *p, int64_t a0, int64_t a1, const char *who) {
+    if (a0 < 0 || a1 > (int64_t)p->angles.size() || a0 >= a1)
+        return fail(CT_ERR_ARG, std::string(who) + ": angle range must satisfy 0 <= begin < end <= n_angles");
+    return CT_OK;
+}
+
+ct_status ct_forward(ct_plan *plan, ct_projector projector, const void *d_vol, ct_dtype vol_dtype,
+                     void *d_proj, ct_dtype proj_dtype, int accumulate, int64_t angle_begin,
+                     int64_t angle_end, void *stream) {
+    if (!plan || !d_vol || !d_proj) return fail(CT_ERR_ARG, "ct_forward: null pointer");
+    if (projector != CT_SIDDON && projector != CT_INTERP) return fail(CT_ERR_ARG, "ct_forward: unknown projector");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward: unknown dtype");
+    ct_status st = check_range(plan, angle_begin, angle_end, "ct_forward");
+    if (st != CT_OK) return st;
+    return launch_forward(plan, projector, d_vol, vol_dtype, d_proj, proj_dtype, accumulate, angle_begin,
+                          angle_end, full_slab(plan->g), (hipStream_t)stream);
+}
+
+ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const void *d_proj,
+                         ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype, int accumulate,
+                         int64_t angle_begin, int64_t angle_end, void *stream) {
+    if (!plan || !d_vol || !d_proj) return fail(CT_ERR_ARG, "ct_backproject: null pointer");
+    if (backprojector != CT_BP_FDK && backprojector != CT_BP_PSEUDO_MATCHED && backprojector != CT_BP_ADJOINT)
+        return fail(CT_ERR_ARG, "ct_backproject: unknown backprojector");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject: unknown dtype");
+    ct_status st = check_range(plan, angle_begin, angle_end, "ct_backproject");
+    if (st != CT_OK) return st;
+    return launch_backproject(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, accumulate,
+                              angle_begin, angle_end, full_slab(plan->g), (hipStream_t)stream);
+}
+
+ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
+                      ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out) {
+    if (!plan || !out) return fail(CT_ERR_ARG, "ct_ooc_plan: null pointer");
+    if (direction != 0 && direction != 1) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0 or 1");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_ooc_plan: unknown dtype");
+    return ooc_plan(plan, direction, projector, vol_dtype, proj_dtype, device_cap_bytes, out);
+}
+
+ct_status ct_forward_host(ct_plan *plan, ct_projector projector, const void *h_vol, ct_dtype vol_dtype,
+                          void *h_proj, ct_dtype proj_dtype, uint64_t device_cap_bytes,
+                          ct_ooc_stats *stats) {
+    if (!plan || !h_vol || !h_proj) return fail(CT_ERR_ARG, "ct_forward_host: null pointer");
+    if (projector != CT_SIDDON && projector != CT_INTERP) return fail(CT_ERR_ARG, "ct_forward_host: unknown projector");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward_host: unknown dtype");
+    return ooc_forward(plan, projector, h_vol, vol_dtype, h_proj, proj_dtype, device_cap_bytes, stats);
+}
+
+ct_status ct_backproject_host(ct_plan *plan, ct_backprojector backprojector, const void *h_proj,
+                              ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
+                              uint64_t device_cap_bytes, ct_ooc_stats *stats) {
+    if (!plan || !h_vol || !h_proj) return fail(CT_ERR_ARG, "ct_backproject_host: null pointer");
+    if (backprojector != CT_BP_FDK && backprojector != CT_BP_PSEUDO_MATCHED && backprojector != CT_BP_ADJOINT)
+        return fail(CT_ERR_ARG, "ct_backproject_host: unknown backprojector");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject_host: unknown dtype");
+    return ooc_backproject(plan, backprojector, h_proj, proj_dtype, h_vol, vol_dtype, device_cap_bytes, stats);
+}
+
+ct_status ct_cgls_workspace_bytes(const ct_plan *plan, ct_dtype vol_dtype, ct_dtype proj_dtype,
+                                  uint64_t *bytes) {
+    if (!plan || !bytes) return fail(CT_ERR_ARG, "ct_cgls_workspace_bytes: null pointer");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls_workspace_bytes: unknown dtype");
+    *bytes = cgls_workspace(plan, vol_dtype, proj_dtype);
+    return CT_OK;
+}
+
+ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype,
+                  int32_t niter, double *d_resid, void *d_workspace, void *stream) {
+    if (!plan || !d_b || !d_x) return fail(CT_ERR_ARG, "ct_cgls: null pointer");
+    if (niter < 0) return fail(CT_ERR_ARG, "ct_cgls: niter must be >= 0");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls: unknown dtype");
+    return cgls_run(plan, d_b, proj_dtype, d_x, vol_dtype, niter, d_resid, d_workspace, (hipStream_t)stream);
+}
+
+ct_status ct_sart_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
+    if (!plan || !bytes) return fail(CT_ERR_ARG, "ct_sart_workspace_bytes: null pointer");
+    *bytes = sart_workspace(plan);
+    return CT_OK;
+}
+
+ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, double lambda, int32_t block,
+                  void *d_workspace, void *stream) {
+    if (!plan || !d_b || !d_x) return fail(CT_ERR_ARG, "ct_sart: null pointer");
+    if (niter < 0) return fail(CT_ERR_ARG, "ct_sart: niter must be >= 0");
+    if (block != 1) return fail(CT_ERR_ARG, "ct_sart: only block = 1 (one angle per update) is supported");
+    if (!std::isfinite(lambda)) return fail(CT_ERR_ARG, "ct_sart: lambda must be finite");
+    return sart_run(plan, d_b, d_x, niter, lambda, d_workspace, (hipStream_t)stream);
+}
+
+ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes) {
+    if (!geometry || !bytes) return fail(CT_ERR_ARG, "ct_tv_workspace_bytes: null pointer");
+    *bytes = tv_workspace(*geometry);
+    return CT_OK;
+}
+
+ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, double lambda, double eps,
+                      void *d_workspace, void *stream) {
+    if (!geometry || !d_x) return fail(CT_ERR_ARG, "ct_tv_steps: null pointer");
+    if (nsteps < 0) return fail(CT_ERR_ARG, "ct_tv_steps: nsteps must be >= 0");
+    if (!(eps > 0) || !std::isfinite(lambda)) return fail(CT_ERR_ARG, "ct_tv_steps: need eps > 0 and finite lambda");
+    for (int a = 0; a < 3; ++a)
+        if (geometry->nVoxel[a] <= 0) return fail(CT_ERR_GEOMETRY, "ct_tv_steps: voxel counts must be positive");
+    return tv_run(*geometry, d_x, nsteps, lambda, eps, d_workspace, (hipStream_t)stream);
+}
+
+ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out, void *stream) {
+    if (!d_a || !d_b || !d_out) return fail(CT_ERR_ARG, "ct_dot: null pointer");
+    if (n < 0) return fail(CT_ERR_ARG, "ct_dot: negative length");
+    if (!dtype_ok(dtype)) return fail(CT_ERR_DTYPE, "ct_dot: unknown dtype");
+    return dot_f64(d_a, d_b, dtype, n, d_out, nullptr, (hipStream_t)stream);
+}
+
+ct_status ct_convert(const void *d_src, ct_dtype src_dtype, void *d_dst, ct_dtype dst_dtype, int64_t n,
+                     void *stream) {
+    if (!d_src || !d_dst) return fail(CT_ERR_ARG, "ct_convert: null pointer");
+    if (n < 0) return fail(CT_ERR_ARG, "ct_convert: negative length");
+    if (!dtype_ok(src_dtype) || !dtype_ok(dst_dtype)) return fail(CT_ERR_DTYPE, "ct_convert: unknown dtype");
+    return convert(d_src, src_dtype, d_dst, dst_dtype, n, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ct.h"
+
+namespace ct {
+
+// Per-angle geometry in voxel-index space (voxel (i,j,k) centre at index coordinates (i,j,k)).
+// Double precision: the source sits ~DSO/d voxels away from the grid, so rays are set up in FP64
+// and traversed in FP32 relative to their entry point.
+struct AngleGeo {
+    double c, s;         // cos, sin of the angle
+    double S[3];         // source position, index units
+    double Dc[3];        // (detector centre - source), index units
+    double eu[3];        // e_u / dVoxel (index units per mm along the detector u axis)
+    double pad[5];
+};
+static_assert(sizeof(AngleGeo) == 128, "AngleGeo layout");
+
+void set_error(const std::string &msg);
+ct_status fail(ct_status st, const std::string &msg);
+ct_status hip_fail(hipError_t e, const char *what);
+
+#define CT_HIP(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::ct::hip_fail(e_, #call);   \
+    } while (0)
+
+size_t dtype_size(ct_dtype t);
+bool dtype_ok(int t);
+
+}  // namespace ct
+
+struct ct_plan {
+    ct_geometry g;
+    std::vector<double> angles;
+    std::vector<ct::AngleGeo> tab;
+    std::mutex mu;
+    struct DevTab {
+        ct::AngleGeo *ptr;
+        hipEvent_t ready;  // recorded after the upload on the stream that first used the plan
+    };
+    std::map<int, DevTab> dtab;  // device copies, per device id
+};
+
+namespace ct {
+
+// Device copy of the per-angle table for the current device.  The first use uploads it in stream
+// order on `st` (no host synchronisation); later uses on any stream wait for that upload.
+ct_status plan_device_table(ct_plan *p, hipStream_t st, const AngleGeo **out);
+
+// Range of axial slices a launch covers and where its memory starts.
+//   own_lo/own_hi: slices whose voxels this launch owns (forward: rays are clipped to them;
+//                  backprojection: voxels written).
+//   mem_lo: slice stored at the base of the volume pointer; mem_n: slices present in memory.
+struct Slab {
+    int64_t own_lo, own_hi;
+    int64_t mem_lo, mem_n;
+    bool first, last;  // the interpolated projector extends ownership to +-inf at the ends
+};
+
+inline Slab full_slab(const ct_geometry &g) {
+    Slab s;
+    s.own_lo = 0;
+    s.own_hi = g.nVoxel[2];
+    s.mem_lo = 0;
+    s.mem_n = g.nVoxel[2];
+    s.first = s.last = true;
+    return s;
+}
+
+// Kernel launchers (resident; pointers are device pointers; projection pointer holds the
+// angles [a0, a1) starting at projection 0).
+ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtype vt, void *proj,
+                         ct_dtype pt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
+                         hipStream_t st);
+ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
+                             ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
+                             hipStream_t st);
+
+// Algorithm helpers (kern_algos.hip)
+ct_status dot_f64(const void *a, const void *b, ct_dtype t, int64_t n, double *out, double *partials,
+                  hipStream_t st);
+ct_status convert(const void *src, ct_dtype st_, void *dst, ct_dtype dt, int64_t n, hipStream_t st);
+size_t dot_partials_count();
+
+ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter,
+                   double *resid, void *work, hipStream_t st);
+size_t cgls_workspace(const ct_plan *p, ct_dtype vt, ct_dtype pt);
+ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, void *work,
+                   hipStream_t st);
+size_t sart_workspace(const ct_plan *p);
+ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work,
+                 hipStream_t st);
+size_t tv_workspace(const ct_geometry &g);
+
+// SART pieces (kern_backproject.hip / kern_forward.hip)
+ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hipStream_t st);
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda,
+                             hipStream_t st);
+
+// Out-of-core (ooc.cpp)
+ct_status ooc_plan(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt,
+                   uint64_t cap, ct_ooc_stats *out);
+ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype vt, void *h_proj,
+                      ct_dtype pt, uint64_t cap, ct_ooc_stats *stats);
+ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj, ct_dtype pt, void *h_vol,
+                          ct_dtype vt, uint64_t cap, ct_ooc_stats *stats);
+
+}  // namespace ct

@@ -1,0 +1,367 @@
+// Device-resident iterative algorithms built on the operators: CGLS (FP64 inner products and
+// residual recurrence, scalars kept in device memory so an iteration never waits on the host),
+// SART (one angle per update) and TV steepest descent.  Reductions use a fixed partition
+// (DOT_BLOCKS contiguous ranges, fixed wave/block trees, fixed final sum), so results are bitwise
+// repeatable regardless of what else shares the device.
+#include <cmath>
+
+#include "dev_common.hpp"
+
+namespace ct {
+
+namespace {
+
+constexpr int DOT_BLOCKS = 1024;
+constexpr int DOT_THREADS = 256;
+constexpr int EW_THREADS = 256;
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+inline unsigned ew_grid(int64_t n) {
+    int64_t g = (n + EW_THREADS - 1) / EW_THREADS;
+    if (g > 65536 * 16) g = 65536 * 16;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+template <typename T>
+__global__ __launch_bounds__(DOT_THREADS) void k_dot_partial(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
+                                                             double *__restrict__ partials) {
+    __shared__ double lds[DOT_THREADS / 64];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)ldf(a, i) * (double)ldf(b, i);
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(DOT_THREADS) void k_sum_partials(const double *__restrict__ partials, int n,
+                                                              double *__restrict__ out) {
+    __shared__ double lds[DOT_THREADS / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) *out = s;
+}
+
+template <typename TS, typename TD>
+__global__ void k_convert(const TS *__restrict__ s, TD *__restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = from_f<TD>(ldf(s, i));
+}
+
+// r = b - r
+template <typename T>
+__global__ void k_rsub(const T *__restrict__ b, T *__restrict__ r, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = from_f<T>(ldf(b, i) - ldf(r, i));
+}
+
+template <typename T>
+__global__ void k_copy(const T *__restrict__ s, T *__restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+
+// y += sign * scal[idx] * x
+template <typename T>
+__global__ void k_axpy_s(T *__restrict__ y, const T *__restrict__ x, const double *__restrict__ scal, int idx,
+                         float sign, int64_t n) {
+    const float a = sign * (float)scal[idx];
+    if (a == 0.0f) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = from_f<T>(fmaf(a, ldf(x, i), ldf(y, i)));
+}
+
+// p = s + scal[idx] * p
+template <typename T>
+__global__ void k_xpby_s(T *__restrict__ p, const T *__restrict__ s, const double *__restrict__ scal, int idx,
+                         int64_t n) {
+    const float bta = (float)scal[idx];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = from_f<T>(fmaf(bta, ldf(p, i), ldf(s, i)));
+}
+
+// CGLS scalar slots
+enum { S_GAMMA = 0, S_DELTA = 1, S_ALPHA = 2, S_BETA = 3, S_RHO = 4, S_STOP = 5, S_TMP = 6, S_COUNT = 8 };
+
+__global__ void k_cgls_start(double *scal, double *resid) {
+    scal[S_STOP] = 0.0;
+    scal[S_ALPHA] = 0.0;
+    scal[S_BETA] = 0.0;
+    if (resid) resid[0] = sqrt(fmax(scal[S_RHO], 0.0));
+}
+
+__global__ void k_cgls_alpha(double *scal, double *resid, int k) {
+    const double delta = scal[S_DELTA];
+    if (scal[S_STOP] != 0.0 || delta == 0.0) {
+        scal[S_STOP] = 1.0;
+        scal[S_ALPHA] = 0.0;
+    } else {
+        const double alpha = scal[S_GAMMA] / delta;
+        scal[S_ALPHA] = alpha;
+        scal[S_RHO] = scal[S_RHO] - alpha * scal[S_GAMMA];
+    }
+    if (resid) resid[k + 1] = sqrt(fmax(scal[S_RHO], 0.0));
+}
+
+__global__ void k_cgls_beta(double *scal) {
+    const double gnew = scal[S_TMP];
+    if (scal[S_STOP] != 0.0) {
+        scal[S_BETA] = 0.0;
+        return;
+    }
+    scal[S_BETA] = scal[S_GAMMA] != 0.0 ? gnew / scal[S_GAMMA] : 0.0;
+    scal[S_GAMMA] = gnew;
+}
+
+// SART residual for one angle: r = (b - r) / chord where chord > thr, else 0
+__global__ void k_sart_resid(const float *__restrict__ b, const float *__restrict__ chord, float *__restrict__ r,
+                             float thr, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float c = chord[i];
+        r[i] = c > thr ? (b[i] - r[i]) / c : 0.0f;
+    }
+}
+
+// TV_eps gradient with forward differences, unit spacing, zero difference at the last index.
+__global__ __launch_bounds__(256) void k_tv_grad(const float *__restrict__ x, float *__restrict__ g, int nx, int ny,
+                                                 int nz, float eps) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t o = k * sz + (int64_t)j * sy + i;
+    auto X = [&](int di, int dj, int dk) { return x[o + dk * sz + dj * sy + di]; };
+    const float xc = X(0, 0, 0);
+    // differences at j
+    const float dxc = i < nx - 1 ? X(1, 0, 0) - xc : 0.0f;
+    const float dyc = j < ny - 1 ? X(0, 1, 0) - xc : 0.0f;
+    const float dzc = k < nz - 1 ? X(0, 0, 1) - xc : 0.0f;
+    float gv = -(dxc + dyc + dzc) / sqrtf(dxc * dxc + dyc * dyc + dzc * dzc + eps);
+    if (i > 0) {  // neighbour j - e_x
+        const float xm = X(-1, 0, 0);
+        const float a = xc - xm;
+        const float b = j < ny - 1 ? X(-1, 1, 0) - xm : 0.0f;
+        const float c = k < nz - 1 ? X(-1, 0, 1) - xm : 0.0f;
+        gv += a / sqrtf(a * a + b * b + c * c + eps);
+    }
+    if (j > 0) {
+        const float xm = X(0, -1, 0);
+        const float a = i < nx - 1 ? X(1, -1, 0) - xm : 0.0f;
+        const float b = xc - xm;
+        const float c = k < nz - 1 ? X(0, -1, 1) - xm : 0.0f;
+        gv += b / sqrtf(a * a + b * b + c * c + eps);
+    }
+    if (k > 0) {
+        const float xm = X(0, 0, -1);
+        const float a = i < nx - 1 ? X(1, 0, -1) - xm : 0.0f;
+        const float b = j < ny - 1 ? X(0, 1, -1) - xm : 0.0f;
+        const float c = xc - xm;
+        gv += c / sqrtf(a * a + b * b + c * c + eps);
+    }
+    g[o] = gv;
+}
+
+// TV scalars: [0] = ||x_in||^2, [1] = alpha, [2] = ||g||^2
+__global__ void k_tv_alpha(double *scal, double lambda) { scal[1] = lambda * sqrt(scal[0]); }
+
+__global__ void k_tv_update(float *__restrict__ x, const float *__restrict__ g, const double *__restrict__ scal,
+                            int64_t n) {
+    const double ng2 = scal[2];
+    if (!(ng2 > 0.0)) return;
+    const float a = (float)(scal[1] / sqrt(ng2));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = fmaf(-a, g[i], x[i]);
+}
+
+struct Workspace {
+    char *base = nullptr;
+    bool owned = false;
+    hipStream_t st = nullptr;
+    size_t off = 0;
+    void *take(size_t bytes) {
+        void *p = base + off;
+        off += align256(bytes);
+        return p;
+    }
+    ct_status acquire(void *user, size_t bytes, hipStream_t s) {
+        st = s;
+        if (user) {
+            base = (char *)user;
+            return CT_OK;
+        }
+        owned = true;
+        CT_HIP(hipMallocAsync((void **)&base, bytes ? bytes : 256, s));
+        return CT_OK;
+    }
+    ~Workspace() {
+        if (owned && base) (void)hipFreeAsync(base, st);
+    }
+};
+
+}  // namespace
+
+size_t dot_partials_count() { return DOT_BLOCKS; }
+
+ct_status dot_f64(const void *a, const void *b, ct_dtype t, int64_t n, double *out, double *partials, hipStream_t st) {
+    Workspace ws;
+    if (!partials) {
+        ct_status s = ws.acquire(nullptr, DOT_BLOCKS * sizeof(double), st);
+        if (s != CT_OK) return s;
+        partials = (double *)ws.take(DOT_BLOCKS * sizeof(double));
+    }
+    CT_DISPATCH1(t, T,
+                 hipLaunchKernelGGL((k_dot_partial<T>), dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, st, (const T *)a,
+                                    (const T *)b, n, partials));
+    CT_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(DOT_THREADS), 0, st, partials, DOT_BLOCKS, out);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+ct_status convert(const void *src, ct_dtype s_t, void *dst, ct_dtype d_t, int64_t n, hipStream_t st) {
+    if (n == 0) return CT_OK;
+    CT_DISPATCH2(s_t, TS, d_t, TD,
+                 hipLaunchKernelGGL((k_convert<TS, TD>), dim3(ew_grid(n)), dim3(EW_THREADS), 0, st, (const TS *)src,
+                                    (TD *)dst, n));
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// CGLS
+
+size_t cgls_workspace(const ct_plan *p, ct_dtype vt, ct_dtype pt) {
+    const ct_geometry &g = p->g;
+    const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
+    const size_t np = (size_t)g.nDetector[0] * g.nDetector[1] * p->angles.size();
+    return 2 * align256(nv * dtype_size(vt)) + 2 * align256(np * dtype_size(pt)) + align256(DOT_BLOCKS * 8) +
+           align256(S_COUNT * 8);
+}
+
+ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter, double *resid,
+                   void *work, hipStream_t st) {
+    const ct_geometry &g = p->g;
+    const int64_t nv = g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
+    const int64_t na = (int64_t)p->angles.size();
+    const int64_t np = g.nDetector[0] * g.nDetector[1] * na;
+    Workspace ws;
+    ct_status s = ws.acquire(work, cgls_workspace(p, vt, pt), st);
+    if (s != CT_OK) return s;
+    void *r = ws.take(np * dtype_size(pt));
+    void *q = ws.take(np * dtype_size(pt));
+    void *sv = ws.take(nv * dtype_size(vt));
+    void *pv = ws.take(nv * dtype_size(vt));
+    double *parts = (double *)ws.take(DOT_BLOCKS * 8);
+    double *scal = (double *)ws.take(S_COUNT * 8);
+    const Slab full = full_slab(g);
+#define CK(e)                          \
+    do {                               \
+        ct_status s_ = (e);            \
+        if (s_ != CT_OK) return s_;    \
+    } while (0)
+    // r = b - A x ; s = A^T r ; p = s ; gamma = <s,s> ; rho = <r,r>
+    CK(launch_forward(p, CT_SIDDON, x, vt, r, pt, 0, 0, na, full, st));
+    CT_DISPATCH1(pt, T, hipLaunchKernelGGL((k_rsub<T>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, (const T *)b, (T *)r, np));
+    CT_HIP(hipGetLastError());
+    CK(launch_backproject(p, CT_BP_ADJOINT, r, pt, sv, vt, 0, 0, na, full, st));
+    CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_copy<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (const T *)sv, (T *)pv, nv));
+    CT_HIP(hipGetLastError());
+    CK(dot_f64(sv, sv, vt, nv, scal + S_GAMMA, parts, st));
+    CK(dot_f64(r, r, pt, np, scal + S_RHO, parts, st));
+    hipLaunchKernelGGL(k_cgls_start, dim3(1), dim3(1), 0, st, scal, resid);
+    CT_HIP(hipGetLastError());
+    for (int32_t k = 0; k < niter; ++k) {
+        // q = A p ; delta = <q,q> ; alpha = gamma / delta
+        CK(launch_forward(p, CT_SIDDON, pv, vt, q, pt, 0, 0, na, full, st));
+        CK(dot_f64(q, q, pt, np, scal + S_DELTA, parts, st));
+        hipLaunchKernelGGL(k_cgls_alpha, dim3(1), dim3(1), 0, st, scal, resid, k);
+        CT_HIP(hipGetLastError());
+        // x += alpha p ; r -= alpha q
+        CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_axpy_s<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (T *)x, (const T *)pv,
+                                               scal, (int)S_ALPHA, 1.0f, nv));
+        CT_DISPATCH1(pt, T, hipLaunchKernelGGL((k_axpy_s<T>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, (T *)r, (const T *)q,
+                                               scal, (int)S_ALPHA, -1.0f, np));
+        CT_HIP(hipGetLastError());
+        // s = A^T r ; gamma' = <s,s> ; beta = gamma'/gamma ; p = s + beta p
+        CK(launch_backproject(p, CT_BP_ADJOINT, r, pt, sv, vt, 0, 0, na, full, st));
+        CK(dot_f64(sv, sv, vt, nv, scal + S_TMP, parts, st));
+        hipLaunchKernelGGL(k_cgls_beta, dim3(1), dim3(1), 0, st, scal);
+        CT_HIP(hipGetLastError());
+        CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_xpby_s<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (T *)pv, (const T *)sv,
+                                               scal, (int)S_BETA, nv));
+        CT_HIP(hipGetLastError());
+    }
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// SART
+
+size_t sart_workspace(const ct_plan *p) {
+    const ct_geometry &g = p->g;
+    const size_t pix = (size_t)g.nDetector[0] * g.nDetector[1];
+    return align256(pix * p->angles.size() * 4) + align256(pix * 4);
+}
+
+ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, void *work, hipStream_t st) {
+    const ct_geometry &g = p->g;
+    const int64_t na = (int64_t)p->angles.size();
+    const int64_t pix = g.nDetector[0] * g.nDetector[1];
+    Workspace ws;
+    ct_status s = ws.acquire(work, sart_workspace(p), st);
+    if (s != CT_OK) return s;
+    float *chord = (float *)ws.take(pix * na * 4);
+    float *r = (float *)ws.take(pix * 4);
+    const float thr = (float)(1e-2 * std::fmin(g.dVoxel[0], std::fmin(g.dVoxel[1], g.dVoxel[2])));
+    CK(launch_ray_chord(p, chord, 0, na, st));
+    const Slab full = full_slab(g);
+    for (int32_t it = 0; it < niter; ++it) {
+        for (int64_t t = 0; t < na; ++t) {
+            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st));
+            hipLaunchKernelGGL(k_sart_resid, dim3(ew_grid(pix)), dim3(EW_THREADS), 0, st, (const float *)b + t * pix,
+                               chord + t * pix, r, thr, pix);
+            CT_HIP(hipGetLastError());
+            CK(launch_sart_update(p, r, (float *)x, t, (float)lambda, st));
+        }
+    }
+    return CT_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// TV steepest descent
+
+size_t tv_workspace(const ct_geometry &g) {
+    const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
+    return align256(nv * 4) + align256(DOT_BLOCKS * 8) + align256(4 * 8);
+}
+
+ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work, hipStream_t st) {
+    const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1], nz = (int)g.nVoxel[2];
+    const int64_t nv = (int64_t)nx * ny * nz;
+    Workspace ws;
+    ct_status s = ws.acquire(work, tv_workspace(g), st);
+    if (s != CT_OK) return s;
+    float *gbuf = (float *)ws.take(nv * 4);
+    double *parts = (double *)ws.take(DOT_BLOCKS * 8);
+    double *scal = (double *)ws.take(4 * 8);
+    CK(dot_f64(x, x, CT_F32, nv, scal + 0, parts, st));
+    hipLaunchKernelGGL(k_tv_alpha, dim3(1), dim3(1), 0, st, scal, lambda);
+    CT_HIP(hipGetLastError());
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz);
+    for (int32_t k = 0; k < nsteps; ++k) {
+        hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, st, (const float *)x, gbuf, nx, ny, nz, (float)eps);
+        CT_HIP(hipGetLastError());
+        CK(dot_f64(gbuf, gbuf, CT_F32, nv, scal + 2, parts, st));
+        hipLaunchKernelGGL(k_tv_update, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (float *)x, (const float *)gbuf, scal, nv);
+        CT_HIP(hipGetLastError());
+    }
+    return CT_OK;
+#undef CK
+}
+
+}  // namespace ct

@@ -1,0 +1,429 @@
+// Out-of-core operators (Algorithm 1: forward; Algorithm 2: backprojection) on one device under a
+// memory cap.  The image is split into equal axial slabs, as tall as the cap allows after the
+// projection buffers; projections move in chunks of K angles.
+//
+// Forward: per slab, the slab is copied in; for each angle chunk the projection kernel runs into
+// one of three device buffers while, on two copy streams, the previous chunk's result goes out
+// and the next chunk's partial sums (from earlier slabs) come in.  Partial sums are accumulated
+// by the projection kernel itself (it adds into the buffer), so no separate accumulation pass is
+// needed.  Backprojection: per slab, projection chunks stream in double-buffered while the
+// previous chunk is backprojected into the resident slab, which is copied out at the end.
+//
+// Pageable caller memory is staged through pinned buffers by host threads while the device
+// computes; pinned caller memory (hipHostMalloc) is copied directly.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "ct_internal.hpp"
+
+namespace ct {
+
+namespace {
+
+constexpr uint64_t RESERVE = 64ull << 20;      // angle table, allocator slack
+constexpr size_t STAGE_PIECE = 64ull << 20;    // slab staging piece
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+void par_memcpy(void *dst, const void *src, size_t n) {
+    if (n < (16u << 20)) {
+        std::memcpy(dst, src, n);
+        return;
+    }
+    const int nt = 8;
+    std::vector<std::thread> th;
+    const size_t part = (n + nt - 1) / nt;
+    for (int i = 0; i < nt; ++i) {
+        const size_t o = i * part;
+        if (o >= n) break;
+        const size_t len = std::min(part, n - o);
+        th.emplace_back([=] { std::memcpy((char *)dst + o, (const char *)src + o, len); });
+    }
+    for (auto &t : th) t.join();
+}
+
+bool is_pinned(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+struct HostBuf {
+    void *p = nullptr;
+    ~HostBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+struct Streams {
+    hipStream_t comp = nullptr, h2d = nullptr, d2h = nullptr;
+    ~Streams() {
+        if (comp) (void)hipStreamDestroy(comp);
+        if (h2d) (void)hipStreamDestroy(h2d);
+        if (d2h) (void)hipStreamDestroy(d2h);
+    }
+};
+struct Events {
+    std::vector<hipEvent_t> e;
+    ~Events() {
+        for (auto x : e) (void)hipEventDestroy(x);
+    }
+    ct_status make(int n) {
+        e.resize(n, nullptr);
+        for (int i = 0; i < n; ++i) CT_HIP(hipEventCreateWithFlags(&e[i], hipEventDisableTiming));
+        return CT_OK;
+    }
+};
+
+struct Layout {
+    int64_t h;        // slab height
+    int64_t nsp;      // number of slabs
+    int64_t K;        // angles per chunk
+    int64_t halo;     // extra slices each side (interpolated forward)
+};
+
+ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt, uint64_t cap,
+                     Layout &L) {
+    const ct_geometry &g = p->g;
+    const int64_t na = (int64_t)p->angles.size();
+    const uint64_t slice = (uint64_t)g.nVoxel[0] * g.nVoxel[1] * dtype_size(vt);
+    const uint64_t pangle = (uint64_t)g.nDetector[0] * g.nDetector[1] * dtype_size(pt);
+    const int nbuf = direction == 0 ? 3 : 2;
+    L.halo = (direction == 0 && proj == CT_INTERP) ? 1 : 0;
+    // chunk size: enough rays (forward) or angles (backprojection) per launch to fill the device
+    const uint64_t pix = (uint64_t)g.nDetector[0] * g.nDetector[1];
+    int64_t K = direction == 0 ? (int64_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(pix, 1)) : 32;
+    K = std::min<int64_t>(K, na);
+    K = std::max<int64_t>(K, 1);
+    // fewest slabs wins (the image is split as little as possible); among equal counts the larger
+    // chunk, down to an eighth of the target chunk (or 1 angle when not even one slice fits)
+    const int64_t kmin = std::max<int64_t>(1, K / 8);
+    bool found = false;
+    for (int64_t k = K; k >= 1; k = (k == 1 ? 0 : std::max<int64_t>(1, k / 2))) {
+        const uint64_t bufs = nbuf * (uint64_t)k * pangle;
+        int64_t h = 0;
+        if (cap > RESERVE + bufs) h = (int64_t)((cap - RESERVE - bufs) / slice) - 2 * L.halo;
+        if (h >= 1) {
+            h = std::min<int64_t>(h, g.nVoxel[2]);
+            const int64_t nsp = (g.nVoxel[2] + h - 1) / h;
+            if (!found || nsp < L.nsp) {
+                L.nsp = nsp;
+                L.h = (g.nVoxel[2] + nsp - 1) / nsp;  // equal slabs, as tall as possible
+                L.K = k;
+                found = true;
+            }
+        }
+        if (found && k <= kmin) break;
+    }
+    if (found) return CT_OK;
+    return fail(CT_ERR_CAP, "device memory cap is below one slice plus the projection buffers");
+}
+
+}  // namespace
+
+ct_status ooc_plan(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt, uint64_t cap,
+                   ct_ooc_stats *out) {
+    Layout L;
+    ct_status s = layout_for(p, direction, proj, vt, pt, cap, L);
+    if (s != CT_OK) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->n_slabs = (int32_t)L.nsp;
+    out->slab_slices = (int32_t)L.h;
+    out->chunk_angles = (int32_t)L.K;
+    out->n_chunks = (int32_t)(((int64_t)p->angles.size() + L.K - 1) / L.K);
+    return CT_OK;
+}
+
+ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype vt, void *h_proj, ct_dtype pt,
+                      uint64_t cap, ct_ooc_stats *stats) {
+    const auto t_start = clk::now();
+    const ct_geometry &g = p->g;
+    Layout L;
+    ct_status s = layout_for(p, 0, kind, vt, pt, cap, L);
+    if (s != CT_OK) return s;
+    ct_ooc_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.n_slabs = (int32_t)L.nsp;
+    st.slab_slices = (int32_t)L.h;
+    st.chunk_angles = (int32_t)L.K;
+    const int64_t na = (int64_t)p->angles.size(), nz = g.nVoxel[2];
+    const int64_t nchunks = (na + L.K - 1) / L.K;
+    st.n_chunks = (int32_t)nchunks;
+    const size_t slice = (size_t)g.nVoxel[0] * g.nVoxel[1] * dtype_size(vt);
+    const size_t pangle = (size_t)g.nDetector[0] * g.nDetector[1] * dtype_size(pt);
+    const size_t chunk_bytes = (size_t)L.K * pangle;
+    const bool vol_pinned = is_pinned(h_vol), proj_pinned = is_pinned(h_proj);
+
+    auto t0 = clk::now();
+    Streams S;
+    CT_HIP(hipStreamCreateWithFlags(&S.comp, hipStreamNonBlocking));
+    CT_HIP(hipStreamCreateWithFlags(&S.h2d, hipStreamNonBlocking));
+    CT_HIP(hipStreamCreateWithFlags(&S.d2h, hipStreamNonBlocking));
+    DevBuf slab, dbuf[3];
+    CT_HIP(hipMalloc(&slab.p, (L.h + 2 * L.halo) * slice));
+    for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
+    HostBuf sin[3], sout[3], svol[2];
+    if (!proj_pinned)
+        for (int j = 0; j < 3; ++j) {
+            CT_HIP(hipHostMalloc(&sin[j].p, chunk_bytes, hipHostMallocDefault));
+            CT_HIP(hipHostMalloc(&sout[j].p, chunk_bytes, hipHostMallocDefault));
+        }
+    if (!vol_pinned)
+        for (auto &b : svol) CT_HIP(hipHostMalloc(&b.p, STAGE_PIECE, hipHostMallocDefault));
+    Events ev_h2d, ev_k, ev_d2h, ev_vol, tk0, tk1;
+    if ((s = ev_h2d.make(3)) != CT_OK || (s = ev_k.make(3)) != CT_OK || (s = ev_d2h.make(3)) != CT_OK ||
+        (s = ev_vol.make(2)) != CT_OK)
+        return s;
+    tk0.e.resize(nchunks, nullptr);
+    tk1.e.resize(nchunks, nullptr);
+    for (int64_t c = 0; c < nchunks; ++c) {
+        CT_HIP(hipEventCreate(&tk0.e[c]));
+        CT_HIP(hipEventCreate(&tk1.e[c]));
+    }
+    st.t_other_mem_s += secs(t0, clk::now());
+
+    // pending output chunks waiting for their staging buffer to be drained into h_proj
+    int64_t pending[3] = {-1, -1, -1};
+    auto drain = [&](int j) -> ct_status {
+        if (pending[j] < 0) return CT_OK;
+        CT_HIP(hipEventSynchronize(ev_d2h.e[j]));
+        const int64_t c = pending[j];
+        const int64_t nang = std::min(L.K, na - c * L.K);
+        if (!proj_pinned) {
+            auto a = clk::now();
+            par_memcpy((char *)h_proj + c * chunk_bytes, sout[j].p, nang * pangle);
+            st.t_stage_s += secs(a, clk::now());
+        }
+        pending[j] = -1;
+        return CT_OK;
+    };
+
+    for (int64_t n = 0; n < L.nsp; ++n) {
+        const int64_t own_lo = n * L.h, own_hi = std::min(nz, own_lo + L.h);
+        if (own_lo >= own_hi) break;
+        const int64_t mem_lo = std::max<int64_t>(0, own_lo - L.halo);
+        const int64_t mem_hi = std::min<int64_t>(nz, own_hi + L.halo);
+        // the previous slab's kernels must finish before its buffer is overwritten
+        auto a = clk::now();
+        CT_HIP(hipStreamSynchronize(S.comp));
+        const char *src = (const char *)h_vol + mem_lo * slice;
+        const size_t total = (mem_hi - mem_lo) * slice;
+        if (vol_pinned) {
+            CT_HIP(hipMemcpyAsync(slab.p, src, total, hipMemcpyHostToDevice, S.h2d));
+        } else {
+            size_t off = 0;
+            int q = 0;
+            bool used[2] = {false, false};
+            while (off < total) {
+                const size_t len = std::min(STAGE_PIECE, total - off);
+                if (used[q]) CT_HIP(hipEventSynchronize(ev_vol.e[q]));
+                auto b = clk::now();
+                par_memcpy(svol[q].p, src + off, len);
+                st.t_stage_s += secs(b, clk::now());
+                CT_HIP(hipMemcpyAsync((char *)slab.p + off, svol[q].p, len, hipMemcpyHostToDevice, S.h2d));
+                CT_HIP(hipEventRecord(ev_vol.e[q], S.h2d));
+                used[q] = true;
+                off += len;
+                q ^= 1;
+            }
+        }
+        CT_HIP(hipStreamSynchronize(S.h2d));
+        st.bytes_h2d += (double)total;
+        st.t_other_mem_s += secs(a, clk::now());
+
+        Slab sl;
+        sl.own_lo = own_lo;
+        sl.own_hi = own_hi;
+        sl.mem_lo = mem_lo;
+        sl.mem_n = mem_hi - mem_lo;
+        sl.first = (n == 0);
+        sl.last = (own_hi == nz);
+        const bool acc = n > 0;
+        for (int64_t c = 0; c < nchunks; ++c) {
+            const int j = (int)(c % 3);
+            const int64_t a0 = c * L.K, a1 = std::min(na, a0 + L.K);
+            const size_t bytes = (a1 - a0) * pangle;
+            if ((s = drain(j)) != CT_OK) return s;
+            if (acc) {
+                // partial sums of earlier slabs for this chunk come in (buffer free once its last D2H ended)
+                CT_HIP(hipStreamWaitEvent(S.h2d, ev_d2h.e[j], 0));
+                const void *from = (const char *)h_proj + a0 * pangle;
+                if (!proj_pinned) {
+                    CT_HIP(hipEventSynchronize(ev_h2d.e[j]));
+                    auto b = clk::now();
+                    par_memcpy(sin[j].p, from, bytes);
+                    st.t_stage_s += secs(b, clk::now());
+                    from = sin[j].p;
+                }
+                CT_HIP(hipMemcpyAsync(dbuf[j].p, from, bytes, hipMemcpyHostToDevice, S.h2d));
+                CT_HIP(hipEventRecord(ev_h2d.e[j], S.h2d));
+                CT_HIP(hipStreamWaitEvent(S.comp, ev_h2d.e[j], 0));
+                st.bytes_h2d += (double)bytes;
+            } else {
+                CT_HIP(hipStreamWaitEvent(S.comp, ev_d2h.e[j], 0));
+            }
+            CT_HIP(hipEventRecord(tk0.e[c], S.comp));
+            if ((s = launch_forward(p, kind, slab.p, vt, dbuf[j].p, pt, acc ? 1 : 0, a0, a1, sl, S.comp)) != CT_OK)
+                return s;
+            CT_HIP(hipEventRecord(tk1.e[c], S.comp));
+            CT_HIP(hipEventRecord(ev_k.e[j], S.comp));
+            CT_HIP(hipStreamWaitEvent(S.d2h, ev_k.e[j], 0));
+            void *to = proj_pinned ? (char *)h_proj + a0 * pangle : sout[j].p;
+            CT_HIP(hipMemcpyAsync(to, dbuf[j].p, bytes, hipMemcpyDeviceToHost, S.d2h));
+            CT_HIP(hipEventRecord(ev_d2h.e[j], S.d2h));
+            st.bytes_d2h += (double)bytes;
+            pending[j] = c;
+        }
+        for (int j = 0; j < 3; ++j)
+            if ((s = drain(j)) != CT_OK) return s;
+        CT_HIP(hipStreamSynchronize(S.comp));
+        for (int64_t c = 0; c < nchunks; ++c) {
+            float ms = 0;
+            CT_HIP(hipEventElapsedTime(&ms, tk0.e[c], tk1.e[c]));
+            st.t_compute_s += ms * 1e-3;
+        }
+    }
+    CT_HIP(hipStreamSynchronize(S.d2h));
+    st.t_total_s = secs(t_start, clk::now());
+    if (stats) *stats = st;
+    return CT_OK;
+}
+
+ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj, ct_dtype pt, void *h_vol, ct_dtype vt,
+                          uint64_t cap, ct_ooc_stats *stats) {
+    const auto t_start = clk::now();
+    const ct_geometry &g = p->g;
+    Layout L;
+    ct_status s = layout_for(p, 1, CT_SIDDON, vt, pt, cap, L);
+    if (s != CT_OK) return s;
+    ct_ooc_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.n_slabs = (int32_t)L.nsp;
+    st.slab_slices = (int32_t)L.h;
+    st.chunk_angles = (int32_t)L.K;
+    const int64_t na = (int64_t)p->angles.size(), nz = g.nVoxel[2];
+    const int64_t nchunks = (na + L.K - 1) / L.K;
+    st.n_chunks = (int32_t)nchunks;
+    const size_t slice = (size_t)g.nVoxel[0] * g.nVoxel[1] * dtype_size(vt);
+    const size_t pangle = (size_t)g.nDetector[0] * g.nDetector[1] * dtype_size(pt);
+    const size_t chunk_bytes = (size_t)L.K * pangle;
+    const bool vol_pinned = is_pinned(h_vol), proj_pinned = is_pinned(h_proj);
+
+    auto t0 = clk::now();
+    Streams S;
+    CT_HIP(hipStreamCreateWithFlags(&S.comp, hipStreamNonBlocking));
+    CT_HIP(hipStreamCreateWithFlags(&S.h2d, hipStreamNonBlocking));
+    CT_HIP(hipStreamCreateWithFlags(&S.d2h, hipStreamNonBlocking));
+    DevBuf slab, dbuf[2];
+    CT_HIP(hipMalloc(&slab.p, L.h * slice));
+    for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
+    HostBuf sin[2], svol[2];
+    if (!proj_pinned)
+        for (auto &b : sin) CT_HIP(hipHostMalloc(&b.p, chunk_bytes, hipHostMallocDefault));
+    if (!vol_pinned)
+        for (auto &b : svol) CT_HIP(hipHostMalloc(&b.p, STAGE_PIECE, hipHostMallocDefault));
+    Events ev_h2d, ev_k, ev_vol, tk0, tk1;
+    if ((s = ev_h2d.make(2)) != CT_OK || (s = ev_k.make(2)) != CT_OK || (s = ev_vol.make(2)) != CT_OK) return s;
+    tk0.e.resize(nchunks, nullptr);
+    tk1.e.resize(nchunks, nullptr);
+    for (int64_t c = 0; c < nchunks; ++c) {
+        CT_HIP(hipEventCreate(&tk0.e[c]));
+        CT_HIP(hipEventCreate(&tk1.e[c]));
+    }
+    st.t_other_mem_s += secs(t0, clk::now());
+
+    for (int64_t n = 0; n < L.nsp; ++n) {
+        const int64_t own_lo = n * L.h, own_hi = std::min(nz, own_lo + L.h);
+        if (own_lo >= own_hi) break;
+        Slab sl;
+        sl.own_lo = own_lo;
+        sl.own_hi = own_hi;
+        sl.mem_lo = own_lo;
+        sl.mem_n = own_hi - own_lo;
+        sl.first = sl.last = true;
+        bool h2d_used[2] = {false, false};
+        for (int64_t c = 0; c < nchunks; ++c) {
+            const int j = (int)(c % 2);
+            const int64_t a0 = c * L.K, a1 = std::min(na, a0 + L.K);
+            const size_t bytes = (a1 - a0) * pangle;
+            // device buffer j is free once the kernel two chunks back has read it
+            CT_HIP(hipStreamWaitEvent(S.h2d, ev_k.e[j], 0));
+            const void *from = (const char *)h_proj + a0 * pangle;
+            if (!proj_pinned) {
+                if (h2d_used[j]) CT_HIP(hipEventSynchronize(ev_h2d.e[j]));
+                auto b = clk::now();
+                par_memcpy(sin[j].p, from, bytes);
+                st.t_stage_s += secs(b, clk::now());
+                from = sin[j].p;
+            }
+            CT_HIP(hipMemcpyAsync(dbuf[j].p, from, bytes, hipMemcpyHostToDevice, S.h2d));
+            CT_HIP(hipEventRecord(ev_h2d.e[j], S.h2d));
+            h2d_used[j] = true;
+            st.bytes_h2d += (double)bytes;
+            CT_HIP(hipStreamWaitEvent(S.comp, ev_h2d.e[j], 0));
+            CT_HIP(hipEventRecord(tk0.e[c], S.comp));
+            if ((s = launch_backproject(p, kind, dbuf[j].p, pt, slab.p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp)) != CT_OK)
+                return s;
+            CT_HIP(hipEventRecord(tk1.e[c], S.comp));
+            CT_HIP(hipEventRecord(ev_k.e[j], S.comp));
+        }
+        // slab out
+        auto a = clk::now();
+        CT_HIP(hipStreamSynchronize(S.comp));
+        for (int64_t c = 0; c < nchunks; ++c) {
+            float ms = 0;
+            CT_HIP(hipEventElapsedTime(&ms, tk0.e[c], tk1.e[c]));
+            st.t_compute_s += ms * 1e-3;
+        }
+        char *dst = (char *)h_vol + own_lo * slice;
+        const size_t total = (own_hi - own_lo) * slice;
+        if (vol_pinned) {
+            CT_HIP(hipMemcpyAsync(dst, slab.p, total, hipMemcpyDeviceToHost, S.d2h));
+            CT_HIP(hipStreamSynchronize(S.d2h));
+        } else {
+            // pipelined: piece q goes D2H while piece q-1 is copied out of staging by the host
+            size_t off = 0, prev_off = 0, prev_len = 0;
+            int q = 0, prev_q = -1;
+            while (off < total || prev_q >= 0) {
+                int cur = -1;
+                size_t len = 0;
+                if (off < total) {
+                    len = std::min(STAGE_PIECE, total - off);
+                    CT_HIP(hipMemcpyAsync(svol[q].p, (char *)slab.p + off, len, hipMemcpyDeviceToHost, S.d2h));
+                    CT_HIP(hipEventRecord(ev_vol.e[q], S.d2h));
+                    cur = q;
+                }
+                if (prev_q >= 0) {
+                    CT_HIP(hipEventSynchronize(ev_vol.e[prev_q]));
+                    auto b = clk::now();
+                    par_memcpy(dst + prev_off, svol[prev_q].p, prev_len);
+                    st.t_stage_s += secs(b, clk::now());
+                }
+                prev_q = cur;
+                prev_off = off;
+                prev_len = len;
+                off += len;
+                q ^= 1;
+            }
+        }
+        st.bytes_d2h += (double)total;
+        st.t_other_mem_s += secs(a, clk::now());
+    }
+    st.t_total_s = secs(t_start, clk::now());
+    if (stats) *stats = st;
+    return CT_OK;
+}
+
+}  // namespace ct

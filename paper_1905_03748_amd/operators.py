@@ -1,0 +1,163 @@
+"""Torch-facing wrappers over the C ABI: tensors in, tensors out, launched on torch's current
+stream.  Only marshalling happens here (pointers, dtypes, shapes, stream handles); every step of
+the computation runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+_TORCH_DT = {torch.float32: A.CT_F32, torch.float16: A.CT_F16, torch.bfloat16: A.CT_BF16}
+_PROJ = {"siddon": A.CT_SIDDON, "interp": A.CT_INTERP}
+_BP = {"fdk": A.CT_BP_FDK, "pm": A.CT_BP_PSEUDO_MATCHED, "pseudo_matched": A.CT_BP_PSEUDO_MATCHED,
+       "adjoint": A.CT_BP_ADJOINT, "matched": A.CT_BP_ADJOINT}
+
+
+def ct_dtype(t: torch.dtype) -> int:
+    try:
+        return _TORCH_DT[t]
+    except KeyError:
+        raise TypeError(f"unsupported storage dtype {t}") from None
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, shape, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+class Plan:
+    """A validated geometry and angle set (``ct_plan``).
+
+    geometry: dict with DSO, DSD, nVoxel (Nx,Ny,Nz), dVoxel, offOrigin, nDetector (Nu,Nv),
+    dDetector, offDetector, accuracy.  Volumes are [Nz, Ny, Nx]; projections [n_angles, Nv, Nu].
+    """
+
+    def __init__(self, geometry: dict, angles):
+        self.geometry = dict(geometry)
+        self.cgeom = A.make_geometry(geometry)
+        self.angles = np.ascontiguousarray(angles, dtype=np.float64)
+        self.handle = A.ct_plan_create(self.cgeom, self.angles)
+        nx, ny, nz = (int(v) for v in geometry["nVoxel"])
+        nu, nv = (int(v) for v in geometry["nDetector"])
+        self.vol_shape = (nz, ny, nx)
+        self.n_angles = len(self.angles)
+        self.proj_shape = (self.n_angles, nv, nu)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            A.ct_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- resident operators ---------------------------------------------------------------------
+    def forward(self, vol: torch.Tensor, projector="siddon", out: torch.Tensor | None = None, out_dtype=None,
+                accumulate=False, angle_begin=0, angle_end=None, stream=None) -> torch.Tensor:
+        angle_end = self.n_angles if angle_end is None else angle_end
+        shape = (angle_end - angle_begin,) + self.proj_shape[1:]
+        if out is None:
+            out = torch.empty(shape, dtype=out_dtype or vol.dtype, device=vol.device)
+        A.ct_forward(self.handle, _PROJ[projector], _dev(vol, self.vol_shape, "vol"), ct_dtype(vol.dtype),
+                     _dev(out, shape, "proj"), ct_dtype(out.dtype), accumulate, angle_begin, angle_end,
+                     _stream(stream))
+        return out
+
+    def backproject(self, proj: torch.Tensor, kind="fdk", out: torch.Tensor | None = None, out_dtype=None,
+                    accumulate=False, angle_begin=0, angle_end=None, stream=None) -> torch.Tensor:
+        angle_end = self.n_angles if angle_end is None else angle_end
+        shape = (angle_end - angle_begin,) + self.proj_shape[1:]
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=out_dtype or proj.dtype, device=proj.device)
+        A.ct_backproject(self.handle, _BP[kind], _dev(proj, shape, "proj"), ct_dtype(proj.dtype),
+                         _dev(out, self.vol_shape, "vol"), ct_dtype(out.dtype), accumulate, angle_begin, angle_end,
+                         _stream(stream))
+        return out
+
+    # -- out-of-core operators (host tensors) ---------------------------------------------------
+    def forward_host(self, vol: torch.Tensor, out: torch.Tensor, projector="siddon", cap_bytes=32 << 30) -> dict:
+        assert vol.device.type == "cpu" and out.device.type == "cpu" and vol.is_contiguous() and out.is_contiguous()
+        s = A.ct_forward_host(self.handle, _PROJ[projector], vol.data_ptr(), ct_dtype(vol.dtype), out.data_ptr(),
+                              ct_dtype(out.dtype), cap_bytes)
+        return s.as_dict()
+
+    def backproject_host(self, proj: torch.Tensor, out: torch.Tensor, kind="fdk", cap_bytes=32 << 30) -> dict:
+        assert proj.device.type == "cpu" and out.device.type == "cpu" and proj.is_contiguous() and out.is_contiguous()
+        s = A.ct_backproject_host(self.handle, _BP[kind], proj.data_ptr(), ct_dtype(proj.dtype), out.data_ptr(),
+                                  ct_dtype(out.dtype), cap_bytes)
+        return s.as_dict()
+
+    def ooc_plan(self, direction=0, projector="siddon", vol_dtype=torch.float32, proj_dtype=torch.float32,
+                 cap_bytes=32 << 30) -> dict:
+        return A.ct_ooc_plan(self.handle, direction, _PROJ[projector], ct_dtype(vol_dtype), ct_dtype(proj_dtype),
+                             cap_bytes).as_dict()
+
+    # -- algorithms -----------------------------------------------------------------------------
+    def cgls_workspace_bytes(self, vol_dtype=torch.float32, proj_dtype=torch.float32) -> int:
+        return A.ct_cgls_workspace_bytes(self.handle, ct_dtype(vol_dtype), ct_dtype(proj_dtype))
+
+    def cgls(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, vol_dtype=None,
+             resid: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+        """Runs CGLS in place on x (zeros if None); returns (x, resid) with resid a device FP64
+        tensor of niter+1 residual norms."""
+        if x is None:
+            x = torch.zeros(self.vol_shape, dtype=vol_dtype or b.dtype, device=b.device)
+        if resid is None:
+            resid = torch.empty(niter + 1, dtype=torch.float64, device=b.device)
+        A.ct_cgls(self.handle, _dev(b, self.proj_shape, "b"), ct_dtype(b.dtype), _dev(x, self.vol_shape, "x"),
+                  ct_dtype(x.dtype), niter, resid.data_ptr(), workspace.data_ptr() if workspace is not None else 0,
+                  _stream(stream))
+        return x, resid
+
+    def sart(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, lam=1.0, workspace=None, stream=None):
+        if x is None:
+            x = torch.zeros(self.vol_shape, dtype=torch.float32, device=b.device)
+        A.ct_sart(self.handle, _dev(b, self.proj_shape, "b"), _dev(x, self.vol_shape, "x"), niter, lam, 1,
+                  workspace.data_ptr() if workspace is not None else 0, _stream(stream))
+        return x
+
+
+def tv_steps(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps: float = 1e-8, workspace=None,
+             stream=None) -> torch.Tensor:
+    """TV steepest descent in place on the FP32 device volume x."""
+    g = A.make_geometry(geometry)
+    nx, ny, nz = (int(v) for v in geometry["nVoxel"])
+    if x.dtype != torch.float32:
+        raise TypeError("tv_steps works on FP32 volumes")
+    A.ct_tv_steps(g, _dev(x, (nz, ny, nx), "x"), nsteps, lam, eps,
+                  workspace.data_ptr() if workspace is not None else 0, _stream(stream))
+    return x
+
+
+def tv_workspace_bytes(geometry: dict) -> int:
+    return A.ct_tv_workspace_bytes(A.make_geometry(geometry))
+
+
+def dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    A.ct_dot(a.data_ptr(), b.data_ptr(), ct_dtype(a.dtype), a.numel(), out.data_ptr(), _stream(stream))
+    return out
+
+
+def convert(src: torch.Tensor, dtype: torch.dtype, stream=None) -> torch.Tensor:
+    out = torch.empty(src.shape, dtype=dtype, device=src.device)
+    A.ct_convert(src.data_ptr(), ct_dtype(src.dtype), out.data_ptr(), ct_dtype(dtype), src.numel(), _stream(stream))
+    return out

@@ -1,0 +1,144 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and exports every function
+declared in include/ct.h; geometry validation; the out-of-core slab/chunk planner (Algorithms 1
+and 2: equal axial slabs as tall as the memory cap allows, projection chunk buffers)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1905_03748_amd import _abi as A
+from paper_1905_03748_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ct_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return A.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 18, names
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in A.SIGNATURES, f"binding lacks {n}"
+    assert A.ct_version().startswith("ct-mi355x")
+
+
+def _geo(**kw):
+    d = inputs.workload("tiny").geometry_dict()
+    d.update(kw)
+    return A.make_geometry(d)
+
+
+def test_plan_create_and_info(lib):
+    w = inputs.workload("tiny")
+    p = A.ct_plan_create(_geo(), w.angles)
+    g, n = A.ct_plan_info(p)
+    assert n == 64 and g.nVoxel[:] == [64, 64, 64] and g.accuracy == 0.5
+    A.ct_plan_destroy(p)
+    p = A.ct_plan_create(_geo(accuracy=0.0), w.angles)   # 0 selects the default spacing
+    assert A.ct_plan_info(p)[0].accuracy == 0.5
+    A.ct_plan_destroy(p)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(DSD=900.0), A.CT_ERR_GEOMETRY),                      # DSD <= DSO
+    (dict(DSO=-1.0), A.CT_ERR_GEOMETRY),
+    (dict(nVoxel=(64, 0, 64)), A.CT_ERR_GEOMETRY),
+    (dict(dVoxel=(1.0, -1.0, 1.0)), A.CT_ERR_GEOMETRY),
+    (dict(dDetector=(0.0, 1.6)), A.CT_ERR_GEOMETRY),
+    (dict(dVoxel=(40.0, 40.0, 1.0)), A.CT_ERR_GEOMETRY),      # volume reaches past the source orbit
+    (dict(offOrigin=(990.0, 0.0, 0.0)), A.CT_ERR_GEOMETRY),
+    (dict(accuracy=1.5), A.CT_ERR_GEOMETRY),
+])
+def test_plan_validation(lib, kw, status):
+    with pytest.raises(A.CtError) as e:
+        A.ct_plan_create(_geo(**kw), [0.0, 1.0])
+    assert e.value.status == status
+    assert A.ct_last_error()
+
+
+def test_plan_rejects_bad_angles(lib):
+    with pytest.raises(A.CtError) as e:
+        A.ct_plan_create(_geo(), [0.0, float("nan")])
+    assert e.value.status == A.CT_ERR_GEOMETRY
+    with pytest.raises(A.CtError) as e:
+        A.ct_plan_create(_geo(), [])
+    assert e.value.status == A.CT_ERR_ARG
+
+
+def test_calls_validate_before_device_work(lib):
+    w = inputs.workload("tiny")
+    p = A.ct_plan_create(_geo(), w.angles)
+    try:
+        for call in (lambda: A.ct_forward(p, A.CT_SIDDON, 0, A.CT_F32, 0, A.CT_F32, 0, 0, 64),
+                     lambda: A.ct_forward(p, 7, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 64),
+                     lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 0, 5, 5),
+                     lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 65),
+                     lambda: A.ct_backproject(p, 9, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 64),
+                     lambda: A.ct_sart(p, 16, 16, 1, 1.0, 4),
+                     lambda: A.ct_cgls(p, 16, A.CT_F32, 16, A.CT_F32, -1)):
+            with pytest.raises(A.CtError) as e:
+                call()
+            assert e.value.status == A.CT_ERR_ARG
+        with pytest.raises(A.CtError) as e:
+            A.ct_forward(p, A.CT_SIDDON, 16, 9, 16, A.CT_F32, 0, 0, 64)
+        assert e.value.status == A.CT_ERR_DTYPE
+    finally:
+        A.ct_plan_destroy(p)
+
+
+def test_ooc_planner_out_of_core_config(lib):
+    # 3072^3 FP32 volume (108 GiB), 3072 projections of 3072^2, 32 GiB device cap
+    w = inputs.workload("ooc")
+    p = A.ct_plan_create(A.make_geometry(w.geometry_dict()), w.angles)
+    try:
+        fw = A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F32, A.CT_F32, 32 << 30)
+        slice_b = 3072 * 3072 * 4
+        assert fw.n_slabs == 4 and fw.slab_slices == 768, fw.as_dict()
+        assert fw.slab_slices * slice_b + 3 * fw.chunk_angles * slice_b <= 32 << 30
+        bp = A.ct_ooc_plan(p, 1, A.CT_SIDDON, A.CT_F32, A.CT_F32, 32 << 30)
+        assert bp.n_slabs >= 4 and bp.slab_slices * slice_b + 2 * bp.chunk_angles * slice_b <= 32 << 30
+        # FP16 storage halves the slabs
+        h = A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F16, A.CT_F16, 32 << 30)
+        assert h.n_slabs == 2 and h.slab_slices == 1536
+        # a cap below one slice plus the buffers fails cleanly
+        with pytest.raises(A.CtError) as e:
+            A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F32, A.CT_F32, 100 << 20)
+        assert e.value.status == A.CT_ERR_CAP
+    finally:
+        A.ct_plan_destroy(p)
+
+
+def test_ooc_planner_equal_slabs_and_halo(lib):
+    w = inputs.workload("tiny")
+    p = A.ct_plan_create(_geo(), w.angles)
+    reserve = 64 << 20
+    try:
+        slice_b = 64 * 64 * 4
+        pangle = 64 * 64 * 4
+        for nslices in (1, 5, 13, 40, 64, 100):
+            cap = reserve + 3 * 64 * pangle + nslices * slice_b
+            for kind, halo in ((A.CT_SIDDON, 0), (A.CT_INTERP, 1)):
+                for direction, nbuf in ((0, 3), (1, 2)):
+                    s = A.ct_ooc_plan(p, direction, kind, A.CT_F32, A.CT_F32, cap)
+                    h = halo if direction == 0 else 0
+                    assert s.n_slabs * s.slab_slices >= 64
+                    assert s.slab_slices == -(-64 // s.n_slabs)            # equal slabs
+                    assert (s.n_slabs - 1) * s.slab_slices < 64
+                    assert reserve + (s.slab_slices + 2 * h) * slice_b + nbuf * s.chunk_angles * pangle <= cap
+                    assert s.n_chunks == -(-64 // s.chunk_angles)
+            # with room for the whole volume and full chunks: one slab
+            if nslices >= 64:
+                assert A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F32, A.CT_F32, cap).n_slabs == 1
+    finally:
+        A.ct_plan_destroy(p)

@@ -1,0 +1,146 @@
+"""GPU parity of the device-resident algorithms (CGLS, SART, TV steepest descent) and the FP64
+reduction against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import rel_l2, say
+from paper_1905_03748_amd import inputs
+from paper_1905_03748_amd.operators import Plan, dot, tv_steps
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def tiny(orc):
+    w = inputs.workload("tiny")
+    ells = inputs.ellipsoids(w)
+    b = inputs.analytic_projections(w, ells)      # exact line integrals of the continuous phantom
+    return w, w.geometry_dict(), b, orc.Geometry.from_dict(w.geometry_dict())
+
+
+def test_dot_fp64(orc):
+    rng = np.random.default_rng(3)
+    for n in (1, 255, 4097, 1_000_003):
+        a = rng.standard_normal(n).astype(np.float32)
+        b = rng.standard_normal(n).astype(np.float32)
+        say(f"[dot] n={n}")
+        got = float(dot(torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV)).cpu())
+        ref = float(np.dot(a.astype(np.float64), b.astype(np.float64)))
+        assert abs(got - ref) <= 1e-12 * np.sqrt(n) * (np.abs(a).max() * np.abs(b).max()) + 1e-14
+
+
+def test_cgls_parity_tiny(tiny, orc):
+    w, geo, b, og = tiny
+    plan = Plan(geo, w.angles)
+    bt = torch.from_numpy(b).to(DEV)
+    A = lambda x: orc.siddon_fwd(og, w.angles, x)
+    At = lambda y: orc.siddon_adj(og, w.angles, y)
+    xr, rr = orc.cgls(A, At, b.astype(np.float64), 5)
+    say("[cgls] tiny 5 iterations")
+    x, res = plan.cgls(bt, 5)
+    x = x.cpu().numpy()
+    res = res.cpu().numpy()
+    e = rel_l2(x, xr)
+    say(f"   x rel L2 {e:.3e}; resid {res} vs {rr}")
+    assert e <= 1e-4
+    np.testing.assert_allclose(res, rr, rtol=1e-5)
+    assert np.all(np.diff(res) <= 1e-6 * res[0])
+
+
+def test_cgls_edge_cases(tiny):
+    w, geo, b, og = tiny
+    plan = Plan(geo, w.angles)
+    # zero data: the first step has A p = 0, the iteration stops and x stays 0
+    z = torch.zeros(plan.proj_shape, device=DEV)
+    x, res = plan.cgls(z, 3)
+    assert float(x.abs().max()) == 0.0 and np.all(res.cpu().numpy() == 0.0)
+    # no iterations: x unchanged, one residual norm
+    bt = torch.from_numpy(b).to(DEV)
+    x0 = torch.full(plan.vol_shape, 0.25, device=DEV)
+    x, res = plan.cgls(bt, 0, x=x0.clone())
+    assert torch.equal(x, x0) and res.numel() == 1
+    # warm start continues the same recurrence: 2 + 3 iterations from zero equal 5 from zero
+    # only approximately (the restart resets the search direction), and never increase the residual
+    x2, r2 = plan.cgls(bt, 2)
+    x5, r5 = plan.cgls(bt, 3, x=x2.clone())
+    assert float(r5[-1]) <= float(r2[-1])
+
+
+@pytest.mark.parametrize("dt,tol", [(torch.float16, 5e-3), (torch.bfloat16, 4e-2)])
+def test_cgls_16bit_storage_reported(tiny, orc, dt, tol):
+    w, geo, b, og = tiny
+    plan = Plan(geo, w.angles)
+    A = lambda x: orc.siddon_fwd(og, w.angles, x)
+    At = lambda y: orc.siddon_adj(og, w.angles, y)
+    xr, _ = orc.cgls(A, At, b.astype(np.float64), 5)
+    bt = torch.from_numpy(b).to(DEV).to(dt)
+    x, res = plan.cgls(bt, 5, vol_dtype=dt)
+    e = rel_l2(x.float().cpu().numpy(), xr)
+    say(f"[cgls 16-bit] {dt}: x rel L2 vs FP64 oracle {e:.3e}")
+    assert e <= tol
+
+
+def test_sart_parity_tiny(tiny, orc):
+    w, geo, b, og = tiny
+    # a smaller angle set keeps the per-angle oracle quick
+    ang = w.angles[::2]
+    bb = b[::2].copy()
+    plan = Plan(geo, ang)
+    say("[sart] tiny 1 sweep, 32 angles")
+    x = plan.sart(torch.from_numpy(bb).to(DEV), 1).cpu().numpy()
+    xr = orc.sart(og, ang, bb.astype(np.float64), 1)
+    e = rel_l2(x, xr)
+    say(f"   rel L2 {e:.3e}")
+    assert e <= 1e-4
+    # a second sweep keeps reducing the data residual
+    x2 = plan.sart(torch.from_numpy(bb).to(DEV), 2).cpu().numpy()
+    r1 = np.linalg.norm(orc.siddon_fwd(og, ang, x.astype(np.float64)) - bb)
+    r2 = np.linalg.norm(orc.siddon_fwd(og, ang, x2.astype(np.float64)) - bb)
+    assert r2 < r1
+
+
+def test_tv_parity(orc):
+    rng = np.random.default_rng(8)
+    for shape in ((23, 17, 31), (64, 64, 64)):
+        nz, ny, nx = shape
+        x0 = (rng.uniform(0, 1, shape) > 0.7).astype(np.float32) * 0.8 + 0.05 * rng.standard_normal(shape).astype(np.float32)
+        geo = dict(DSO=1000.0, DSD=1500.0, nVoxel=(nx, ny, nz), dVoxel=(1.0, 1.0, 1.0), offOrigin=(0, 0, 0),
+                   nDetector=(8, 8), dDetector=(1.0, 1.0), offDetector=(0, 0), accuracy=0.5)
+        say(f"[tv] shape={shape}")
+        xt = torch.from_numpy(x0).to(DEV)
+        tv_steps(geo, xt, 5, 0.01)
+        xr = orc.tv_steps(x0.astype(np.float64), 5, 0.01)
+        e = rel_l2(xt.cpu().numpy(), xr)
+        say(f"   rel L2 {e:.3e}")
+        assert e <= 1e-5
+        # the gradient itself: one step of lam = 1 from x0 moves by alpha = ||x0|| along -g/||g||
+        g = orc.tv_grad(x0.astype(np.float64))
+        assert np.linalg.norm(g) > 0
+    # constant image: no motion
+    xc = torch.full((8, 9, 10), 0.3, device=DEV)
+    geo = dict(DSO=1000.0, DSD=1500.0, nVoxel=(10, 9, 8), dVoxel=(1.0, 1.0, 1.0), offOrigin=(0, 0, 0),
+               nDetector=(8, 8), dDetector=(1.0, 1.0), offDetector=(0, 0), accuracy=0.5)
+    tv_steps(geo, xc, 5, 0.01)
+    assert float((xc - 0.3).abs().max()) == 0.0
+
+
+def test_medium_cgls_sart_run(orc):
+    """The 512^3 / 360-angle workload with Poisson noise: CGLS and SART iterations run and reduce the
+    data residual (their iterates are compared with the oracle on the small workload above)."""
+    w = inputs.workload("medium")
+    plan = Plan(w.geometry_dict(), w.angles)
+    vol = torch.from_numpy(inputs.voxelize(w)).to(DEV)
+    # measured data stand-in: projections of the voxel phantom plus photon noise
+    b = plan.forward(vol, "siddon").cpu().numpy()
+    b = torch.from_numpy(inputs.add_poisson_noise(b, w.noise_photons, w.seed + 100)).to(DEV)
+    say("[medium] CGLS 4 iterations")
+    x, res = plan.cgls(b, 4)
+    res = res.cpu().numpy()
+    assert np.all(np.diff(res) < 0)
+    say("[medium] SART 1 sweep")
+    xs = plan.sart(b, 1)
+    r0 = float(torch.linalg.vector_norm(b.double()))
+    r1 = float(torch.linalg.vector_norm((plan.forward(xs, "siddon") - b).double()))
+    assert r1 < 0.5 * r0
