@@ -31,6 +31,11 @@ SIDDON_SEG_PER_VP = 1.132
 BYTES_PER_VP = {"siddon": 4.0 * SIDDON_SEG_PER_VP, "fdk": 16.0}
 
 
+def A_sart_ws(plan):
+    from paper_1905_03748_amd import _abi
+    return _abi.ct_sart_workspace_bytes(plan.handle)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -73,6 +78,194 @@ def cpu_baseline(w, vol, proj_sample_s=8.0, bp_sample_s=8.0):
                       f"({dt_b:.1f} s) of the 512^3/360/512^2 workload, extrapolated to one full Ax + A^T y"}
 
 
+def serving_bench(dev, n_requests=12, seed=7, slots=8):
+    """Reconstruction requests (10 CGLS iterations + 5 TV steps each) with volumes uniform in
+    {128,192,256,384,512}^3 and angle counts uniform in {90,180,360,720}: one-at-a-time capacity,
+    continuous batching of the same set, and Poisson arrivals at 0.9x the one-at-a-time capacity."""
+    import torch
+    from paper_1905_03748_amd import inputs
+    from paper_1905_03748_amd.operators import Plan
+    from paper_1905_03748_amd.serve import Request, Server
+
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice([128, 192, 256, 384, 512], n_requests)
+    angs = rng.choice([90, 180, 360, 720], n_requests)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    reqs = []
+    for r, (n, na) in enumerate(zip(sizes, angs)):
+        w = inputs.workload(f"serve_{int(n)}", n_angles=int(na), seed=1000 + r)
+        x = inputs.voxelize_torch(w, device=dev)
+        plan = Plan(w.geometry_dict(), w.angles)
+        p = plan.forward(x, "siddon")
+        # photon noise, 1e5 photons per ray (densities read as 1/cm, lengths in mm)
+        counts = torch.poisson(1e5 * torch.exp(-p / 10.0), generator=gen).clamp_min(1.0)
+        b = (-10.0 * torch.log(counts / 1e5)).float().cpu().pin_memory()
+        plan.close()
+        reqs.append(Request(w.geometry_dict(), w.angles, b, niter=10, tv_steps=5, tv_lambda=0.01, rid=r))
+    torch.cuda.synchronize()
+
+    def clone(q):
+        return Request(q.geometry, q.angles, q.b, niter=q.niter, tv_steps=q.tv_steps, tv_lambda=q.tv_lambda, rid=q.rid)
+
+    budget = 200 << 30
+    out = {"requests": n_requests, "mix": [f"{int(n)}^3 x {int(a)}" for n, a in zip(sizes, angs)],
+           "per_request": "10 CGLS iterations + 5 TV steps (lambda 0.01)", "hbm_budget_gib": budget >> 30}
+    # warm the allocator and kernels once
+    srv = Server(budget, max_slots=1, device=dev)
+    srv.submit(clone(reqs[0])).done.wait()
+    srv.close()
+    for name, nslots in (("one_at_a_time", 1), ("batched", slots)):
+        srv = Server(budget, max_slots=nslots, device=dev)
+        t0 = time.perf_counter()
+        for q in reqs:
+            srv.submit(clone(q))
+        srv.drain()
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        log(f"[bench] serving {name}: {dt:.2f} s")
+        out[name] = {"slots": nslots, "wall_s": round(dt, 3), "throughput_req_s": round(n_requests / dt, 3),
+                     "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                     "throughput_gvps": round(st["throughput_gvps"], 1), "max_active": st["max_active"]}
+    cap = out["one_at_a_time"]["throughput_req_s"]
+    qps = 0.9 * cap
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / qps, n_requests)
+    srv = Server(budget, max_slots=slots, device=dev)
+    t0 = time.perf_counter()
+    for q, g in zip(reqs, np.cumsum(gaps)):
+        while time.perf_counter() - t0 < g:
+            time.sleep(0.0005)
+        srv.submit(clone(q))
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    out["poisson"] = {"qps": round(qps, 3), "load": 0.9, "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                      "max_active": st["max_active"], "peak_hbm_gib": round(st["peak_hbm_bytes"] / 2 ** 30, 2)}
+    out["batched_vs_one_at_a_time"] = round(out["batched"]["throughput_req_s"] / cap, 3)
+    return out
+
+
+def precision_bench(dev, cgls_iters=20):
+    """1024^3 volume, 720 angles, 1024^2 detector: FP32 vs FP16 vs BF16 storage (FP32 arithmetic).
+    Speed of Ax (Siddon), A^T y (FDK, exact adjoint), relative L2 error against the FP64 oracle on
+    seeded samples of rays / voxels (both against the oracle on the original FP32 inputs, which
+    includes the storage rounding, and on the rounded inputs, which is the kernel error alone),
+    and the CGLS reconstruction after `cgls_iters` iterations relative to the FP32 one."""
+    import torch
+    import oracle
+    from paper_1905_03748_amd import inputs
+    from paper_1905_03748_amd.operators import Plan
+
+    w = inputs.workload("precision")
+    og = oracle.Geometry.from_dict(w.geometry_dict())
+    plan = Plan(w.geometry_dict(), w.angles)
+    x32 = inputs.voxelize_torch(w, device=dev)
+    rng = np.random.default_rng(44)
+    y32 = torch.from_numpy(rng.uniform(0.0, 50.0, plan.proj_shape).astype(np.float32)).to(dev)
+    ray_idx = inputs.sample_indices(int(np.prod(plan.proj_shape)), 1500, 45)
+    vox_idx = inputs.sample_indices(int(np.prod(plan.vol_shape)), 300, 46)
+    x_host = x32.cpu().numpy().astype(np.float64)
+    y_host = y32.cpu().numpy()
+    ref_ax = oracle.siddon_rays(og, w.angles, ray_idx, x_host)
+    ref_bp = oracle.bp_voxels(og, w.angles, y_host.astype(np.float64), vox_idx, oracle.W_FDK)
+    b = plan.forward(x32, "siddon")
+    b = (b + 0.0).contiguous()
+
+    def ms(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    def rel(a, r):
+        return float(np.linalg.norm(a - r) / np.linalg.norm(r))
+
+    out = {"workload": "1024^3 of 0.25 mm, 720 angles, 1024^2 detector of 0.4 mm", "dtypes": {}}
+    x_ref = None
+    for name, dt in (("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)):
+        log(f"[precision] {name}")
+        xd = x32.to(dt)
+        yd = y32.to(dt)
+        p = torch.empty(plan.proj_shape, dtype=dt, device=dev)
+        v = torch.empty(plan.vol_shape, dtype=dt, device=dev)
+        r = {"ax_ms": round(ms(lambda: plan.forward(xd, "siddon", out=p)), 2),
+             "fdk_ms": round(ms(lambda: plan.backproject(yd, "fdk", out=v)), 2),
+             "adjoint_ms": round(ms(lambda: plan.backproject(yd, "adjoint", out=v), 1), 2)}
+        ax = plan.forward(xd, "siddon", out=p).float().cpu().numpy().ravel()[ray_idx]
+        r["ax_rel_l2_vs_fp64"] = rel(ax, ref_ax)
+        r["ax_rel_l2_kernel_only"] = rel(ax, oracle.siddon_rays(og, w.angles, ray_idx,
+                                                                 xd.float().cpu().numpy().astype(np.float64)))
+        bp = plan.backproject(yd, "fdk", out=v).float().cpu().numpy().ravel()[vox_idx]
+        r["fdk_rel_l2_vs_fp64"] = rel(bp, ref_bp)
+        r["fdk_rel_l2_kernel_only"] = rel(bp, oracle.bp_voxels(og, w.angles, yd.float().cpu().numpy().astype(np.float64),
+                                                               vox_idx, oracle.W_FDK))
+        bd = b.to(dt)
+        t = time.perf_counter()
+        xr, res = plan.cgls(bd, cgls_iters, vol_dtype=dt)
+        torch.cuda.synchronize()
+        r["cgls_s"] = round(time.perf_counter() - t, 2)
+        xr = xr.float()
+        if x_ref is None:
+            x_ref = xr
+        r["cgls_rel_l2_vs_f32_recon"] = float(torch.linalg.vector_norm((xr - x_ref).double()) /
+                                              torch.linalg.vector_norm(x_ref.double()))
+        r["cgls_rel_l2_vs_phantom"] = float(torch.linalg.vector_norm((xr - x32).double()) /
+                                            torch.linalg.vector_norm(x32.double()))
+        out["dtypes"][name] = r
+        del xd, yd, p, v, bd, xr
+        torch.cuda.empty_cache()
+    f32 = out["dtypes"]["f32"]
+    for name in ("f16", "bf16"):
+        d = out["dtypes"][name]
+        d["ax_speedup_vs_f32"] = round(f32["ax_ms"] / d["ax_ms"], 3)
+        d["fdk_speedup_vs_f32"] = round(f32["fdk_ms"] / d["fdk_ms"], 3)
+    return out
+
+
+def ooc_bench(dev, cap_gib=32):
+    """3072^3 FP32 volume (108 GiB) and 3072 projections of 3072^2 (108 GiB) in pinned host memory,
+    device memory capped at cap_gib GiB: one out-of-core Siddon Ax and one FDK A^T y."""
+    import torch
+    from paper_1905_03748_amd import inputs
+    from paper_1905_03748_amd.operators import Plan
+
+    w = inputs.workload("ooc")
+    plan = Plan(w.geometry_dict(), w.angles)
+    cap = cap_gib << 30
+    log("[ooc] allocating pinned host arrays")
+    t = time.perf_counter()
+    vol = torch.empty(plan.vol_shape, dtype=torch.float32, pin_memory=True)
+    proj = torch.empty(plan.proj_shape, dtype=torch.float32, pin_memory=True)
+    t_alloc = time.perf_counter() - t
+    log(f"[ooc] pinned 216 GiB in {t_alloc:.1f} s; building the phantom slab by slab")
+    ells = inputs.ellipsoids(w)
+    nz = w.nvox[2]
+    step = 256
+    for z0 in range(0, nz, step):
+        ws = inputs.Workload("slab", (w.nvox[0], w.nvox[1], min(step, nz - z0)), w.dvox, w.ndet, w.ddet, 1, 0, 0,
+                             off_origin=(0.0, 0.0, (z0 + min(step, nz - z0) / 2.0 - nz / 2.0) * w.dvox[2]))
+        vol[z0:z0 + ws.nvox[2]].copy_(inputs.voxelize_torch(ws, ells, device=dev).cpu())
+    out = {"workload": "3072^3 FP32 (108 GiB) volume, 3072 angles of 3072^2 (108 GiB), pinned host memory",
+           "cap_gib": cap_gib, "pin_alloc_s": round(t_alloc, 1)}
+    log("[ooc] forward")
+    st = plan.forward_host(vol, proj, "siddon", cap_bytes=cap)
+    out["forward"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    out["forward"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
+    out["forward"]["h2d_gbs"] = round(st["bytes_h2d"] / st["t_total_s"] / 1e9, 1)
+    log(f"[ooc] forward done: {out['forward']}")
+    log("[ooc] backprojection")
+    st = plan.backproject_host(proj, vol, "fdk", cap_bytes=cap)
+    out["backprojection"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    out["backprojection"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
+    out["backprojection"]["h2d_gbs"] = round(st["bytes_h2d"] / st["t_total_s"] / 1e9, 1)
+    log(f"[ooc] backprojection done: {out['backprojection']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +273,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--precision", action="store_true", help="print the 16-bit storage report instead")
+    ap.add_argument("--ooc", action="store_true", help="print the 3072^3 out-of-core report instead")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB copy (ct_convert F32->F32) for HBM counter calibration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the build targets single-GPU boxes (no collectives); "
@@ -91,6 +289,12 @@ def main():
     from paper_1905_03748_amd.operators import Plan
 
     dev = torch.device("cuda:0")
+    if args.precision:
+        print(json.dumps({"precision": precision_bench(dev)}), flush=True)
+        return
+    if args.ooc:
+        print(json.dumps({"out_of_core": ooc_bench(dev)}), flush=True)
+        return
     w = inputs.workload("medium")
     log(f"[bench] building phantom {w.nvox} with {w.n_ellipsoids} ellipsoids")
     vol = inputs.voxelize(w)
@@ -169,10 +373,30 @@ def main():
             ex[k.replace("_ms", "_gvps")] = round(vp / (ex[k] * 1e-3) / 1e9, 2)
             ex[k] = round(ex[k], 3)
         xs = torch.zeros_like(x)
-        r = torch.empty(4, dtype=torch.float64, device=dev)
+        r = torch.empty(8, dtype=torch.float64, device=dev)
         ws = torch.empty(plan.cgls_workspace_bytes(), dtype=torch.uint8, device=dev)
-        ex["cgls_iter_ms"] = round(timed(lambda: plan.cgls(p, 3, x=xs.zero_(), resid=r, workspace=ws), 1) / 3, 3)
+        t1 = timed(lambda: plan.cgls(p, 1, x=xs.zero_(), resid=r, workspace=ws), 1)
+        t4 = timed(lambda: plan.cgls(p, 4, x=xs.zero_(), resid=r, workspace=ws), 1)
+        ex["cgls_iter_ms"] = round((t4 - t1) / 3, 3)
+        sws = torch.empty(A_sart_ws(plan), dtype=torch.uint8, device=dev)
+        ex["sart_sweep_ms"] = round(timed(lambda: plan.sart(p, 1, x=xs.zero_(), workspace=sws), 1), 3)
+        from paper_1905_03748_amd.operators import tv_steps, tv_workspace_bytes
+        tws = torch.empty(tv_workspace_bytes(plan.geometry), dtype=torch.uint8, device=dev)
+        xt = x.clone()
+        ex["tv_5steps_ms"] = round(timed(lambda: tv_steps(plan.geometry, xt, 5, 0.01, workspace=tws), 1), 3)
         out["ops"].update(ex)
+
+    if not args.no_serving:
+        log("[bench] serving")
+        out["serving"] = serving_bench(dev)
+        out["serving_p50_s"] = out["serving"]["poisson"]["p50_s"]
+        out["serving_p99_s"] = out["serving"]["poisson"]["p99_s"]
+
+    if args.copy_calibration:
+        from paper_1905_03748_amd.operators import convert
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        convert(src, torch.float32)
+        torch.cuda.synchronize()
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

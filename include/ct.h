@@ -160,11 +160,13 @@ ct_status ct_backproject_host(ct_plan *plan, ct_backprojector backprojector, con
  * not be used concurrently by another call. */
 
 /* CGLS (Bjorck) with A = CT_SIDDON and A^T = CT_BP_ADJOINT over all plan angles: from the
- * initial d_x, minimises ||A x - b||.  Volume-shaped vectors (x, p, s) are stored in vol_dtype and
- * projection-shaped ones (r, q) in proj_dtype; inner products, step sizes and the residual-norm
- * recurrence rho_{k+1} = rho_k - alpha_k gamma_k are FP64.  d_resid (device, niter+1 doubles, may
- * be NULL) receives sqrt(rho_k); if A p = 0 the iteration stops and the last value repeats.
- * d_b: device projections (all angles).  d_x: device volume, in: x0, out: result. */
+ * initial d_x, minimises ||A x - b||.  x is stored in vol_dtype and b in proj_dtype; the
+ * recurrence vectors (r, q projection-shaped; s, p volume-shaped) are FP32, because CGLS search
+ * directions are unnormalised and overflow FP16's range on realistic problems.  Inner products,
+ * step sizes and the residual-norm recurrence rho_{k+1} = rho_k - alpha_k gamma_k are FP64.
+ * d_resid (device, niter+1 doubles, may be NULL) receives sqrt(rho_k); if A p = 0 the iteration
+ * stops and the last value repeats.  d_b: device projections (all angles).  d_x: device volume,
+ * in: x0, out: result. */
 ct_status ct_cgls_workspace_bytes(const ct_plan *plan, ct_dtype vol_dtype, ct_dtype proj_dtype,
                                   uint64_t *bytes);
 ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype,

@@ -66,6 +66,7 @@ struct Slab {
     int64_t own_lo, own_hi;
     int64_t mem_lo, mem_n;
     bool first, last;  // the interpolated projector extends ownership to +-inf at the ends
+    bool scratch_ok;   // the launch may allocate device scratch (resident calls; not under a cap)
 };
 
 inline Slab full_slab(const ct_geometry &g) {
@@ -75,6 +76,7 @@ inline Slab full_slab(const ct_geometry &g) {
     s.mem_lo = 0;
     s.mem_n = g.nVoxel[2];
     s.first = s.last = true;
+    s.scratch_ok = true;
     return s;
 }
 

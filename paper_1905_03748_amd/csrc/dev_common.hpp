@@ -43,6 +43,25 @@ __device__ __forceinline__ float ldf(const T *p, int64_t i) {
     return to_f(p[i]);
 }
 
+// Buffer loads (CDNA raw buffer instructions with 32-bit byte offsets).  The hardware range check
+// returns 0 for offsets at or beyond the resource size (negative offsets wrap to huge unsigned
+// values), which the backprojectors use as the detector's zero padding; it also keeps addresses
+// 32-bit.  Word 3 of the resource selects the 32-bit data format of the gfx9 family.
+constexpr int BUF_WORD3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t proj_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, BUF_WORD3);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off, float *) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off, f16s *) {
+    return (float)__builtin_bit_cast(f16s, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off, bf16s *) {
+    return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)) << 16);
+}
+
 // Wave64 sum of a double, fixed butterfly order (bitwise repeatable).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

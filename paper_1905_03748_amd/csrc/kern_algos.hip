@@ -52,11 +52,21 @@ __global__ void k_convert(const TS *__restrict__ s, TD *__restrict__ d, int64_t 
         d[i] = from_f<TD>(ldf(s, i));
 }
 
-// r = b - r
+// r (FP32) = b - r, b in its storage type
 template <typename T>
-__global__ void k_rsub(const T *__restrict__ b, T *__restrict__ r, int64_t n) {
+__global__ void k_rsub_from(const T *__restrict__ b, float *__restrict__ r, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        r[i] = from_f<T>(ldf(b, i) - ldf(r, i));
+        r[i] = ldf(b, i) - r[i];
+}
+
+// y (storage type) += sign * scal[idx] * x (FP32)
+template <typename T>
+__global__ void k_axpy_mixed(T *__restrict__ y, const float *__restrict__ x, const double *__restrict__ scal, int idx,
+                             float sign, int64_t n) {
+    const float a = sign * (float)scal[idx];
+    if (a == 0.0f) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = from_f<T>(fmaf(a, x[i], ldf(y, i)));
 }
 
 template <typename T>
@@ -235,12 +245,14 @@ ct_status convert(const void *src, ct_dtype s_t, void *dst, ct_dtype d_t, int64_
 // ---------------------------------------------------------------------------------------------
 // CGLS
 
-size_t cgls_workspace(const ct_plan *p, ct_dtype vt, ct_dtype pt) {
+// The recurrence vectors r, q (projection-shaped) and s, p (volume-shaped) are FP32 whatever the
+// storage of x and b: CGLS search directions are unnormalised (A p grows like the operator norm
+// squared times the data), which overflows FP16's range on realistic problems.
+size_t cgls_workspace(const ct_plan *p, ct_dtype, ct_dtype) {
     const ct_geometry &g = p->g;
     const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
     const size_t np = (size_t)g.nDetector[0] * g.nDetector[1] * p->angles.size();
-    return 2 * align256(nv * dtype_size(vt)) + 2 * align256(np * dtype_size(pt)) + align256(DOT_BLOCKS * 8) +
-           align256(S_COUNT * 8);
+    return 2 * align256(nv * 4) + 2 * align256(np * 4) + align256(DOT_BLOCKS * 8) + align256(S_COUNT * 8);
 }
 
 ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter, double *resid,
@@ -252,10 +264,10 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
     Workspace ws;
     ct_status s = ws.acquire(work, cgls_workspace(p, vt, pt), st);
     if (s != CT_OK) return s;
-    void *r = ws.take(np * dtype_size(pt));
-    void *q = ws.take(np * dtype_size(pt));
-    void *sv = ws.take(nv * dtype_size(vt));
-    void *pv = ws.take(nv * dtype_size(vt));
+    float *r = (float *)ws.take(np * 4);
+    float *q = (float *)ws.take(np * 4);
+    float *sv = (float *)ws.take(nv * 4);
+    float *pv = (float *)ws.take(nv * 4);
     double *parts = (double *)ws.take(DOT_BLOCKS * 8);
     double *scal = (double *)ws.take(S_COUNT * 8);
     const Slab full = full_slab(g);
@@ -265,35 +277,35 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
         if (s_ != CT_OK) return s_;    \
     } while (0)
     // r = b - A x ; s = A^T r ; p = s ; gamma = <s,s> ; rho = <r,r>
-    CK(launch_forward(p, CT_SIDDON, x, vt, r, pt, 0, 0, na, full, st));
-    CT_DISPATCH1(pt, T, hipLaunchKernelGGL((k_rsub<T>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, (const T *)b, (T *)r, np));
+    CK(launch_forward(p, CT_SIDDON, x, vt, r, CT_F32, 0, 0, na, full, st));
+    CT_DISPATCH1(pt, T, hipLaunchKernelGGL((k_rsub_from<T>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, (const T *)b, r, np));
     CT_HIP(hipGetLastError());
-    CK(launch_backproject(p, CT_BP_ADJOINT, r, pt, sv, vt, 0, 0, na, full, st));
-    CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_copy<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (const T *)sv, (T *)pv, nv));
+    CK(launch_backproject(p, CT_BP_ADJOINT, r, CT_F32, sv, CT_F32, 0, 0, na, full, st));
+    hipLaunchKernelGGL((k_copy<float>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (const float *)sv, pv, nv);
     CT_HIP(hipGetLastError());
-    CK(dot_f64(sv, sv, vt, nv, scal + S_GAMMA, parts, st));
-    CK(dot_f64(r, r, pt, np, scal + S_RHO, parts, st));
+    CK(dot_f64(sv, sv, CT_F32, nv, scal + S_GAMMA, parts, st));
+    CK(dot_f64(r, r, CT_F32, np, scal + S_RHO, parts, st));
     hipLaunchKernelGGL(k_cgls_start, dim3(1), dim3(1), 0, st, scal, resid);
     CT_HIP(hipGetLastError());
     for (int32_t k = 0; k < niter; ++k) {
         // q = A p ; delta = <q,q> ; alpha = gamma / delta
-        CK(launch_forward(p, CT_SIDDON, pv, vt, q, pt, 0, 0, na, full, st));
-        CK(dot_f64(q, q, pt, np, scal + S_DELTA, parts, st));
+        CK(launch_forward(p, CT_SIDDON, pv, CT_F32, q, CT_F32, 0, 0, na, full, st));
+        CK(dot_f64(q, q, CT_F32, np, scal + S_DELTA, parts, st));
         hipLaunchKernelGGL(k_cgls_alpha, dim3(1), dim3(1), 0, st, scal, resid, k);
         CT_HIP(hipGetLastError());
-        // x += alpha p ; r -= alpha q
-        CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_axpy_s<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (T *)x, (const T *)pv,
-                                               scal, (int)S_ALPHA, 1.0f, nv));
-        CT_DISPATCH1(pt, T, hipLaunchKernelGGL((k_axpy_s<T>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, (T *)r, (const T *)q,
-                                               scal, (int)S_ALPHA, -1.0f, np));
+        // x += alpha p (x in its storage type) ; r -= alpha q
+        CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_axpy_mixed<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (T *)x,
+                                               (const float *)pv, scal, (int)S_ALPHA, 1.0f, nv));
+        hipLaunchKernelGGL((k_axpy_s<float>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, r, (const float *)q, scal,
+                           (int)S_ALPHA, -1.0f, np);
         CT_HIP(hipGetLastError());
         // s = A^T r ; gamma' = <s,s> ; beta = gamma'/gamma ; p = s + beta p
-        CK(launch_backproject(p, CT_BP_ADJOINT, r, pt, sv, vt, 0, 0, na, full, st));
-        CK(dot_f64(sv, sv, vt, nv, scal + S_TMP, parts, st));
+        CK(launch_backproject(p, CT_BP_ADJOINT, r, CT_F32, sv, CT_F32, 0, 0, na, full, st));
+        CK(dot_f64(sv, sv, CT_F32, nv, scal + S_TMP, parts, st));
         hipLaunchKernelGGL(k_cgls_beta, dim3(1), dim3(1), 0, st, scal);
         CT_HIP(hipGetLastError());
-        CT_DISPATCH1(vt, T, hipLaunchKernelGGL((k_xpby_s<T>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (T *)pv, (const T *)sv,
-                                               scal, (int)S_BETA, nv));
+        hipLaunchKernelGGL((k_xpby_s<float>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, pv, (const float *)sv, scal,
+                           (int)S_BETA, nv);
         CT_HIP(hipGetLastError());
     }
     return CT_OK;

@@ -53,16 +53,25 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
     if (i >= A.nx || j >= A.ny) return;
     const float x = fmaf((float)i, A.dx, A.x0);
     const float y = fmaf((float)j, A.dy, A.y0);
-    const float zb = fmaf((float)kb, A.dz, A.z0);
+    float zk[BP_NZ];
+#pragma unroll
+    for (int k = 0; k < BP_NZ; ++k) zk[k] = fmaf((float)(kb + k), A.dz, A.z0);
+    // with accumulate the sums start from the stored values, so a sequence of launches over
+    // consecutive angle ranges performs exactly the additions of one launch over all of them
     float acc[BP_NZ];
 #pragma unroll
-    for (int k = 0; k < BP_NZ; ++k) acc[k] = 0.0f;
+    for (int k = 0; k < BP_NZ; ++k) {
+        const int kk = kb + k;
+        acc[k] = (A.accumulate && kk < A.own_hi) ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i]) : 0.0f;
+    }
     const int64_t psz = (int64_t)A.nu * A.nv;
+    constexpr int ES = (int)sizeof(TP);
+    const int rowb = A.nu * ES;
     for (int t = 0; t < A.nang; ++t) {
         const AngleGeo &G = A.tab[A.a0 + t];
         const float c = (float)G.c, s = (float)G.s;
         const float Ld = A.DSO - (x * c + y * s);
-        const float iL = 1.0f / Ld;
+        const float iL = __builtin_amdgcn_rcpf(Ld);
         const float m = A.DSD * iL;
         const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
         const float af = floorf(as);
@@ -71,9 +80,9 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
         const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
         const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
         if (wa0 == 0.0f && wa1 == 0.0f) continue;
-        const int ia0 = clampi(ia, 0, A.nu - 1), ia1 = clampi(ia + 1, 0, A.nu - 1);
-        const float bs0 = fmaf(m * zb, A.inv_dv, A.bv0);
-        const float bst = m * A.dz * A.inv_dv;
+        const int ca0 = clampi(ia, 0, A.nu - 1) * ES;
+        const int dca = (clampi(ia + 1, 0, A.nu - 1) - clampi(ia, 0, A.nu - 1)) * ES;
+        const float mv = m * A.inv_dv;
         float w = 0.0f, rxy2 = 0.0f, wpm = 0.0f;
         if (W == CT_BP_FDK) {
             const float q = A.DSO * iL;
@@ -83,24 +92,29 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
             rxy2 = sx * sx + sy * sy;
             wpm = A.pm_const * iL * iL * iL;
         }
-        const TP *P = proj + (int64_t)t * psz;
+        const __amdgpu_buffer_rsrc_t R = proj_rsrc(proj + (int64_t)t * psz, psz * ES);
+        // all taps of the column are issued before any is used, so they are in flight together
+        float p[BP_NZ][4], fb[BP_NZ];
 #pragma unroll
         for (int k = 0; k < BP_NZ; ++k) {
-            const float bs = fmaf((float)k, bst, bs0);
+            // each voxel's row coordinate comes from its own absolute height, so a voxel's value
+            // does not depend on how the volume is cut into launches or slabs
+            const float bs = fmaf(zk[k], mv, A.bv0);
             const float bf = floorf(bs);
-            const float fb = bs - bf;
-            const int ib = (int)bf;
-            const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-            const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
-            const int r0 = clampi(ib, 0, A.nv - 1) * A.nu, r1 = clampi(ib + 1, 0, A.nv - 1) * A.nu;
-            const float v0 = fmaf(wa1, ldf(P, r0 + ia1), wa0 * ldf(P, r0 + ia0));
-            const float v1 = fmaf(wa1, ldf(P, r1 + ia1), wa0 * ldf(P, r1 + ia0));
-            const float v = fmaf(wb1, v1, wb0 * v0);
+            fb[k] = bs - bf;
+            const int o00 = (int)bf * rowb + ca0;  // rows outside the detector read 0
+            p[k][0] = bload(R, o00, (TP *)nullptr);
+            p[k][1] = bload(R, o00 + dca, (TP *)nullptr);
+            p[k][2] = bload(R, o00 + rowb, (TP *)nullptr);
+            p[k][3] = bload(R, o00 + rowb + dca, (TP *)nullptr);
+        }
+#pragma unroll
+        for (int k = 0; k < BP_NZ; ++k) {
+            const float v0 = fmaf(wa1, p[k][1], wa0 * p[k][0]);
+            const float v1 = fmaf(wa1, p[k][3], wa0 * p[k][2]);
+            const float v = fmaf(fb[k], v1 - v0, v0);
             float wk = w;
-            if (W != CT_BP_FDK) {
-                const float z = fmaf((float)k, A.dz, zb);
-                wk = wpm * sqrtf(fmaf(z, z, rxy2));
-            }
+            if (W != CT_BP_FDK) wk = wpm * sqrtf(fmaf(zk[k], zk[k], rxy2));
             acc[k] = fmaf(wk, v, acc[k]);
         }
     }
@@ -109,111 +123,133 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
         const int kk = kb + k;
         if (kk >= A.own_hi) break;
         const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
-        const float prev = A.accumulate ? to_f(vol[o]) : 0.0f;
-        vol[o] = from_f<TV>(prev + acc[k]);
+        vol[o] = from_f<TV>(acc[k]);
     }
 }
 
 // Exact transpose of the Siddon projector, gathered per voxel.
+//
+// For one angle and one detector column a, every ray lies in the vertical plane through the source
+// and that column, so all rows share the (x, y) trace and its parameter interval [t0, t1] inside
+// the voxel column's square (set up once, in FP64).  Along a row b the height is z(t) = t v_b (the
+// source is in the z = 0 plane), so inside the column the row covers [t0 v_b, t1 v_b]: a short
+// segment, sorted in z by b.  Each candidate row is visited once per column and its exact chord is
+// split over the one or two voxels of the thread's z run that it crosses; the per-voxel sums live
+// in LDS (one slot per thread per voxel, conflict-free), in a fixed order (angle, a, b), so the
+// result is deterministic.
+constexpr int ADJ_NZ = 16;
+
 template <typename TP, typename TV>
 __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj, TV *__restrict__ vol, BpArgs A) {
-    const int i = blockIdx.x * BP_TX + (threadIdx.x % BP_TX);
-    const int j = blockIdx.y * BP_TY + (threadIdx.x / BP_TX);
-    const int kb = A.own_lo + blockIdx.z * BP_NZ;
-    if (i >= A.nx || j >= A.ny) return;
-    // column square (mm, FP64)
+    __shared__ float accs[ADJ_NZ * 256];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * BP_TX + (tid % BP_TX);
+    const int j = blockIdx.y * BP_TY + (tid / BP_TX);
+    const int kb = A.own_lo + blockIdx.z * ADJ_NZ;
+    const bool live = i < A.nx && j < A.ny;
+#pragma unroll
+    for (int k = 0; k < ADJ_NZ; ++k) {
+        const int kk = kb + k;
+        accs[k * 256 + tid] = (live && A.accumulate && kk < A.own_hi)
+                                  ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i])
+                                  : 0.0f;
+    }
+    if (!live) return;  // no barrier follows: each thread owns its LDS slots
+    // column square (mm, FP64 for the ray set-up; FP32 copies for the candidate range)
     const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;
     const double xl = xc - 0.5 * A.ddx, xh = xc + 0.5 * A.ddx;
     const double yl = yc - 0.5 * A.ddy, yh = yc + 0.5 * A.ddy;
-    const float zl0 = (float)(A.dz0 + (kb - 0.5) * A.ddz);  // lower face of voxel kb
-    const float dz = A.dz;
-    float acc[BP_NZ];
-#pragma unroll
-    for (int k = 0; k < BP_NZ; ++k) acc[k] = 0.0f;
+    const float fxl = (float)xl, fxh = (float)xh, fyl = (float)yl, fyh = (float)yh;
+    const float zface0 = (float)(A.dz0 - 0.5 * A.ddz);           // lower face of voxel 0
+    const float zl0 = fmaf((float)kb, A.dz, zface0);             // lower face of voxel kb
+    const float dz = A.dz, idz = 1.0f / A.dz;
+    const int nzr = min(ADJ_NZ, A.own_hi - kb);
+    const float zr_hi = zl0 + nzr * dz;
+    const float v0 = (float)(A.offv - A.cv * A.dv), dv = (float)A.dv;
+    const float fDSO = A.DSO, fDSD = A.DSD;
     const int64_t psz = (int64_t)A.nu * A.nv;
-    const float bscale = A.inv_dv;
     for (int t = 0; t < A.nang; ++t) {
         const AngleGeo &G = A.tab[A.a0 + t];
         const double c = G.c, s = G.s;
         const double Sx = A.dDSO * c, Sy = A.dDSO * s;
-        // detector column range: central projection of the square's corners onto the u axis
-        double umin = 1e300, umax = -1e300;
+        // detector columns whose rays can meet the square: central projection of its corners
+        // (FP32 with a margin: the range only has to contain every hit column)
+        const float fc = (float)c, fs = (float)s;
+        float umin = FLT_MAX, umax = -FLT_MAX;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double X = (q & 1) ? xh : xl, Y = (q & 2) ? yh : yl;
-            const double Ld = A.dDSO - (X * c + Y * s);
-            const double u = A.dDSD * (Y * c - X * s) / Ld;
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
+            const float X = (q & 1) ? fxh : fxl, Y = (q & 2) ? fyh : fyl;
+            const float u = fDSD * (Y * fc - X * fs) / (fDSO - (X * fc + Y * fs));
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
         }
-        // clamp in floating point before converting, so the casts stay in range
-        const int alo = (int)fmax(ceil((umin - A.offu) / A.du + A.cu - 1e-6), 0.0);
-        const int ahi = (int)fmin(floor((umax - A.offu) / A.du + A.cu + 1e-6), (double)(A.nu - 1));
+        const float aum = (float)A.cu - (float)A.offu / (float)A.du, iau = 1.0f / (float)A.du;
+        const int alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - 1e-3f), 0.0f);
+        const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + 1e-3f), (float)(A.nu - 1));
         const TP *P = proj + (int64_t)t * psz;
         for (int a = alo; a <= ahi; ++a) {
             const double ua = (a - A.cu) * A.du + A.offu;
             // ray (x, y) trace: S + t (P - S), P - S = -DSD (c, s) + ua (-s, c)
             const double Dx = -A.dDSD * c - ua * s, Dy = -A.dDSD * s + ua * c;
-            const double Lxy = sqrt(Dx * Dx + Dy * Dy);
-            double t0 = -1e300, t1 = 1e300;
-            if (fabs(Dx) < 1e-12 * Lxy) {
+            const double Lxy2 = Dx * Dx + Dy * Dy;
+            double t0 = 0.0, t1 = 1.0;
+            if (Dx * Dx < 1e-24 * Lxy2) {
                 if (Sx < xl || Sx > xh) continue;
             } else {
-                const double ta = (xl - Sx) / Dx, tb = (xh - Sx) / Dx;
+                const double iDx = 1.0 / Dx;
+                const double ta = (xl - Sx) * iDx, tb = (xh - Sx) * iDx;
                 t0 = fmax(t0, fmin(ta, tb));
                 t1 = fmin(t1, fmax(ta, tb));
             }
-            if (fabs(Dy) < 1e-12 * Lxy) {
+            if (Dy * Dy < 1e-24 * Lxy2) {
                 if (Sy < yl || Sy > yh) continue;
             } else {
-                const double ta = (yl - Sy) / Dy, tb = (yh - Sy) / Dy;
+                const double iDy = 1.0 / Dy;
+                const double ta = (yl - Sy) * iDy, tb = (yh - Sy) * iDy;
                 t0 = fmax(t0, fmin(ta, tb));
                 t1 = fmin(t1, fmax(ta, tb));
             }
-            t0 = fmax(t0, 0.0);
-            t1 = fmin(t1, 1.0);
             if (!(t0 < t1)) continue;
-            // z along the ray: z(t) = t v_b (source in the z = 0 plane); local parameter tau = t - t0
             const float T = (float)(t1 - t0);
             const float ft0 = (float)t0;
             const float it0 = (float)(1.0 / t0), it1 = (float)(1.0 / t1);
-            const float lxy2 = (float)(Lxy * Lxy);
-#pragma unroll
-            for (int k = 0; k < BP_NZ; ++k) {
-                const float zl = fmaf((float)k, dz, zl0), zh = zl + dz;
-                // rows whose ray can meet z in [zl, zh] for t in [t0, t1]: v in [vmin, vmax]
-                const float vmin = fminf(zl * it0, zl * it1), vmax = fmaxf(zh * it0, zh * it1);
-                const int blo = (int)fmaxf(ceilf(fmaf(vmin - (float)A.offv, bscale, (float)A.cv) - 1e-4f), 0.0f);
-                const int bhi = (int)fminf(floorf(fmaf(vmax - (float)A.offv, bscale, (float)A.cv) + 1e-4f),
-                                           (float)(A.nv - 1));
-                float sum = 0.0f;
-                for (int b = blo; b <= bhi; ++b) {
-                    const float vb = (float)((b - A.cv) * A.dv + A.offv);
-                    const float Z0 = ft0 * vb;  // z where the ray enters the column
-                    float ta, tb;
-                    if (fabsf(vb) > 0.0f) {
-                        const float iv = 1.0f / vb;
-                        const float q0 = (zl - Z0) * iv, q1 = (zh - Z0) * iv;
-                        ta = fmaxf(0.0f, fminf(q0, q1));
-                        tb = fminf(T, fmaxf(q0, q1));
-                    } else {
-                        ta = 0.0f;
-                        tb = (zl <= 0.0f && 0.0f <= zh) ? T : 0.0f;
-                    }
-                    const float len = fmaxf(tb - ta, 0.0f) * sqrtf(fmaf(vb, vb, lxy2));
-                    sum = fmaf(len, ldf(P, (int64_t)b * A.nu + a), sum);
+            const float lxy2 = (float)Lxy2;
+            // rows whose z range inside the column meets the thread's z run [zl0, zr_hi]
+            const float vmin = fminf(zl0 * it0, zl0 * it1), vmax = fmaxf(zr_hi * it0, zr_hi * it1);
+            const int blo = (int)fmaxf(ceilf((vmin - v0) / dv - 1e-3f), 0.0f);
+            const int bhi = (int)fminf(floorf((vmax - v0) / dv + 1e-3f), (float)(A.nv - 1));
+            for (int b = blo; b <= bhi; ++b) {
+                const float y = ldf(P, (int64_t)b * A.nu + a);
+                const float vb = fmaf((float)b, dv, v0);
+                const float za = ft0 * vb;           // height where the row enters the column
+                const float zb = fmaf(vb, T, za);    // ... and where it leaves
+                const float lo = fminf(za, zb), hi = fmaxf(za, zb);
+                const float full = T * sqrtf(fmaf(vb, vb, lxy2));  // chord inside the column
+                const float ext = hi - lo;
+                // one voxel of slack on each side: the overlaps below use absolute voxel faces, so
+                // rounding in this index only adds zero-length terms, and every voxel's sum is the
+                // same whichever z run (launch, slab) holds it
+                const int k0 = max((int)floorf((lo - zl0) * idz) - 1, 0);
+                const int kend = min((int)floorf((hi - zl0) * idz) + 1, nzr - 1);
+                int k = k0;
+                for (; k <= kend; ++k) {
+                    const float zl = fmaf((float)(kb + k), dz, zface0);
+                    const float ov = fminf(hi, zl + dz) - fmaxf(lo, zl);
+                    // the chord splits over the voxels in proportion to the height covered
+                    // a level row (zero height range) lies in the voxel whose [zl, zl + dz) holds it
+                    const float len = ext > 0.0f ? full * (fmaxf(ov, 0.0f) / ext)
+                                                 : ((lo >= zl && lo < zl + dz) ? full : 0.0f);
+                    accs[k * 256 + tid] = fmaf(len, y, accs[k * 256 + tid]);
                 }
-                acc[k] += sum;
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < BP_NZ; ++k) {
+    for (int k = 0; k < ADJ_NZ; ++k) {
         const int kk = kb + k;
         if (kk >= A.own_hi) break;
         const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
-        const float prev = A.accumulate ? to_f(vol[o]) : 0.0f;
-        vol[o] = from_f<TV>(prev + acc[k]);
+        vol[o] = from_f<TV>(accs[k * 256 + tid]);
     }
 }
 
@@ -319,7 +355,8 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     const int64_t nzown = slab.own_hi - slab.own_lo;
     if (nzown <= 0) return CT_OK;
     BpArgs A = make_bp_args(p, tab, a0, a1, slab, accumulate);
-    const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((nzown + BP_NZ - 1) / BP_NZ));
+    const int nzrun = kind == CT_BP_ADJOINT ? ADJ_NZ : BP_NZ;
+    const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((nzown + nzrun - 1) / nzrun));
     const dim3 block(256);
     if (kind == CT_BP_FDK) {
         CT_DISPATCH2(pt, TP, vt, TV,

@@ -6,8 +6,7 @@
 // quantities are O(grid size) and plane crossings are formed as t0 + n * dt by one FMA each.
 //
 // Launch shape: 256-thread blocks covering 64 pixels along u (one wave = 64 adjacent pixels of
-// one detector row, whose rays are nearly parallel and walk neighbouring voxels in lock-step) by
-// 4 rows.  Blocks are linearised as (u-tile fastest, then angle, then v-band) so the blocks in
+// one detector row, whose rays are nearly parallel and walk neighbouring voxels) by 4 rows.  Blocks are linearised as (u-tile fastest, then angle, then v-band) so the blocks in
 // flight at any moment share a band of detector rows across many angles, i.e. an axial slab of
 // the volume, which keeps the working set inside the 256 MB last-level cache.
 #include <cfloat>
@@ -85,13 +84,67 @@ __device__ __forceinline__ void pixel_of(const FwdArgs &A, int &ai, int &a, int 
     b = vb * FWD_TV + (threadIdx.x / FWD_TU);
 }
 
+// Memory view of the volume: offset = (z - mem_lo) * sz + y * sy + x * sx.  Blocks whose rays run
+// mostly along x read a transposed copy (y fastest), so that the 64 lanes of a wave, which hold 64
+// adjacent pixels of a detector row (neighbouring rays displaced along e_u), read neighbouring
+// addresses; blocks whose rays run mostly along y read the natural layout.
+// Volumes below 4 GiB are read with buffer loads and 32-bit byte offsets (no 64-bit address
+// arithmetic per gather); larger ones with 64-bit element offsets.
+template <typename TV, bool BUF>
+struct View;
+
+template <typename TV>
+struct View<TV, true> {
+    using Off = int;
+    __amdgpu_buffer_rsrc_t r;
+    int sx, sy, sz;  // bytes
+    __device__ __forceinline__ float operator()(int off) const { return bload(r, off, (TV *)nullptr); }
+};
+
+template <typename TV>
+struct View<TV, false> {
+    using Off = int64_t;
+    const TV *p;
+    int64_t sx, sy, sz;  // elements
+    __device__ __forceinline__ float operator()(int64_t off) const { return ldf(p, off); }
+};
+
+template <typename TV, bool BUF>
+__device__ __forceinline__ View<TV, BUF> pick_view(const TV *vol, const TV *volT, const FwdArgs &A, const AngleGeo &G) {
+    View<TV, BUF> v;
+    const bool along_x = volT != nullptr && fabs(G.Dc[0]) > fabs(G.Dc[1]);
+    const TV *base = along_x ? volT : vol;
+    using Off = typename View<TV, BUF>::Off;
+    const Off unit = BUF ? (Off)sizeof(TV) : (Off)1;
+    v.sx = along_x ? (Off)A.ny * unit : unit;
+    v.sy = along_x ? unit : (Off)A.nx * unit;
+    v.sz = (Off)A.nx * (Off)A.ny * unit;
+    if constexpr (BUF) {
+        v.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<TV *>(base), (short)0,
+                                                (int)((int64_t)A.nx * A.ny * A.mem_n * (int64_t)sizeof(TV)), BUF_WORD3);
+    } else {
+        v.p = base;
+    }
+    return v;
+}
+
 // ------------------------------------------------------------------------------------------
 // Siddon: exact length of the ray inside each voxel it crosses (incremental traversal in the
 // manner of Jacobs et al. 1998: step to whichever voxel plane comes next).
+//
+// The step is branch-free: every axis whose next crossing equals the current minimum steps (a ray
+// through an edge or corner steps several axes at once, which is Siddon's zero-length piece).
+// The traversal stops at Te, the smaller of the clip exit and, per axis, the FP32 time of the
+// crossing that would leave the owned grid -- computed by the same expression the loop uses -- so
+// voxel indices never leave the grid and need no per-step checks.  Pieces are produced BATCH at a
+// time and their gathers issued together, so several loads per lane are in flight.
 
-template <typename TV>
-__device__ __forceinline__ float siddon_ray(const TV *__restrict__ vol, const FwdArgs &A, const AngleGeo &G,
-                                            int a, int b) {
+constexpr int SID_BATCH = 8;
+constexpr int INT_BATCH = 4;
+
+template <typename VIEW>
+__device__ __forceinline__ float siddon_ray(const VIEW V, const FwdArgs &A, const AngleGeo &G, int a, int b) {
+    using IDX = typename VIEW::Off;
     const double lo[3] = {-0.5, -0.5, A.own_lo - 0.5};
     const double hi[3] = {A.nx - 0.5, A.ny - 0.5, A.own_hi - 0.5};
     RaySetup R;
@@ -99,8 +152,9 @@ __device__ __forceinline__ float siddon_ray(const TV *__restrict__ vol, const Fw
 
     const int ilo[3] = {0, 0, A.own_lo};
     const int ihi[3] = {A.nx - 1, A.ny - 1, A.own_hi - 1};
-    int idx[3], step[3];
-    float tn0[3], dtn[3];
+    int idx[3];
+    float tn0[3], dtn[3], st[3];
+    float Te = (float)(R.t1 - R.t0);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const double E = G.S[ax] + R.t0 * R.D[ax];
@@ -108,63 +162,63 @@ __device__ __forceinline__ float siddon_ray(const TV *__restrict__ vol, const Fw
         i = i < ilo[ax] ? ilo[ax] : (i > ihi[ax] ? ihi[ax] : i);
         idx[ax] = i;
         if (R.par[ax]) {
-            step[ax] = 0;
+            st[ax] = 0.0f;
             tn0[ax] = FLT_MAX;
             dtn[ax] = 0.0f;
         } else {
             const double f = E - i;  // entry offset from the voxel centre, about [-0.5, 0.5]
             const int s = R.D[ax] > 0 ? 1 : -1;
             const double inv = 1.0 / fabs(R.D[ax]);
-            step[ax] = s;
+            st[ax] = (float)s;
             tn0[ax] = (float)((0.5 - s * f) * inv);
             dtn[ax] = (float)inv;
+            const int nexit = s > 0 ? ihi[ax] - i : i - ilo[ax];
+            Te = fminf(Te, fmaf((float)nexit, dtn[ax], tn0[ax]));
         }
     }
-    const float T = (float)(R.t1 - R.t0);
-    const int64_t sy = A.nx, sz = (int64_t)A.nx * A.ny;
-    int64_t lin = (int64_t)(idx[2] - A.mem_lo) * sz + (int64_t)idx[1] * sy + idx[0];
-    const int64_t st0 = step[0], st1 = step[1] * sy, st2 = step[2] * sz;
-    int ix = idx[0], iy = idx[1], iz = idx[2];
-    const unsigned nzown = (unsigned)(A.own_hi - A.own_lo);
+    const IDX s0 = (IDX)(int)st[0] * V.sx, s1 = (IDX)(int)st[1] * V.sy, s2 = (IDX)(int)st[2] * V.sz;
+    IDX lin = (IDX)(idx[2] - A.mem_lo) * V.sz + (IDX)idx[1] * V.sy + (IDX)idx[0] * V.sx;
     float tx = tn0[0], ty = tn0[1], tz = tn0[2];
-    int n0 = 0, n1 = 0, n2 = 0;
+    float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
     float tc = 0.0f, acc = 0.0f;
-    const int maxit = A.nx + A.ny + (A.own_hi - A.own_lo) + 4;
-    for (int it = 0; it < maxit; ++it) {
-        const float tn = fminf(fminf(tx, ty), fminf(tz, T));
-        acc = fmaf(tn - tc, ldf(vol, lin), acc);
-        if (tn >= T) break;
-        tc = tn;
-        if (tx <= ty && tx <= tz) {
-            ix += step[0];
-            if ((unsigned)ix >= (unsigned)A.nx) break;
-            lin += st0;
-            ++n0;
-            tx = fmaf((float)n0, dtn[0], tn0[0]);
-        } else if (ty <= tz) {
-            iy += step[1];
-            if ((unsigned)iy >= (unsigned)A.ny) break;
-            lin += st1;
-            ++n1;
-            ty = fmaf((float)n1, dtn[1], tn0[1]);
-        } else {
-            iz += step[2];
-            if ((unsigned)(iz - A.own_lo) >= nzown) break;
-            lin += st2;
-            ++n2;
-            tz = fmaf((float)n2, dtn[2], tn0[2]);
+    const int maxtrips = (A.nx + A.ny + (A.own_hi - A.own_lo) + 3) / SID_BATCH + 2;
+    for (int trip = 0; trip < maxtrips; ++trip) {
+        float len[SID_BATCH];
+        IDX off[SID_BATCH];
+#pragma unroll
+        for (int u = 0; u < SID_BATCH; ++u) {
+            const float tn = fminf(fminf(fminf(tx, ty), tz), Te);
+            len[u] = tn - tc;
+            off[u] = lin;
+            const bool act = tn < Te;
+            const bool cx = act && tx == tn, cy = act && ty == tn, cz = act && tz == tn;
+            lin += (cx ? s0 : (IDX)0) + (cy ? s1 : (IDX)0) + (cz ? s2 : (IDX)0);
+            n0 += cx ? 1.0f : 0.0f;
+            n1 += cy ? 1.0f : 0.0f;
+            n2 += cz ? 1.0f : 0.0f;
+            tx = fmaf(n0, dtn[0], tn0[0]);
+            ty = fmaf(n1, dtn[1], tn0[1]);
+            tz = fmaf(n2, dtn[2], tn0[2]);
+            tc = tn;
         }
+        float v[SID_BATCH];
+#pragma unroll
+        for (int u = 0; u < SID_BATCH; ++u) v[u] = V(off[u]);
+#pragma unroll
+        for (int u = 0; u < SID_BATCH; ++u) acc = fmaf(len[u], v[u], acc);
+        if (!(tc < Te)) break;
     }
     return (float)(acc * R.L);
 }
 
-template <typename TV, typename TP>
-__global__ __launch_bounds__(256) void k_siddon(const TV *__restrict__ vol, TP *__restrict__ proj, FwdArgs A) {
+template <typename TV, typename TP, bool BUF>
+__global__ __launch_bounds__(256) void k_siddon(const TV *__restrict__ vol, const TV *__restrict__ volT,
+                                                TP *__restrict__ proj, FwdArgs A) {
     int ai, a, b;
     pixel_of(A, ai, a, b);
     if (a >= A.nu || b >= A.nv) return;
     const AngleGeo &G = A.tab[A.a0 + ai];
-    const float v = siddon_ray(vol, A, G, a, b);
+    const float v = siddon_ray(pick_view<TV, BUF>(vol, volT, A, G), A, G, a, b);
     const int64_t o = ((int64_t)ai * A.nv + b) * A.nu + a;
     const float prev = A.accumulate ? to_f(proj[o]) : 0.0f;
     proj[o] = from_f<TP>(prev + v);
@@ -173,20 +227,13 @@ __global__ __launch_bounds__(256) void k_siddon(const TV *__restrict__ vol, TP *
 // ------------------------------------------------------------------------------------------
 // Interpolated projector: samples at s_k = (k + 1/2) delta mm from the source, every k whose
 // sample lies in the grid box grown by half a voxel (outside it the zero-padded trilinear
-// interpolant vanishes); p = delta * sum of the interpolant at the samples.
+// interpolant vanishes); p = delta * sum of the interpolant at the samples.  All rays of a wave
+// reach sample j at the same distance from the source, so the lanes stay in step through the
+// volume and the eight taps of a wave fall on a few cache lines.
 
-template <typename TV>
-__device__ __forceinline__ float vox(const TV *__restrict__ vol, const FwdArgs &A, int x, int y, int z) {
-    const bool ok = (unsigned)x < (unsigned)A.nx && (unsigned)y < (unsigned)A.ny &&
-                    (unsigned)(z - A.mem_lo) < (unsigned)A.mem_n;
-    const int xc = ok ? x : 0, yc = ok ? y : 0, zc = ok ? z - A.mem_lo : 0;
-    const float v = ldf(vol, ((int64_t)zc * A.ny + yc) * A.nx + xc);
-    return ok ? v : 0.0f;
-}
-
-template <typename TV>
-__device__ __forceinline__ float interp_ray(const TV *__restrict__ vol, const FwdArgs &A, const AngleGeo &G,
-                                            int a, int b) {
+template <typename VIEW>
+__device__ __forceinline__ float interp_ray(const VIEW V, const FwdArgs &A, const AngleGeo &G, int a, int b) {
+    using IDX = typename VIEW::Off;
     const double lo[3] = {-1.0, -1.0, -1.0};
     const double hi[3] = {(double)A.nx, (double)A.ny, (double)A.nz};
     RaySetup R;
@@ -217,46 +264,103 @@ __device__ __forceinline__ float interp_ray(const TV *__restrict__ vol, const Fw
         // samples whose z (relative to ib[2]) lies in [zlo, zhi), with a margin; the exact test
         // below is the same FP32 expression in every slab, so each sample has one owner
         if (!R.par[2] && fabs(stp[2]) > 0.0) {
-            const double za = A.first ? -1e30 : (A.own_lo - 0.5 - B[2]) / stp[2];
-            const double zb = A.last ? 1e30 : (A.own_hi - 0.5 - B[2]) / stp[2];
-            const double j0 = floor(fmin(za, zb)) - 2, j1 = ceil(fmax(za, zb)) + 2;
+            // sample index where z meets each owned boundary; an open end (first or last slab)
+            // lies at -inf / +inf in z, which is -inf or +inf in j depending on the z direction
+            const double up = stp[2] > 0.0 ? 1.0 : -1.0;
+            const double ja = A.first ? -up * 1e30 : (A.own_lo - 0.5 - B[2]) / stp[2];
+            const double jb = A.last ? up * 1e30 : (A.own_hi - 0.5 - B[2]) / stp[2];
+            const double j0 = floor(fmin(ja, jb)) - 2, j1 = ceil(fmax(ja, jb)) + 2;
             jlo = (int)fmax((double)jlo, j0);
             jhi = (int)fmin((double)jhi, j1);
         }
     }
+    const int zm_hi = A.mem_n - 1;
     float acc = 0.0f;
-    for (int j = jlo; j <= jhi; ++j) {
-        const float px = fmaf((float)j, fs[0], fb[0]);
-        const float py = fmaf((float)j, fs[1], fb[1]);
-        const float pz = fmaf((float)j, fs[2], fb[2]);
-        if (slab && !(pz >= zlo && pz < zhi)) continue;
-        const float flx = floorf(px), fly = floorf(py), flz = floorf(pz);
-        const float rx = px - flx, ry = py - fly, rz = pz - flz;
-        const int x0 = ib[0] + (int)flx, y0 = ib[1] + (int)fly, z0 = ib[2] + (int)flz;
-        const float c00 = fmaf(rx, vox(vol, A, x0 + 1, y0, z0) - vox(vol, A, x0, y0, z0), vox(vol, A, x0, y0, z0));
-        const float c10 = fmaf(rx, vox(vol, A, x0 + 1, y0 + 1, z0) - vox(vol, A, x0, y0 + 1, z0),
-                               vox(vol, A, x0, y0 + 1, z0));
-        const float c01 = fmaf(rx, vox(vol, A, x0 + 1, y0, z0 + 1) - vox(vol, A, x0, y0, z0 + 1),
-                               vox(vol, A, x0, y0, z0 + 1));
-        const float c11 = fmaf(rx, vox(vol, A, x0 + 1, y0 + 1, z0 + 1) - vox(vol, A, x0, y0 + 1, z0 + 1),
-                               vox(vol, A, x0, y0 + 1, z0 + 1));
-        const float c0 = fmaf(ry, c10 - c00, c00);
-        const float c1 = fmaf(ry, c11 - c01, c01);
-        acc += fmaf(rz, c1 - c0, c0);
+    // INT_BATCH samples per trip: all their taps are issued before any is used
+    for (int j0 = jlo; j0 <= jhi; j0 += INT_BATCH) {
+        float wgt[INT_BATCH][6];
+        IDX off[INT_BATCH][8];
+#pragma unroll
+        for (int u = 0; u < INT_BATCH; ++u) {
+            const int j = min(j0 + u, jhi);
+            const float px = fmaf((float)j, fs[0], fb[0]);
+            const float py = fmaf((float)j, fs[1], fb[1]);
+            const float pz = fmaf((float)j, fs[2], fb[2]);
+            const bool own = (j0 + u <= jhi) && (!slab || (pz >= zlo && pz < zhi));
+            const float flx = floorf(px), fly = floorf(py), flz = floorf(pz);
+            const float rx = px - flx, ry = py - fly, rz = pz - flz;
+            const int x0 = ib[0] + (int)flx, y0 = ib[1] + (int)fly, z0 = ib[2] + (int)flz - A.mem_lo;
+            // zero padding: taps outside the grid (or outside the slices in memory) weigh 0
+            const bool vx0 = (unsigned)x0 < (unsigned)A.nx, vx1 = (unsigned)(x0 + 1) < (unsigned)A.nx;
+            const bool vy0 = (unsigned)y0 < (unsigned)A.ny, vy1 = (unsigned)(y0 + 1) < (unsigned)A.ny;
+            const bool vz0 = (unsigned)z0 < (unsigned)A.mem_n, vz1 = (unsigned)(z0 + 1) < (unsigned)A.mem_n;
+            const IDX ox0 = (IDX)(vx0 ? x0 : 0) * V.sx, ox1 = (IDX)(vx1 ? x0 + 1 : A.nx - 1) * V.sx;
+            const IDX oy0 = (IDX)(vy0 ? y0 : 0) * V.sy, oy1 = (IDX)(vy1 ? y0 + 1 : A.ny - 1) * V.sy;
+            const IDX oz0 = (IDX)(vz0 ? z0 : 0) * V.sz, oz1 = (IDX)(vz1 ? z0 + 1 : zm_hi) * V.sz;
+            wgt[u][0] = vx0 ? 1.0f - rx : 0.0f;
+            wgt[u][1] = vx1 ? rx : 0.0f;
+            wgt[u][2] = vy0 ? 1.0f - ry : 0.0f;
+            wgt[u][3] = vy1 ? ry : 0.0f;
+            wgt[u][4] = (own && vz0) ? 1.0f - rz : 0.0f;
+            wgt[u][5] = (own && vz1) ? rz : 0.0f;
+            const IDX r00 = oz0 + oy0, r01 = oz0 + oy1, r10 = oz1 + oy0, r11 = oz1 + oy1;
+            off[u][0] = r00 + ox0;
+            off[u][1] = r00 + ox1;
+            off[u][2] = r01 + ox0;
+            off[u][3] = r01 + ox1;
+            off[u][4] = r10 + ox0;
+            off[u][5] = r10 + ox1;
+            off[u][6] = r11 + ox0;
+            off[u][7] = r11 + ox1;
+        }
+        float v[INT_BATCH][8];
+#pragma unroll
+        for (int u = 0; u < INT_BATCH; ++u)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[u][q] = V(off[u][q]);
+#pragma unroll
+        for (int u = 0; u < INT_BATCH; ++u) {
+            const float *w = wgt[u];
+            const float c00 = fmaf(w[1], v[u][1], w[0] * v[u][0]), c01 = fmaf(w[1], v[u][3], w[0] * v[u][2]);
+            const float c10 = fmaf(w[1], v[u][5], w[0] * v[u][4]), c11 = fmaf(w[1], v[u][7], w[0] * v[u][6]);
+            const float c0 = fmaf(w[3], c01, w[2] * c00), c1 = fmaf(w[3], c11, w[2] * c10);
+            acc += fmaf(w[5], c1, w[4] * c0);
+        }
     }
     return (float)(acc * A.delta);
 }
 
-template <typename TV, typename TP>
-__global__ __launch_bounds__(256) void k_interp(const TV *__restrict__ vol, TP *__restrict__ proj, FwdArgs A) {
+template <typename TV, typename TP, bool BUF>
+__global__ __launch_bounds__(256) void k_interp(const TV *__restrict__ vol, const TV *__restrict__ volT,
+                                                TP *__restrict__ proj, FwdArgs A) {
     int ai, a, b;
     pixel_of(A, ai, a, b);
     if (a >= A.nu || b >= A.nv) return;
     const AngleGeo &G = A.tab[A.a0 + ai];
-    const float v = interp_ray(vol, A, G, a, b);
+    const float v = interp_ray(pick_view<TV, BUF>(vol, volT, A, G), A, G, a, b);
     const int64_t o = ((int64_t)ai * A.nv + b) * A.nu + a;
     const float prev = A.accumulate ? to_f(proj[o]) : 0.0f;
     proj[o] = from_f<TP>(prev + v);
+}
+
+// [z][y][x] -> [z][x][y], 32 x 32 tiles through LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_xy(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny) {
+    __shared__ T tile[32][33];
+    const int64_t zoff = (int64_t)blockIdx.z * nx * ny;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int x = x0 + tx, y = y0 + ty + r;
+        if (x < nx && y < ny) tile[ty + r][tx] = src[zoff + (int64_t)y * nx + x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int y = y0 + tx, x = x0 + ty + r;
+        if (x < nx && y < ny) dst[zoff + (int64_t)x * ny + y] = tile[tx][ty + r];
+    }
 }
 
 // Chord of each ray through the whole grid box (= A 1 of the Siddon projector), FP64 set-up.
@@ -317,25 +421,57 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     if (slab.own_hi <= slab.own_lo) return CT_OK;
+    const ct_geometry &g = p->g;
+    const int64_t nx = g.nVoxel[0], ny = g.nVoxel[1];
+    const int64_t elems = nx * ny * slab.mem_n;
+    const size_t vbytes = (size_t)elems * dtype_size(vt);
+    // transposed copy for the blocks whose rays run along x (stream-ordered scratch; without it
+    // every block reads the natural layout)
+    void *volT = nullptr;
+    const bool want_t = slab.scratch_ok && nx > 1 && ny > 1;
+    if (want_t && hipMallocAsync(&volT, vbytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        volT = nullptr;
+    }
+    if (volT) {
+        const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)slab.mem_n);
+        CT_DISPATCH1(vt, T,
+                     hipLaunchKernelGGL((k_transpose_xy<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)volT, (int)nx, (int)ny));
+        CT_HIP(hipGetLastError());
+    }
+    // 32-bit signed byte offsets: volumes (or slabs) below 2 GiB
+    const bool buf = (uint64_t)vbytes < (uint64_t(1) << 31);
     // launch in pieces of at most 2^30 blocks' worth of angles
-    const int64_t vb = (p->g.nDetector[1] + FWD_TV - 1) / FWD_TV;
-    const int64_t ub = (p->g.nDetector[0] + FWD_TU - 1) / FWD_TU;
+    const int64_t vb = (g.nDetector[1] + FWD_TV - 1) / FWD_TV;
+    const int64_t ub = (g.nDetector[0] + FWD_TU - 1) / FWD_TU;
     const int64_t max_ang = std::max<int64_t>(1, (int64_t(1) << 30) / (vb * ub));
-    const size_t proj_angle = (size_t)p->g.nDetector[0] * p->g.nDetector[1] * dtype_size(pt);
+    const size_t proj_angle = (size_t)g.nDetector[0] * g.nDetector[1] * dtype_size(pt);
     for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
         const int64_t c1 = std::min(a1, c0 + max_ang);
         FwdArgs A = make_args(p, tab, c0, c1, slab, accumulate);
         char *pp = (char *)proj + (size_t)(c0 - a0) * proj_angle;
         const dim3 grid(fwd_grid(A)), block(256);
+#define CT_FWD_LAUNCH(KERN, IDX)                                                                             \
+    CT_DISPATCH2(vt, TV, pt, TP,                                                                             \
+                 hipLaunchKernelGGL((KERN<TV, TP, IDX>), grid, block, 0, st, (const TV *)vol, (const TV *)volT, \
+                                    (TP *)pp, A))
         if (kind == CT_SIDDON) {
-            CT_DISPATCH2(vt, TV, pt, TP,
-                         hipLaunchKernelGGL((k_siddon<TV, TP>), grid, block, 0, st, (const TV *)vol, (TP *)pp, A));
+            if (buf) {
+                CT_FWD_LAUNCH(k_siddon, true);
+            } else {
+                CT_FWD_LAUNCH(k_siddon, false);
+            }
         } else {
-            CT_DISPATCH2(vt, TV, pt, TP,
-                         hipLaunchKernelGGL((k_interp<TV, TP>), grid, block, 0, st, (const TV *)vol, (TP *)pp, A));
+            if (buf) {
+                CT_FWD_LAUNCH(k_interp, true);
+            } else {
+                CT_FWD_LAUNCH(k_interp, false);
+            }
         }
+#undef CT_FWD_LAUNCH
         CT_HIP(hipGetLastError());
     }
+    if (volT) CT_HIP(hipFreeAsync(volT, st));
     return CT_OK;
 }
 

@@ -250,6 +250,7 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
         sl.mem_n = mem_hi - mem_lo;
         sl.first = (n == 0);
         sl.last = (own_hi == nz);
+        sl.scratch_ok = false;
         const bool acc = n > 0;
         for (int64_t c = 0; c < nchunks; ++c) {
             const int j = (int)(c % 3);
@@ -353,6 +354,7 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
         sl.mem_lo = own_lo;
         sl.mem_n = own_hi - own_lo;
         sl.first = sl.last = true;
+        sl.scratch_ok = false;
         bool h2d_used[2] = {false, false};
         for (int64_t c = 0; c < nchunks; ++c) {
             const int j = (int)(c % 2);

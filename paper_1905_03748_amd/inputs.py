@@ -300,3 +300,36 @@ def sample_indices(n_total: int, n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     n = min(n, n_total)
     return np.sort(rng.choice(n_total, size=n, replace=False)).astype(np.int64)
+
+
+def voxelize_torch(w: Workload, ells: list[Ellipsoid] | None = None, device="cpu"):
+    """Same recipe as ``voxelize`` (centre-inside test, densities add), evaluated with torch on
+    ``device`` one ellipsoid bounding box at a time; FP32 result [z][y][x]."""
+    import torch
+    if ells is None:
+        ells = ellipsoids(w)
+    nx, ny, nz = w.nvox
+    dx, dy, dz = w.dvox
+    ox, oy, oz = w.off_origin
+    vol = torch.zeros((nz, ny, nx), dtype=torch.float32, device=device)
+    cx = torch.tensor(voxel_centres_1d(nx, dx, ox), dtype=torch.float64, device=device)
+    cy = torch.tensor(voxel_centres_1d(ny, dy, oy), dtype=torch.float64, device=device)
+    cz = torch.tensor(voxel_centres_1d(nz, dz, oz), dtype=torch.float64, device=device)
+    for e in ells:
+        r = float(np.max(e.semi))
+        lo, hi = [], []
+        for i, (n, d, o) in enumerate(zip((nx, ny, nz), (dx, dy, dz), (ox, oy, oz))):
+            lo.append(int(max(0, math.floor((e.centre[i] - r - o) / d + (n - 1) / 2.0))))
+            hi.append(int(min(n - 1, math.ceil((e.centre[i] + r - o) / d + (n - 1) / 2.0))))
+        if any(h < l for l, h in zip(lo, hi)):
+            continue
+        Rt = torch.tensor(e.R.T / e.semi[:, None], dtype=torch.float64, device=device)
+        Z = (cz[lo[2]:hi[2] + 1] - e.centre[2])[:, None, None]
+        Y = (cy[lo[1]:hi[1] + 1] - e.centre[1])[None, :, None]
+        X = (cx[lo[0]:hi[0] + 1] - e.centre[0])[None, None, :]
+        q0 = Rt[0, 0] * X + Rt[0, 1] * Y + Rt[0, 2] * Z
+        q1 = Rt[1, 0] * X + Rt[1, 1] * Y + Rt[1, 2] * Z
+        q2 = Rt[2, 0] * X + Rt[2, 1] * Y + Rt[2, 2] * Z
+        inside = (q0 * q0 + q1 * q1 + q2 * q2 <= 1.0).to(torch.float32)
+        vol[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] += float(e.rho) * inside
+    return vol
