@@ -115,7 +115,7 @@ def serving_bench(dev, n_requests=12, seed=7, slots=8):
     srv = Server(budget, max_slots=1, device=dev)
     srv.submit(clone(reqs[0])).done.wait()
     srv.close()
-    for name, nslots in (("one_at_a_time", 1), ("batched", slots)):
+    for name, nslots in (("one_at_a_time", 1), ("batched_2", 2), ("batched_4", 4), ("batched_8", 8)):
         srv = Server(budget, max_slots=nslots, device=dev)
         t0 = time.perf_counter()
         for q in reqs:
@@ -129,6 +129,8 @@ def serving_bench(dev, n_requests=12, seed=7, slots=8):
                      "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
                      "throughput_gvps": round(st["throughput_gvps"], 1), "max_active": st["max_active"]}
     cap = out["one_at_a_time"]["throughput_req_s"]
+    best = max(("batched_2", "batched_4", "batched_8"), key=lambda k: out[k]["throughput_req_s"])
+    slots = out[best]["slots"]
     qps = 0.9 * cap
     gaps = np.random.default_rng(seed + 1).exponential(1.0 / qps, n_requests)
     srv = Server(budget, max_slots=slots, device=dev)
@@ -140,9 +142,10 @@ def serving_bench(dev, n_requests=12, seed=7, slots=8):
     srv.drain()
     st = srv.stats()
     srv.close()
-    out["poisson"] = {"qps": round(qps, 3), "load": 0.9, "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
-                      "max_active": st["max_active"], "peak_hbm_gib": round(st["peak_hbm_bytes"] / 2 ** 30, 2)}
-    out["batched_vs_one_at_a_time"] = round(out["batched"]["throughput_req_s"] / cap, 3)
+    out["poisson"] = {"qps": round(qps, 3), "load": 0.9, "slots": slots, "p50_s": round(st["p50_s"], 3),
+                      "p99_s": round(st["p99_s"], 3), "max_active": st["max_active"],
+                      "peak_hbm_gib": round(st["peak_hbm_bytes"] / 2 ** 30, 2)}
+    out["batched_vs_one_at_a_time"] = round(out[best]["throughput_req_s"] / cap, 3)
     return out
 
 

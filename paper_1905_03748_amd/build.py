@@ -32,11 +32,12 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON
+def _compile(src: str, verbose: bool, defines=(), tag="") -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
+    dflags = [f"-D{d}" for d in defines]
+    cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON + dflags
     if src.endswith(".hip"):
-        cmd = [_hipcc(), "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE_FLAGS
+        cmd = [_hipcc(), "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE_FLAGS + dflags
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,20 +48,24 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
+    """Compile and link.  `defines` (NAME=VALUE strings) and `out` build a variant library for
+    tuning experiments; the default builds libct.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    lib = out or LIB
+    tag = "" if out is None else "." + os.path.basename(out)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, defines, tag), srcs))
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -82,9 +82,12 @@ inline Slab full_slab(const ct_geometry &g) {
 
 // Kernel launchers (resident; pointers are device pointers; projection pointer holds the
 // angles [a0, a1) starting at projection 0).
+// volT: optional [z][x][y] copy of vol kept by the caller (then no scratch copy is made)
 ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtype vt, void *proj,
                          ct_dtype pt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
-                         hipStream_t st);
+                         hipStream_t st, const void *volT = nullptr);
+ct_status launch_transpose_xy(const void *vol, ct_dtype vt, void *volT, int64_t nx, int64_t ny, int64_t nz,
+                              hipStream_t st);
 ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
                              hipStream_t st);
@@ -107,7 +110,7 @@ size_t tv_workspace(const ct_geometry &g);
 
 // SART pieces (kern_backproject.hip / kern_forward.hip)
 ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hipStream_t st);
-ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda,
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, float *volT, int64_t angle, float lambda,
                              hipStream_t st);
 
 // Out-of-core (ooc.cpp)

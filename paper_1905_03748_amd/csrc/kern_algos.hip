@@ -314,10 +314,13 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
 // ---------------------------------------------------------------------------------------------
 // SART
 
+// chords of every ray, one angle's residual, and a [z][x][y] copy of x kept in step by the update
+// (the per-angle projections read it instead of re-transposing x at every angle)
 size_t sart_workspace(const ct_plan *p) {
     const ct_geometry &g = p->g;
     const size_t pix = (size_t)g.nDetector[0] * g.nDetector[1];
-    return align256(pix * p->angles.size() * 4) + align256(pix * 4);
+    const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
+    return align256(pix * p->angles.size() * 4) + align256(pix * 4) + align256(nv * 4);
 }
 
 ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, void *work, hipStream_t st) {
@@ -329,16 +332,18 @@ ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lam
     if (s != CT_OK) return s;
     float *chord = (float *)ws.take(pix * na * 4);
     float *r = (float *)ws.take(pix * 4);
+    float *xT = (float *)ws.take(g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2] * 4);
     const float thr = (float)(1e-2 * std::fmin(g.dVoxel[0], std::fmin(g.dVoxel[1], g.dVoxel[2])));
     CK(launch_ray_chord(p, chord, 0, na, st));
+    CK(launch_transpose_xy(x, CT_F32, xT, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
     const Slab full = full_slab(g);
     for (int32_t it = 0; it < niter; ++it) {
         for (int64_t t = 0; t < na; ++t) {
-            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st));
+            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st, xT));
             hipLaunchKernelGGL(k_sart_resid, dim3(ew_grid(pix)), dim3(EW_THREADS), 0, st, (const float *)b + t * pix,
                                chord + t * pix, r, thr, pix);
             CT_HIP(hipGetLastError());
-            CK(launch_sart_update(p, r, (float *)x, t, (float)lambda, st));
+            CK(launch_sart_update(p, r, (float *)x, xT, t, (float)lambda, st));
         }
     }
     return CT_OK;

@@ -21,7 +21,13 @@ namespace ct {
 namespace {
 
 constexpr int BP_TX = 16, BP_TY = 16;
-constexpr int BP_NZ = 8;
+#ifndef CT_BP_NZ
+#define CT_BP_NZ 8
+#endif
+#ifndef CT_ADJ_NZ
+#define CT_ADJ_NZ 16
+#endif
+constexpr int BP_NZ = CT_BP_NZ;  // voxels per thread (FDK / pseudo-matched)
 
 struct BpArgs {
     const AngleGeo *tab;
@@ -130,14 +136,18 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
 // Exact transpose of the Siddon projector, gathered per voxel.
 //
 // For one angle and one detector column a, every ray lies in the vertical plane through the source
-// and that column, so all rows share the (x, y) trace and its parameter interval [t0, t1] inside
-// the voxel column's square (set up once, in FP64).  Along a row b the height is z(t) = t v_b (the
-// source is in the z = 0 plane), so inside the column the row covers [t0 v_b, t1 v_b]: a short
-// segment, sorted in z by b.  Each candidate row is visited once per column and its exact chord is
-// split over the one or two voxels of the thread's z run that it crosses; the per-voxel sums live
-// in LDS (one slot per thread per voxel, conflict-free), in a fixed order (angle, a, b), so the
-// result is deterministic.
-constexpr int ADJ_NZ = 16;
+// and that column, so all rows share the (x, y) trace and its parameter interval [t0, t0 + T] inside
+// the voxel column's square.  The trace is clipped in a frame centred on the column: only the
+// signed distance of the column centre from the trace (a 2-D cross product of ~1e3 mm vectors,
+// which cancels) is formed in FP64; the clip itself works on O(1 mm) local quantities in FP32.
+// Along row b the height is z(t) = t v_b (the source is in the z = 0 plane), so inside the column
+// the row covers [t0 v_b, (t0 + T) v_b]: a short segment, sorted in z by b.  Each candidate row is
+// visited once per column; its exact chord goes to the voxel of the thread's z run that holds it, or
+// is split in proportion to height when it crosses a voxel face.  Voxel ranges are computed from
+// absolute indices, so a voxel's sum does not depend on how the volume is cut into launches or
+// slabs.  The per-voxel sums live in LDS (one slot per thread per voxel, conflict-free) and are
+// added in a fixed order (angle, a, b): deterministic.
+constexpr int ADJ_NZ = CT_ADJ_NZ;  // voxels per thread (exact adjoint)
 
 template <typename TP, typename TV>
 __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj, TV *__restrict__ vol, BpArgs A) {
@@ -155,91 +165,97 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
                                   : 0.0f;
     }
     if (!live) return;  // no barrier follows: each thread owns its LDS slots
-    // column square (mm, FP64 for the ray set-up; FP32 copies for the candidate range)
-    const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;
-    const double xl = xc - 0.5 * A.ddx, xh = xc + 0.5 * A.ddx;
-    const double yl = yc - 0.5 * A.ddy, yh = yc + 0.5 * A.ddy;
-    const float fxl = (float)xl, fxh = (float)xh, fyl = (float)yl, fyh = (float)yh;
-    const float zface0 = (float)(A.dz0 - 0.5 * A.ddz);           // lower face of voxel 0
-    const float zl0 = fmaf((float)kb, A.dz, zface0);             // lower face of voxel kb
+    const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;  // column centre (mm)
+    const float hx = 0.5f * A.dx, hy = 0.5f * A.dy;
+    const float fxc = (float)xc, fyc = (float)yc;
+    const float zface0 = (float)(A.dz0 - 0.5 * A.ddz);  // lower face of voxel 0
     const float dz = A.dz, idz = 1.0f / A.dz;
     const int nzr = min(ADJ_NZ, A.own_hi - kb);
-    const float zr_hi = zl0 + nzr * dz;
-    const float v0 = (float)(A.offv - A.cv * A.dv), dv = (float)A.dv;
-    const float fDSO = A.DSO, fDSD = A.DSD;
+    const float zl0 = fmaf((float)kb, dz, zface0), zr_hi = fmaf((float)(kb + nzr), dz, zface0);
+    const float v0 = (float)(A.offv - A.cv * A.dv), dv = (float)A.dv, idv = 1.0f / dv;
+    const float aum = (float)(A.cu - A.offu / A.du), iau = (float)(1.0 / A.du);
     const int64_t psz = (int64_t)A.nu * A.nv;
+    constexpr int ES = (int)sizeof(TP);
+    const int rowb = A.nu * ES;
     for (int t = 0; t < A.nang; ++t) {
         const AngleGeo &G = A.tab[A.a0 + t];
         const double c = G.c, s = G.s;
-        const double Sx = A.dDSO * c, Sy = A.dDSO * s;
+        const double Wx = xc - A.dDSO * c, Wy = yc - A.dDSO * s;  // source -> column centre
+        const float fc = (float)c, fs = (float)s;
         // detector columns whose rays can meet the square: central projection of its corners
         // (FP32 with a margin: the range only has to contain every hit column)
-        const float fc = (float)c, fs = (float)s;
         float umin = FLT_MAX, umax = -FLT_MAX;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float X = (q & 1) ? fxh : fxl, Y = (q & 2) ? fyh : fyl;
-            const float u = fDSD * (Y * fc - X * fs) / (fDSO - (X * fc + Y * fs));
+            const float X = fxc + ((q & 1) ? hx : -hx), Y = fyc + ((q & 2) ? hy : -hy);
+            const float u = A.DSD * (Y * fc - X * fs) * __builtin_amdgcn_rcpf(A.DSO - (X * fc + Y * fs));
             umin = fminf(umin, u);
             umax = fmaxf(umax, u);
         }
-        const float aum = (float)A.cu - (float)A.offu / (float)A.du, iau = 1.0f / (float)A.du;
         const int alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - 1e-3f), 0.0f);
         const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + 1e-3f), (float)(A.nu - 1));
-        const TP *P = proj + (int64_t)t * psz;
+        const __amdgpu_buffer_rsrc_t R = proj_rsrc(proj + (int64_t)t * psz, psz * ES);
         for (int a = alo; a <= ahi; ++a) {
             const double ua = (a - A.cu) * A.du + A.offu;
-            // ray (x, y) trace: S + t (P - S), P - S = -DSD (c, s) + ua (-s, c)
+            // (x, y) direction of the rays of column a: P - S = -DSD (c, s) + ua (-s, c)
             const double Dx = -A.dDSD * c - ua * s, Dy = -A.dDSD * s + ua * c;
-            const double Lxy2 = Dx * Dx + Dy * Dy;
-            double t0 = 0.0, t1 = 1.0;
-            if (Dx * Dx < 1e-24 * Lxy2) {
-                if (Sx < xl || Sx > xh) continue;
-            } else {
-                const double iDx = 1.0 / Dx;
-                const double ta = (xl - Sx) * iDx, tb = (xh - Sx) * iDx;
-                t0 = fmax(t0, fmin(ta, tb));
-                t1 = fmin(t1, fmax(ta, tb));
+            const float cross = (float)(Wx * Dy - Wy * Dx);   // = |D| * signed distance
+            const float dotp = (float)(Wx * Dx + Wy * Dy);    // = |D|^2 * t of the closest point
+            const float fDx = (float)Dx, fDy = (float)Dy;
+            const float L2 = fmaf(fDx, fDx, fDy * fDy);
+            const float iL = __builtin_amdgcn_rsqf(L2);
+            const float ux = fDx * iL, uy = fDy * iL;
+            const float dperp = cross * iL;
+            // closest point of the trace to the column centre, relative to the centre
+            const float fx = -dperp * uy, fy = dperp * ux;
+            // slab clip of fx + s ux in [-hx, hx], fy + s uy in [-hy, hy]  (s in mm)
+            float s0 = -FLT_MAX, s1 = FLT_MAX;
+            if (fabsf(ux) > 1e-7f) {
+                const float r = __builtin_amdgcn_rcpf(ux);
+                const float qa = (-hx - fx) * r, qb = (hx - fx) * r;
+                s0 = fmaxf(s0, fminf(qa, qb));
+                s1 = fminf(s1, fmaxf(qa, qb));
+            } else if (fabsf(fx) > hx) {
+                continue;
             }
-            if (Dy * Dy < 1e-24 * Lxy2) {
-                if (Sy < yl || Sy > yh) continue;
-            } else {
-                const double iDy = 1.0 / Dy;
-                const double ta = (yl - Sy) * iDy, tb = (yh - Sy) * iDy;
-                t0 = fmax(t0, fmin(ta, tb));
-                t1 = fmin(t1, fmax(ta, tb));
+            if (fabsf(uy) > 1e-7f) {
+                const float r = __builtin_amdgcn_rcpf(uy);
+                const float qa = (-hy - fy) * r, qb = (hy - fy) * r;
+                s0 = fmaxf(s0, fminf(qa, qb));
+                s1 = fminf(s1, fmaxf(qa, qb));
+            } else if (fabsf(fy) > hy) {
+                continue;
             }
-            if (!(t0 < t1)) continue;
-            const float T = (float)(t1 - t0);
-            const float ft0 = (float)t0;
-            const float it0 = (float)(1.0 / t0), it1 = (float)(1.0 / t1);
-            const float lxy2 = (float)Lxy2;
-            // rows whose z range inside the column meets the thread's z run [zl0, zr_hi]
+            if (!(s0 < s1)) continue;
+            const float T = (s1 - s0) * iL;                       // t-length inside the column
+            const float t0 = fmaf(s0, iL, dotp * (iL * iL));      // t where the trace enters
+            const float t1 = t0 + T;
+            // rows whose height range inside the column meets the thread's z run [zl0, zr_hi]
+            const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t1);
             const float vmin = fminf(zl0 * it0, zl0 * it1), vmax = fmaxf(zr_hi * it0, zr_hi * it1);
-            const int blo = (int)fmaxf(ceilf((vmin - v0) / dv - 1e-3f), 0.0f);
-            const int bhi = (int)fminf(floorf((vmax - v0) / dv + 1e-3f), (float)(A.nv - 1));
-            for (int b = blo; b <= bhi; ++b) {
-                const float y = ldf(P, (int64_t)b * A.nu + a);
+            const int blo = (int)fmaxf(ceilf((vmin - v0) * idv - 1e-3f), 0.0f);
+            const int bhi = (int)fminf(floorf((vmax - v0) * idv + 1e-3f), (float)(A.nv - 1));
+            int off = blo * rowb + a * ES;
+            for (int b = blo; b <= bhi; ++b, off += rowb) {
+                const float y = bload(R, off, (TP *)nullptr);
                 const float vb = fmaf((float)b, dv, v0);
-                const float za = ft0 * vb;           // height where the row enters the column
-                const float zb = fmaf(vb, T, za);    // ... and where it leaves
-                const float lo = fminf(za, zb), hi = fmaxf(za, zb);
-                const float full = T * sqrtf(fmaf(vb, vb, lxy2));  // chord inside the column
-                const float ext = hi - lo;
-                // one voxel of slack on each side: the overlaps below use absolute voxel faces, so
-                // rounding in this index only adds zero-length terms, and every voxel's sum is the
-                // same whichever z run (launch, slab) holds it
-                const int k0 = max((int)floorf((lo - zl0) * idz) - 1, 0);
-                const int kend = min((int)floorf((hi - zl0) * idz) + 1, nzr - 1);
-                int k = k0;
-                for (; k <= kend; ++k) {
-                    const float zl = fmaf((float)(kb + k), dz, zface0);
-                    const float ov = fminf(hi, zl + dz) - fmaxf(lo, zl);
-                    // the chord splits over the voxels in proportion to the height covered
-                    // a level row (zero height range) lies in the voxel whose [zl, zl + dz) holds it
-                    const float len = ext > 0.0f ? full * (fmaxf(ov, 0.0f) / ext)
-                                                 : ((lo >= zl && lo < zl + dz) ? full : 0.0f);
-                    accs[k * 256 + tid] = fmaf(len, y, accs[k * 256 + tid]);
+                const float za = t0 * vb;            // height where the row enters the column
+                const float ext = T * vb;            // signed height change across the column
+                const float lo = fminf(za, za + ext), hi = fmaxf(za, za + ext);
+                const float full = T * sqrtf(fmaf(vb, vb, L2));   // chord inside the column
+                const int klo = (int)floorf((lo - zface0) * idz) - kb;
+                const int khi = (int)floorf((hi - zface0) * idz) - kb;
+                if (klo == khi) {
+                    // the row stays inside one voxel
+                    if ((unsigned)klo < (unsigned)nzr) accs[klo * 256 + tid] = fmaf(full, y, accs[klo * 256 + tid]);
+                } else {
+                    const float iext = __builtin_amdgcn_rcpf(hi - lo);
+                    const int ke = min(khi, nzr - 1);
+                    for (int k = max(klo, 0); k <= ke; ++k) {
+                        const float zl = fmaf((float)(kb + k), dz, zface0);
+                        const float ov = fmaxf(fminf(hi, zl + dz) - fmaxf(lo, zl), 0.0f);
+                        accs[k * 256 + tid] = fmaf(full * (ov * iext), y, accs[k * 256 + tid]);
+                    }
                 }
             }
         }
@@ -255,8 +271,8 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
 
 // SART update for one angle t with FDK weights:
 //   x_j += lambda * (w_j * bilinear(r)) / (w_j * bilinear(1))   where w_j * bilinear(1) > 1e-6
-__global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r, float *__restrict__ vol, BpArgs A,
-                                                     float lambda) {
+__global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r, float *__restrict__ vol,
+                                                     float *__restrict__ volT, BpArgs A, float lambda) {
     const int i = blockIdx.x * BP_TX + (threadIdx.x % BP_TX);
     const int j = blockIdx.y * BP_TY + (threadIdx.x / BP_TX);
     const int kb = blockIdx.z * BP_NZ;
@@ -295,7 +311,9 @@ __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r
         const float V = w * ((wa0 + wa1) * (wb0 + wb1));
         if (V > 1e-6f) {
             const int64_t o = ((int64_t)kk * A.ny + j) * A.nx + i;
-            vol[o] = fmaf(lambda, num / V, vol[o]);
+            const float nv = fmaf(lambda, num / V, vol[o]);
+            vol[o] = nv;
+            if (volT) volT[((int64_t)kk * A.nx + i) * A.ny + j] = nv;  // keep the [z][x][y] copy in step
         }
     }
 }
@@ -373,13 +391,14 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     return CT_OK;
 }
 
-ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda, hipStream_t st) {
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, float *volT, int64_t angle, float lambda,
+                             hipStream_t st) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     BpArgs A = make_bp_args(p, tab, angle, angle + 1, full_slab(p->g), 1);
     const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((A.nz + BP_NZ - 1) / BP_NZ));
-    hipLaunchKernelGGL(k_sart_update, grid, dim3(256), 0, st, r, vol, A, lambda);
+    hipLaunchKernelGGL(k_sart_update, grid, dim3(256), 0, st, r, vol, volT, A, lambda);
     CT_HIP(hipGetLastError());
     return CT_OK;
 }

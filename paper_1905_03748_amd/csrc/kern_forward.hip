@@ -139,8 +139,14 @@ __device__ __forceinline__ View<TV, BUF> pick_view(const TV *vol, const TV *volT
 // voxel indices never leave the grid and need no per-step checks.  Pieces are produced BATCH at a
 // time and their gathers issued together, so several loads per lane are in flight.
 
-constexpr int SID_BATCH = 8;
-constexpr int INT_BATCH = 4;
+#ifndef CT_SID_BATCH
+#define CT_SID_BATCH 8
+#endif
+#ifndef CT_INT_BATCH
+#define CT_INT_BATCH 4
+#endif
+constexpr int SID_BATCH = CT_SID_BATCH;  // Siddon pieces per trip
+constexpr int INT_BATCH = CT_INT_BATCH;  // interpolation samples per trip
 
 template <typename VIEW>
 __device__ __forceinline__ float siddon_ray(const VIEW V, const FwdArgs &A, const AngleGeo &G, int a, int b) {
@@ -415,8 +421,18 @@ unsigned fwd_grid(const FwdArgs &A) {
 
 }  // namespace
 
+ct_status launch_transpose_xy(const void *vol, ct_dtype vt, void *volT, int64_t nx, int64_t ny, int64_t nz,
+                              hipStream_t st) {
+    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)nz);
+    CT_DISPATCH1(vt, T,
+                 hipLaunchKernelGGL((k_transpose_xy<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)volT, (int)nx, (int)ny));
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
 ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtype vt, void *proj, ct_dtype pt,
-                         int accumulate, int64_t a0, int64_t a1, const Slab &slab, hipStream_t st) {
+                         int accumulate, int64_t a0, int64_t a1, const Slab &slab, hipStream_t st,
+                         const void *volT_given) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
@@ -427,17 +443,21 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
     const size_t vbytes = (size_t)elems * dtype_size(vt);
     // transposed copy for the blocks whose rays run along x (stream-ordered scratch; without it
     // every block reads the natural layout)
-    void *volT = nullptr;
-    const bool want_t = slab.scratch_ok && nx > 1 && ny > 1;
-    if (want_t && hipMallocAsync(&volT, vbytes, st) != hipSuccess) {
+    void *volT = const_cast<void *>(volT_given);
+    void *own_t = nullptr;
+#ifdef CT_NO_TRANSPOSE
+    const bool want_t = false;
+#else
+    const bool want_t = !volT && slab.scratch_ok && nx > 1 && ny > 1;
+#endif
+    if (want_t && hipMallocAsync(&own_t, vbytes, st) != hipSuccess) {
         (void)hipGetLastError();
-        volT = nullptr;
+        own_t = nullptr;
     }
-    if (volT) {
-        const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)slab.mem_n);
-        CT_DISPATCH1(vt, T,
-                     hipLaunchKernelGGL((k_transpose_xy<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)volT, (int)nx, (int)ny));
-        CT_HIP(hipGetLastError());
+    if (own_t) {
+        ct_status ts = launch_transpose_xy(vol, vt, own_t, nx, ny, slab.mem_n, st);
+        if (ts != CT_OK) return ts;
+        volT = own_t;
     }
     // 32-bit signed byte offsets: volumes (or slabs) below 2 GiB
     const bool buf = (uint64_t)vbytes < (uint64_t(1) << 31);
@@ -471,7 +491,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
 #undef CT_FWD_LAUNCH
         CT_HIP(hipGetLastError());
     }
-    if (volT) CT_HIP(hipFreeAsync(volT, st));
+    if (own_t) CT_HIP(hipFreeAsync(own_t, st));
     return CT_OK;
 }
 
