@@ -31,6 +31,25 @@ SIDDON_SEG_PER_VP = 1.132
 BYTES_PER_VP = {"siddon": 4.0 * SIDDON_SEG_PER_VP, "fdk": 16.0}
 
 
+def kernel_source_hash(name):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1905_03748_amd", "csrc", name)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel_key):
+    """HBM traffic of a kernel per launch from the committed counter runs (profiles/traffic.json):
+    FETCH_SIZE and WRITE_SIZE scaled by what the same counters read for a plain copy of known
+    size.  None when the kernel's source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel_key)
+    if not rec or rec.get("source_sha256") != kernel_source_hash(rec["source"]):
+        return None
+    return rec
+
+
 def A_sart_ws(plan):
     from paper_1905_03748_amd import _abi
     return _abi.ct_sart_workspace_bytes(plan.handle)
@@ -240,18 +259,34 @@ def ooc_bench(dev, cap_gib=32):
     plan = Plan(w.geometry_dict(), w.angles)
     cap = cap_gib << 30
     log("[ooc] allocating pinned host arrays")
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipHostMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_uint]
+    hip.hipHostFree.argtypes = [ctypes.c_void_p]
+
+    def pinned(shape):
+        # exact-size pinned allocation (torch's pinned allocator may round sizes up)
+        n = int(np.prod(shape))
+        ptr = ctypes.c_void_p()
+        if hip.hipHostMalloc(ctypes.byref(ptr), n * 4, 0) != 0:
+            raise MemoryError(f"hipHostMalloc of {n * 4} bytes failed")
+        arr = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_float)), shape=(n,))
+        return torch.from_numpy(arr).view(*shape), ptr
+
     t = time.perf_counter()
-    vol = torch.empty(plan.vol_shape, dtype=torch.float32, pin_memory=True)
-    proj = torch.empty(plan.proj_shape, dtype=torch.float32, pin_memory=True)
+    vol, vptr = pinned(plan.vol_shape)
+    proj, pptr = pinned(plan.proj_shape)
     t_alloc = time.perf_counter() - t
     log(f"[ooc] pinned 216 GiB in {t_alloc:.1f} s; building the phantom slab by slab")
     ells = inputs.ellipsoids(w)
     nz = w.nvox[2]
     step = 256
     for z0 in range(0, nz, step):
-        ws = inputs.Workload("slab", (w.nvox[0], w.nvox[1], min(step, nz - z0)), w.dvox, w.ndet, w.ddet, 1, 0, 0,
-                             off_origin=(0.0, 0.0, (z0 + min(step, nz - z0) / 2.0 - nz / 2.0) * w.dvox[2]))
-        vol[z0:z0 + ws.nvox[2]].copy_(inputs.voxelize_torch(ws, ells, device=dev).cpu())
+        h = min(step, nz - z0)
+        ws = inputs.Workload("slab", (w.nvox[0], w.nvox[1], h), w.dvox, w.ndet, w.ddet, 1, 0, 0,
+                             off_origin=(0.0, 0.0, (z0 + h / 2.0 - nz / 2.0) * w.dvox[2]))
+        vol[z0:z0 + h].copy_(inputs.voxelize_torch(ws, ells, device=dev))
+        torch.cuda.synchronize()
     out = {"workload": "3072^3 FP32 (108 GiB) volume, 3072 angles of 3072^2 (108 GiB), pinned host memory",
            "cap_gib": cap_gib, "pin_alloc_s": round(t_alloc, 1)}
     log("[ooc] forward")
@@ -266,6 +301,9 @@ def ooc_bench(dev, cap_gib=32):
     out["backprojection"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
     out["backprojection"]["h2d_gbs"] = round(st["bytes_h2d"] / st["t_total_s"] / 1e9, 1)
     log(f"[ooc] backprojection done: {out['backprojection']}")
+    del vol, proj
+    hip.hipHostFree(vptr)
+    hip.hipHostFree(pptr)
     return out
 
 
@@ -349,10 +387,15 @@ def main():
                 "siddon_fwd_gvps": round(vp / (fwd_ms * 1e-3) / 1e9, 2),
                 "fdk_bp_gvps": round(vp / (bp_ms * 1e-3) / 1e9, 2)},
         "roofline": {"bound": "hbm", "kernel": "k_siddon" if dom == "siddon" else "k_bp_voxel<FDK>",
-                     "byte_model": "gather model: %s B per voxel.proj" % BYTES_PER_VP[dom],
+                     "byte_model": "gather model: %s B per voxel.proj" % round(BYTES_PER_VP[dom], 3),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
+    rec = recorded_traffic("siddon_fwd" if dom == "siddon" else "fdk_bp")
+    if rec is not None:
+        gb = (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024 / 1e9
+        out["roofline"]["traffic"] = round(gb, 2)
+        out["roofline"]["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; %s)" % rec["profile"]
 
     if not args.no_extras:
         def timed(fn, reps=3):

