@@ -82,12 +82,22 @@ inline Slab full_slab(const ct_geometry &g) {
 
 // Kernel launchers (resident; pointers are device pointers; projection pointer holds the
 // angles [a0, a1) starting at projection 0).
-// volT: optional [z][x][y] copy of vol kept by the caller (then no scratch copy is made)
+// vcopy: optional copy of vol in the layout the projector reads, kept by the caller (then no
+// scratch copy is made): for Siddon the column-major slots of launch_zcols, for the interpolated
+// projector the [z][x][y] transpose of launch_transpose_xy.
 ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtype vt, void *proj,
                          ct_dtype pt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
-                         hipStream_t st, const void *volT = nullptr);
+                         hipStream_t st, const void *vcopy = nullptr);
 ct_status launch_transpose_xy(const void *vol, ct_dtype vt, void *volT, int64_t nx, int64_t ny, int64_t nz,
                               hipStream_t st);
+// [z][y][x] -> [y][x][slot], slot z + 1 holding voxel z, slots 0 and nz + 1 zero
+// (nx * ny * (nz + 2) elements)
+ct_status launch_zcols(const void *vol, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
+// inverse: column-major slots -> [z][y][x]
+ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
+inline int64_t zcol_elems(const ct_geometry &g) { return g.nVoxel[0] * g.nVoxel[1] * (g.nVoxel[2] + 2); }
+// whether the column Siddon walk is valid for angles [a0, a1) of the plan
+bool zcol_ok(const ct_plan *p, int64_t a0, int64_t a1);
 ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
                              hipStream_t st);
@@ -110,8 +120,10 @@ size_t tv_workspace(const ct_geometry &g);
 
 // SART pieces (kern_backproject.hip / kern_forward.hip)
 ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hipStream_t st);
-ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, float *volT, int64_t angle, float lambda,
-                             hipStream_t st);
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda, hipStream_t st);
+// the same update on the column-major copy (launch_zcols layout), residual rT in [u][v] layout
+ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t angle, float lambda,
+                                 hipStream_t st);
 
 // Out-of-core (ooc.cpp)
 ct_status ooc_plan(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt,

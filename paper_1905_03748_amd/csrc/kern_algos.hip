@@ -136,6 +136,30 @@ __global__ void k_sart_resid(const float *__restrict__ b, const float *__restric
     }
 }
 
+// The same residual written transposed, rT[u][v], through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void k_sart_resid_t(const float *__restrict__ b, const float *__restrict__ chord,
+                                                      const float *__restrict__ r, float *__restrict__ rT, float thr,
+                                                      int nu, int nv) {
+    __shared__ float tile[32][33];
+    const int u0 = blockIdx.x * 32, v0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int u = u0 + tx, v = v0 + ty + k;
+        if (u < nu && v < nv) {
+            const int64_t i = (int64_t)v * nu + u;
+            const float c = chord[i];
+            tile[ty + k][tx] = c > thr ? (b[i] - r[i]) / c : 0.0f;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int v = v0 + tx, u = u0 + ty + k;
+        if (u < nu && v < nv) rT[(int64_t)u * nv + v] = tile[tx][ty + k];
+    }
+}
+
 // TV_eps gradient with forward differences, unit spacing, zero difference at the last index.
 __global__ __launch_bounds__(256) void k_tv_grad(const float *__restrict__ x, float *__restrict__ g, int nx, int ny,
                                                  int nz, float eps) {
@@ -314,13 +338,12 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
 // ---------------------------------------------------------------------------------------------
 // SART
 
-// chords of every ray, one angle's residual, and a [z][x][y] copy of x kept in step by the update
-// (the per-angle projections read it instead of re-transposing x at every angle)
+// chords of every ray, one angle's residual (and its transpose), and a column-major copy of x
+// that the sweep projects from and updates in place (x is restored from it at the end)
 size_t sart_workspace(const ct_plan *p) {
     const ct_geometry &g = p->g;
     const size_t pix = (size_t)g.nDetector[0] * g.nDetector[1];
-    const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
-    return align256(pix * p->angles.size() * 4) + align256(pix * 4) + align256(nv * 4);
+    return align256(pix * p->angles.size() * 4) + 2 * align256(pix * 4) + align256((size_t)zcol_elems(g) * 4);
 }
 
 ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, void *work, hipStream_t st) {
@@ -332,18 +355,35 @@ ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lam
     if (s != CT_OK) return s;
     float *chord = (float *)ws.take(pix * na * 4);
     float *r = (float *)ws.take(pix * 4);
-    float *xT = (float *)ws.take(g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2] * 4);
+    float *rT = (float *)ws.take(pix * 4);
+    float *xz = (float *)ws.take((size_t)zcol_elems(g) * 4);
     const float thr = (float)(1e-2 * std::fmin(g.dVoxel[0], std::fmin(g.dVoxel[1], g.dVoxel[2])));
+    const int nu = (int)g.nDetector[0], nv = (int)g.nDetector[1];
     CK(launch_ray_chord(p, chord, 0, na, st));
-    CK(launch_transpose_xy(x, CT_F32, xT, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
     const Slab full = full_slab(g);
+    if (zcol_ok(p, 0, na)) {
+        // the sweep works on the column-major copy only
+        CK(launch_zcols(x, CT_F32, xz, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
+        const dim3 tg((unsigned)((nu + 31) / 32), (unsigned)((nv + 31) / 32));
+        for (int32_t it = 0; it < niter; ++it) {
+            for (int64_t t = 0; t < na; ++t) {
+                CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st, xz));
+                hipLaunchKernelGGL(k_sart_resid_t, tg, dim3(256), 0, st, (const float *)b + t * pix, chord + t * pix,
+                                   (const float *)r, rT, thr, nu, nv);
+                CT_HIP(hipGetLastError());
+                CK(launch_sart_update_col(p, rT, xz, t, (float)lambda, st));
+            }
+        }
+        CK(launch_zcols_inv(xz, CT_F32, x, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
+        return CT_OK;
+    }
     for (int32_t it = 0; it < niter; ++it) {
         for (int64_t t = 0; t < na; ++t) {
-            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st, xT));
+            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st));
             hipLaunchKernelGGL(k_sart_resid, dim3(ew_grid(pix)), dim3(EW_THREADS), 0, st, (const float *)b + t * pix,
                                chord + t * pix, r, thr, pix);
             CT_HIP(hipGetLastError());
-            CK(launch_sart_update(p, r, (float *)x, xT, t, (float)lambda, st));
+            CK(launch_sart_update(p, r, (float *)x, t, (float)lambda, st));
         }
     }
     return CT_OK;

@@ -11,6 +11,7 @@
 // box: the rays of detector column a all lie in one vertical plane, so their (x, y) traces are the
 // same line and the parameter interval [t0, t1] inside the voxel column's square is shared by all
 // rows b and all voxels of the column; only the z overlap depends on the row and the voxel.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -126,6 +127,148 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
     }
 #pragma unroll
     for (int k = 0; k < BP_NZ; ++k) {
+        const int kk = kb + k;
+        if (kk >= A.own_hi) break;
+        const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
+        vol[o] = from_f<TV>(acc[k]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// The same backprojection with the projection taps staged in LDS.  For each group of up to
+// BPL_K angles the block projects the eight corners of its 16 x 16 x BP_NZ voxel tile: a
+// perspective map sends the box into the convex hull of its corners' images, so the detector
+// window [floor(min a*) - 1, ...] x [floor(min b*) - 1, ...] of WW x HW pixels (sized on the host
+// from an analytic bound) holds every tap of every voxel of the tile.  The windows are copied
+// into LDS row by row (lanes on consecutive pixels, zeros outside the detector), and the voxels
+// read their bilinear taps there.  The per-voxel arithmetic is that of k_bp_voxel.
+#ifndef CT_BPL_NZ
+#define CT_BPL_NZ 8
+#endif
+constexpr int BPL_NZ = CT_BPL_NZ;  // voxels per thread
+constexpr int BPL_K = 8;           // angles per staging round (at most)
+constexpr int BPL_FLOATS = 4096;   // staged floats per block (16 KiB)
+
+// PITCH: LDS row pitch (floats) of a window, a compile-time constant so that both rows of a
+// bilinear tap pair are one base address with immediate offsets.
+template <int W, int PITCH, typename TP, typename TV>
+__global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV *__restrict__ vol, BpArgs A, int WW,
+                                                int HW, int K) {
+    __shared__ float win[BPL_FLOATS];
+    __shared__ int org[BPL_K][2];
+    const int i0 = blockIdx.x * BP_TX, j0 = blockIdx.y * BP_TY;
+    const int i = i0 + (threadIdx.x % BP_TX);
+    const int j = j0 + (threadIdx.x / BP_TX);
+    const int kb = A.own_lo + blockIdx.z * BPL_NZ;
+    const bool live = i < A.nx && j < A.ny;
+    const float x = fmaf((float)i, A.dx, A.x0);
+    const float y = fmaf((float)j, A.dy, A.y0);
+    float zk[BPL_NZ];
+#pragma unroll
+    for (int k = 0; k < BPL_NZ; ++k) zk[k] = fmaf((float)(kb + k), A.dz, A.z0);
+    float acc[BPL_NZ];
+#pragma unroll
+    for (int k = 0; k < BPL_NZ; ++k) {
+        const int kk = kb + k;
+        acc[k] = (live && A.accumulate && kk < A.own_hi) ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i])
+                                                          : 0.0f;
+    }
+    const int64_t psz = (int64_t)A.nu * A.nv;
+    const int wsz = PITCH * HW;
+    const float lamax = (float)(WW - 2), lbmax = (float)(HW - 2);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    for (int t0 = 0; t0 < A.nang; t0 += K) {
+        const int nk = min(K, A.nang - t0);
+        __syncthreads();  // the previous round's taps have been read
+        if (wave == 0) {
+            // lanes 8q .. 8q+7: the tile's corners under angle t0 + q
+            const int q = lane >> 3, cn = lane & 7;
+            float as = 0.0f, bs = 0.0f;
+            if (q < nk) {
+                const AngleGeo &G = A.tab[A.a0 + t0 + q];
+                const float c = (float)G.c, s = (float)G.s;
+                const float xc = fmaf((float)(i0 + ((cn & 1) ? BP_TX - 1 : 0)), A.dx, A.x0);
+                const float yc = fmaf((float)(j0 + ((cn & 2) ? BP_TY - 1 : 0)), A.dy, A.y0);
+                const float zc = fmaf((float)(kb + ((cn & 4) ? BPL_NZ - 1 : 0)), A.dz, A.z0);
+                const float iL = __builtin_amdgcn_rcpf(A.DSO - (xc * c + yc * s));
+                const float m = A.DSD * iL;
+                as = fmaf(m * (yc * c - xc * s), A.inv_du, A.au0);
+                bs = fmaf(zc, m * A.inv_dv, A.bv0);
+            }
+            float amin = as, bmin = bs;
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                amin = fminf(amin, __shfl_xor(amin, off, 64));
+                bmin = fminf(bmin, __shfl_xor(bmin, off, 64));
+            }
+            if (cn == 0 && q < nk) {
+                org[q][0] = (int)floorf(amin) - 1;
+                org[q][1] = (int)floorf(bmin) - 1;
+            }
+        }
+        __syncthreads();
+        // stage: wave w copies the windows of angles w, w + 4, ...; lane = window column
+        for (int q = wave; q < nk; q += 4) {
+            const int u = org[q][0] + lane;
+            const bool uok = lane < WW && (unsigned)u < (unsigned)A.nu;
+            const TP *pq = proj + (int64_t)(t0 + q) * psz + u;
+            float *wq = win + q * wsz + lane;
+            for (int r = 0; r < HW; ++r) {
+                const int v = org[q][1] + r;
+                float val = 0.0f;
+                if (uok && (unsigned)v < (unsigned)A.nv) val = to_f(pq[(int64_t)v * A.nu]);
+                if (lane < WW) wq[r * PITCH] = val;
+            }
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int q = 0; q < nk; ++q) {
+            const AngleGeo &G = A.tab[A.a0 + t0 + q];
+            const float c = (float)G.c, s = (float)G.s;
+            const float Ld = A.DSO - (x * c + y * s);
+            const float iL = __builtin_amdgcn_rcpf(Ld);
+            const float m = A.DSD * iL;
+            const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
+            const float af = floorf(as);
+            const float fa = as - af;
+            const float wa0 = 1.0f - fa, wa1 = fa;  // taps off the detector are zeros in the window
+            // window-local column and row (exact integers in FP32), clamped into the window
+            const float la = __builtin_amdgcn_fmed3f(af - (float)org[q][0], 0.0f, lamax);
+            const float ob = (float)org[q][1];
+            const float mv = m * A.inv_dv;
+            float w = 0.0f, rxy2 = 0.0f, wpm = 0.0f;
+            if (W == CT_BP_FDK) {
+                const float qq = A.DSO * iL;
+                w = qq * qq;
+            } else {
+                const float sx = x - A.DSO * c, sy = y - A.DSO * s;
+                rxy2 = sx * sx + sy * sy;
+                wpm = A.pm_const * iL * iL * iL;
+            }
+            // byte offset of the window column in LDS (exact in FP32)
+            const float cb = fmaf(la, 4.0f, (float)(q * wsz * 4));
+#pragma unroll
+            for (int k = 0; k < BPL_NZ; ++k) {
+                // the row coordinate comes from the voxel's absolute height (independent of the
+                // tile and slab the voxel is processed in)
+                const float bs = fmaf(zk[k], mv, A.bv0);
+                const float bf = floorf(bs);
+                const float fb = bs - bf;
+                const float lb = __builtin_amdgcn_fmed3f(bf - ob, 0.0f, lbmax);
+                const float *t = (const float *)((const char *)win + (int)fmaf(lb, (float)(4 * PITCH), cb));
+                const float v0 = fmaf(wa1, t[1], wa0 * t[0]);
+                const float v1 = fmaf(wa1, t[PITCH + 1], wa0 * t[PITCH]);
+                const float v = fmaf(fb, v1 - v0, v0);
+                float wk = w;
+                if (W != CT_BP_FDK) wk = wpm * sqrtf(fmaf(zk[k], zk[k], rxy2));
+                acc[k] = fmaf(wk, v, acc[k]);
+            }
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < BPL_NZ; ++k) {
         const int kk = kb + k;
         if (kk >= A.own_hi) break;
         const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
@@ -272,7 +415,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
 // SART update for one angle t with FDK weights:
 //   x_j += lambda * (w_j * bilinear(r)) / (w_j * bilinear(1))   where w_j * bilinear(1) > 1e-6
 __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r, float *__restrict__ vol,
-                                                     float *__restrict__ volT, BpArgs A, float lambda) {
+                                                     BpArgs A, float lambda) {
     const int i = blockIdx.x * BP_TX + (threadIdx.x % BP_TX);
     const int j = blockIdx.y * BP_TY + (threadIdx.x / BP_TX);
     const int kb = blockIdx.z * BP_NZ;
@@ -313,9 +456,85 @@ __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r
             const int64_t o = ((int64_t)kk * A.ny + j) * A.nx + i;
             const float nv = fmaf(lambda, num / V, vol[o]);
             vol[o] = nv;
-            if (volT) volT[((int64_t)kk * A.nx + i) * A.ny + j] = nv;  // keep the [z][x][y] copy in step
         }
     }
+}
+
+// The same update on the column-major copy ([y][x][slot], slot k + 1 = voxel k) with the residual
+// transposed to [u][v]: one wave per (column, 64 slices), lanes on consecutive slices, so both the
+// residual taps (consecutive v) and the volume (consecutive slots) are contiguous.
+__global__ __launch_bounds__(256) void k_sart_update_col(const float *__restrict__ rT, float *__restrict__ vz,
+                                                         BpArgs A, float lambda, int zwaves) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t col = gw / zwaves;
+    const int kk = (int)(gw % zwaves) * 64 + (threadIdx.x & 63);
+    if (col >= (int64_t)A.nx * A.ny) return;
+    const int i = (int)(col % A.nx), j = (int)(col / A.nx);
+    const float x = fmaf((float)i, A.dx, A.x0);
+    const float y = fmaf((float)j, A.dy, A.y0);
+    const AngleGeo &G = A.tab[A.a0];
+    const float c = (float)G.c, s = (float)G.s;
+    const float Ld = A.DSO - (x * c + y * s);
+    const float iL = 1.0f / Ld;
+    const float m = A.DSD * iL;
+    const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
+    const float af = floorf(as);
+    const float fa = as - af;
+    const int ia = (int)af;
+    const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
+    const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
+    if ((wa0 == 0.0f && wa1 == 0.0f) || kk >= A.nz) return;
+    const int64_t c0 = (int64_t)clampi(ia, 0, A.nu - 1) * A.nv, c1 = (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
+    const float q = A.DSO * iL;
+    const float w = q * q;
+    const float z = fmaf((float)kk, A.dz, A.z0);
+    const float bs = fmaf(m * z, A.inv_dv, A.bv0);
+    const float bf = floorf(bs);
+    const float fb = bs - bf;
+    const int ib = (int)bf;
+    const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+    const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+    const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
+    const float v0 = fmaf(wa1, rT[c1 + b0], wa0 * rT[c0 + b0]);
+    const float v1 = fmaf(wa1, rT[c1 + b1], wa0 * rT[c0 + b1]);
+    const float num = w * fmaf(wb1, v1, wb0 * v0);
+    const float V = w * ((wa0 + wa1) * (wb0 + wb1));
+    if (V > 1e-6f) {
+        float *o = vz + col * (A.nz + 2) + kk + 1;
+        *o = fmaf(lambda, num / V, *o);
+    }
+}
+
+// Detector window (columns WW, rows HW) that holds the taps of one 16 x 16 x BP_NZ tile under any
+// angle, or false when it does not fit the staging buffer.  For two points of the tile the
+// detector coordinate u = m t (t transverse to the ray, m = DSD / depth) differs by at most
+// m_max |dt| + |t|_max |dm| with |dt| <= D (the tile's xy diagonal) and
+// |dm| <= DSD D / (DSO - R)^2, R bounding the distance of any voxel from the axis; likewise
+// for v = m z with the tile's z extent.  Margins: one pixel each side plus the second tap.
+bool bp_window(const ct_geometry &g, int &WW, int &HW) {
+    double R = 0.0, Zmax = 0.0;
+    for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy) {
+            const double xe = g.offOrigin[0] + (cx ? 0.5 : -0.5) * g.nVoxel[0] * g.dVoxel[0];
+            const double ye = g.offOrigin[1] + (cy ? 0.5 : -0.5) * g.nVoxel[1] * g.dVoxel[1];
+            R = std::max(R, std::sqrt(xe * xe + ye * ye));
+        }
+    for (int cz = 0; cz < 2; ++cz)
+        Zmax = std::max(Zmax, std::fabs(g.offOrigin[2] + (cz ? 0.5 : -0.5) * g.nVoxel[2] * g.dVoxel[2]));
+    const double D = std::sqrt(std::pow((BP_TX - 1) * g.dVoxel[0], 2) + std::pow((BP_TY - 1) * g.dVoxel[1], 2));
+    // corners of edge tiles may lie up to one tile outside the grid
+    R += D;
+    Zmax += BPL_NZ * g.dVoxel[2];
+    if (!(g.DSO - R > 0.0)) return false;
+    const double mmax = g.DSD / (g.DSO - R);
+    const double dm = g.DSD * D / ((g.DSO - R) * (g.DSO - R));
+    const double eu = (mmax * D + R * dm) / g.dDetector[0];
+    const double ev = (mmax * (BPL_NZ - 1) * g.dVoxel[2] + Zmax * dm) / g.dDetector[1];
+    if (!(eu < 60.0 && ev < 1000.0)) return false;
+    WW = (int)std::ceil(eu) + 4;
+    HW = (int)std::ceil(ev) + 4;
+    return WW <= 64 && (WW <= 40 ? 40 : 64) * HW <= BPL_FLOATS;
 }
 
 BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const Slab &slab, int accumulate) {
@@ -376,6 +595,34 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     const int nzrun = kind == CT_BP_ADJOINT ? ADJ_NZ : BP_NZ;
     const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((nzown + nzrun - 1) / nzrun));
     const dim3 block(256);
+    int WW = 0, HW = 0;
+#ifndef CT_NO_BP_LDS
+    if (kind != CT_BP_ADJOINT && bp_window(p->g, WW, HW)) {
+        const bool narrow = WW <= 40;
+        const int K = std::min(BPL_K, BPL_FLOATS / ((narrow ? 40 : 64) * HW));
+        const dim3 lgrid(grid.x, grid.y, (unsigned)((nzown + BPL_NZ - 1) / BPL_NZ));
+#define CT_BPL(KIND, PITCH)                                                                                      \
+    CT_DISPATCH2(pt, TP, vt, TV,                                                                                 \
+                 hipLaunchKernelGGL((k_bp_lds<KIND, PITCH, TP, TV>), lgrid, block, 0, st, (const TP *)proj,        \
+                                    (TV *)vol, A, WW, HW, K))
+        if (kind == CT_BP_FDK) {
+            if (narrow) {
+                CT_BPL(CT_BP_FDK, 40);
+            } else {
+                CT_BPL(CT_BP_FDK, 64);
+            }
+        } else {
+            if (narrow) {
+                CT_BPL(CT_BP_PSEUDO_MATCHED, 40);
+            } else {
+                CT_BPL(CT_BP_PSEUDO_MATCHED, 64);
+            }
+        }
+#undef CT_BPL
+        CT_HIP(hipGetLastError());
+        return CT_OK;
+    }
+#endif
     if (kind == CT_BP_FDK) {
         CT_DISPATCH2(pt, TP, vt, TV,
                      hipLaunchKernelGGL((k_bp_voxel<CT_BP_FDK, TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));
@@ -391,14 +638,27 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     return CT_OK;
 }
 
-ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, float *volT, int64_t angle, float lambda,
-                             hipStream_t st) {
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda, hipStream_t st) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     BpArgs A = make_bp_args(p, tab, angle, angle + 1, full_slab(p->g), 1);
     const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((A.nz + BP_NZ - 1) / BP_NZ));
-    hipLaunchKernelGGL(k_sart_update, grid, dim3(256), 0, st, r, vol, volT, A, lambda);
+    hipLaunchKernelGGL(k_sart_update, grid, dim3(256), 0, st, r, vol, A, lambda);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t angle, float lambda,
+                                 hipStream_t st) {
+    const AngleGeo *tab = nullptr;
+    ct_status s = plan_device_table(p, st, &tab);
+    if (s != CT_OK) return s;
+    BpArgs A = make_bp_args(p, tab, angle, angle + 1, full_slab(p->g), 1);
+    const int zwaves = (A.nz + 63) / 64;
+    const int64_t waves = (int64_t)A.nx * A.ny * zwaves;
+    hipLaunchKernelGGL(k_sart_update_col, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, rT, vz, A, lambda,
+                       zwaves);
     CT_HIP(hipGetLastError());
     return CT_OK;
 }

@@ -9,6 +9,7 @@
 // one detector row, whose rays are nearly parallel and walk neighbouring voxels) by 4 rows.  Blocks are linearised as (u-tile fastest, then angle, then v-band) so the blocks in
 // flight at any moment share a band of detector rows across many angles, i.e. an axial slab of
 // the volume, which keeps the working set inside the 256 MB last-level cache.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -38,6 +39,7 @@ struct FwdArgs {
     int32_t accumulate;
     double delta;            // interpolated projector sample spacing (mm)
     int32_t ublocks;
+    int32_t cblocks, rgroups;  // column Siddon: column groups per angle, row groups per column
 };
 
 struct RaySetup {
@@ -236,6 +238,320 @@ __global__ __launch_bounds__(FWD_TU * FWD_TV) void k_siddon(const TV *__restrict
     const int64_t o = ((int64_t)ai * A.nv + b) * A.nu + a;
     const float prev = A.accumulate ? to_f(proj[o]) : 0.0f;
     proj[o] = from_f<TP>(prev + v);
+}
+
+// ------------------------------------------------------------------------------------------
+// Column Siddon (resident volumes).
+//
+// A detector column and the source span a vertical plane, so every row of that column follows the
+// same xy line S + t D_xy and crosses the x and y planes at the same t.  A wave takes one column
+// and 64 * ROWS of its rows (lane = row): it walks the shared xy path with wave-uniform state and
+// every lane splits each xy piece at its own z crossing.  While |Dz| < max(|Dx|, |Dy|) (index
+// units) an xy piece climbs less than one slice, so it holds at most one z crossing and meets two
+// consecutive voxels of one column.  The volume is read from a column-major copy ([y][x][z] with a
+// zero slot below and above each column), where those two voxels are one 8-byte load (4-byte for
+// 16-bit storage) and the lanes, holding consecutive rows, read consecutive addresses.  Rows
+// outside the grid in z clamp to the zero slots, so no per-row clipping is needed.
+//
+// Per row the z coordinate is kept relative to the slot of its entry point (z = Zr + t Dz with
+// Zr in [0, 1)), so the crossing time (lo + 1 - Zr) / Dz is one FMA without cancellation.
+
+constexpr int ZC_COLS = 4;  // columns (waves) per block
+
+template <typename TV>
+struct ZPair;
+template <>
+struct ZPair<float> {
+    static __device__ __forceinline__ void ld(const float *col, uint32_t k, float &a, float &b) {
+        float2 v;
+        __builtin_memcpy(&v, col + k, sizeof(v));
+        a = v.x;
+        b = v.y;
+    }
+};
+template <>
+struct ZPair<f16s> {
+    static __device__ __forceinline__ void ld(const f16s *col, uint32_t k, float &a, float &b) {
+        uint32_t w;
+        __builtin_memcpy(&w, col + k, sizeof(w));
+        a = (float)__builtin_bit_cast(f16s, (uint16_t)(w & 0xffffu));
+        b = (float)__builtin_bit_cast(f16s, (uint16_t)(w >> 16));
+    }
+};
+template <>
+struct ZPair<bf16s> {
+    static __device__ __forceinline__ void ld(const bf16s *col, uint32_t k, float &a, float &b) {
+        uint32_t w;
+        __builtin_memcpy(&w, col + k, sizeof(w));
+        a = __uint_as_float(w << 16);
+        b = __uint_as_float(w & 0xffff0000u);
+    }
+};
+
+#ifndef CT_ZC_BATCH
+#define CT_ZC_BATCH 8
+#endif
+constexpr int ZC_B = CT_ZC_BATCH;  // xy pieces per trip
+
+// Per-row state of the column walk.
+template <int ROWS>
+struct ZRows {
+    float Zr[ROWS];    // z at the xy entry, relative to slot k0 (in [0, 1))
+    float Dz[ROWS];    // dz/dt (index units)
+    float inv[ROWS];   // 1 / Dz (0 for rows parallel to the xy plane)
+    float c1[ROWS];    // (1 - Zr) / Dz, or +-FLT_MAX for parallel rows
+    float lmin[ROWS];  // pair slots are clamped to [lmin, lmax] (relative to k0)
+    float lmax[ROWS];
+    uint32_t kb[ROWS]; // byte offset of slot k0 in a column
+    bool up[ROWS];     // Dz >= 0
+};
+
+// ORI: +1 all rows of the wave rise, -1 all fall, 0 mixed.  The xy walk (tx, ty, lin, ...) is the
+// same in every lane.
+template <int ORI, int ROWS, typename TV>
+__device__ __forceinline__ void zc_walk(const TV *__restrict__ vz, int64_t lin, const int64_t sX, const int64_t sY,
+                                        const float tx0, const float ty0, const float dtx, const float dty,
+                                        const float Te, const ZRows<ROWS> &Z, float (&acc)[ROWS], const int maxtrips) {
+    float fz[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) fz[r] = floorf(Z.Zr[r]);
+    float tx = tx0, ty = ty0, nxc = 0.0f, nyc = 0.0f, tp = 0.0f;
+    for (int trip = 0; trip < maxtrips; ++trip) {
+        float ta[ZC_B], tb[ZC_B];
+        int64_t ln[ZC_B];
+#pragma unroll
+        for (int u = 0; u < ZC_B; ++u) {
+            const float tn = fminf(fminf(tx, ty), Te);
+            ta[u] = tp;
+            tb[u] = tn;
+            ln[u] = lin;
+            // at Te the walk stops: the column index never leaves the grid
+            const bool act = tn < Te;
+            const bool cx = act && tx == tn, cy = act && ty == tn;
+            lin += (cx ? sX : (int64_t)0) + (cy ? sY : (int64_t)0);
+            nxc += cx ? 1.0f : 0.0f;
+            nyc += cy ? 1.0f : 0.0f;
+            tx = fmaf(nxc, dtx, tx0);
+            ty = fmaf(nyc, dty, ty0);
+            tp = tn;
+        }
+        float w1[ZC_B][ROWS], w2[ZC_B][ROWS], va[ZC_B][ROWS], vb[ZC_B][ROWS];
+#pragma unroll
+        for (int u = 0; u < ZC_B; ++u) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const float fb = floorf(fmaf(tb[u], Z.Dz[r], Z.Zr[r]));
+                float lo = ORI > 0 ? fz[r] : (ORI < 0 ? fb : fminf(fz[r], fb));
+                lo = __builtin_amdgcn_fmed3f(lo, Z.lmin[r], Z.lmax[r]);
+                fz[r] = fb;
+                // the piece [ta, tb] meets slot lo on one side of tc and slot lo+1 on the other
+                const float m = __builtin_amdgcn_fmed3f(fmaf(lo, Z.inv[r], Z.c1[r]), ta[u], tb[u]);
+                w1[u][r] = m - ta[u];
+                w2[u][r] = tb[u] - m;
+                const uint32_t k = (uint32_t)((int)lo * (int)sizeof(TV)) + Z.kb[r];
+                ZPair<TV>::ld((const TV *)((const char *)(vz + ln[u]) + k), 0u, va[u][r], vb[u][r]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ZC_B; ++u) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                // rising rows meet lo first, falling rows lo+1 first
+                float first, second;
+                if constexpr (ORI > 0) {
+                    first = va[u][r];
+                    second = vb[u][r];
+                } else if constexpr (ORI < 0) {
+                    first = vb[u][r];
+                    second = va[u][r];
+                } else {
+                    first = Z.up[r] ? va[u][r] : vb[u][r];
+                    second = Z.up[r] ? vb[u][r] : va[u][r];
+                }
+                acc[r] = fmaf(w1[u][r], first, acc[r]);
+                acc[r] = fmaf(w2[u][r], second, acc[r]);
+            }
+        }
+        if (!(tp < Te)) break;
+    }
+}
+
+template <typename TV, typename TP, int ROWS>
+__global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restrict__ vz, TP *__restrict__ proj,
+                                                             FwdArgs A) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int bid = blockIdx.x;
+    const int cb = bid % A.cblocks;
+    const int rest = bid / A.cblocks;
+    const int ai = rest % A.nang;
+    const int rg = rest / A.nang;
+    const int a = cb * ZC_COLS + wave;
+    if (a >= A.nu) return;
+    const AngleGeo &G = A.tab[A.a0 + ai];
+    const int64_t nzp = (int64_t)A.nz + 2;
+
+    // shared xy line of the column, clipped to the grid's xy box (FP64)
+    const double ua = (a - A.cu) * A.du + A.offu;
+    const double D[2] = {G.Dc[0] + ua * G.eu[0], G.Dc[1] + ua * G.eu[1]};
+    const double mx = D[0] * A.dx, my = D[1] * A.dy;
+    const double Lxy2 = mx * mx + my * my;
+    const double Lref = sqrt(Lxy2);
+    const double lo2[2] = {-0.5, -0.5}, hi2[2] = {A.nx - 0.5, A.ny - 0.5};
+    bool par[2];
+    double t0 = 0.0, t1 = 1.0;
+    bool hit = true;
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        par[ax] = fabs(ax == 0 ? mx : my) < 1e-12 * Lref;
+        if (par[ax]) {
+            if (G.S[ax] < lo2[ax] || G.S[ax] > hi2[ax]) hit = false;
+        } else {
+            const double ta = (lo2[ax] - G.S[ax]) / D[ax];
+            const double tb = (hi2[ax] - G.S[ax]) / D[ax];
+            t0 = fmax(t0, fmin(ta, tb));
+            t1 = fmin(t1, fmax(ta, tb));
+        }
+    }
+    hit = hit && t0 < t1;
+
+    float acc[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
+    const int brow = rg * (64 * ROWS) + lane;
+    double L[ROWS];
+    ZRows<ROWS> Z;
+    bool all_up = true, all_down = true;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        // lanes past the last row repeat its geometry (their results are not stored)
+        const int b = min(brow + 64 * r, A.nv - 1);
+        const double vbm = (b - A.cv) * A.dv + A.offv;
+        const double Dz = vbm / A.dz;
+        const double mz = Dz * A.dz;
+        L[r] = sqrt(Lxy2 + mz * mz);
+        const double ze = G.S[2] + t0 * Dz + 1.5;  // slot coordinate: voxel k spans [k + 1, k + 2)
+        const double k0 = floor(ze);
+        const double zr = ze - k0;
+        const bool parz = fabs(mz) < 1e-12 * L[r];
+        Z.Zr[r] = (float)zr;
+        Z.Dz[r] = parz ? 0.0f : (float)Dz;
+        Z.up[r] = parz || Dz > 0.0;
+        // |k0| < 2^22 (checked on the host), so these are exact in FP32; the slot k0 + lo is in
+        // [0, nz], and the byte offset is formed modulo 2^32
+        const float lmin = (float)(-k0), lmax = (float)((double)A.nz - k0);
+        Z.lmin[r] = lmin;
+        Z.lmax[r] = lmax;
+        Z.kb[r] = (uint32_t)((int64_t)k0 * (int64_t)sizeof(TV));
+        if (parz) {
+            // constant z: the crossing of the plane above the clamped slot is in the future
+            // (+inf) unless the clamp moved the slot below the row
+            const float lo = fminf(fmaxf(floorf((float)zr), lmin), lmax);
+            Z.inv[r] = 0.0f;
+            Z.c1[r] = (lo + 1.0f > (float)zr) ? FLT_MAX : -FLT_MAX;
+        } else {
+            Z.inv[r] = (float)(1.0 / Dz);
+            Z.c1[r] = (float)((1.0 - zr) / Dz);
+        }
+        all_up = all_up && Z.up[r];
+        all_down = all_down && !Z.up[r];
+    }
+
+    if (hit) {
+        int idx[2];
+        float tn0[2], dtn[2];
+        int sg[2];
+        float Te = (float)(t1 - t0);
+        const int ihi[2] = {A.nx - 1, A.ny - 1};
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            const double E = G.S[ax] + t0 * D[ax];
+            int i = (int)floor(E + 0.5);
+            i = i < 0 ? 0 : (i > ihi[ax] ? ihi[ax] : i);
+            idx[ax] = i;
+            if (par[ax]) {
+                sg[ax] = 0;
+                tn0[ax] = FLT_MAX;
+                dtn[ax] = 0.0f;
+            } else {
+                const double f = E - i;
+                const int s = D[ax] > 0 ? 1 : -1;
+                const double inv = 1.0 / fabs(D[ax]);
+                sg[ax] = s;
+                tn0[ax] = (float)((0.5 - s * f) * inv);
+                dtn[ax] = (float)inv;
+                const int nexit = s > 0 ? ihi[ax] - i : i;
+                Te = fminf(Te, fmaf((float)nexit, dtn[ax], tn0[ax]));
+            }
+        }
+        const int64_t sX = (int64_t)sg[0] * nzp, sY = (int64_t)sg[1] * A.nx * nzp;
+        const int64_t lin = ((int64_t)idx[1] * A.nx + idx[0]) * nzp;
+        const int maxtrips = (A.nx + A.ny + 2) / ZC_B + 2;
+        all_up = __all(all_up);
+        all_down = __all(all_down);
+        if (all_up)
+            zc_walk<1>(vz, lin, sX, sY, tn0[0], tn0[1], dtn[0], dtn[1], Te, Z, acc, maxtrips);
+        else if (all_down)
+            zc_walk<-1>(vz, lin, sX, sY, tn0[0], tn0[1], dtn[0], dtn[1], Te, Z, acc, maxtrips);
+        else
+            zc_walk<0>(vz, lin, sX, sY, tn0[0], tn0[1], dtn[0], dtn[1], Te, Z, acc, maxtrips);
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int b = brow + 64 * r;
+        if (b >= A.nv) continue;
+        const int64_t o = ((int64_t)ai * A.nv + b) * A.nu + a;
+        const float prev = A.accumulate ? to_f(proj[o]) : 0.0f;
+        proj[o] = from_f<TP>(prev + (float)(acc[r] * L[r]));
+    }
+}
+
+// [z][y][x] -> column-major slots [y][x][z + 1] with zero slots 0 and nz + 1, 32 x 32 (z, x) tiles
+template <typename T>
+__global__ __launch_bounds__(256) void k_zcols(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz) {
+    __shared__ T tile[32][33];
+    const int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t nzp = (int64_t)nz + 2;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int x = x0 + tx, z = z0 + ty + r;
+        if (x < nx && z < nz) tile[ty + r][tx] = src[((int64_t)z * ny + y) * nx + x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int z = z0 + tx, x = x0 + ty + r;
+        if (x < nx && z < nz) dst[((int64_t)y * nx + x) * nzp + z + 1] = tile[tx][ty + r];
+    }
+    if (threadIdx.x < 32) {
+        const int x = x0 + threadIdx.x;
+        if (x < nx) {
+            const int64_t c = ((int64_t)y * nx + x) * nzp;
+            if (blockIdx.y == 0) dst[c] = from_f<T>(0.0f);
+            if (blockIdx.y == gridDim.y - 1) dst[c + nz + 1] = from_f<T>(0.0f);
+        }
+    }
+}
+
+// column-major slots -> [z][y][x]
+template <typename T>
+__global__ __launch_bounds__(256) void k_zcols_inv(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz) {
+    __shared__ T tile[32][33];
+    const int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t nzp = (int64_t)nz + 2;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int z = z0 + tx, x = x0 + ty + r;
+        if (x < nx && z < nz) tile[ty + r][tx] = src[((int64_t)y * nx + x) * nzp + z + 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int x = x0 + tx, z = z0 + ty + r;
+        if (x < nx && z < nz) dst[((int64_t)z * ny + y) * nx + x] = tile[tx][ty + r];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -438,15 +754,132 @@ ct_status launch_transpose_xy(const void *vol, ct_dtype vt, void *volT, int64_t 
     return CT_OK;
 }
 
+ct_status launch_zcols(const void *vol, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, hipStream_t st) {
+    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
+    CT_DISPATCH1(vt, T,
+                 hipLaunchKernelGGL((k_zcols<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)vz, (int)nx, (int)ny,
+                                    (int)nz));
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, int64_t ny, int64_t nz, hipStream_t st) {
+    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
+    CT_DISPATCH1(vt, T,
+                 hipLaunchKernelGGL((k_zcols_inv<T>), tg, dim3(256), 0, st, (const T *)vz, (T *)vol, (int)nx, (int)ny,
+                                    (int)nz));
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+bool zcol_ok(const ct_plan *p, int64_t a0, int64_t a1) {
+    // every xy piece must climb less than one slice: |Dz| < max(|Dx|, |Dy|) for every ray.
+    // max(|Dx|, |Dy|) is convex and piecewise linear in the detector coordinate u, so its minimum
+    // over the detector lies at an end or where Dx, Dy or Dx +- Dy vanish.
+    const ct_geometry &g = p->g;
+    const double nu = (double)g.nDetector[0], nv = (double)g.nDetector[1];
+    const double u0 = (0 - (nu - 1) / 2.0) * g.dDetector[0] + g.offDetector[0];
+    const double u1 = ((nu - 1) - (nu - 1) / 2.0) * g.dDetector[0] + g.offDetector[0];
+    const double v0 = (0 - (nv - 1) / 2.0) * g.dDetector[1] + g.offDetector[1];
+    const double v1 = ((nv - 1) - (nv - 1) / 2.0) * g.dDetector[1] + g.offDetector[1];
+    const double dzmax = std::max(fabs(v0), fabs(v1)) / g.dVoxel[2];
+    for (int64_t i = a0; i < a1; ++i) {
+        const AngleGeo &G = p->tab[(size_t)i];
+        const double ulo = std::min(u0, u1), uhi = std::max(u0, u1);
+        double cand[6] = {ulo, uhi, 0, 0, 0, 0};
+        int nc = 2;
+        auto root = [&](double c0, double c1) {
+            if (c1 != 0.0) {
+                const double r = -c0 / c1;
+                if (r > ulo && r < uhi) cand[nc++] = r;
+            }
+        };
+        root(G.Dc[0], G.eu[0]);
+        root(G.Dc[1], G.eu[1]);
+        root(G.Dc[0] + G.Dc[1], G.eu[0] + G.eu[1]);
+        root(G.Dc[0] - G.Dc[1], G.eu[0] - G.eu[1]);
+        double fmin_ = 1e300;
+        for (int k = 0; k < nc; ++k) {
+            const double dx = G.Dc[0] + cand[k] * G.eu[0], dy = G.Dc[1] + cand[k] * G.eu[1];
+            fmin_ = std::min(fmin_, std::max(fabs(dx), fabs(dy)));
+        }
+        if (!(dzmax < 0.999 * fmin_)) return false;
+        // slot offsets of a row's entry point stay far inside FP32's exact integers
+        if (fabs(G.S[2]) + dzmax + 2.0 > 4194304.0) return false;
+    }
+    return true;
+}
+
 ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtype vt, void *proj, ct_dtype pt,
                          int accumulate, int64_t a0, int64_t a1, const Slab &slab, hipStream_t st,
-                         const void *volT_given) {
+                         const void *vcopy) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     if (slab.own_hi <= slab.own_lo) return CT_OK;
     const ct_geometry &g = p->g;
     const int64_t nx = g.nVoxel[0], ny = g.nVoxel[1];
+#ifndef CT_NO_ZCOL
+    // Siddon on a resident volume: column walk over the column-major copy
+    const bool whole = slab.own_lo == 0 && slab.own_hi == g.nVoxel[2] && slab.mem_lo == 0 &&
+                       slab.mem_n == g.nVoxel[2];
+    if (kind == CT_SIDDON && whole && (vcopy || slab.scratch_ok) && zcol_ok(p, a0, a1)) {
+        const int64_t nz = g.nVoxel[2];
+        void *vz = const_cast<void *>(vcopy);
+        void *own_z = nullptr;
+        if (!vz) {
+            const size_t zbytes = (size_t)(nx * ny * (nz + 2)) * dtype_size(vt);
+            if (hipMallocAsync(&own_z, zbytes, st) == hipSuccess) {
+                ct_status zs = launch_zcols(vol, vt, own_z, nx, ny, nz, st);
+                if (zs != CT_OK) return zs;
+                vz = own_z;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (vz) {
+            const int64_t nu = g.nDetector[0], nv = g.nDetector[1];
+            const int64_t cblocks = (nu + ZC_COLS - 1) / ZC_COLS;
+            // two rows per lane when the launch is large enough to fill the chip with them
+#ifdef CT_ZC_ROWS
+            const int rows = CT_ZC_ROWS;
+#else
+            const int rows = cblocks * (a1 - a0) * ((nv + 127) / 128) >= 4096 ? 2 : 1;
+#endif
+            const int64_t rgroups = (nv + 64 * rows - 1) / (64 * rows);
+            const int64_t max_ang = std::max<int64_t>(1, (int64_t(1) << 30) / (cblocks * rgroups));
+            const size_t proj_angle = (size_t)nu * nv * dtype_size(pt);
+            for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
+                const int64_t c1 = std::min(a1, c0 + max_ang);
+                FwdArgs A = make_args(p, tab, c0, c1, slab, accumulate);
+                A.cblocks = (int32_t)cblocks;
+                A.rgroups = (int32_t)rgroups;
+                char *pp = (char *)proj + (size_t)(c0 - a0) * proj_angle;
+                const dim3 grid((unsigned)(cblocks * (c1 - c0) * rgroups)), block(64 * ZC_COLS);
+#ifdef CT_ZC_ROWS
+                if (rows == 4) {
+                    CT_DISPATCH2(vt, TV, pt, TP,
+                                 hipLaunchKernelGGL((k_siddon_col<TV, TP, 4>), grid, block, 0, st, (const TV *)vz,
+                                                    (TP *)pp, A));
+                } else
+#endif
+                if (rows == 2) {
+                    CT_DISPATCH2(vt, TV, pt, TP,
+                                 hipLaunchKernelGGL((k_siddon_col<TV, TP, 2>), grid, block, 0, st, (const TV *)vz,
+                                                    (TP *)pp, A));
+                } else {
+                    CT_DISPATCH2(vt, TV, pt, TP,
+                                 hipLaunchKernelGGL((k_siddon_col<TV, TP, 1>), grid, block, 0, st, (const TV *)vz,
+                                                    (TP *)pp, A));
+                }
+                CT_HIP(hipGetLastError());
+            }
+            if (own_z) CT_HIP(hipFreeAsync(own_z, st));
+            return CT_OK;
+        }
+    }
+#endif
+    const void *volT_given = kind == CT_SIDDON ? nullptr : vcopy;
     const int64_t elems = nx * ny * slab.mem_n;
     const size_t vbytes = (size_t)elems * dtype_size(vt);
     // transposed copy for the blocks whose rays run along x (stream-ordered scratch; without it
