@@ -91,6 +91,8 @@ def load():
             "orc_interp_rays": (None, [g, pd, pi, i64, pd, pd]),
             "orc_bp": (None, [g, pd, i64, pd, C.c_int, pd]),
             "orc_bp_voxels": (None, [g, pd, i64, pd, C.c_int, pi, i64, pd]),
+            "orc_siddon_rays_f32": (None, [g, pd, pi, i64, C.POINTER(C.c_float), pd]),
+            "orc_bp_voxels_f32": (None, [g, pd, i64, C.POINTER(C.c_float), C.c_int, pi, i64, pd]),
             "orc_bp_coverage": (None, [g, d, pd]),
             "orc_bp_transpose": (None, [g, pd, i64, pd, C.c_int, pd]),
         }
@@ -155,9 +157,16 @@ def siddon_fwd(geo: Geometry, angles, vol, return_counts=False):
 
 
 def siddon_rays(geo: Geometry, angles, ray_idx, vol):
-    angles, vol = _f64(angles), _f64(vol)
+    """Selected rays.  A C-contiguous FP32 volume is read in place (widened per element), so
+    volumes too large to copy to FP64 can be sampled."""
+    angles = _f64(angles)
     idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
     out = np.zeros(len(idx))
+    if vol.dtype == np.float32 and vol.flags["C_CONTIGUOUS"]:
+        load().orc_siddon_rays_f32(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx),
+                                   vol.ctypes.data_as(C.POINTER(C.c_float)), _pd(out))
+        return out
+    vol = _f64(vol)
     load().orc_siddon_rays(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx), _pd(vol), _pd(out))
     return out
 
@@ -202,9 +211,16 @@ def bp(geo: Geometry, angles, proj, kind=W_FDK):
 
 
 def bp_voxels(geo: Geometry, angles, proj, vox_idx, kind=W_FDK):
-    angles, proj = _f64(angles), _f64(proj)
+    """Selected voxels.  A C-contiguous FP32 projection array is read in place."""
+    angles = _f64(angles)
     idx = np.ascontiguousarray(vox_idx, dtype=np.int64)
     out = np.zeros(len(idx))
+    if proj.dtype == np.float32 and proj.flags["C_CONTIGUOUS"]:
+        load().orc_bp_voxels_f32(C.byref(geo.c()), _pd(angles), len(angles),
+                                 proj.ctypes.data_as(C.POINTER(C.c_float)), int(kind), _pi(idx), len(idx),
+                                 _pd(out))
+        return out
+    proj = _f64(proj)
     load().orc_bp_voxels(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), int(kind), _pi(idx),
                          len(idx), _pd(out))
     return out

@@ -103,7 +103,8 @@ static void scratch_init(scratch_t *s, const orc_geom *g) {
 }
 
 static double siddon_core(const orc_geom *g, const double S[3], const double P[3], const double *vol,
-                          double *scat, double y, int64_t target, int64_t *nseg, scratch_t *sc) {
+                          const float *volf, double *scat, double y, int64_t target, int64_t *nseg,
+                          scratch_t *sc) {
     double lo[3], hi[3], D[3];
     box_bounds(g, lo, hi);
     for (int a = 0; a < 3; ++a) D[a] = P[a] - S[a];
@@ -165,6 +166,7 @@ static double siddon_core(const orc_geom *g, const double S[3], const double P[3
         double len = L * (tb - ta);
         segs++;
         if (vol) acc += len * vol[lin];
+        if (volf) acc += len * (double)volf[lin];
         if (scat) scat[lin] += y * len;
         if (target >= 0 && lin == target) acc += len;
     }
@@ -242,9 +244,9 @@ static double interp_ray(const orc_geom *g, const double S[3], const double P[3]
  * central ray; pseudo-matched weight (dx dy dz)/(du dv) * DSD^2 |SX| / L^3, the ray-tube density
  * that makes the sum approximate the transpose of the ray-driven projector. */
 
-static double proj_at(const orc_geom *g, const double *pr, int64_t a, int64_t b) {
+static double proj_at(const orc_geom *g, const double *pr, const float *prf, int64_t a, int64_t b) {
     if (a < 0 || b < 0 || a >= g->ndet[0] || b >= g->ndet[1]) return 0.0;
-    return pr[b * g->ndet[0] + a];
+    return pr ? pr[b * g->ndet[0] + a] : (double)prf[b * g->ndet[0] + a];
 }
 
 static void voxel_centre(const orc_geom *g, int64_t i, int64_t j, int64_t k, double X[3]) {
@@ -275,7 +277,7 @@ static void project_voxel(const orc_geom *g, double th, const double X[3], int k
 }
 
 static double bp_voxel(const orc_geom *g, const double *angles, int64_t na, const double *proj,
-                       int kind, int64_t i, int64_t j, int64_t k) {
+                       const float *projf, int kind, int64_t i, int64_t j, int64_t k) {
     double X[3];
     voxel_centre(g, i, j, k, X);
     const int64_t psz = g->ndet[0] * g->ndet[1];
@@ -286,9 +288,10 @@ static double bp_voxel(const orc_geom *g, const double *angles, int64_t na, cons
         double a0 = floor(as), b0 = floor(bs);
         double fa = as - a0, fb = bs - b0;
         int64_t ia = (int64_t)a0, ib = (int64_t)b0;
-        const double *pr = proj + t * psz;
-        double v = (1 - fa) * (1 - fb) * proj_at(g, pr, ia, ib) + fa * (1 - fb) * proj_at(g, pr, ia + 1, ib) +
-                   (1 - fa) * fb * proj_at(g, pr, ia, ib + 1) + fa * fb * proj_at(g, pr, ia + 1, ib + 1);
+        const double *pr = proj ? proj + t * psz : NULL;
+        const float *prf = projf ? projf + t * psz : NULL;
+        double v = (1 - fa) * (1 - fb) * proj_at(g, pr, prf, ia, ib) + fa * (1 - fb) * proj_at(g, pr, prf, ia + 1, ib) +
+                   (1 - fa) * fb * proj_at(g, pr, prf, ia, ib + 1) + fa * fb * proj_at(g, pr, prf, ia + 1, ib + 1);
         acc += w * v;
     }
     return acc;
@@ -318,7 +321,7 @@ double orc_siddon_ray(const orc_geom *g, const double *S, const double *P, const
                       int64_t *nseg) {
     scratch_t sc;
     scratch_init(&sc, g);
-    double r = siddon_core(g, S, P, vol, NULL, 0.0, -1, nseg, &sc);
+    double r = siddon_core(g, S, P, vol, NULL, NULL, 0.0, -1, nseg, &sc);
     free(sc.buf);
     return r;
 }
@@ -347,7 +350,7 @@ void orc_siddon_fwd(const orc_geom *g, const double *angles, int64_t na, const d
             for (int64_t a = 0; a < nu; ++a) {
                 int64_t ns = 0;
                 pixel_pos(g, angles[t], (double)a, (double)b, P);
-                proj[(t * nv + b) * nu + a] = siddon_core(g, S, P, vol, NULL, 0.0, -1, &ns, &sc);
+                proj[(t * nv + b) * nu + a] = siddon_core(g, S, P, vol, NULL, NULL, 0.0, -1, &ns, &sc);
                 rowsegs += ns;
             }
             if (seg_count_per_angle) {
@@ -374,7 +377,7 @@ void orc_siddon_rays(const orc_geom *g, const double *angles, const int64_t *ray
             double S[3], P[3];
             source_pos(g, angles[t], S);
             pixel_pos(g, angles[t], (double)a, (double)b, P);
-            out[q] = siddon_core(g, S, P, vol, NULL, 0.0, -1, NULL, &sc);
+            out[q] = siddon_core(g, S, P, vol, NULL, NULL, 0.0, -1, NULL, &sc);
         }
         free(sc.buf);
     }
@@ -410,7 +413,7 @@ void orc_siddon_adj(const orc_geom *g, const double *angles, int64_t na, const d
                 double y = proj[(t * nv + b) * nu + a];
                 if (y == 0.0) continue;
                 pixel_pos(g, angles[t], (double)a, (double)b, P);
-                siddon_core(g, S, P, NULL, mine, y, -1, NULL, &sc);
+                siddon_core(g, S, P, NULL, NULL, mine, y, -1, NULL, &sc);
             }
         }
         free(sc.buf);
@@ -467,7 +470,7 @@ void orc_siddon_adj_voxels(const orc_geom *g, const double *angles, int64_t na, 
                         double y = proj[(t * nv + b) * nu + a];
                         if (y == 0.0) continue;
                         pixel_pos(g, angles[t], (double)a, (double)b, P);
-                        acc += y * siddon_core(g, S, P, NULL, NULL, 0.0, lin, NULL, &sc);
+                        acc += y * siddon_core(g, S, P, NULL, NULL, NULL, 0.0, lin, NULL, &sc);
                     }
             }
             out[q] = acc;
@@ -520,7 +523,7 @@ void orc_bp(const orc_geom *g, const double *angles, int64_t na, const double *p
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < nz * ny; ++r) {
         int64_t k = r / ny, j = r % ny;
-        for (int64_t i = 0; i < nx; ++i) vol[(k * ny + j) * nx + i] = bp_voxel(g, angles, na, proj, kind, i, j, k);
+        for (int64_t i = 0; i < nx; ++i) vol[(k * ny + j) * nx + i] = bp_voxel(g, angles, na, proj, NULL, kind, i, j, k);
     }
 }
 
@@ -530,7 +533,39 @@ void orc_bp_voxels(const orc_geom *g, const double *angles, int64_t na, const do
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < n; ++q) {
         int64_t lin = vox_idx[q];
-        out[q] = bp_voxel(g, angles, na, proj, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
+        out[q] = bp_voxel(g, angles, na, proj, NULL, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
+    }
+}
+
+/* The same samplers reading FP32 inputs (each element is widened to FP64 when read; the
+ * arithmetic is that of the FP64 versions).  For inputs too large to hold twice. */
+void orc_siddon_rays_f32(const orc_geom *g, const double *angles, const int64_t *ray_idx, int64_t n,
+                         const float *vol, double *out) {
+    const int64_t nu = g->ndet[0], nv = g->ndet[1];
+#pragma omp parallel
+    {
+        scratch_t sc;
+        scratch_init(&sc, g);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n; ++q) {
+            int64_t r = ray_idx[q];
+            int64_t a = r % nu, b = (r / nu) % nv, t = r / (nu * nv);
+            double S[3], P[3];
+            source_pos(g, angles[t], S);
+            pixel_pos(g, angles[t], (double)a, (double)b, P);
+            out[q] = siddon_core(g, S, P, NULL, vol, NULL, 0.0, -1, NULL, &sc);
+        }
+        free(sc.buf);
+    }
+}
+
+void orc_bp_voxels_f32(const orc_geom *g, const double *angles, int64_t na, const float *proj, int kind,
+                       const int64_t *vox_idx, int64_t n, double *out) {
+    const int64_t nx = g->nvox[0], ny = g->nvox[1];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t lin = vox_idx[q];
+        out[q] = bp_voxel(g, angles, na, NULL, proj, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
     }
 }
 

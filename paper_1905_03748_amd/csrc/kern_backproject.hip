@@ -143,11 +143,21 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
 // into LDS row by row (lanes on consecutive pixels, zeros outside the detector), and the voxels
 // read their bilinear taps there.  The per-voxel arithmetic is that of k_bp_voxel.
 #ifndef CT_BPL_NZ
-#define CT_BPL_NZ 8
+#define CT_BPL_NZ 16
 #endif
 constexpr int BPL_NZ = CT_BPL_NZ;  // voxels per thread
-constexpr int BPL_K = 8;           // angles per staging round (at most)
-constexpr int BPL_FLOATS = 4096;   // staged floats per block (16 KiB)
+#ifndef CT_BPL_K
+#define CT_BPL_K 8
+#endif
+#ifndef CT_BPL_FLOATS
+#define CT_BPL_FLOATS 4096
+#endif
+#ifndef CT_BPL_PITCH
+#define CT_BPL_PITCH 37
+#endif
+constexpr int BPL_K = CT_BPL_K;            // angles per staging round (at most)
+constexpr int BPL_FLOATS = CT_BPL_FLOATS;  // staged floats per block
+constexpr int BPL_PN = CT_BPL_PITCH;       // row pitch of narrow windows (the common case)
 
 // PITCH: LDS row pitch (floats) of a window, a compile-time constant so that both rows of a
 // bilinear tap pair are one base address with immediate offsets.
@@ -181,9 +191,9 @@ __global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV 
     for (int t0 = 0; t0 < A.nang; t0 += K) {
         const int nk = min(K, A.nang - t0);
         __syncthreads();  // the previous round's taps have been read
-        if (wave == 0) {
-            // lanes 8q .. 8q+7: the tile's corners under angle t0 + q
-            const int q = lane >> 3, cn = lane & 7;
+        // lanes 8q' .. 8q'+7 of wave 0: the tile's corners under angle t0 + q0 + q'
+        for (int q0 = 0; wave == 0 && q0 < nk; q0 += 8) {
+            const int q = q0 + (lane >> 3), cn = lane & 7;
             float as = 0.0f, bs = 0.0f;
             if (q < nk) {
                 const AngleGeo &G = A.tab[A.a0 + t0 + q];
@@ -208,13 +218,13 @@ __global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV 
             }
         }
         __syncthreads();
-        // stage: wave w copies the windows of angles w, w + 4, ...; lane = window column
-        for (int q = wave; q < nk; q += 4) {
+        // stage: wave w copies rows w, w + 4, ... of every window; lane = window column
+        for (int q = 0; q < nk; ++q) {
             const int u = org[q][0] + lane;
             const bool uok = lane < WW && (unsigned)u < (unsigned)A.nu;
             const TP *pq = proj + (int64_t)(t0 + q) * psz + u;
             float *wq = win + q * wsz + lane;
-            for (int r = 0; r < HW; ++r) {
+            for (int r = wave; r < HW; r += 4) {
                 const int v = org[q][1] + r;
                 float val = 0.0f;
                 if (uok && (unsigned)v < (unsigned)A.nv) val = to_f(pq[(int64_t)v * A.nu]);
@@ -534,7 +544,7 @@ bool bp_window(const ct_geometry &g, int &WW, int &HW) {
     if (!(eu < 60.0 && ev < 1000.0)) return false;
     WW = (int)std::ceil(eu) + 4;
     HW = (int)std::ceil(ev) + 4;
-    return WW <= 64 && (WW <= 40 ? 40 : 64) * HW <= BPL_FLOATS;
+    return WW <= 64 && (WW <= BPL_PN ? BPL_PN : 64) * HW <= BPL_FLOATS;
 }
 
 BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const Slab &slab, int accumulate) {
@@ -598,8 +608,8 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     int WW = 0, HW = 0;
 #ifndef CT_NO_BP_LDS
     if (kind != CT_BP_ADJOINT && bp_window(p->g, WW, HW)) {
-        const bool narrow = WW <= 40;
-        const int K = std::min(BPL_K, BPL_FLOATS / ((narrow ? 40 : 64) * HW));
+        const bool narrow = WW <= BPL_PN;
+        const int K = std::min(BPL_K, BPL_FLOATS / ((narrow ? BPL_PN : 64) * HW));
         const dim3 lgrid(grid.x, grid.y, (unsigned)((nzown + BPL_NZ - 1) / BPL_NZ));
 #define CT_BPL(KIND, PITCH)                                                                                      \
     CT_DISPATCH2(pt, TP, vt, TV,                                                                                 \
@@ -607,13 +617,13 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                                     (TV *)vol, A, WW, HW, K))
         if (kind == CT_BP_FDK) {
             if (narrow) {
-                CT_BPL(CT_BP_FDK, 40);
+                CT_BPL(CT_BP_FDK, BPL_PN);
             } else {
                 CT_BPL(CT_BP_FDK, 64);
             }
         } else {
             if (narrow) {
-                CT_BPL(CT_BP_PSEUDO_MATCHED, 40);
+                CT_BPL(CT_BP_PSEUDO_MATCHED, BPL_PN);
             } else {
                 CT_BPL(CT_BP_PSEUDO_MATCHED, 64);
             }

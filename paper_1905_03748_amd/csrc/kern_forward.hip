@@ -256,7 +256,13 @@ __global__ __launch_bounds__(FWD_TU * FWD_TV) void k_siddon(const TV *__restrict
 // Per row the z coordinate is kept relative to the slot of its entry point (z = Zr + t Dz with
 // Zr in [0, 1)), so the crossing time (lo + 1 - Zr) / Dz is one FMA without cancellation.
 
-constexpr int ZC_COLS = 4;  // columns (waves) per block
+#ifndef CT_ZC_COLS
+#define CT_ZC_COLS 4
+#endif
+#ifndef CT_ZC_XCD_W
+#define CT_ZC_XCD_W 4
+#endif
+constexpr int ZC_COLS = CT_ZC_COLS;  // columns (waves) per block
 
 template <typename TV>
 struct ZPair;
@@ -381,7 +387,16 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
                                                              FwdArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int bid = blockIdx.x;
+    int bid = blockIdx.x;
+#if CT_ZC_XCD_W > 1
+    // workgroups are dealt to the 8 XCDs in turn: give each XCD CT_ZC_XCD_W consecutive column
+    // groups out of every 8 * CT_ZC_XCD_W, so rays that share voxels share an L2
+    {
+        constexpr int W = CT_ZC_XCD_W, C = 8 * W;
+        const int full = (int)(gridDim.x / C) * C;
+        if (bid < full) bid = (bid / C) * C + (bid % 8) * W + (bid % C) / 8;
+    }
+#endif
     const int cb = bid % A.cblocks;
     const int rest = bid / A.cblocks;
     const int ai = rest % A.nang;

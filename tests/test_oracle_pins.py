@@ -526,3 +526,21 @@ def test_T4_tv_decreases(orc):
     tv0 = orc.tv_value(vol)
     x = orc.tv_steps(vol, 5, 0.001)
     assert orc.tv_value(x) < tv0
+
+
+def test_fp32_input_samplers_equal_fp64_on_widened_data(orc):
+    """The per-ray and per-voxel samplers that read FP32 arrays in place (for inputs too large to
+    copy) perform the FP64 arithmetic of the pinned FP64 samplers on the exactly widened values."""
+    geo = _geo(orc, nVoxel=(11, 9, 7), dVoxel=(1.1, 0.9, 1.3), offOrigin=(0.3, -0.2, 0.4),
+               nDetector=(13, 10), dDetector=(1.5, 1.7), offDetector=(0.4, -0.3))
+    rng = np.random.default_rng(31)
+    angles = inputs.uniform_angles(12)
+    vol = rng.uniform(0, 1, geo.vol_shape).astype(np.float32)
+    proj = rng.uniform(0, 1, geo.proj_shape(len(angles))).astype(np.float32)
+    rays = rng.choice(proj.size, 40, replace=False)
+    vox = rng.choice(vol.size, 40, replace=False)
+    np.testing.assert_array_equal(orc.siddon_rays(geo, angles, rays, vol),
+                                  orc.siddon_rays(geo, angles, rays, vol.astype(np.float64)))
+    for kind in (orc.W_FDK, orc.W_PM):
+        np.testing.assert_array_equal(orc.bp_voxels(geo, angles, proj, vox, kind),
+                                      orc.bp_voxels(geo, angles, proj.astype(np.float64), vox, kind))
