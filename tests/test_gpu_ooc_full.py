@@ -1,12 +1,11 @@
 """Out-of-core operators at the full size of the splitting workload: a 3072^3 FP32 volume and 3072
-projections of 3072^2 (108 GiB each, in pinned host memory) under a 32 GiB device cap.  One
-Siddon A x and one FDK A^T y (Algorithms 1 and 2), each checked on seeded samples of its output
-against the oracle, which reads the FP32 host arrays in place.
+projections of 3072^2 (108 GiB each, in pageable host memory, which the streamer stages through its
+own pinned ring) under a 32 GiB device cap.  One Siddon A x and one FDK A^T y (Algorithms 1 and 2),
+each checked on seeded samples of its output against the oracle, which reads the FP32 host arrays
+in place.
 
 It needs about 220 GiB of host memory and several minutes, so it runs only when CT_FULL_OOC=1."""
-import ctypes
 import os
-import time
 
 import numpy as np
 import pytest
@@ -23,32 +22,13 @@ DEV = "cuda:0"
 CAP = 32 << 30
 
 
-def _pinned(shape):
-    """Exact-size pinned host array (hipHostMalloc) and its pointer."""
-    hip = ctypes.CDLL("libamdhip64.so")
-    hip.hipHostMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_uint]
-    n = int(np.prod(shape))
-    ptr = ctypes.c_void_p()
-    assert hip.hipHostMalloc(ctypes.byref(ptr), n * 4, 0) == 0, "hipHostMalloc failed"
-    arr = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_float)), shape=(n,)).reshape(shape)
-    return arr, ptr
-
-
-def _free(ptr):
-    hip = ctypes.CDLL("libamdhip64.so")
-    hip.hipHostFree.argtypes = [ctypes.c_void_p]
-    hip.hipHostFree(ptr)
-
-
 def test_full_size_out_of_core(orc):
     w = inputs.workload("ooc")
     plan = Plan(w.geometry_dict(), w.angles)
     og = orc.Geometry.from_dict(w.geometry_dict())
-    say("[ooc full] pinning 216 GiB")
-    t = time.perf_counter()
-    vol, vptr = _pinned(plan.vol_shape)
-    proj, pptr = _pinned(plan.proj_shape)
-    say(f"[ooc full] pinned in {time.perf_counter() - t:.1f} s; phantom slab by slab")
+    vol = np.empty(plan.vol_shape, dtype=np.float32)
+    proj = np.empty(plan.proj_shape, dtype=np.float32)
+    say("[ooc full] phantom slab by slab")
     try:
         ells = inputs.ellipsoids(w)
         nz = w.nvox[2]
@@ -81,5 +61,3 @@ def test_full_size_out_of_core(orc):
         assert e <= TOL_BP
     finally:
         del vol, proj
-        _free(vptr)
-        _free(pptr)
