@@ -98,9 +98,13 @@ ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, i
 inline int64_t zcol_elems(const ct_geometry &g) { return g.nVoxel[0] * g.nVoxel[1] * (g.nVoxel[2] + 2); }
 // whether the column Siddon walk is valid for angles [a0, a1) of the plan
 bool zcol_ok(const ct_plan *p, int64_t a0, int64_t a1);
+// adj_scratch (optional, adj_bytes): device memory for the exact adjoint's transposed projection
+// copy (adj_chunk_bytes_per_angle bytes per angle); without it a launch that may allocate takes
+// stream-ordered scratch, and one that may not falls back to the slower gather kernel.
 ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
-                             hipStream_t st);
+                             hipStream_t st, void *adj_scratch = nullptr, size_t adj_bytes = 0);
+size_t adj_chunk_bytes_per_angle(const ct_geometry &g);
 
 // Algorithm helpers (kern_algos.hip)
 ct_status dot_f64(const void *a, const void *b, ct_dtype t, int64_t n, double *out, double *partials,

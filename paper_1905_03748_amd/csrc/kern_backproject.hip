@@ -422,6 +422,157 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Exact adjoint with lanes on the voxels of one column (resident launches).
+//
+// A wave takes one voxel column and 64 * R of its voxels (lane = voxel; a lane's R voxels are 64
+// apart), so the candidate detector columns of every angle and the column's parameter interval
+// [t0, t1] on each of them are the same in all lanes: the FP64 clip is computed once per wave.
+// Along the ray of row b the height is z = t v_b, so voxel [zl, zh) is met for t in
+// [zl / v_b, zh / v_b] (ordered) clipped to [t0, t1]; the rows that can meet it have v_b in
+// [min(zl / t0, zl / t1), max(zh / t0, zh / t1)], at most NR consecutive rows (NR from a host
+// bound).  The projections are read from a copy [angle][u][1 + v] of pairs (y |P - S|, 1 / v_b)
+// with a zero row below and above each column, so the rows of consecutive voxels are consecutive
+// addresses and every row costs one 8-byte load, two products and four compares.
+
+// proj [angle][v][u] -> yq [angle][u][v + 1] (nv + 2 rows, zero first and last), 32 x 32 tiles
+template <typename TP>
+__global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, float2 *__restrict__ yq, BpArgs A) {
+    __shared__ float tile[32][33];
+    const int u0 = blockIdx.x * 32, r0 = blockIdx.y * 32, t = blockIdx.z;  // r = b + 1
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int nvp = A.nv + 2;
+    const TP *pt = proj + (int64_t)t * A.nu * A.nv;
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int u = u0 + tx, b = r0 + ty + k - 1;
+        float y = 0.0f;
+        if (u < A.nu && b >= 0 && b < A.nv) y = to_f(pt[(int64_t)b * A.nu + u]);
+        tile[ty + k][tx] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int r = r0 + tx, u = u0 + ty + k;
+        if (u < A.nu && r < nvp) {
+            const int b = r - 1;
+            float2 q = make_float2(0.0f, 0.0f);
+            if (b >= 0 && b < A.nv) {
+                const double ua = (u - A.cu) * A.du + A.offu, vb = (b - A.cv) * A.dv + A.offv;
+                // |P - S| (mm per unit t) is the same for every angle in a circular orbit
+                q.x = (float)(tile[tx][ty + k] * sqrt(A.dDSD * A.dDSD + ua * ua + vb * vb));
+                q.y = vb != 0.0 ? (float)(1.0 / vb) : 1e30f;
+            }
+            yq[((int64_t)t * A.nu + u) * nvp + r] = q;
+        }
+    }
+}
+
+template <typename TV, int R, int NR>
+__global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
+                                                 int zgroups, int xblocks) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    int bid = blockIdx.x;
+    const int zg = bid % zgroups;
+    bid /= zgroups;
+    const int i = (bid % xblocks) * 4 + wave;
+    const int j = bid / xblocks;
+    if (i >= A.nx) return;  // whole wave; no barriers follow
+    const float zface0 = (float)(A.dz0 - 0.5 * A.ddz);  // lower face of voxel 0
+    const float dz = A.dz;
+    float acc[R], zl[R], zh[R];
+    bool kin[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
+        kin[r] = k < A.own_hi;
+        zl[r] = fmaf((float)k, dz, zface0);
+        zh[r] = fmaf((float)(k + 1), dz, zface0);
+        acc[r] = (kin[r] && A.accumulate) ? to_f(vol[((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i]) : 0.0f;
+    }
+    const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;  // column centre (mm)
+    const float hx = 0.5f * A.dx, hy = 0.5f * A.dy;
+    const float fxc = (float)xc, fyc = (float)yc;
+    const float v0 = (float)(A.offv - A.cv * A.dv), idv = 1.0f / (float)A.dv;
+    const float nv0 = -v0 * idv;
+    const float bmax = (float)(A.nv + 1 - NR);
+    const float aum = (float)(A.cu - A.offu / A.du), iau = (float)(1.0 / A.du);
+    const int nvp = A.nv + 2;
+    for (int t = 0; t < A.nang; ++t) {
+        const AngleGeo &G = A.tab[A.a0 + t];
+        const double c = G.c, s = G.s;
+        const double Wx = xc - A.dDSO * c, Wy = yc - A.dDSO * s;  // source -> column centre
+        const float fc = (float)c, fs = (float)s;
+        float umin = FLT_MAX, umax = -FLT_MAX;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float X = fxc + ((q & 1) ? hx : -hx), Y = fyc + ((q & 2) ? hy : -hy);
+            const float u = A.DSD * (Y * fc - X * fs) * __builtin_amdgcn_rcpf(A.DSO - (X * fc + Y * fs));
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+        }
+        const int alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - 1e-3f), 0.0f);
+        const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + 1e-3f), (float)(A.nu - 1));
+        for (int a = alo; a <= ahi; ++a) {
+            const double ua = (a - A.cu) * A.du + A.offu;
+            const double Dx = -A.dDSD * c - ua * s, Dy = -A.dDSD * s + ua * c;
+            const float cross = (float)(Wx * Dy - Wy * Dx);
+            const float dotp = (float)(Wx * Dx + Wy * Dy);
+            const float fDx = (float)Dx, fDy = (float)Dy;
+            const float L2 = fmaf(fDx, fDx, fDy * fDy);
+            const float iL = __builtin_amdgcn_rsqf(L2);
+            const float ux = fDx * iL, uy = fDy * iL;
+            const float dperp = cross * iL;
+            const float fx = -dperp * uy, fy = dperp * ux;
+            float s0 = -FLT_MAX, s1 = FLT_MAX;
+            if (fabsf(ux) > 1e-7f) {
+                const float rr = __builtin_amdgcn_rcpf(ux);
+                const float qa = (-hx - fx) * rr, qb = (hx - fx) * rr;
+                s0 = fmaxf(s0, fminf(qa, qb));
+                s1 = fminf(s1, fmaxf(qa, qb));
+            } else if (fabsf(fx) > hx) {
+                continue;
+            }
+            if (fabsf(uy) > 1e-7f) {
+                const float rr = __builtin_amdgcn_rcpf(uy);
+                const float qa = (-hy - fy) * rr, qb = (hy - fy) * rr;
+                s0 = fmaxf(s0, fminf(qa, qb));
+                s1 = fminf(s1, fmaxf(qa, qb));
+            } else if (fabsf(fy) > hy) {
+                continue;
+            }
+            if (!(s0 < s1)) continue;
+            const float T = (s1 - s0) * iL;
+            const float t0 = fmaf(s0, iL, dotp * (iL * iL));
+            const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
+            const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp + 1;  // indexed by row b >= -1
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]
+                const float vlo = fminf(zl[r] * it0, zl[r] * it1);
+                const float bl = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
+                const float2 *cb = col + (int)bl;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const float2 w = cb[q];
+                    // parameters relative to t0 (one rounding each), clipped to [0, T]: a row that
+                    // stays inside the voxel gets exactly T
+                    const float tA = fmaf(zl[r], w.y, -t0), tB = fmaf(zh[r], w.y, -t0);
+                    const float lo = fmaxf(fminf(tA, tB), 0.0f), hi = fminf(fmaxf(tA, tB), T);
+                    acc[r] = fmaf(fmaxf(hi - lo, 0.0f), w.x, acc[r]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!kin[r]) continue;
+        const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
+        vol[((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i] = from_f<TV>(acc[r]);
+    }
+}
+
 // SART update for one angle t with FDK weights:
 //   x_j += lambda * (w_j * bilinear(r)) / (w_j * bilinear(1))   where w_j * bilinear(1) > 1e-6
 __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r, float *__restrict__ vol,
@@ -547,6 +698,28 @@ bool bp_window(const ct_geometry &g, int &WW, int &HW) {
     return WW <= 64 && (WW <= BPL_PN ? BPL_PN : 64) * HW <= BPL_FLOATS;
 }
 
+// Rows of one detector column that can meet one voxel, at most: the heights z of the voxel and
+// the ray parameters t in the voxel column give v = z / t over an interval of width at most
+// (dz / t_min + |z|_max (1/t0 - 1/t1)) / dv, with t_min = (DSO - R) / DSD and
+// t1 - t0 <= sqrt(2) max(dx, dy) / DSD, R bounding the distance of any voxel from the axis.  An
+// interval of width W holds at most floor(W) + 1 integers.
+int adj_rows(const ct_geometry &g) {
+    double R = 0.0, Zmax = 0.0;
+    for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy) {
+            const double xe = g.offOrigin[0] + (cx ? 0.5 : -0.5) * g.nVoxel[0] * g.dVoxel[0];
+            const double ye = g.offOrigin[1] + (cy ? 0.5 : -0.5) * g.nVoxel[1] * g.dVoxel[1];
+            R = std::max(R, std::sqrt(xe * xe + ye * ye));
+        }
+    for (int cz = 0; cz < 2; ++cz)
+        Zmax = std::max(Zmax, std::fabs(g.offOrigin[2] + (cz ? 0.5 : -0.5) * g.nVoxel[2] * g.dVoxel[2]));
+    if (!(g.DSO - R > 0.0)) return 1 << 20;
+    const double tmin = (g.DSO - R) / g.DSD;
+    const double dt = std::sqrt(2.0) * std::max(g.dVoxel[0], g.dVoxel[1]) / g.DSD;
+    const double W = (g.dVoxel[2] / tmin + Zmax * dt / (tmin * tmin)) / g.dDetector[1];
+    return (int)std::floor(W * 1.001 + 1e-3) + 1;
+}
+
 BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const Slab &slab, int accumulate) {
     const ct_geometry &g = p->g;
     BpArgs A;
@@ -594,8 +767,13 @@ BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, con
 
 }  // namespace
 
+size_t adj_chunk_bytes_per_angle(const ct_geometry &g) {
+    return (size_t)g.nDetector[0] * (size_t)(g.nDetector[1] + 2) * sizeof(float2);
+}
+
 ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
-                             ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab, hipStream_t st) {
+                             ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab, hipStream_t st,
+                             void *adj_scratch, size_t adj_bytes) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
@@ -641,6 +819,72 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                      hipLaunchKernelGGL((k_bp_voxel<CT_BP_PSEUDO_MATCHED, TP, TV>), grid, block, 0, st, (const TP *)proj,
                                         (TV *)vol, A));
     } else {
+#ifndef CT_NO_ADJ_COL
+        // voxel lanes over a transposed, pre-scaled copy of the projections, made in angle
+        // sub-chunks that fit the scratch (the caller's, else stream-ordered scratch of the whole
+        // range when the launch may allocate); accumulators pass between sub-chunks in FP32
+        const int nr = std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2);
+        const size_t per_angle = adj_chunk_bytes_per_angle(p->g);
+        void *yq = adj_scratch, *own = nullptr;
+        size_t qcap = adj_scratch ? adj_bytes : 0;
+        if (nr <= 4 && !yq && slab.scratch_ok) {
+            if (hipMallocAsync(&own, (size_t)(a1 - a0) * per_angle, st) == hipSuccess) {
+                yq = own;
+                qcap = (size_t)(a1 - a0) * per_angle;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (nr <= 4 && yq && qcap >= per_angle) {
+            const int64_t kq = std::min<int64_t>(a1 - a0, (int64_t)(qcap / per_angle));
+            const int R = nzown <= 64 ? 1 : (nzown <= 128 ? 2 : (nzown <= 256 ? 4 : 8));
+            const int zgroups = (int)((nzown + 64 * R - 1) / (64 * R));
+            const int xblocks = (A.nx + 3) / 4;
+            const dim3 ag((unsigned)((int64_t)zgroups * xblocks * A.ny));
+            const size_t pangle = (size_t)A.nu * A.nv * dtype_size(pt);
+            for (int64_t c0 = a0; c0 < a1; c0 += kq) {
+                const int64_t c1 = std::min(a1, c0 + kq);
+                const BpArgs Ac = make_bp_args(p, tab, c0, c1, slab, c0 == a0 ? accumulate : 1);
+                const void *pc = (const char *)proj + (size_t)(c0 - a0) * pangle;
+                const dim3 pg((unsigned)((A.nu + 31) / 32), (unsigned)((A.nv + 2 + 31) / 32), (unsigned)(c1 - c0));
+                CT_DISPATCH1(pt, TP,
+                             hipLaunchKernelGGL((k_adj_prep<TP>), pg, dim3(256), 0, st, (const TP *)pc, (float2 *)yq, Ac));
+                CT_HIP(hipGetLastError());
+#define CT_ADJ(RR, NN)                                                                                          \
+    CT_DISPATCH1(vt, TV,                                                                                        \
+                 hipLaunchKernelGGL((k_adj_col<TV, RR, NN>), ag, block, 0, st, (const float2 *)yq, (TV *)vol, Ac, \
+                                    zgroups, xblocks))
+#define CT_ADJ_R(NN)        \
+    switch (R) {            \
+        case 1:             \
+            CT_ADJ(1, NN);  \
+            break;          \
+        case 2:             \
+            CT_ADJ(2, NN);  \
+            break;          \
+        case 4:             \
+            CT_ADJ(4, NN);  \
+            break;          \
+        default:            \
+            CT_ADJ(8, NN);  \
+            break;          \
+    }
+                if (nr <= 2) {
+                    CT_ADJ_R(2);
+                } else if (nr == 3) {
+                    CT_ADJ_R(3);
+                } else {
+                    CT_ADJ_R(4);
+                }
+#undef CT_ADJ_R
+#undef CT_ADJ
+                CT_HIP(hipGetLastError());
+            }
+            if (own) CT_HIP(hipFreeAsync(own, st));
+            return CT_OK;
+        }
+        if (own) CT_HIP(hipFreeAsync(own, st));
+#endif
         CT_DISPATCH2(pt, TP, vt, TV,
                      hipLaunchKernelGGL((k_bp_adjoint<TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));
     }

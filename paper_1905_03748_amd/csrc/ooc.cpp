@@ -26,6 +26,7 @@ namespace ct {
 namespace {
 
 constexpr uint64_t RESERVE = 64ull << 20;      // angle table, allocator slack
+constexpr int64_t ADJ_SUB = 4;                  // angles per exact-adjoint sub-chunk under a cap
 constexpr size_t STAGE_PIECE = 64ull << 20;    // slab staging piece
 
 using clk = std::chrono::steady_clock;
@@ -123,7 +124,9 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     const int64_t kmin = std::max<int64_t>(1, K / 8);
     bool found = false;
     for (int64_t k = K; k >= 1; k = (k == 1 ? 0 : std::max<int64_t>(1, k / 2))) {
-        const uint64_t bufs = nbuf * (uint64_t)k * pangle;
+        // backprojection: plus the exact adjoint's transposed copy of up to ADJ_SUB angles
+        const uint64_t bufs = nbuf * (uint64_t)k * pangle +
+                              (direction == 1 ? (uint64_t)std::min<int64_t>(k, ADJ_SUB) * adj_chunk_bytes_per_angle(g) : 0);
         int64_t h = 0;
         if (cap > RESERVE + bufs) h = (int64_t)((cap - RESERVE - bufs) / slice) - 2 * L.halo;
         if (h >= 1) {
@@ -343,9 +346,11 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     CT_HIP(hipStreamCreateWithFlags(&S.comp, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.h2d, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.d2h, hipStreamNonBlocking));
-    DevBuf slab, dbuf[2];
+    DevBuf slab, dbuf[2], adj;
     CT_HIP(hipMalloc(&slab.p, L.h * slice));
     for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
+    const size_t adj_bytes = (size_t)std::min<int64_t>(L.K, ADJ_SUB) * adj_chunk_bytes_per_angle(g);
+    if (kind == CT_BP_ADJOINT) CT_HIP(hipMalloc(&adj.p, adj_bytes));
     HostBuf sin[2], svol[2];
     if (!proj_pinned)
         for (auto &b : sin) CT_HIP(hipHostMalloc(&b.p, chunk_bytes, hipHostMallocDefault));
@@ -392,7 +397,8 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
             st.bytes_h2d += (double)bytes;
             CT_HIP(hipStreamWaitEvent(S.comp, ev_h2d.e[j], 0));
             CT_HIP(hipEventRecord(tk0.e[c], S.comp));
-            if ((s = launch_backproject(p, kind, dbuf[j].p, pt, slab.p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp)) != CT_OK)
+            if ((s = launch_backproject(p, kind, dbuf[j].p, pt, slab.p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp, adj.p,
+                                        adj.p ? adj_bytes : 0)) != CT_OK)
                 return s;
             CT_HIP(hipEventRecord(tk1.e[c], S.comp));
             CT_HIP(hipEventRecord(ev_k.e[j], S.comp));
