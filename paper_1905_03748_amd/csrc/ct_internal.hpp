@@ -83,8 +83,9 @@ inline Slab full_slab(const ct_geometry &g) {
 // Kernel launchers (resident; pointers are device pointers; projection pointer holds the
 // angles [a0, a1) starting at projection 0).
 // vcopy: optional copy of vol in the layout the projector reads, kept by the caller (then no
-// scratch copy is made): for Siddon the column-major slots of launch_zcols, for the interpolated
-// projector the [z][x][y] transpose of launch_transpose_xy.
+// scratch copy is made): for Siddon the column-major slots of launch_zcols (for a slab launch:
+// its mem_n slices, mem_n + 2 slots per column), for the interpolated projector the [z][x][y]
+// transpose of launch_transpose_xy.
 ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtype vt, void *proj,
                          ct_dtype pt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
                          hipStream_t st, const void *vcopy = nullptr);
@@ -93,6 +94,10 @@ ct_status launch_transpose_xy(const void *vol, ct_dtype vt, void *volT, int64_t 
 // [z][y][x] -> [y][x][slot], slot z + 1 holding voxel z, slots 0 and nz + 1 zero
 // (nx * ny * (nz + 2) elements)
 ct_status launch_zcols(const void *vol, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
+// slices [0, nz) of src ([z][y][x]) into slots slot0 + z of columns of nzp slots; pads bit 0 / 1
+// zero slot 0 / nzp - 1
+ct_status launch_zcols_piece(const void *src, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, int64_t nzp,
+                             int64_t slot0, int pads, hipStream_t st);
 // inverse: column-major slots -> [z][y][x]
 ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
 inline int64_t zcol_elems(const ct_geometry &g) { return g.nVoxel[0] * g.nVoxel[1] * (g.nVoxel[2] + 2); }

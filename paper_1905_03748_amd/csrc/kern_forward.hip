@@ -404,7 +404,9 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
     const int a = cb * ZC_COLS + wave;
     if (a >= A.nu) return;
     const AngleGeo &G = A.tab[A.a0 + ai];
-    const int64_t nzp = (int64_t)A.nz + 2;
+    // the copy holds slices [mem_lo, mem_lo + mem_n) of the volume (all of it when resident)
+    const int nzc = A.mem_n;
+    const int64_t nzp = (int64_t)nzc + 2;
 
     // shared xy line of the column, clipped to the grid's xy box (FP64)
     const double ua = (a - A.cu) * A.du + A.offu;
@@ -437,6 +439,35 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
     double L[ROWS];
     ZRows<ROWS> Z;
     bool all_up = true, all_down = true;
+    // the wave walks only where one of its rows is inside the owned slices: [t0, t1] shrinks to
+    // the hull of the rows' own intervals (outside them every row reads zero slots anyway)
+    {
+        const double zlo = A.own_lo - 0.5, zhi = A.own_hi - 0.5;
+        double win0 = 1e300, win1 = -1e300;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int b = min(brow + 64 * r, A.nv - 1);
+            const double Dz = ((b - A.cv) * A.dv + A.offv) / A.dz;
+            if (fabs(Dz * A.dz) < 1e-12 * Lref) {
+                if (G.S[2] >= zlo && G.S[2] <= zhi) {
+                    win0 = fmin(win0, t0);
+                    win1 = fmax(win1, t1);
+                }
+            } else {
+                const double ta = (zlo - G.S[2]) / Dz, tb = (zhi - G.S[2]) / Dz;
+                win0 = fmin(win0, fmin(ta, tb));
+                win1 = fmax(win1, fmax(ta, tb));
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            win0 = fmin(win0, __shfl_xor(win0, off, 64));
+            win1 = fmax(win1, __shfl_xor(win1, off, 64));
+        }
+        t0 = fmax(t0, win0 - 1e-9);
+        t1 = fmin(t1, win1 + 1e-9);
+        hit = hit && t0 < t1;
+    }
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         // lanes past the last row repeat its geometry (their results are not stored)
@@ -445,7 +476,8 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
         const double Dz = vbm / A.dz;
         const double mz = Dz * A.dz;
         L[r] = sqrt(Lxy2 + mz * mz);
-        const double ze = G.S[2] + t0 * Dz + 1.5;  // slot coordinate: voxel k spans [k + 1, k + 2)
+        // slot coordinate: voxel mem_lo + k spans [k + 1, k + 2)
+        const double ze = G.S[2] - A.mem_lo + t0 * Dz + 1.5;
         const double k0 = floor(ze);
         const double zr = ze - k0;
         const bool parz = fabs(mz) < 1e-12 * L[r];
@@ -454,7 +486,7 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
         Z.up[r] = parz || Dz > 0.0;
         // |k0| < 2^22 (checked on the host), so these are exact in FP32; the slot k0 + lo is in
         // [0, nz], and the byte offset is formed modulo 2^32
-        const float lmin = (float)(-k0), lmax = (float)((double)A.nz - k0);
+        const float lmin = (float)(-k0), lmax = (float)((double)nzc - k0);
         Z.lmin[r] = lmin;
         Z.lmax[r] = lmax;
         Z.kb[r] = (uint32_t)((int64_t)k0 * (int64_t)sizeof(TV));
@@ -521,13 +553,14 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
     }
 }
 
-// [z][y][x] -> column-major slots [y][x][z + 1] with zero slots 0 and nz + 1, 32 x 32 (z, x) tiles
+// [z][y][x] -> column-major slots: slices [0, nz) of src go to slots slot0 + z of columns of nzp
+// slots ([y][x][slot]); pads: bit 0 zeroes slot 0, bit 1 zeroes slot nzp - 1.  32 x 32 (z, x) tiles.
 template <typename T>
-__global__ __launch_bounds__(256) void k_zcols(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz) {
+__global__ __launch_bounds__(256) void k_zcols(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz,
+                                               int64_t nzp, int slot0, int pads) {
     __shared__ T tile[32][33];
     const int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int64_t nzp = (int64_t)nz + 2;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int x = x0 + tx, z = z0 + ty + r;
@@ -537,14 +570,14 @@ __global__ __launch_bounds__(256) void k_zcols(const T *__restrict__ src, T *__r
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int z = z0 + tx, x = x0 + ty + r;
-        if (x < nx && z < nz) dst[((int64_t)y * nx + x) * nzp + z + 1] = tile[tx][ty + r];
+        if (x < nx && z < nz) dst[((int64_t)y * nx + x) * nzp + slot0 + z] = tile[tx][ty + r];
     }
     if (threadIdx.x < 32) {
         const int x = x0 + threadIdx.x;
         if (x < nx) {
             const int64_t c = ((int64_t)y * nx + x) * nzp;
-            if (blockIdx.y == 0) dst[c] = from_f<T>(0.0f);
-            if (blockIdx.y == gridDim.y - 1) dst[c + nz + 1] = from_f<T>(0.0f);
+            if ((pads & 1) && blockIdx.y == 0) dst[c] = from_f<T>(0.0f);
+            if ((pads & 2) && blockIdx.y == gridDim.y - 1) dst[c + nzp - 1] = from_f<T>(0.0f);
         }
     }
 }
@@ -770,10 +803,15 @@ ct_status launch_transpose_xy(const void *vol, ct_dtype vt, void *volT, int64_t 
 }
 
 ct_status launch_zcols(const void *vol, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, hipStream_t st) {
+    return launch_zcols_piece(vol, vt, vz, nx, ny, nz, nz + 2, 1, 3, st);
+}
+
+ct_status launch_zcols_piece(const void *src, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, int64_t nzp,
+                             int64_t slot0, int pads, hipStream_t st) {
     const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
     CT_DISPATCH1(vt, T,
-                 hipLaunchKernelGGL((k_zcols<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)vz, (int)nx, (int)ny,
-                                    (int)nz));
+                 hipLaunchKernelGGL((k_zcols<T>), tg, dim3(256), 0, st, (const T *)src, (T *)vz, (int)nx, (int)ny,
+                                    (int)nz, nzp, (int)slot0, pads));
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
@@ -820,7 +858,7 @@ bool zcol_ok(const ct_plan *p, int64_t a0, int64_t a1) {
         }
         if (!(dzmax < 0.999 * fmin_)) return false;
         // slot offsets of a row's entry point stay far inside FP32's exact integers
-        if (fabs(G.S[2]) + dzmax + 2.0 > 4194304.0) return false;
+        if (fabs(G.S[2]) + (double)g.nVoxel[2] + dzmax + 2.0 > 4194304.0) return false;
     }
     return true;
 }
@@ -836,9 +874,11 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
     const int64_t nx = g.nVoxel[0], ny = g.nVoxel[1];
 #ifndef CT_NO_ZCOL
     // Siddon on a resident volume: column walk over the column-major copy
+    // a slab launch must bring its own copy (mem_n + 2 slots per column) and own all it holds
     const bool whole = slab.own_lo == 0 && slab.own_hi == g.nVoxel[2] && slab.mem_lo == 0 &&
                        slab.mem_n == g.nVoxel[2];
-    if (kind == CT_SIDDON && whole && (vcopy || slab.scratch_ok) && zcol_ok(p, a0, a1)) {
+    const bool slab_ok = vcopy && slab.own_lo == slab.mem_lo && slab.own_hi == slab.mem_lo + slab.mem_n;
+    if (kind == CT_SIDDON && (whole ? (vcopy || slab.scratch_ok) : slab_ok) && zcol_ok(p, a0, a1)) {
         const int64_t nz = g.nVoxel[2];
         void *vz = const_cast<void *>(vcopy);
         void *own_z = nullptr;

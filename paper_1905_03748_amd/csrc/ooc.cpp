@@ -27,6 +27,7 @@ namespace {
 
 constexpr uint64_t RESERVE = 64ull << 20;      // angle table, allocator slack
 constexpr int64_t ADJ_SUB = 4;                  // angles per exact-adjoint sub-chunk under a cap
+constexpr int64_t ZSTAGE = 8;                   // slices per column-major upload piece
 constexpr size_t STAGE_PIECE = 64ull << 20;    // slab staging piece
 
 using clk = std::chrono::steady_clock;
@@ -104,6 +105,8 @@ struct Layout {
     int64_t nsp;      // number of slabs
     int64_t K;        // angles per chunk
     int64_t halo;     // extra slices each side (interpolated forward)
+    bool col;         // Siddon forward: the slab is held column-major (2 zero slots per column)
+                      // and uploaded through a device stage of ZSTAGE slices
 };
 
 ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt, uint64_t cap,
@@ -114,6 +117,8 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     const uint64_t pangle = (uint64_t)g.nDetector[0] * g.nDetector[1] * dtype_size(pt);
     const int nbuf = direction == 0 ? 3 : 2;
     L.halo = (direction == 0 && proj == CT_INTERP) ? 1 : 0;
+    L.col = direction == 0 && proj == CT_SIDDON && zcol_ok(p, 0, na);
+    const int64_t extra = L.col ? 2 + ZSTAGE : 2 * L.halo;  // slices held besides the slab
     // chunk size: enough rays (forward) or angles (backprojection) per launch to fill the device
     const uint64_t pix = (uint64_t)g.nDetector[0] * g.nDetector[1];
     int64_t K = direction == 0 ? (int64_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(pix, 1)) : 32;
@@ -128,7 +133,7 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
         const uint64_t bufs = nbuf * (uint64_t)k * pangle +
                               (direction == 1 ? (uint64_t)std::min<int64_t>(k, ADJ_SUB) * adj_chunk_bytes_per_angle(g) : 0);
         int64_t h = 0;
-        if (cap > RESERVE + bufs) h = (int64_t)((cap - RESERVE - bufs) / slice) - 2 * L.halo;
+        if (cap > RESERVE + bufs) h = (int64_t)((cap - RESERVE - bufs) / slice) - extra;
         if (h >= 1) {
             h = std::min<int64_t>(h, g.nVoxel[2]);
             const int64_t nsp = (g.nVoxel[2] + h - 1) / h;
@@ -185,8 +190,9 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
     CT_HIP(hipStreamCreateWithFlags(&S.comp, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.h2d, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.d2h, hipStreamNonBlocking));
-    DevBuf slab, dbuf[3];
-    CT_HIP(hipMalloc(&slab.p, (L.h + 2 * L.halo) * slice));
+    DevBuf slab, stage, dbuf[3];
+    CT_HIP(hipMalloc(&slab.p, (L.h + (L.col ? 2 : 2 * L.halo)) * slice));
+    if (L.col) CT_HIP(hipMalloc(&stage.p, ZSTAGE * slice));
     for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
     HostBuf sin[3], sout[3], svol[2];
     if (!proj_pinned)
@@ -232,29 +238,47 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
         // the previous slab's kernels must finish before its buffer is overwritten
         auto a = clk::now();
         CT_HIP(hipStreamSynchronize(S.comp));
-        const char *src = (const char *)h_vol + mem_lo * slice;
-        const size_t total = (mem_hi - mem_lo) * slice;
-        if (vol_pinned) {
-            CT_HIP(hipMemcpyAsync(slab.p, src, total, hipMemcpyHostToDevice, S.h2d));
-        } else {
-            size_t off = 0;
-            int q = 0;
-            bool used[2] = {false, false};
-            while (off < total) {
-                const size_t len = std::min(STAGE_PIECE, total - off);
-                if (used[q]) CT_HIP(hipEventSynchronize(ev_vol.e[q]));
-                auto b = clk::now();
-                par_memcpy(svol[q].p, src + off, len);
-                st.t_stage_s += secs(b, clk::now());
-                CT_HIP(hipMemcpyAsync((char *)slab.p + off, svol[q].p, len, hipMemcpyHostToDevice, S.h2d));
-                CT_HIP(hipEventRecord(ev_vol.e[q], S.h2d));
-                used[q] = true;
-                off += len;
-                q ^= 1;
+        // host bytes [src, src + total) to device dst, through the pinned ring when pageable
+        auto upload = [&](void *dst, const char *src, size_t total) -> ct_status {
+            if (vol_pinned) {
+                CT_HIP(hipMemcpyAsync(dst, src, total, hipMemcpyHostToDevice, S.h2d));
+            } else {
+                size_t off = 0;
+                int q = 0;
+                bool used[2] = {false, false};
+                while (off < total) {
+                    const size_t len = std::min(STAGE_PIECE, total - off);
+                    if (used[q]) CT_HIP(hipEventSynchronize(ev_vol.e[q]));
+                    auto b = clk::now();
+                    par_memcpy(svol[q].p, src + off, len);
+                    st.t_stage_s += secs(b, clk::now());
+                    CT_HIP(hipMemcpyAsync((char *)dst + off, svol[q].p, len, hipMemcpyHostToDevice, S.h2d));
+                    CT_HIP(hipEventRecord(ev_vol.e[q], S.h2d));
+                    used[q] = true;
+                    off += len;
+                    q ^= 1;
+                }
             }
+            CT_HIP(hipStreamSynchronize(S.h2d));
+            st.bytes_h2d += (double)total;
+            return CT_OK;
+        };
+        if (L.col) {
+            // column-major slab: pieces of ZSTAGE slices through the stage, transposed into place
+            const int64_t nzp = (own_hi - own_lo) + 2;
+            for (int64_t z0 = own_lo; z0 < own_hi; z0 += ZSTAGE) {
+                const int64_t zn = std::min(ZSTAGE, own_hi - z0);
+                if ((s = upload(stage.p, (const char *)h_vol + z0 * slice, zn * slice)) != CT_OK) return s;
+                const int pads = (z0 == own_lo ? 1 : 0) | (z0 + zn == own_hi ? 2 : 0);
+                if ((s = launch_zcols_piece(stage.p, vt, slab.p, g.nVoxel[0], g.nVoxel[1], zn, nzp, 1 + (z0 - own_lo),
+                                            pads, S.comp)) != CT_OK)
+                    return s;
+                CT_HIP(hipStreamSynchronize(S.comp));  // the stage is reused by the next piece
+            }
+        } else {
+            if ((s = upload(slab.p, (const char *)h_vol + mem_lo * slice, (mem_hi - mem_lo) * slice)) != CT_OK)
+                return s;
         }
-        CT_HIP(hipStreamSynchronize(S.h2d));
-        st.bytes_h2d += (double)total;
         st.t_other_mem_s += secs(a, clk::now());
 
         Slab sl;
@@ -290,7 +314,8 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
                 CT_HIP(hipStreamWaitEvent(S.comp, ev_d2h.e[j], 0));
             }
             CT_HIP(hipEventRecord(tk0.e[c], S.comp));
-            if ((s = launch_forward(p, kind, slab.p, vt, dbuf[j].p, pt, acc ? 1 : 0, a0, a1, sl, S.comp)) != CT_OK)
+            if ((s = launch_forward(p, kind, slab.p, vt, dbuf[j].p, pt, acc ? 1 : 0, a0, a1, sl, S.comp,
+                                    L.col ? slab.p : nullptr)) != CT_OK)
                 return s;
             CT_HIP(hipEventRecord(tk1.e[c], S.comp));
             CT_HIP(hipEventRecord(ev_k.e[j], S.comp));

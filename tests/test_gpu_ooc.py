@@ -26,9 +26,11 @@ def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=
     halo = 1 if (direction == 0 and projector == "interp") else 0
     k = min(na, max(1, (8 << 20) // (nu * nv))) if direction == 0 else min(32, na)
     kmin = max(1, k // 8)
-    # backprojection plans also hold the exact adjoint's transposed copy of up to 4 angles
+    # backprojection plans also hold the exact adjoint's transposed copy of up to 4 angles; a
+    # Siddon forward holds its slab column-major (two zero slots per column) and an 8-slice stage
     adj = min(kmin, 4) * nu * (nv + 2) * 8 if direction == 1 else 0
-    return RESERVE + nbuf * kmin * pangle + adj + (slices + 2 * halo) * slice_b
+    extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0)
+    return RESERVE + nbuf * kmin * pangle + adj + (slices + extra) * slice_b
 
 
 @pytest.fixture(scope="module")
