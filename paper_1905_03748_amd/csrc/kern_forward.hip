@@ -603,6 +603,160 @@ __global__ __launch_bounds__(256) void k_zcols_inv(const T *__restrict__ src, T 
 }
 
 // ------------------------------------------------------------------------------------------
+// Interpolated projector over a zero-padded column-major copy (resident volumes).
+//
+// The copy holds voxel (x, y, z) at ((y + 1) PX + x + 1) PZ + z + 1 with PX = nx + 3, PY = ny + 3,
+// PZ = nz + 3 and zeros elsewhere, so every tap of a sample inside the grid box grown by one voxel
+// is in range and the zero padding of the interpolant needs no tests.  A wave takes one detector
+// column and 64 * ROWS of its rows (lane = row): the rows share the xy line, and at the same
+// sample index their sample points stay within about a voxel of each other in xy, so the four
+// (x, y) tap columns of a sample are mostly common to the wave and each holds the two z taps of
+// every lane in one 8-byte load at consecutive addresses.
+
+template <typename TV>
+__global__ __launch_bounds__(256) void k_pcols(const TV *__restrict__ src, TV *__restrict__ dst, int nx, int ny, int nz) {
+    // one thread per padded (slot, column): tiles of 32 slots x 32 padded x for one padded y
+    __shared__ TV tile[32][33];
+    const int PX = nx + 3, PZ = nz + 3;
+    const int xp0 = blockIdx.x * 32, zp0 = blockIdx.y * 32, yp = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int y = yp - 1;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int x = xp0 + tx - 1, z = zp0 + ty + r - 1;
+        TV v = from_f<TV>(0.0f);
+        if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) v = src[((int64_t)z * ny + y) * nx + x];
+        tile[ty + r][tx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int zp = zp0 + tx, xp = xp0 + ty + r;
+        if (xp < PX && zp < PZ) dst[((int64_t)yp * PX + xp) * PZ + zp] = tile[tx][ty + r];
+    }
+}
+
+#ifndef CT_IC_BATCH
+#define CT_IC_BATCH 4
+#endif
+constexpr int IC_B = CT_IC_BATCH;  // samples per trip
+
+template <typename TV, typename TP, int ROWS>
+__global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restrict__ vp, TP *__restrict__ proj,
+                                                             FwdArgs A) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    int bid = blockIdx.x;
+#if CT_ZC_XCD_W > 1
+    {
+        constexpr int W = CT_ZC_XCD_W, C = 8 * W;
+        const int full = (int)(gridDim.x / C) * C;
+        if (bid < full) bid = (bid / C) * C + (bid % 8) * W + (bid % C) / 8;
+    }
+#endif
+    const int cb = bid % A.cblocks;
+    const int rest = bid / A.cblocks;
+    const int ai = rest % A.nang;
+    const int rg = rest / A.nang;
+    const int a = cb * ZC_COLS + wave;
+    if (a >= A.nu) return;
+    const AngleGeo &G = A.tab[A.a0 + ai];
+    const int64_t PX = A.nx + 3, PZ = A.nz + 3;
+    const double lo[3] = {-1.0, -1.0, -1.0};
+    const double hi[3] = {(double)A.nx, (double)A.ny, (double)A.nz};
+    // per row: samples k0 .. k0 + n - 1, sample j at fb + j fs relative to voxel ib
+    int ib[ROWS][3], nsm[ROWS];
+    float fb[ROWS][3], fs[ROWS][3];
+    int nmax = 0;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int b = min(rg * (64 * ROWS) + 64 * r + lane, A.nv - 1);
+        RaySetup R;
+        nsm[r] = 0;
+        ib[r][0] = ib[r][1] = ib[r][2] = 0;
+        fb[r][0] = fb[r][1] = fb[r][2] = 0.0f;
+        fs[r][0] = fs[r][1] = fs[r][2] = 0.0f;
+        if (ray_clip(G, A, a, b, lo, hi, R)) {
+            const double s_in = R.t0 * R.L, s_out = R.t1 * R.L;
+            const double k0 = ceil(s_in / A.delta - 0.5);
+            const double k1 = floor(s_out / A.delta - 0.5);
+            if (k1 >= k0) {
+                const double tk0 = (k0 + 0.5) * A.delta / R.L;
+                const double dt = A.delta / R.L;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const double B = G.S[ax] + tk0 * R.D[ax];
+                    ib[r][ax] = (int)floor(B);
+                    fb[r][ax] = (float)(B - ib[r][ax]);
+                    fs[r][ax] = (float)(dt * R.D[ax]);
+                }
+                nsm[r] = (int)(k1 - k0) + 1;
+            }
+        }
+        nmax = max(nmax, nsm[r]);
+    }
+    // lanes stop together: the wave runs to its longest row, shorter rows add zero
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
+    float acc[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
+    const int64_t cy = PX * PZ;
+    const float xhi = (float)A.nx, yhi = (float)A.ny, zhi = (float)A.nz;
+    for (int j0 = 0; j0 < nmax; j0 += IC_B) {
+        float w[IC_B][ROWS][3], v[IC_B][ROWS][8];
+#pragma unroll
+        for (int u = 0; u < IC_B; ++u) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                // rows with fewer samples repeat their last one (and add nothing)
+                const int j = max(0, min(j0 + u, nsm[r] - 1));
+                const float px = fmaf((float)j, fs[r][0], fb[r][0]);
+                const float py = fmaf((float)j, fs[r][1], fb[r][1]);
+                const float pz = fmaf((float)j, fs[r][2], fb[r][2]);
+                const float flx = floorf(px), fly = floorf(py), flz = floorf(pz);
+                w[u][r][0] = px - flx;
+                w[u][r][1] = py - fly;
+                w[u][r][2] = pz - flz;
+                // tap (x0, y0, z0) with each index kept in [-1, n] (samples lie in the box grown by
+                // one voxel up to rounding), so all eight taps are inside the padded copy
+                const int x0 = (int)__builtin_amdgcn_fmed3f(flx + (float)ib[r][0], -1.0f, xhi);
+                const int y0 = (int)__builtin_amdgcn_fmed3f(fly + (float)ib[r][1], -1.0f, yhi);
+                const int z0 = (int)__builtin_amdgcn_fmed3f(flz + (float)ib[r][2], -1.0f, zhi);
+                const int64_t c = nsm[r] > 0 ? ((int64_t)(y0 + 1) * PX + (x0 + 1)) * PZ + (z0 + 1) : 0;
+                const TV *q = vp + c;
+                ZPair<TV>::ld(q, 0u, v[u][r][0], v[u][r][1]);
+                ZPair<TV>::ld(q + PZ, 0u, v[u][r][2], v[u][r][3]);
+                ZPair<TV>::ld(q + cy, 0u, v[u][r][4], v[u][r][5]);
+                ZPair<TV>::ld(q + cy + PZ, 0u, v[u][r][6], v[u][r][7]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < IC_B; ++u) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const float *q = v[u][r];
+                const float rx = w[u][r][0], ry = w[u][r][1], rz = w[u][r][2];
+                // z lerps of the columns (x0, y0), (x0 + 1, y0), (x0, y0 + 1), (x0 + 1, y0 + 1)
+                const float c00 = fmaf(rz, q[1] - q[0], q[0]), c10 = fmaf(rz, q[3] - q[2], q[2]);
+                const float c01 = fmaf(rz, q[5] - q[4], q[4]), c11 = fmaf(rz, q[7] - q[6], q[6]);
+                const float c0 = fmaf(rx, c10 - c00, c00), c1 = fmaf(rx, c11 - c01, c01);
+                const float val = fmaf(ry, c1 - c0, c0);
+                acc[r] += (j0 + u < nsm[r]) ? val : 0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int b = rg * (64 * ROWS) + 64 * r + lane;
+        if (b >= A.nv) continue;
+        const int64_t o = ((int64_t)ai * A.nv + b) * A.nu + a;
+        const float prev = A.accumulate ? to_f(proj[o]) : 0.0f;
+        proj[o] = from_f<TP>(prev + (float)(acc[r] * A.delta));
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Interpolated projector: samples at s_k = (k + 1/2) delta mm from the source, every k whose
 // sample lies in the grid box grown by half a voxel (outside it the zero-padded trilinear
 // interpolant vanishes); p = delta * sum of the interpolant at the samples.  All rays of a wave
@@ -932,6 +1086,46 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
             if (own_z) CT_HIP(hipFreeAsync(own_z, st));
             return CT_OK;
         }
+    }
+    // interpolated projector on a resident volume: zero-padded column-major copy
+    if (kind == CT_INTERP && whole && slab.scratch_ok) {
+        const int64_t nz = g.nVoxel[2];
+        const size_t pbytes = (size_t)((nx + 3) * (ny + 3) * (nz + 3)) * dtype_size(vt);
+        void *vpad = nullptr;
+        if (hipMallocAsync(&vpad, pbytes, st) == hipSuccess) {
+            const dim3 tg((unsigned)((nx + 3 + 31) / 32), (unsigned)((nz + 3 + 31) / 32), (unsigned)(ny + 3));
+            CT_DISPATCH1(vt, T,
+                         hipLaunchKernelGGL((k_pcols<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)vpad, (int)nx,
+                                            (int)ny, (int)nz));
+            CT_HIP(hipGetLastError());
+            const int64_t nu = g.nDetector[0], nv = g.nDetector[1];
+            const int64_t cblocks = (nu + ZC_COLS - 1) / ZC_COLS;
+            const int rows = cblocks * (a1 - a0) * ((nv + 127) / 128) >= 4096 ? 2 : 1;
+            const int64_t rgroups = (nv + 64 * rows - 1) / (64 * rows);
+            const int64_t max_ang = std::max<int64_t>(1, (int64_t(1) << 30) / (cblocks * rgroups));
+            const size_t proj_angle = (size_t)nu * nv * dtype_size(pt);
+            for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
+                const int64_t c1 = std::min(a1, c0 + max_ang);
+                FwdArgs A = make_args(p, tab, c0, c1, slab, accumulate);
+                A.cblocks = (int32_t)cblocks;
+                A.rgroups = (int32_t)rgroups;
+                char *pp = (char *)proj + (size_t)(c0 - a0) * proj_angle;
+                const dim3 grid((unsigned)(cblocks * (c1 - c0) * rgroups)), block(64 * ZC_COLS);
+                if (rows == 2) {
+                    CT_DISPATCH2(vt, TV, pt, TP,
+                                 hipLaunchKernelGGL((k_interp_col<TV, TP, 2>), grid, block, 0, st, (const TV *)vpad,
+                                                    (TP *)pp, A));
+                } else {
+                    CT_DISPATCH2(vt, TV, pt, TP,
+                                 hipLaunchKernelGGL((k_interp_col<TV, TP, 1>), grid, block, 0, st, (const TV *)vpad,
+                                                    (TP *)pp, A));
+                }
+                CT_HIP(hipGetLastError());
+            }
+            CT_HIP(hipFreeAsync(vpad, st));
+            return CT_OK;
+        }
+        (void)hipGetLastError();
     }
 #endif
     const void *volT_given = kind == CT_SIDDON ? nullptr : vcopy;
