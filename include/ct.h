@@ -166,7 +166,9 @@ ct_status ct_backproject_host(ct_plan *plan, ct_backprojector backprojector, con
  * step sizes and the residual-norm recurrence rho_{k+1} = rho_k - alpha_k gamma_k are FP64.
  * d_resid (device, niter+1 doubles, may be NULL) receives sqrt(rho_k); if A p = 0 the iteration
  * stops and the last value repeats.  d_b: device projections (all angles).  d_x: device volume,
- * in: x0, out: result. */
+ * in: x0, out: result.  The workspace also holds the Siddon projector's column-major copy of the
+ * projected volume and the exact adjoint's transposed projection copy, so with d_workspace given
+ * an iteration allocates nothing (in geometries whose cone angle the column kernels cover). */
 ct_status ct_cgls_workspace_bytes(const ct_plan *plan, ct_dtype vol_dtype, ct_dtype proj_dtype,
                                   uint64_t *bytes);
 ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype,

@@ -272,11 +272,14 @@ ct_status convert(const void *src, ct_dtype s_t, void *dst, ct_dtype d_t, int64_
 // The recurrence vectors r, q (projection-shaped) and s, p (volume-shaped) are FP32 whatever the
 // storage of x and b: CGLS search directions are unnormalised (A p grows like the operator norm
 // squared times the data), which overflows FP16's range on realistic problems.
+// r, q (projections), s, p (volumes), partials and scalars, the Siddon column copy of the volume
+// being projected, and the exact adjoint's transposed projection copy: no allocation per iteration
 size_t cgls_workspace(const ct_plan *p, ct_dtype, ct_dtype) {
     const ct_geometry &g = p->g;
     const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
     const size_t np = (size_t)g.nDetector[0] * g.nDetector[1] * p->angles.size();
-    return 2 * align256(nv * 4) + 2 * align256(np * 4) + align256(DOT_BLOCKS * 8) + align256(S_COUNT * 8);
+    return 2 * align256(nv * 4) + 2 * align256(np * 4) + align256(DOT_BLOCKS * 8) + align256(S_COUNT * 8) +
+           align256((size_t)zcol_elems(g) * 4) + align256(p->angles.size() * adj_chunk_bytes_per_angle(g));
 }
 
 ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter, double *resid,
@@ -294,17 +297,29 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
     float *pv = (float *)ws.take(nv * 4);
     double *parts = (double *)ws.take(DOT_BLOCKS * 8);
     double *scal = (double *)ws.take(S_COUNT * 8);
+    void *vz = ws.take((size_t)zcol_elems(g) * 4);
+    const size_t qbytes = (size_t)na * adj_chunk_bytes_per_angle(g);
+    void *yq = ws.take(qbytes);
     const Slab full = full_slab(g);
+    const bool col = zcol_ok(p, 0, na);
 #define CK(e)                          \
     do {                               \
         ct_status s_ = (e);            \
         if (s_ != CT_OK) return s_;    \
     } while (0)
+    // A v through the column copy in the workspace (refreshed from v first)
+    auto fwd = [&](const void *v, ct_dtype t, float *out) -> ct_status {
+        if (col) {
+            ct_status s_ = launch_zcols(v, t, vz, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st);
+            if (s_ != CT_OK) return s_;
+        }
+        return launch_forward(p, CT_SIDDON, v, t, out, CT_F32, 0, 0, na, full, st, col ? vz : nullptr);
+    };
     // r = b - A x ; s = A^T r ; p = s ; gamma = <s,s> ; rho = <r,r>
-    CK(launch_forward(p, CT_SIDDON, x, vt, r, CT_F32, 0, 0, na, full, st));
+    CK(fwd(x, vt, r));
     CT_DISPATCH1(pt, T, hipLaunchKernelGGL((k_rsub_from<T>), dim3(ew_grid(np)), dim3(EW_THREADS), 0, st, (const T *)b, r, np));
     CT_HIP(hipGetLastError());
-    CK(launch_backproject(p, CT_BP_ADJOINT, r, CT_F32, sv, CT_F32, 0, 0, na, full, st));
+    CK(launch_backproject(p, CT_BP_ADJOINT, r, CT_F32, sv, CT_F32, 0, 0, na, full, st, yq, qbytes));
     hipLaunchKernelGGL((k_copy<float>), dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (const float *)sv, pv, nv);
     CT_HIP(hipGetLastError());
     CK(dot_f64(sv, sv, CT_F32, nv, scal + S_GAMMA, parts, st));
@@ -313,7 +328,7 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
     CT_HIP(hipGetLastError());
     for (int32_t k = 0; k < niter; ++k) {
         // q = A p ; delta = <q,q> ; alpha = gamma / delta
-        CK(launch_forward(p, CT_SIDDON, pv, CT_F32, q, CT_F32, 0, 0, na, full, st));
+        CK(fwd(pv, CT_F32, q));
         CK(dot_f64(q, q, CT_F32, np, scal + S_DELTA, parts, st));
         hipLaunchKernelGGL(k_cgls_alpha, dim3(1), dim3(1), 0, st, scal, resid, k);
         CT_HIP(hipGetLastError());
@@ -324,7 +339,7 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
                            (int)S_ALPHA, -1.0f, np);
         CT_HIP(hipGetLastError());
         // s = A^T r ; gamma' = <s,s> ; beta = gamma'/gamma ; p = s + beta p
-        CK(launch_backproject(p, CT_BP_ADJOINT, r, CT_F32, sv, CT_F32, 0, 0, na, full, st));
+        CK(launch_backproject(p, CT_BP_ADJOINT, r, CT_F32, sv, CT_F32, 0, 0, na, full, st, yq, qbytes));
         CK(dot_f64(sv, sv, CT_F32, nv, scal + S_TMP, parts, st));
         hipLaunchKernelGGL(k_cgls_beta, dim3(1), dim3(1), 0, st, scal);
         CT_HIP(hipGetLastError());

@@ -256,8 +256,10 @@ __global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV 
                 rxy2 = sx * sx + sy * sy;
                 wpm = A.pm_const * iL * iL * iL;
             }
-            // byte offset of the window column in LDS (exact in FP32)
+            // LDS byte offset of the window column (exact in FP32), rebased so that the absolute row
+            // index can be used directly; the clamp keeps rows 0 .. HW - 2 of the window
             const float cb = fmaf(la, 4.0f, (float)(q * wsz * 4));
+            const float cbr = fmaf(-ob, (float)(4 * PITCH), cb), cbmax = fmaf(lbmax, (float)(4 * PITCH), cb);
 #pragma unroll
             for (int k = 0; k < BPL_NZ; ++k) {
                 // the row coordinate comes from the voxel's absolute height (independent of the
@@ -265,8 +267,8 @@ __global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV 
                 const float bs = fmaf(zk[k], mv, A.bv0);
                 const float bf = floorf(bs);
                 const float fb = bs - bf;
-                const float lb = __builtin_amdgcn_fmed3f(bf - ob, 0.0f, lbmax);
-                const float *t = (const float *)((const char *)win + (int)fmaf(lb, (float)(4 * PITCH), cb));
+                const float off = __builtin_amdgcn_fmed3f(fmaf(bf, (float)(4 * PITCH), cbr), cb, cbmax);
+                const float *t = (const float *)((const char *)win + (int)off);
                 const float v0 = fmaf(wa1, t[1], wa0 * t[0]);
                 const float v1 = fmaf(wa1, t[PITCH + 1], wa0 * t[PITCH]);
                 const float v = fmaf(fb, v1 - v0, v0);
@@ -546,13 +548,14 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
             const float T = (s1 - s0) * iL;
             const float t0 = fmaf(s0, iL, dotp * (iL * iL));
             const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
-            const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp + 1;  // indexed by row b >= -1
+            const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]
                 const float vlo = fminf(zl[r] * it0, zl[r] * it1);
                 const float bl = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
-                const float2 *cb = col + (int)bl;
+                // uniform column base plus an unsigned 32-bit byte offset of row bl
+                const float2 *cb = (const float2 *)((const char *)col + (uint32_t)((int)bl + 1) * 8u);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
                     const float2 w = cb[q];

@@ -46,12 +46,19 @@ class Request:
     def latency(self) -> float:
         return self.t_done - self.t_submit
 
+    def work(self) -> float:
+        return float(np.prod(self.geometry["nVoxel"])) * len(self.angles)
+
     def device_bytes(self) -> int:
         nx, ny, nz = self.geometry["nVoxel"]
         vol = int(nx) * int(ny) * int(nz) * 4
         proj = int(np.prod(self.b.shape)) * 4
-        # b, x, CGLS workspace (r, q: projections; s, p: volumes), TV gradient, small scalars
-        return proj + vol + (2 * proj + 2 * vol) + vol + (1 << 20)
+        nv = int(self.b.shape[1])
+        yq = proj // nv * (nv + 2) * 2                     # adjoint's transposed copy (8 B per pixel)
+        col = int(nx) * int(ny) * (int(nz) + 2) * 4        # projector's column-major copy
+        # b, x, CGLS workspace (r, q: projections; s, p: volumes; the two copies), TV gradient,
+        # small scalars
+        return proj + vol + (2 * proj + 2 * vol + col + yq) + vol + (1 << 20)
 
 
 class _Slot:
@@ -64,9 +71,15 @@ class _Slot:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, device="cuda:0"):
+    """max_overlap_work: a request joins others already on the device only while their summed
+    work (voxels x angles) stays within this bound, so reconstructions large enough to fill the GPU
+    on their own run alone (overlapping them only makes their cache working sets compete) while
+    small ones share it; None admits whenever a slot and memory are free."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, device="cuda:0", max_overlap_work=None):
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
+        self.max_overlap_work = max_overlap_work
         self.slots = [_Slot(self.device) for _ in range(max_slots)]
         self.queue: collections.deque[Request] = collections.deque()
         self.finished: list[Request] = []
@@ -153,14 +166,18 @@ class Server:
         while not self._stop:
             progressed = False
             for s in self.slots:
-                if s.req is not None and s.event.query():
+                if s.req is not None and s.event is not None and s.event.query():
                     self._finish(s)
                     progressed = True
             with self._lock:
                 free = [s for s in self.slots if s.req is None]
-                while free and self.queue and self.in_use + self.queue[0].device_bytes() <= self.budget:
+                while free and self.queue and self.in_use + self.queue[0].device_bytes() <= self.budget and \
+                        self._may_overlap(self.queue[0]):
                     req = self.queue.popleft()
                     slot = free.pop()
+                    # the slot is taken before the lock is released, so drain() never sees the
+                    # request neither queued nor in a slot
+                    slot.req = req
                     slot.bytes = req.device_bytes()
                     self.in_use += slot.bytes
                     self.peak_in_use = max(self.peak_in_use, self.in_use)
@@ -175,6 +192,12 @@ class Server:
             if not progressed:
                 self._wake.wait(0.0005)
                 self._wake.clear()
+
+    def _may_overlap(self, req: Request) -> bool:
+        active = [s.req.work() for s in self.slots if s.req is not None]
+        if not active or self.max_overlap_work is None:
+            return True
+        return sum(active) + req.work() <= self.max_overlap_work
 
     # -- reporting --------------------------------------------------------------------------------------
     def stats(self) -> dict:

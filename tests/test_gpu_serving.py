@@ -88,3 +88,25 @@ def test_served_result_matches_oracle(orc, reqs):
     e = rel_l2(q.x.numpy(), x)
     say(f"[serve vs oracle] rel L2 {e:.3e}")
     assert e <= 1e-3
+
+
+def test_overlap_limit_serialises_large_work(reqs):
+    """With an overlap bound below every request's work, requests never share the device, and
+    the results are still those of the requests run alone."""
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4, max_overlap_work=1.0)
+    try:
+        qs = [srv.submit(_clone(r)) for r, _ in reqs]
+        assert srv.drain(300)
+        st = srv.stats()
+        say(f"[serve overlap bound] stats {st}")
+        assert st["max_active"] == 1
+    finally:
+        srv.close()
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+    try:
+        alone = [srv.submit(_clone(r)) for r, _ in reqs]
+        assert srv.drain(300)
+    finally:
+        srv.close()
+    for q, a in zip(qs, alone):
+        assert torch.equal(q.x, a.x), q.rid
