@@ -6,7 +6,10 @@ arrival order whenever a slot is free and the request's device footprint fits th
 admitted request gets its own stream, its projections are copied in once, and its whole
 reconstruction is enqueued at once (the library's CGLS and TV keep their scalars on the device, so
 nothing waits on the host).  Work of co-resident requests therefore overlaps on the GPU, and new
-requests join as soon as earlier ones finish and release their memory.
+requests join as soon as earlier ones finish and release their memory.  An optional bound on the
+summed work of co-resident requests keeps reconstructions that fill the GPU by themselves from
+sharing it (their kernels are bound by cache and memory traffic, which overlap only splits), while
+small requests still run side by side.
 
 Kernels are deterministic and their launch shapes depend only on the request, so a request's
 result is bitwise the same whether it runs alone or among others.
