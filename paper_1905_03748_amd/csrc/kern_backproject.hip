@@ -28,6 +28,9 @@ constexpr int BP_TX = 16, BP_TY = 16;
 #ifndef CT_ADJ_NZ
 #define CT_ADJ_NZ 16
 #endif
+#ifndef CT_ADJ_XCD_W
+#define CT_ADJ_XCD_W 4
+#endif
 constexpr int BP_NZ = CT_BP_NZ;  // voxels per thread (FDK / pseudo-matched)
 
 struct BpArgs {
@@ -476,6 +479,15 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     int bid = blockIdx.x;
+#if CT_ADJ_XCD_W > 1
+    // workgroups are dealt to the 8 XCDs in turn: give each XCD CT_ADJ_XCD_W consecutive blocks
+    // (neighbouring columns, which read the same detector columns) out of every 8 * CT_ADJ_XCD_W
+    {
+        constexpr int W = CT_ADJ_XCD_W, C = 8 * W;
+        const int full = (int)(gridDim.x / C) * C;
+        if (bid < full) bid = (bid / C) * C + (bid % 8) * W + (bid % C) / 8;
+    }
+#endif
     const int zg = bid % zgroups;
     bid /= zgroups;
     const int i = (bid % xblocks) * 4 + wave;
@@ -840,7 +852,11 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         }
         if (nr <= 4 && yq && qcap >= per_angle) {
             const int64_t kq = std::min<int64_t>(a1 - a0, (int64_t)(qcap / per_angle));
+#ifdef CT_ADJ_R
+            const int R = std::min<int>(CT_ADJ_R, nzown <= 64 ? 1 : (nzown <= 128 ? 2 : (nzown <= 256 ? 4 : 8)));
+#else
             const int R = nzown <= 64 ? 1 : (nzown <= 128 ? 2 : (nzown <= 256 ? 4 : 8));
+#endif
             const int zgroups = (int)((nzown + 64 * R - 1) / (64 * R));
             const int xblocks = (A.nx + 3) / 4;
             const dim3 ag((unsigned)((int64_t)zgroups * xblocks * A.ny));
