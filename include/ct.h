@@ -140,7 +140,10 @@ typedef struct {
 } ct_ooc_stats;
 
 /* Pure host planner used by the *_host calls: slab height and chunk size for a cap.
- * direction: 0 = forward (3 projection chunk buffers), 1 = backprojection (2 buffers).
+ * direction: 0 = forward (3 projection chunk buffers), 1 = FDK or pseudo-matched backprojection
+ * (2 buffers), 2 = exact-adjoint backprojection (2 buffers plus the kernel's transposed FP32 copy
+ * of one chunk, 8 (Nv + 2) Nu bytes per angle; chunks of up to 128 angles, because each chunk
+ * re-reads the slab's accumulators).  projector matters for direction 0 only.
  * Errors: CT_ERR_ARG, CT_ERR_DTYPE, CT_ERR_CAP. */
 ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
                       ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out);
@@ -173,6 +176,25 @@ ct_status ct_cgls_workspace_bytes(const ct_plan *plan, ct_dtype vol_dtype, ct_dt
                                   uint64_t *bytes);
 ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype,
                   int32_t niter, double *d_resid, void *d_workspace, void *stream);
+
+/* Out-of-core CGLS (Section 3.2 runs CGLS on images larger than device memory): the iteration of
+ * ct_cgls with every vector in host memory.  Each iteration runs one ct_forward_host (CT_SIDDON)
+ * and one ct_backproject_host (CT_BP_ADJOINT) under device_cap_bytes; the vector updates
+ * (x += alpha p, r -= alpha q, p = s + beta p: FP32 fused multiply-adds with the scalars rounded
+ * to FP32) and the FP64 inner products run on up to 16 host threads over fixed blocks, so the
+ * result does not depend on the thread count.  A start x0 that is all zeros skips the projection
+ * of x0 (A 0 = 0 exactly).
+ * h_b: host projections, FP32, [n_angles][Nv][Nu], read only.  h_x: host volume, FP32, [Nz][Ny][Nx],
+ * in: x0, out: result.  h_workspace: caller-owned host memory (pageable or pinned) of at least
+ * ct_cgls_host_workspace_bytes bytes, holding r, q, s and p; not to be shared with a concurrent
+ * call.  resid: host, niter+1 doubles receiving sqrt(rho_k) (may be NULL); if A p = 0 the
+ * iteration stops and the last value repeats.  stats (may be NULL): byte counts and times summed
+ * over the operator calls, the split of the forward calls, t_total_s of the whole call, and the
+ * host vector work added to t_other_mem_s.  Errors: as ct_forward_host and ct_backproject_host,
+ * CT_ERR_ARG for a NULL pointer or niter < 0, CT_ERR_STATE if a host thread cannot start. */
+ct_status ct_cgls_host_workspace_bytes(const ct_plan *plan, uint64_t *bytes);
+ct_status ct_cgls_host(ct_plan *plan, const float *h_b, float *h_x, int32_t niter, double *resid,
+                       void *h_workspace, uint64_t device_cap_bytes, ct_ooc_stats *stats);
 
 /* SART (Andersen and Kak; Section 3.2 uses its ordered-subset form) with A = CT_SIDDON and
  * B = CT_BP_FDK, one angle per update (block must be 1), angles in natural order, relaxation

@@ -65,6 +65,8 @@ SIGNATURES = {
     "ct_backproject_host": [_P, _INT, _P, _INT, _P, _INT, _U64, C.POINTER(ct_ooc_stats)],
     "ct_cgls_workspace_bytes": [_P, _INT, _INT, C.POINTER(_U64)],
     "ct_cgls": [_P, _P, _INT, _P, _INT, _I32, _P, _P, _P],
+    "ct_cgls_host_workspace_bytes": [_P, C.POINTER(_U64)],
+    "ct_cgls_host": [_P, _P, _P, _I32, _P, _P, _U64, C.POINTER(ct_ooc_stats)],
     "ct_sart_workspace_bytes": [_P, C.POINTER(_U64)],
     "ct_sart": [_P, _P, _P, _I32, _D, _I32, _P, _P],
     "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
@@ -172,6 +174,19 @@ def ct_cgls_workspace_bytes(plan, vol_dtype, proj_dtype) -> int:
 def ct_cgls(plan, d_b, proj_dtype, d_x, vol_dtype, niter, d_resid=0, d_workspace=0, stream=0):
     return _check(lib().ct_cgls(plan, d_b, proj_dtype, d_x, vol_dtype, niter, d_resid or None, d_workspace or None,
                                 stream or None))
+
+
+def ct_cgls_host_workspace_bytes(plan) -> int:
+    b = _U64()
+    _check(lib().ct_cgls_host_workspace_bytes(plan, C.byref(b)))
+    return b.value
+
+
+def ct_cgls_host(plan, h_b, h_x, niter, h_resid, h_workspace, device_cap_bytes) -> ct_ooc_stats:
+    s = ct_ooc_stats()
+    _check(lib().ct_cgls_host(plan, h_b, h_x, niter, h_resid or None, h_workspace, int(device_cap_bytes),
+                              C.byref(s)))
+    return s
 
 
 def ct_sart_workspace_bytes(plan) -> int:

@@ -183,7 +183,7 @@ ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const vo
 ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
                       ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out) {
     if (!plan || !out) return fail(CT_ERR_ARG, "ct_ooc_plan: null pointer");
-    if (direction != 0 && direction != 1) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0 or 1");
+    if (direction < 0 || direction > 2) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0, 1 or 2");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_ooc_plan: unknown dtype");
     return ooc_plan(plan, direction, projector, vol_dtype, proj_dtype, device_cap_bytes, out);
 }
@@ -221,6 +221,19 @@ ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x
     if (niter < 0) return fail(CT_ERR_ARG, "ct_cgls: niter must be >= 0");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls: unknown dtype");
     return cgls_run(plan, d_b, proj_dtype, d_x, vol_dtype, niter, d_resid, d_workspace, (hipStream_t)stream);
+}
+
+ct_status ct_cgls_host_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
+    if (!plan || !bytes) return fail(CT_ERR_ARG, "ct_cgls_host_workspace_bytes: null pointer");
+    *bytes = cgls_host_workspace(plan);
+    return CT_OK;
+}
+
+ct_status ct_cgls_host(ct_plan *plan, const float *h_b, float *h_x, int32_t niter, double *resid, void *h_workspace,
+                       uint64_t device_cap_bytes, ct_ooc_stats *stats) {
+    if (!plan || !h_b || !h_x || !h_workspace) return fail(CT_ERR_ARG, "ct_cgls_host: null pointer");
+    if (niter < 0) return fail(CT_ERR_ARG, "ct_cgls_host: niter must be >= 0");
+    return cgls_host_run(plan, h_b, h_x, niter, resid, h_workspace, device_cap_bytes, stats);
 }
 
 ct_status ct_sart_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {

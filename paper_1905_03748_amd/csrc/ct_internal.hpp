@@ -142,4 +142,9 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
 ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj, ct_dtype pt, void *h_vol,
                           ct_dtype vt, uint64_t cap, ct_ooc_stats *stats);
 
+// Out-of-core CGLS (ooc_cgls.cpp): host workspace r, q, s, p in FP32
+size_t cgls_host_workspace(const ct_plan *p);
+ct_status cgls_host_run(ct_plan *p, const float *b, float *x, int32_t niter, double *resid, void *work,
+                        uint64_t cap, ct_ooc_stats *stats);
+
 }  // namespace ct

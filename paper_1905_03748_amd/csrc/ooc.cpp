@@ -26,7 +26,6 @@ namespace ct {
 namespace {
 
 constexpr uint64_t RESERVE = 64ull << 20;      // angle table, allocator slack
-constexpr int64_t ADJ_SUB = 4;                  // angles per exact-adjoint sub-chunk under a cap
 constexpr int64_t ZSTAGE = 8;                   // slices per column-major upload piece
 constexpr size_t STAGE_PIECE = 64ull << 20;    // slab staging piece
 
@@ -109,6 +108,7 @@ struct Layout {
                       // and uploaded through a device stage of ZSTAGE slices
 };
 
+// direction: 0 forward, 1 backprojection (FDK, pseudo-matched), 2 exact-adjoint backprojection
 ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt, uint64_t cap,
                      Layout &L) {
     const ct_geometry &g = p->g;
@@ -119,9 +119,13 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     L.halo = (direction == 0 && proj == CT_INTERP) ? 1 : 0;
     L.col = direction == 0 && proj == CT_SIDDON && zcol_ok(p, 0, na);
     const int64_t extra = L.col ? 2 + ZSTAGE : 2 * L.halo;  // slices held besides the slab
-    // chunk size: enough rays (forward) or angles (backprojection) per launch to fill the device
+    // chunk size: enough rays (forward) or angles (backprojection) per launch to fill the device.
+    // The exact adjoint's lanes run down voxel columns, so its slab accumulators are read and
+    // written with a stride of one slice once per launch: it takes more angles per launch, each
+    // with its transposed projection copy.
     const uint64_t pix = (uint64_t)g.nDetector[0] * g.nDetector[1];
-    int64_t K = direction == 0 ? (int64_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(pix, 1)) : 32;
+    int64_t K = direction == 0 ? (int64_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(pix, 1))
+                               : (direction == 1 ? 32 : 128);
     K = std::min<int64_t>(K, na);
     K = std::max<int64_t>(K, 1);
     // fewest slabs wins (the image is split as little as possible); among equal counts the larger
@@ -129,9 +133,8 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     const int64_t kmin = std::max<int64_t>(1, K / 8);
     bool found = false;
     for (int64_t k = K; k >= 1; k = (k == 1 ? 0 : std::max<int64_t>(1, k / 2))) {
-        // backprojection: plus the exact adjoint's transposed copy of up to ADJ_SUB angles
-        const uint64_t bufs = nbuf * (uint64_t)k * pangle +
-                              (direction == 1 ? (uint64_t)std::min<int64_t>(k, ADJ_SUB) * adj_chunk_bytes_per_angle(g) : 0);
+        const uint64_t bufs =
+            nbuf * (uint64_t)k * pangle + (direction == 2 ? (uint64_t)k * adj_chunk_bytes_per_angle(g) : 0);
         int64_t h = 0;
         if (cap > RESERVE + bufs) h = (int64_t)((cap - RESERVE - bufs) / slice) - extra;
         if (h >= 1) {
@@ -351,7 +354,7 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     const auto t_start = clk::now();
     const ct_geometry &g = p->g;
     Layout L;
-    ct_status s = layout_for(p, 1, CT_SIDDON, vt, pt, cap, L);
+    ct_status s = layout_for(p, kind == CT_BP_ADJOINT ? 2 : 1, CT_SIDDON, vt, pt, cap, L);
     if (s != CT_OK) return s;
     ct_ooc_stats st;
     std::memset(&st, 0, sizeof(st));
@@ -374,7 +377,7 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     DevBuf slab, dbuf[2], adj;
     CT_HIP(hipMalloc(&slab.p, L.h * slice));
     for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
-    const size_t adj_bytes = (size_t)std::min<int64_t>(L.K, ADJ_SUB) * adj_chunk_bytes_per_angle(g);
+    const size_t adj_bytes = (size_t)L.K * adj_chunk_bytes_per_angle(g);  // one transposed copy per chunk
     if (kind == CT_BP_ADJOINT) CT_HIP(hipMalloc(&adj.p, adj_bytes));
     HostBuf sin[2], svol[2];
     if (!proj_pinned)

@@ -127,6 +127,32 @@ class Plan:
                   _stream(stream))
         return x, resid
 
+    def cgls_host_workspace_bytes(self) -> int:
+        return A.ct_cgls_host_workspace_bytes(self.handle)
+
+    def cgls_host(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, cap_bytes=32 << 30,
+                  workspace: torch.Tensor | None = None):
+        """Out-of-core CGLS on FP32 host tensors, in place on x (zeros if None); returns
+        (x, resid, stats) with resid a NumPy array of niter+1 residual norms."""
+        for t, name in ((b, "b"),) + (((x, "x"),) if x is not None else ()):
+            if t.device.type != "cpu" or not t.is_contiguous() or t.dtype != torch.float32:
+                raise ValueError(f"{name} must be a contiguous FP32 host tensor")
+        if tuple(b.shape) != self.proj_shape:
+            raise ValueError(f"b has shape {tuple(b.shape)}, expected {self.proj_shape}")
+        if x is None:
+            x = torch.zeros(self.vol_shape, dtype=torch.float32)
+        elif tuple(x.shape) != self.vol_shape:
+            raise ValueError(f"x has shape {tuple(x.shape)}, expected {self.vol_shape}")
+        need = self.cgls_host_workspace_bytes()
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8)
+        if workspace.device.type != "cpu" or workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace must be host memory of at least {need} bytes")
+        resid = np.zeros(niter + 1, dtype=np.float64)
+        st = A.ct_cgls_host(self.handle, b.data_ptr(), x.data_ptr(), niter, resid.ctypes.data, workspace.data_ptr(),
+                            cap_bytes)
+        return x, resid, st.as_dict()
+
     def sart(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, lam=1.0, workspace=None, stream=None):
         if x is None:
             x = torch.zeros(self.vol_shape, dtype=torch.float32, device=b.device)

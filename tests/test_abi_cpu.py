@@ -107,7 +107,13 @@ def test_ooc_planner_out_of_core_config(lib):
         assert fw.n_slabs == 4 and fw.slab_slices == 768, fw.as_dict()
         assert fw.slab_slices * slice_b + 3 * fw.chunk_angles * slice_b <= 32 << 30
         bp = A.ct_ooc_plan(p, 1, A.CT_SIDDON, A.CT_F32, A.CT_F32, 32 << 30)
-        assert bp.n_slabs >= 4 and bp.slab_slices * slice_b + 2 * bp.chunk_angles * slice_b <= 32 << 30
+        assert bp.n_slabs == 4 and bp.slab_slices * slice_b + 2 * bp.chunk_angles * slice_b <= 32 << 30
+        # the exact adjoint adds its transposed copy (3072 x 3074 float pairs per angle) and keeps
+        # the fewest slabs, taking the largest chunk that allows them
+        adj = A.ct_ooc_plan(p, 2, A.CT_SIDDON, A.CT_F32, A.CT_F32, 32 << 30)
+        per = 3072 * 3074 * 8
+        assert adj.n_slabs == 4 and adj.chunk_angles == 32, adj.as_dict()
+        assert adj.slab_slices * slice_b + adj.chunk_angles * (2 * slice_b + per) <= 32 << 30
         # FP16 storage halves the slabs
         h = A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F16, A.CT_F16, 32 << 30)
         assert h.n_slabs == 2 and h.slab_slices == 1536
@@ -129,13 +135,14 @@ def test_ooc_planner_equal_slabs_and_halo(lib):
         for nslices in (1, 5, 13, 40, 64, 100):
             cap = reserve + 3 * 64 * pangle + nslices * slice_b
             for kind, halo in ((A.CT_SIDDON, 0), (A.CT_INTERP, 1)):
-                for direction, nbuf in ((0, 3), (1, 2)):
+                for direction, nbuf in ((0, 3), (1, 2), (2, 2)):
                     s = A.ct_ooc_plan(p, direction, kind, A.CT_F32, A.CT_F32, cap)
                     h = halo if direction == 0 else 0
+                    adj = s.chunk_angles * 64 * 66 * 8 if direction == 2 else 0
                     assert s.n_slabs * s.slab_slices >= 64
                     assert s.slab_slices == -(-64 // s.n_slabs)            # equal slabs
                     assert (s.n_slabs - 1) * s.slab_slices < 64
-                    assert reserve + (s.slab_slices + 2 * h) * slice_b + nbuf * s.chunk_angles * pangle <= cap
+                    assert reserve + (s.slab_slices + 2 * h) * slice_b + nbuf * s.chunk_angles * pangle + adj <= cap
                     assert s.n_chunks == -(-64 // s.chunk_angles)
             # with room for the whole volume and full chunks: one slab
             if nslices >= 64:

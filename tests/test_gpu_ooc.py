@@ -17,18 +17,19 @@ RESERVE = 64 << 20
 
 def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=torch.float32):
     """A cap that leaves exactly `slices` slices next to the planner's smallest chunk buffers (the
-    planner shrinks chunks down to an eighth of its target when that gives fewer slabs)."""
+    planner shrinks chunks down to an eighth of its target when that gives fewer slabs).
+    direction 0: forward; 1: FDK or pseudo-matched backprojection; 2: exact adjoint."""
     nz, ny, nx = plan.vol_shape
     na, nv, nu = plan.proj_shape
     slice_b = nx * ny * torch.empty(0, dtype=dt).element_size()
     pangle = nu * nv * torch.empty(0, dtype=pdt).element_size()
     nbuf = 3 if direction == 0 else 2
     halo = 1 if (direction == 0 and projector == "interp") else 0
-    k = min(na, max(1, (8 << 20) // (nu * nv))) if direction == 0 else min(32, na)
+    k = min(na, max(1, (8 << 20) // (nu * nv))) if direction == 0 else min(32 if direction == 1 else 128, na)
     kmin = max(1, k // 8)
-    # backprojection plans also hold the exact adjoint's transposed copy of up to 4 angles; a
-    # Siddon forward holds its slab column-major (two zero slots per column) and an 8-slice stage
-    adj = min(kmin, 4) * nu * (nv + 2) * 8 if direction == 1 else 0
+    # the exact adjoint also holds its transposed FP32 copy of each chunk; a Siddon forward holds
+    # its slab column-major (two zero slots per column) and an 8-slice stage
+    adj = kmin * nu * (nv + 2) * 8 if direction == 2 else 0
     extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0)
     return RESERVE + nbuf * kmin * pangle + adj + (slices + extra) * slice_b
 
@@ -73,7 +74,7 @@ def test_backprojection_split_bitwise(case, orc, slices, pinned):
     yh = torch.from_numpy(y)
     yd = yh.to(DEV)
     for kind in ("fdk", "pm", "adjoint"):
-        cap = _cap_for(plan, slices, 1)
+        cap = _cap_for(plan, slices, 2 if kind == "adjoint" else 1)
         say(f"[ooc backprojection] slices={slices} pinned={pinned} kind={kind}")
         src = yh.pin_memory() if pinned else yh.clone()
         out = torch.full(plan.vol_shape, -7.0)
