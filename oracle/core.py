@@ -93,6 +93,7 @@ def load():
             "orc_bp_voxels": (None, [g, pd, i64, pd, C.c_int, pi, i64, pd]),
             "orc_siddon_rays_f32": (None, [g, pd, pi, i64, C.POINTER(C.c_float), pd]),
             "orc_bp_voxels_f32": (None, [g, pd, i64, C.POINTER(C.c_float), C.c_int, pi, i64, pd]),
+            "orc_siddon_adj_voxels_f32": (None, [g, pd, i64, C.POINTER(C.c_float), pi, i64, pd]),
             "orc_bp_coverage": (None, [g, d, pd]),
             "orc_bp_transpose": (None, [g, pd, i64, pd, C.c_int, pd]),
         }
@@ -179,9 +180,16 @@ def siddon_adj(geo: Geometry, angles, proj):
 
 
 def siddon_adj_voxels(geo: Geometry, angles, proj, vox_idx):
-    angles, proj = _f64(angles), _f64(proj)
+    """Selected voxels.  A C-contiguous FP32 projection array is read in place."""
+    angles = _f64(angles)
     idx = np.ascontiguousarray(vox_idx, dtype=np.int64)
     out = np.zeros(len(idx))
+    if proj.dtype == np.float32 and proj.flags["C_CONTIGUOUS"]:
+        load().orc_siddon_adj_voxels_f32(C.byref(geo.c()), _pd(angles), len(angles),
+                                         proj.ctypes.data_as(C.POINTER(C.c_float)), _pi(idx), len(idx),
+                                         _pd(out))
+        return out
+    proj = _f64(proj)
     load().orc_siddon_adj_voxels(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), _pi(idx),
                                  len(idx), _pd(out))
     return out

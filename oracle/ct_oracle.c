@@ -429,8 +429,8 @@ void orc_siddon_adj(const orc_geom *g, const double *angles, int64_t na, const d
 /* The transpose of the Siddon projector at selected voxels only: for each voxel and angle, every
  * pixel whose ray can meet the voxel (bounding box of the 8 projected corners, widened by one
  * pixel) is traversed and the length it spends in that voxel is weighted by the pixel value. */
-void orc_siddon_adj_voxels(const orc_geom *g, const double *angles, int64_t na, const double *proj,
-                           const int64_t *vox_idx, int64_t n, double *out) {
+static void adj_voxels(const orc_geom *g, const double *angles, int64_t na, const double *proj,
+                       const float *projf, const int64_t *vox_idx, int64_t n, double *out) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
     const int64_t nx = g->nvox[0], ny = g->nvox[1];
 #pragma omp parallel
@@ -467,7 +467,8 @@ void orc_siddon_adj_voxels(const orc_geom *g, const double *angles, int64_t na, 
                 source_pos(g, angles[t], S);
                 for (int64_t b = b0; b <= b1; ++b)
                     for (int64_t a = a0; a <= a1; ++a) {
-                        double y = proj[(t * nv + b) * nu + a];
+                        const int64_t o = (t * nv + b) * nu + a;
+                        double y = projf ? (double)projf[o] : proj[o];
                         if (y == 0.0) continue;
                         pixel_pos(g, angles[t], (double)a, (double)b, P);
                         acc += y * siddon_core(g, S, P, NULL, NULL, NULL, 0.0, lin, NULL, &sc);
@@ -477,6 +478,17 @@ void orc_siddon_adj_voxels(const orc_geom *g, const double *angles, int64_t na, 
         }
         free(sc.buf);
     }
+}
+
+void orc_siddon_adj_voxels(const orc_geom *g, const double *angles, int64_t na, const double *proj,
+                           const int64_t *vox_idx, int64_t n, double *out) {
+    adj_voxels(g, angles, na, proj, NULL, vox_idx, n, out);
+}
+
+/* The same with FP32 projections read in place (each value widened exactly to FP64). */
+void orc_siddon_adj_voxels_f32(const orc_geom *g, const double *angles, int64_t na, const float *proj,
+                               const int64_t *vox_idx, int64_t n, double *out) {
+    adj_voxels(g, angles, na, NULL, proj, vox_idx, n, out);
 }
 
 void orc_interp_fwd(const orc_geom *g, const double *angles, int64_t na, const double *vol,

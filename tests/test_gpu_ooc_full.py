@@ -1,8 +1,8 @@
 """Out-of-core operators at the full size of the splitting workload: a 3072^3 FP32 volume and 3072
 projections of 3072^2 (108 GiB each, in pageable host memory, which the streamer stages through its
-own pinned ring) under a 32 GiB device cap.  One Siddon A x and one FDK A^T y (Algorithms 1 and 2),
-each checked on seeded samples of its output against the oracle, which reads the FP32 host arrays
-in place.
+own pinned ring) under a 32 GiB device cap.  One Siddon A x, one FDK A^T y and one exact-adjoint A^T y
+(Algorithms 1 and 2), each checked on seeded samples of its output against the oracle, which reads
+the FP32 host arrays in place.
 
 It needs about 220 GiB of host memory and several minutes, so it runs only when CT_FULL_OOC=1."""
 import os
@@ -58,6 +58,16 @@ def test_full_size_out_of_core(orc):
         ref = orc.bp_voxels(og, w.angles, proj.reshape(-1), vox, orc.W_FDK)
         e = rel_l2(vol.reshape(-1)[vox].astype(np.float64), ref)
         say(f"[ooc full] backprojection vs oracle on 48 voxels: rel L2 {e:.3e}")
+        assert e <= TOL_BP
+
+        say("[ooc full] exact-adjoint backprojection under the cap")
+        st = plan.backproject_host(pt, vt, "adjoint", cap_bytes=CAP)
+        say(f"[ooc full] exact adjoint: {st}")
+        assert st["n_slabs"] > 1
+        vox = inputs.sample_indices(vol.size, 32, 303)
+        ref = orc.siddon_adj_voxels(og, w.angles, proj, vox)
+        e = rel_l2(vol.reshape(-1)[vox].astype(np.float64), ref)
+        say(f"[ooc full] exact adjoint vs oracle on 32 voxels: rel L2 {e:.3e}")
         assert e <= TOL_BP
     finally:
         del vol, proj

@@ -544,3 +544,5 @@ def test_fp32_input_samplers_equal_fp64_on_widened_data(orc):
     for kind in (orc.W_FDK, orc.W_PM):
         np.testing.assert_array_equal(orc.bp_voxels(geo, angles, proj, vox, kind),
                                       orc.bp_voxels(geo, angles, proj.astype(np.float64), vox, kind))
+    np.testing.assert_array_equal(orc.siddon_adj_voxels(geo, angles, proj, vox),
+                                  orc.siddon_adj_voxels(geo, angles, proj.astype(np.float64), vox))
