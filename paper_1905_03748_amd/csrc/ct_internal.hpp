@@ -67,6 +67,7 @@ struct Slab {
     int64_t mem_lo, mem_n;
     bool first, last;  // the interpolated projector extends ownership to +-inf at the ends
     bool scratch_ok;   // the launch may allocate device scratch (resident calls; not under a cap)
+    bool zcol = false; // exact-adjoint backprojection only: the slab is column-major, [y][x][mem_n]
 };
 
 inline Slab full_slab(const ct_geometry &g) {
@@ -100,6 +101,11 @@ ct_status launch_zcols_piece(const void *src, ct_dtype vt, void *vz, int64_t nx,
                              int64_t slot0, int pads, hipStream_t st);
 // inverse: column-major slots -> [z][y][x]
 ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
+// slots [slot0, slot0 + zn) of column-major columns of nzp slots -> [zn][ny][nx]
+ct_status launch_zcols_inv_piece(const void *vz, ct_dtype vt, void *dst, int64_t nx, int64_t ny, int64_t zn,
+                                 int64_t nzp, int64_t slot0, hipStream_t st);
+// the exact adjoint runs its column kernel (which supports column-major slabs) for this geometry
+bool adj_col_ok(const ct_plan *p);
 inline int64_t zcol_elems(const ct_geometry &g) { return g.nVoxel[0] * g.nVoxel[1] * (g.nVoxel[2] + 2); }
 // whether the column Siddon walk is valid for angles [a0, a1) of the plan
 bool zcol_ok(const ct_plan *p, int64_t a0, int64_t a1);

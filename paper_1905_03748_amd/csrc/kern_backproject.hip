@@ -47,6 +47,7 @@ struct BpArgs {
     float pm_const;         // dx dy dz / (du dv) * DSD^2
     int32_t own_lo, own_hi; // voxels written: k in [own_lo, own_hi)
     int32_t mem_lo;         // slice at the volume pointer
+    int32_t zcol_n;         // exact adjoint: 0 = [z][y][x] volume; else column-major [y][x][zcol_n]
     int32_t accumulate;
     // exact adjoint (FP64 set-up)
     double ddx, ddy, ddz, dx0, dy0, dz0;
@@ -495,6 +496,10 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
     if (i >= A.nx) return;  // whole wave; no barriers follow
     const float zface0 = (float)(A.dz0 - 0.5 * A.ddz);  // lower face of voxel 0
     const float dz = A.dz;
+    // voxel k of this column: slices of a [z][y][x] volume, or consecutive slots of a column-major
+    // slab (lanes then read and write consecutive addresses)
+    const int64_t vbase = A.zcol_n ? ((int64_t)j * A.nx + i) * A.zcol_n - A.mem_lo : (int64_t)j * A.nx + i;
+    const int64_t vstep = A.zcol_n ? 1 : (int64_t)A.nx * A.ny;
     float acc[R], zl[R], zh[R];
     bool kin[R];
 #pragma unroll
@@ -503,7 +508,8 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
         kin[r] = k < A.own_hi;
         zl[r] = fmaf((float)k, dz, zface0);
         zh[r] = fmaf((float)(k + 1), dz, zface0);
-        acc[r] = (kin[r] && A.accumulate) ? to_f(vol[((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i]) : 0.0f;
+        const int64_t o = A.zcol_n ? vbase + k : vbase + (int64_t)(k - A.mem_lo) * vstep;
+        acc[r] = (kin[r] && A.accumulate) ? to_f(vol[o]) : 0.0f;
     }
     const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;  // column centre (mm)
     const float hx = 0.5f * A.dx, hy = 0.5f * A.dy;
@@ -584,7 +590,8 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
     for (int r = 0; r < R; ++r) {
         if (!kin[r]) continue;
         const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
-        vol[((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i] = from_f<TV>(acc[r]);
+        const int64_t o = A.zcol_n ? vbase + k : vbase + (int64_t)(k - A.mem_lo) * vstep;
+        vol[o] = from_f<TV>(acc[r]);
     }
 }
 
@@ -776,11 +783,20 @@ BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, con
     A.own_lo = (int32_t)slab.own_lo;
     A.own_hi = (int32_t)slab.own_hi;
     A.mem_lo = (int32_t)slab.mem_lo;
+    A.zcol_n = slab.zcol ? (int32_t)slab.mem_n : 0;
     A.accumulate = accumulate;
     return A;
 }
 
 }  // namespace
+
+bool adj_col_ok(const ct_plan *p) {
+#ifdef CT_NO_ADJ_COL
+    return false;
+#else
+    return std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2) <= 4;
+#endif
+}
 
 size_t adj_chunk_bytes_per_angle(const ct_geometry &g) {
     return (size_t)g.nDetector[0] * (size_t)(g.nDetector[1] + 2) * sizeof(float2);
@@ -794,6 +810,8 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     if (s != CT_OK) return s;
     const int64_t nzown = slab.own_hi - slab.own_lo;
     if (nzown <= 0) return CT_OK;
+    if (slab.zcol && (kind != CT_BP_ADJOINT || !adj_col_ok(p)))
+        return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's column kernel");
     BpArgs A = make_bp_args(p, tab, a0, a1, slab, accumulate);
     const int nzrun = kind == CT_BP_ADJOINT ? ADJ_NZ : BP_NZ;
     const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((nzown + nzrun - 1) / nzrun));
@@ -852,10 +870,21 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         }
         if (nr <= 4 && yq && qcap >= per_angle) {
             const int64_t kq = std::min<int64_t>(a1 - a0, (int64_t)(qcap / per_angle));
+            // voxels per lane R: a wave covers 64 R voxels of its column and sets up each (angle,
+            // detector column) once for them, which costs about 2/R of the per-voxel work; pick the
+            // R that minimises (voxels covered, idle lanes included) x (1 + 2/R)
+            int R = 8;
+            double best = DBL_MAX;
+            for (int r : {8, 6, 4, 2, 1}) {
+                const int64_t covered = (nzown + 64 * r - 1) / (64 * r) * (64 * r);
+                const double cost = (double)covered * (1.0 + 2.0 / r);
+                if (cost < best) {  // ties keep the larger R
+                    best = cost;
+                    R = r;
+                }
+            }
 #ifdef CT_ADJ_R
-            const int R = std::min<int>(CT_ADJ_R, nzown <= 64 ? 1 : (nzown <= 128 ? 2 : (nzown <= 256 ? 4 : 8)));
-#else
-            const int R = nzown <= 64 ? 1 : (nzown <= 128 ? 2 : (nzown <= 256 ? 4 : 8));
+            R = CT_ADJ_R;
 #endif
             const int zgroups = (int)((nzown + 64 * R - 1) / (64 * R));
             const int xblocks = (A.nx + 3) / 4;
@@ -884,6 +913,9 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         case 4:             \
             CT_ADJ(4, NN);  \
             break;          \
+        case 6:             \
+            CT_ADJ(6, NN);  \
+            break;          \
         default:            \
             CT_ADJ(8, NN);  \
             break;          \
@@ -903,7 +935,9 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
             return CT_OK;
         }
         if (own) CT_HIP(hipFreeAsync(own, st));
+        if (slab.zcol) return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's scratch");
 #endif
+        if (slab.zcol) return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's column kernel");
         CT_DISPATCH2(pt, TP, vt, TV,
                      hipLaunchKernelGGL((k_bp_adjoint<TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));
     }

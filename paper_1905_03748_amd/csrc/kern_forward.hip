@@ -582,17 +582,18 @@ __global__ __launch_bounds__(256) void k_zcols(const T *__restrict__ src, T *__r
     }
 }
 
-// column-major slots -> [z][y][x]
+// column-major slots -> [z][y][x]: slots slot0 .. slot0 + nz - 1 of columns of nzp slots go to
+// slices 0 .. nz - 1 of dst
 template <typename T>
-__global__ __launch_bounds__(256) void k_zcols_inv(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz) {
+__global__ __launch_bounds__(256) void k_zcols_inv(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz,
+                                                   int64_t nzp, int slot0) {
     __shared__ T tile[32][33];
     const int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int64_t nzp = (int64_t)nz + 2;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int z = z0 + tx, x = x0 + ty + r;
-        if (x < nx && z < nz) tile[ty + r][tx] = src[((int64_t)y * nx + x) * nzp + z + 1];
+        if (x < nx && z < nz) tile[ty + r][tx] = src[((int64_t)y * nx + x) * nzp + slot0 + z];
     }
     __syncthreads();
 #pragma unroll
@@ -971,10 +972,17 @@ ct_status launch_zcols_piece(const void *src, ct_dtype vt, void *vz, int64_t nx,
 }
 
 ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, int64_t ny, int64_t nz, hipStream_t st) {
-    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
+    return launch_zcols_inv_piece(vz, vt, vol, nx, ny, nz, nz + 2, 1, st);
+}
+
+ct_status launch_zcols_inv_piece(const void *vz, ct_dtype vt, void *dst, int64_t nx, int64_t ny, int64_t zn,
+                                 int64_t nzp, int64_t slot0, hipStream_t st) {
+    if (zn <= 0) return CT_OK;
+    if (slot0 < 0 || slot0 + zn > nzp) return fail(CT_ERR_ARG, "column-major piece outside its columns");
+    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((zn + 31) / 32), (unsigned)ny);
     CT_DISPATCH1(vt, T,
-                 hipLaunchKernelGGL((k_zcols_inv<T>), tg, dim3(256), 0, st, (const T *)vz, (T *)vol, (int)nx, (int)ny,
-                                    (int)nz));
+                 hipLaunchKernelGGL((k_zcols_inv<T>), tg, dim3(256), 0, st, (const T *)vz, (T *)dst, (int)nx, (int)ny,
+                                    (int)zn, nzp, (int)slot0));
     CT_HIP(hipGetLastError());
     return CT_OK;
 }

@@ -118,7 +118,9 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     const int nbuf = direction == 0 ? 3 : 2;
     L.halo = (direction == 0 && proj == CT_INTERP) ? 1 : 0;
     L.col = direction == 0 && proj == CT_SIDDON && zcol_ok(p, 0, na);
-    const int64_t extra = L.col ? 2 + ZSTAGE : 2 * L.halo;  // slices held besides the slab
+    // slices held besides the slab: the forward's column stage, the interpolated projector's halo,
+    // or the exact adjoint's stage for turning its column-major slab back into slices
+    const int64_t extra = L.col ? 2 + ZSTAGE : (direction == 2 && adj_col_ok(p) ? ZSTAGE : 2 * L.halo);
     // chunk size: enough rays (forward) or angles (backprojection) per launch to fill the device.
     // The exact adjoint's lanes run down voxel columns, so its slab accumulators are read and
     // written with a stride of one slice once per launch: it takes more angles per launch, each
@@ -374,8 +376,12 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     CT_HIP(hipStreamCreateWithFlags(&S.comp, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.h2d, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.d2h, hipStreamNonBlocking));
-    DevBuf slab, dbuf[2], adj;
+    // the exact adjoint accumulates into a column-major slab (its lanes run down the columns), which
+    // goes out through a stage of ZSTAGE slices
+    const bool zcol = kind == CT_BP_ADJOINT && adj_col_ok(p);
+    DevBuf slab, dbuf[2], adj, stage;
     CT_HIP(hipMalloc(&slab.p, L.h * slice));
+    if (zcol) CT_HIP(hipMalloc(&stage.p, ZSTAGE * slice));
     for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
     const size_t adj_bytes = (size_t)L.K * adj_chunk_bytes_per_angle(g);  // one transposed copy per chunk
     if (kind == CT_BP_ADJOINT) CT_HIP(hipMalloc(&adj.p, adj_bytes));
@@ -404,6 +410,7 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
         sl.mem_n = own_hi - own_lo;
         sl.first = sl.last = true;
         sl.scratch_ok = false;
+        sl.zcol = zcol;
         bool h2d_used[2] = {false, false};
         for (int64_t c = 0; c < nchunks; ++c) {
             const int j = (int)(c % 2);
@@ -441,26 +448,29 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
         }
         char *dst = (char *)h_vol + own_lo * slice;
         const size_t total = (own_hi - own_lo) * slice;
-        if (vol_pinned) {
-            CT_HIP(hipMemcpyAsync(dst, slab.p, total, hipMemcpyDeviceToHost, S.d2h));
-            CT_HIP(hipStreamSynchronize(S.d2h));
-        } else {
+        // device bytes [src, src + len) to host hdst, through the pinned ring when pageable
+        auto download = [&](const char *src, char *hdst, size_t len_all) -> ct_status {
+            if (vol_pinned) {
+                CT_HIP(hipMemcpyAsync(hdst, src, len_all, hipMemcpyDeviceToHost, S.d2h));
+                CT_HIP(hipStreamSynchronize(S.d2h));
+                return CT_OK;
+            }
             // pipelined: piece q goes D2H while piece q-1 is copied out of staging by the host
             size_t off = 0, prev_off = 0, prev_len = 0;
             int q = 0, prev_q = -1;
-            while (off < total || prev_q >= 0) {
+            while (off < len_all || prev_q >= 0) {
                 int cur = -1;
                 size_t len = 0;
-                if (off < total) {
-                    len = std::min(STAGE_PIECE, total - off);
-                    CT_HIP(hipMemcpyAsync(svol[q].p, (char *)slab.p + off, len, hipMemcpyDeviceToHost, S.d2h));
+                if (off < len_all) {
+                    len = std::min(STAGE_PIECE, len_all - off);
+                    CT_HIP(hipMemcpyAsync(svol[q].p, src + off, len, hipMemcpyDeviceToHost, S.d2h));
                     CT_HIP(hipEventRecord(ev_vol.e[q], S.d2h));
                     cur = q;
                 }
                 if (prev_q >= 0) {
                     CT_HIP(hipEventSynchronize(ev_vol.e[prev_q]));
                     auto b = clk::now();
-                    par_memcpy(dst + prev_off, svol[prev_q].p, prev_len);
+                    par_memcpy(hdst + prev_off, svol[prev_q].p, prev_len);
                     st.t_stage_s += secs(b, clk::now());
                 }
                 prev_q = cur;
@@ -469,6 +479,20 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
                 off += len;
                 q ^= 1;
             }
+            return CT_OK;
+        };
+        if (zcol) {
+            const int64_t nzown = own_hi - own_lo;
+            for (int64_t z0 = 0; z0 < nzown; z0 += ZSTAGE) {
+                const int64_t zn = std::min(ZSTAGE, nzown - z0);
+                if ((s = launch_zcols_inv_piece(slab.p, vt, stage.p, g.nVoxel[0], g.nVoxel[1], zn, nzown, z0,
+                                                S.comp)) != CT_OK)
+                    return s;
+                CT_HIP(hipStreamSynchronize(S.comp));
+                if ((s = download((const char *)stage.p, dst + z0 * slice, zn * slice)) != CT_OK) return s;
+            }
+        } else {
+            if ((s = download((const char *)slab.p, dst, total)) != CT_OK) return s;
         }
         st.bytes_d2h += (double)total;
         st.t_other_mem_s += secs(a, clk::now());

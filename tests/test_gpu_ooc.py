@@ -27,10 +27,11 @@ def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=
     halo = 1 if (direction == 0 and projector == "interp") else 0
     k = min(na, max(1, (8 << 20) // (nu * nv))) if direction == 0 else min(32 if direction == 1 else 128, na)
     kmin = max(1, k // 8)
-    # the exact adjoint also holds its transposed FP32 copy of each chunk; a Siddon forward holds
-    # its slab column-major (two zero slots per column) and an 8-slice stage
+    # the exact adjoint also holds its transposed FP32 copy of each chunk and an 8-slice stage for
+    # its column-major slab; a Siddon forward holds its slab column-major (two zero slots per
+    # column) and an 8-slice stage
     adj = kmin * nu * (nv + 2) * 8 if direction == 2 else 0
-    extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0)
+    extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0) + (8 if direction == 2 else 0)
     return RESERVE + nbuf * kmin * pangle + adj + (slices + extra) * slice_b
 
 

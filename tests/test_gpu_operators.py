@@ -80,6 +80,23 @@ def test_backprojection_parity(data, orc, name):
         assert e <= TOL_BP, (name, kind, e)
 
 
+@pytest.mark.parametrize("nz", [200, 300, 511, 700])
+def test_adjoint_column_heights(orc, nz):
+    """Tall, thin volumes whose column heights make the exact adjoint cover 4, 6, 8 and 6 voxels per
+    lane (with idle lanes in the last z group for 300, 511 and 700), against the oracle."""
+    w = inputs.Workload(f"tall{nz}", (12, 10, nz), (1.0, 1.1, 1.0), (24, nz + 24), (1.6, 1.55), 7, 0, 3,
+                        off_origin=(0.4, -0.3, 0.7))
+    w.angles = np.sort(np.random.default_rng(nz).uniform(0, 2 * np.pi, 7))
+    plan = Plan(w.geometry_dict(), w.angles)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    y = inputs.random_array(plan.proj_shape, 500 + nz, kind="uniform")
+    say(f"[adjoint column heights] nz={nz}")
+    v = plan.backproject(torch.from_numpy(y).to(DEV), "adjoint").cpu().numpy()
+    e = rel_l2(v, orc.siddon_adj(og, w.angles, y.astype(np.float64)))
+    say(f"   rel L2 = {e:.3e}")
+    assert e <= TOL_BP, (nz, e)
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_gpu_adjoint_dot_product(data, name):
     """<A x, y> = <x, A^T y> for the GPU pair, in FP64 over the FP32 outputs.  Non-negative x and y
