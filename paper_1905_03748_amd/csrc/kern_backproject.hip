@@ -474,7 +474,8 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
     }
 }
 
-template <typename TV, int R, int NR>
+// ZC: the volume is a column-major slab of A.zcol_n slots per column (else [z][y][x] slices)
+template <typename TV, int R, int NR, bool ZC>
 __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
                                                  int zgroups, int xblocks) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -496,10 +497,12 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
     if (i >= A.nx) return;  // whole wave; no barriers follow
     const float zface0 = (float)(A.dz0 - 0.5 * A.ddz);  // lower face of voxel 0
     const float dz = A.dz;
-    // voxel k of this column: slices of a [z][y][x] volume, or consecutive slots of a column-major
-    // slab (lanes then read and write consecutive addresses)
-    const int64_t vbase = A.zcol_n ? ((int64_t)j * A.nx + i) * A.zcol_n - A.mem_lo : (int64_t)j * A.nx + i;
-    const int64_t vstep = A.zcol_n ? 1 : (int64_t)A.nx * A.ny;
+    // voxel k of this column: a slice of a [z][y][x] volume, or a slot of a column-major slab
+    // (lanes then read and write consecutive addresses)
+    auto vidx = [&](int k) -> int64_t {
+        return ZC ? ((int64_t)j * A.nx + i) * A.zcol_n + (k - A.mem_lo)
+                  : ((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i;
+    };
     float acc[R], zl[R], zh[R];
     bool kin[R];
 #pragma unroll
@@ -508,7 +511,7 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
         kin[r] = k < A.own_hi;
         zl[r] = fmaf((float)k, dz, zface0);
         zh[r] = fmaf((float)(k + 1), dz, zface0);
-        const int64_t o = A.zcol_n ? vbase + k : vbase + (int64_t)(k - A.mem_lo) * vstep;
+        const int64_t o = vidx(k);
         acc[r] = (kin[r] && A.accumulate) ? to_f(vol[o]) : 0.0f;
     }
     const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;  // column centre (mm)
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
     for (int r = 0; r < R; ++r) {
         if (!kin[r]) continue;
         const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
-        const int64_t o = A.zcol_n ? vbase + k : vbase + (int64_t)(k - A.mem_lo) * vstep;
+        const int64_t o = vidx(k);
         vol[o] = from_f<TV>(acc[r]);
     }
 }
@@ -898,10 +901,12 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                 CT_DISPATCH1(pt, TP,
                              hipLaunchKernelGGL((k_adj_prep<TP>), pg, dim3(256), 0, st, (const TP *)pc, (float2 *)yq, Ac));
                 CT_HIP(hipGetLastError());
-#define CT_ADJ(RR, NN)                                                                                          \
-    CT_DISPATCH1(vt, TV,                                                                                        \
-                 hipLaunchKernelGGL((k_adj_col<TV, RR, NN>), ag, block, 0, st, (const float2 *)yq, (TV *)vol, Ac, \
-                                    zgroups, xblocks))
+#define CT_ADJ(RR, NN)                                                                                           \
+    CT_DISPATCH1(vt, TV,                                                                                         \
+                 if (slab.zcol) hipLaunchKernelGGL((k_adj_col<TV, RR, NN, true>), ag, block, 0, st,               \
+                                                   (const float2 *)yq, (TV *)vol, Ac, zgroups, xblocks);          \
+                 else hipLaunchKernelGGL((k_adj_col<TV, RR, NN, false>), ag, block, 0, st, (const float2 *)yq,    \
+                                         (TV *)vol, Ac, zgroups, xblocks))
 #define CT_ADJ_R(NN)        \
     switch (R) {            \
         case 1:             \
