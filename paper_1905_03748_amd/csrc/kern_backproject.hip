@@ -647,15 +647,23 @@ __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r
 }
 
 // The same update on the column-major copy ([y][x][slot], slot k + 1 = voxel k) with the residual
-// transposed to [u][v]: one wave per (column, 64 slices), lanes on consecutive slices, so both the
-// residual taps (consecutive v) and the volume (consecutive slots) are contiguous.
+// transposed to [u][v].
+#ifndef CT_SART_R
+#define CT_SART_R 8
+#endif
+constexpr int SART_R = CT_SART_R;  // voxels per lane of the column update
+
+// One wave per voxel column and group of 64 SART_R heights (lane = height, SART_R heights 64 apart):
+// the column's detector coordinate, FDK weight and column taps are set up once, and the lanes read
+// the transposed residual rT[u][v] at consecutive rows and update consecutive slots of the
+// column-major copy.
 __global__ __launch_bounds__(256) void k_sart_update_col(const float *__restrict__ rT, float *__restrict__ vz,
                                                          BpArgs A, float lambda, int zwaves) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
     const int64_t col = gw / zwaves;
-    const int kk = (int)(gw % zwaves) * 64 + (threadIdx.x & 63);
     if (col >= (int64_t)A.nx * A.ny) return;
+    const int kk0 = (int)(gw % zwaves) * 64 * SART_R + (threadIdx.x & 63);
     const int i = (int)(col % A.nx), j = (int)(col / A.nx);
     const float x = fmaf((float)i, A.dx, A.x0);
     const float y = fmaf((float)j, A.dy, A.y0);
@@ -670,25 +678,32 @@ __global__ __launch_bounds__(256) void k_sart_update_col(const float *__restrict
     const int ia = (int)af;
     const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
     const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
-    if ((wa0 == 0.0f && wa1 == 0.0f) || kk >= A.nz) return;
-    const int64_t c0 = (int64_t)clampi(ia, 0, A.nu - 1) * A.nv, c1 = (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
+    if (wa0 == 0.0f && wa1 == 0.0f) return;
+    const float *r0 = rT + (int64_t)clampi(ia, 0, A.nu - 1) * A.nv;
+    const float *r1 = rT + (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
     const float q = A.DSO * iL;
     const float w = q * q;
-    const float z = fmaf((float)kk, A.dz, A.z0);
-    const float bs = fmaf(m * z, A.inv_dv, A.bv0);
-    const float bf = floorf(bs);
-    const float fb = bs - bf;
-    const int ib = (int)bf;
-    const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-    const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
-    const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
-    const float v0 = fmaf(wa1, rT[c1 + b0], wa0 * rT[c0 + b0]);
-    const float v1 = fmaf(wa1, rT[c1 + b1], wa0 * rT[c0 + b1]);
-    const float num = w * fmaf(wb1, v1, wb0 * v0);
-    const float V = w * ((wa0 + wa1) * (wb0 + wb1));
-    if (V > 1e-6f) {
-        float *o = vz + col * (A.nz + 2) + kk + 1;
-        *o = fmaf(lambda, num / V, *o);
+    const float wva = w * (wa0 + wa1);
+    const float mv = m * A.inv_dv;
+    float *vc = vz + col * (A.nz + 2) + 1;
+#pragma unroll
+    for (int r = 0; r < SART_R; ++r) {
+        const int kk = kk0 + 64 * r;
+        if (kk >= A.nz) break;
+        const float z = fmaf((float)kk, A.dz, A.z0);
+        const float bs = fmaf(z, mv, A.bv0);
+        const float bf = floorf(bs);
+        const float fb = bs - bf;
+        const int ib = (int)bf;
+        const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+        const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+        const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
+        const float v0 = fmaf(wa1, r1[b0], wa0 * r0[b0]);
+        const float v1 = fmaf(wa1, r1[b1], wa0 * r0[b1]);
+        const float num = w * fmaf(wb1, v1, wb0 * v0);
+        const float V = wva * (wb0 + wb1);
+        // num / V through the hardware reciprocal (within 1 ulp)
+        if (V > 1e-6f) vc[kk] = fmaf(lambda, num * __builtin_amdgcn_rcpf(V), vc[kk]);
     }
 }
 
@@ -967,7 +982,7 @@ ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     BpArgs A = make_bp_args(p, tab, angle, angle + 1, full_slab(p->g), 1);
-    const int zwaves = (A.nz + 63) / 64;
+    const int zwaves = (A.nz + 64 * SART_R - 1) / (64 * SART_R);
     const int64_t waves = (int64_t)A.nx * A.ny * zwaves;
     hipLaunchKernelGGL(k_sart_update_col, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, rT, vz, A, lambda,
                        zwaves);
