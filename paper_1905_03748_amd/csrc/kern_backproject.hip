@@ -474,8 +474,14 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
     }
 }
 
-// ZC: the volume is a column-major slab of A.zcol_n slots per column (else [z][y][x] slices)
-template <typename TV, int R, int NR, bool ZC>
+// ZC: the volume is a column-major slab of A.zcol_n slots per column (else [z][y][x] slices).
+// ORD: no voxel of the launch has its lower face below the source plane z = 0 and its upper face
+// above it.  A voxel above the plane is only met by rows climbing from the source (v_b > 0), for
+// which zl / v_b < zh / v_b, and a voxel below only by falling rows, for which the order flips; the
+// kernel then orders each voxel's faces once (za, zb) instead of ordering the two parameters of
+// every row.  Rows of the other sign get an empty interval either way, so both forms give the same
+// bits.
+template <typename TV, int R, int NR, bool ZC, bool ORD>
 __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
                                                  int zgroups, int xblocks) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -503,14 +509,18 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
         return ZC ? ((int64_t)j * A.nx + i) * A.zcol_n + (k - A.mem_lo)
                   : ((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i;
     };
-    float acc[R], zl[R], zh[R];
+    // za, zb: the voxel's faces in the order its rows reach them (lower face first unless ORD and
+    // the voxel lies below the source plane)
+    float acc[R], za[R], zb[R];
     bool kin[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
         kin[r] = k < A.own_hi;
-        zl[r] = fmaf((float)k, dz, zface0);
-        zh[r] = fmaf((float)(k + 1), dz, zface0);
+        const float zl = fmaf((float)k, dz, zface0), zh = fmaf((float)(k + 1), dz, zface0);
+        const bool flip = ORD && zh <= 0.0f;
+        za[r] = flip ? zh : zl;
+        zb[r] = flip ? zl : zh;
         const int64_t o = vidx(k);
         acc[r] = (kin[r] && A.accumulate) ? to_f(vol[o]) : 0.0f;
     }
@@ -572,8 +582,10 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
             const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]
-                const float vlo = fminf(zl[r] * it0, zl[r] * it1);
+                // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]: the lowest
+                // v = z / t over the lower face and t in [t0, t1] (with ORD, za * it1 for voxels
+                // above the plane and zb * it0 for voxels below)
+                const float vlo = ORD ? fminf(za[r] * it1, zb[r] * it0) : fminf(za[r] * it0, za[r] * it1);
                 const float bl = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
                 // uniform column base plus an unsigned 32-bit byte offset of row bl
                 const float2 *cb = (const float2 *)((const char *)col + (uint32_t)((int)bl + 1) * 8u);
@@ -582,8 +594,9 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
                     const float2 w = cb[q];
                     // parameters relative to t0 (one rounding each), clipped to [0, T]: a row that
                     // stays inside the voxel gets exactly T
-                    const float tA = fmaf(zl[r], w.y, -t0), tB = fmaf(zh[r], w.y, -t0);
-                    const float lo = fmaxf(fminf(tA, tB), 0.0f), hi = fminf(fmaxf(tA, tB), T);
+                    const float tA = fmaf(za[r], w.y, -t0), tB = fmaf(zb[r], w.y, -t0);
+                    const float lo = ORD ? fmaxf(tA, 0.0f) : fmaxf(fminf(tA, tB), 0.0f);
+                    const float hi = ORD ? fminf(tB, T) : fminf(fmaxf(tA, tB), T);
                     acc[r] = fmaf(fmaxf(hi - lo, 0.0f), w.x, acc[r]);
                 }
             }
@@ -904,6 +917,13 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
 #ifdef CT_ADJ_R
             R = CT_ADJ_R;
 #endif
+            // no voxel of the launch straddles the source plane (the kernel's own FP32 faces)
+            bool ord = true;
+            {
+                const float dzf = A.dz, zf0 = (float)(A.dz0 - 0.5 * A.ddz);
+                for (int64_t k = slab.own_lo; k < slab.own_hi && ord; ++k)
+                    ord = !(std::fma((float)k, dzf, zf0) < 0.0f && std::fma((float)(k + 1), dzf, zf0) > 0.0f);
+            }
             const int zgroups = (int)((nzown + 64 * R - 1) / (64 * R));
             const int xblocks = (A.nx + 3) / 4;
             const dim3 ag((unsigned)((int64_t)zgroups * xblocks * A.ny));
@@ -916,12 +936,17 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                 CT_DISPATCH1(pt, TP,
                              hipLaunchKernelGGL((k_adj_prep<TP>), pg, dim3(256), 0, st, (const TP *)pc, (float2 *)yq, Ac));
                 CT_HIP(hipGetLastError());
-#define CT_ADJ(RR, NN)                                                                                           \
-    CT_DISPATCH1(vt, TV,                                                                                         \
-                 if (slab.zcol) hipLaunchKernelGGL((k_adj_col<TV, RR, NN, true>), ag, block, 0, st,               \
-                                                   (const float2 *)yq, (TV *)vol, Ac, zgroups, xblocks);          \
-                 else hipLaunchKernelGGL((k_adj_col<TV, RR, NN, false>), ag, block, 0, st, (const float2 *)yq,    \
-                                         (TV *)vol, Ac, zgroups, xblocks))
+#define CT_ADJ_L(RR, NN, Z, O)                                                                                  \
+    hipLaunchKernelGGL((k_adj_col<TV, RR, NN, Z, O>), ag, block, 0, st, (const float2 *)yq, (TV *)vol, Ac, zgroups, \
+                       xblocks)
+#define CT_ADJ(RR, NN)                                  \
+    CT_DISPATCH1(vt, TV, if (slab.zcol) {               \
+        if (ord) CT_ADJ_L(RR, NN, true, true);          \
+        else CT_ADJ_L(RR, NN, true, false);             \
+    } else {                                            \
+        if (ord) CT_ADJ_L(RR, NN, false, true);         \
+        else CT_ADJ_L(RR, NN, false, false);            \
+    })
 #define CT_ADJ_R(NN)        \
     switch (R) {            \
         case 1:             \
@@ -949,6 +974,7 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                 }
 #undef CT_ADJ_R
 #undef CT_ADJ
+#undef CT_ADJ_L
                 CT_HIP(hipGetLastError());
             }
             if (own) CT_HIP(hipFreeAsync(own, st));
