@@ -699,24 +699,35 @@ __global__ __launch_bounds__(256) void k_sart_update_col(const float *__restrict
     const float wva = w * (wa0 + wa1);
     const float mv = m * A.inv_dv;
     float *vc = vz + col * (A.nz + 2) + 1;
+    // all loads of the wave's SART_R heights first (indices clamped into the column), then the
+    // updates: the loads of every height are in flight together
+    float wb0[SART_R], wb1[SART_R], t00[SART_R], t01[SART_R], t10[SART_R], t11[SART_R], xo[SART_R];
 #pragma unroll
     for (int r = 0; r < SART_R; ++r) {
-        const int kk = kk0 + 64 * r;
-        if (kk >= A.nz) break;
+        const int kk = min(kk0 + 64 * r, A.nz - 1);
         const float z = fmaf((float)kk, A.dz, A.z0);
         const float bs = fmaf(z, mv, A.bv0);
         const float bf = floorf(bs);
         const float fb = bs - bf;
         const int ib = (int)bf;
-        const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-        const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+        wb0[r] = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+        wb1[r] = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
         const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
-        const float v0 = fmaf(wa1, r1[b0], wa0 * r0[b0]);
-        const float v1 = fmaf(wa1, r1[b1], wa0 * r0[b1]);
-        const float num = w * fmaf(wb1, v1, wb0 * v0);
-        const float V = wva * (wb0 + wb1);
+        t00[r] = r0[b0];
+        t10[r] = r1[b0];
+        t01[r] = r0[b1];
+        t11[r] = r1[b1];
+        xo[r] = vc[kk];
+    }
+#pragma unroll
+    for (int r = 0; r < SART_R; ++r) {
+        const int kk = kk0 + 64 * r;
+        const float v0 = fmaf(wa1, t10[r], wa0 * t00[r]);
+        const float v1 = fmaf(wa1, t11[r], wa0 * t01[r]);
+        const float num = w * fmaf(wb1[r], v1, wb0[r] * v0);
+        const float V = wva * (wb0[r] + wb1[r]);
         // num / V through the hardware reciprocal (within 1 ulp)
-        if (V > 1e-6f) vc[kk] = fmaf(lambda, num * __builtin_amdgcn_rcpf(V), vc[kk]);
+        if (kk < A.nz && V > 1e-6f) vc[kk] = fmaf(lambda, num * __builtin_amdgcn_rcpf(V), xo[r]);
     }
 }
 
