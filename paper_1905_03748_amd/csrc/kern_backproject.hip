@@ -595,9 +595,16 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
                     // parameters relative to t0 (one rounding each), clipped to [0, T]: a row that
                     // stays inside the voxel gets exactly T
                     const float tA = fmaf(za[r], w.y, -t0), tB = fmaf(zb[r], w.y, -t0);
-                    const float lo = ORD ? fmaxf(tA, 0.0f) : fmaxf(fminf(tA, tB), 0.0f);
-                    const float hi = ORD ? fminf(tB, T) : fminf(fmaxf(tA, tB), T);
-                    acc[r] = fmaf(fmaxf(hi - lo, 0.0f), w.x, acc[r]);
+                    float len;
+                    if (ORD) {
+                        // tA <= tB for the rows that can meet the voxel; rows of the other sign have
+                        // both parameters below 0, which clamp to the same value
+                        len = __builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T);
+                    } else {
+                        const float lo = fmaxf(fminf(tA, tB), 0.0f), hi = fminf(fmaxf(tA, tB), T);
+                        len = fmaxf(hi - lo, 0.0f);
+                    }
+                    acc[r] = fmaf(len, w.x, acc[r]);
                 }
             }
         }
