@@ -103,6 +103,25 @@ def test_ooc_16bit_storage(case, orc):
     assert rel_l2(out.float().numpy(), ref) <= 4 * 2.0 ** -11
 
 
+def test_ooc_adjoint_16bit_volume(case, orc):
+    """The exact adjoint out of core into an FP16 volume: its column-major slab holds FP16 partial
+    sums between angle chunks, so the result is within a few FP16 roundings of the oracle."""
+    w, vol, y = case
+    plan = Plan(w.geometry_dict(), w.angles)
+    cap = _cap_for(plan, 9, 2, dt=torch.float16)
+    info = plan.ooc_plan(2, vol_dtype=torch.float16, cap_bytes=cap)
+    say(f"[ooc adjoint 16-bit] plan={info}")
+    assert info["n_slabs"] > 1
+    out = torch.zeros(plan.vol_shape, dtype=torch.float16)
+    st = plan.backproject_host(torch.from_numpy(y), out, "adjoint", cap_bytes=cap)
+    assert st["n_slabs"] == info["n_slabs"]
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    ref = orc.siddon_adj(og, w.angles, y.astype(np.float64))
+    e = rel_l2(out.float().numpy(), ref)
+    say(f"   rel L2 vs oracle {e:.3e}")
+    assert e <= 4 * 2.0 ** -11
+
+
 def test_ooc_cap_errors(case):
     w, vol, y = case
     plan = Plan(w.geometry_dict(), w.angles)
