@@ -172,6 +172,33 @@ def serving_bench(dev, n_requests=12, seed=7, slots=8):
                       "peak_hbm_gib": round(st["peak_hbm_bytes"] / 2 ** 30, 2)}
     out["batched_vs_one_at_a_time"] = round(out[best]["throughput_req_s"] / cap, 3)
     out["best_batched_mode"] = best
+    # a second, separate mix of small requests, which do not fill the GPU on their own
+    small = []
+    for r in range(24):
+        n, na = (128, 90) if r % 2 == 0 else (128, 180)
+        w = inputs.workload(f"serve_{n}", n_angles=na, seed=2000 + r)
+        x = inputs.voxelize_torch(w, device=dev)
+        plan = Plan(w.geometry_dict(), w.angles)
+        b = plan.forward(x, "siddon").cpu().pin_memory()
+        plan.close()
+        small.append(Request(w.geometry_dict(), w.angles, b, niter=10, tv_steps=5, tv_lambda=0.01, rid=100 + r))
+    torch.cuda.synchronize()
+    sm = {"requests": len(small), "mix": "128^3 x 90 and 128^3 x 180, alternating; same per-request work"}
+    for name, nslots in (("one_at_a_time", 1), ("batched_4", 4), ("batched_8", 8)):
+        srv = Server(budget, max_slots=nslots, device=dev)
+        t0 = time.perf_counter()
+        for q in small:
+            srv.submit(clone(q))
+        srv.drain()
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        log(f"[bench] serving small requests {name}: {dt:.2f} s")
+        sm[name] = {"slots": nslots, "wall_s": round(dt, 3), "throughput_req_s": round(len(small) / dt, 3),
+                    "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3), "max_active": st["max_active"]}
+    sm["batched_vs_one_at_a_time"] = round(max(sm["batched_4"]["throughput_req_s"], sm["batched_8"]["throughput_req_s"])
+                                           / sm["one_at_a_time"]["throughput_req_s"], 3)
+    out["small_requests"] = sm
     return out
 
 
