@@ -16,11 +16,11 @@ Algorithms (``algos.py``, numpy over the operators): CGLS, SART, TV steepest des
 from .core import (Geometry, W_FDK, W_PM, bp, bp_coverage, bp_transpose, bp_voxels, get_threads,
                    interp_fwd, interp_ray, interp_rays, ray_endpoints, set_threads, siddon_adj,
                    siddon_adj_voxels, siddon_fwd, siddon_ray, siddon_rays, load)
-from .algos import cgls, sart, tv_grad, tv_value, tv_steps
+from .algos import cgls, os_sart, sart, tv_grad, tv_value, tv_steps
 
 __all__ = [
     "Geometry", "W_FDK", "W_PM", "bp", "bp_coverage", "bp_transpose", "bp_voxels", "get_threads",
     "interp_fwd", "interp_ray", "interp_rays", "ray_endpoints", "set_threads", "siddon_adj",
-    "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "load", "cgls", "sart",
+    "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "load", "cgls", "os_sart", "sart",
     "tv_grad", "tv_value", "tv_steps",
 ]

@@ -85,6 +85,34 @@ def sart(geo: core.Geometry, angles, b, niter, lam=1.0, x0=None):
     return x
 
 
+def os_sart(geo: core.Geometry, angles, b, niter, block, lam=1.0, x0=None):
+    """OS-SART, the ordered-subset form of SART that Section 3.2 runs: the angles, in natural order,
+    are cut into consecutive subsets of `block` angles (the last one may be shorter), and each
+    subset S makes one update
+
+        W_p = 1/(A_S 1)_p,  V_j = (B_S 1)_j,  x += lam * B_S(W * (b_S - A_S x)) / V
+
+    with the thresholds of `sart`.  block = 1 is SART; block = number of angles is one SIRT step
+    per sweep.
+    """
+    angles = np.asarray(angles, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(geo.vol_shape) if x0 is None else np.array(x0, dtype=np.float64)
+    ones_vol = np.ones(geo.vol_shape)
+    dmin = min(geo.dVoxel)
+    for _ in range(niter):
+        for s0 in range(0, len(angles), block):
+            th = angles[s0:s0 + block]
+            chord = core.siddon_fwd(geo, th, ones_vol)
+            W = np.where(chord > SART_RAY_FRACTION * dmin, 1.0 / np.where(chord > 0, chord, 1.0), 0.0)
+            r = W * (b[s0:s0 + block] - core.siddon_fwd(geo, th, x))
+            num = core.bp(geo, th, r, core.W_FDK)
+            V = core.bp(geo, th, np.ones_like(r), core.W_FDK)
+            upd = np.where(V > SART_VOXEL_MIN, num / np.where(V > 0, V, 1.0), 0.0)
+            x = x + lam * upd
+    return x
+
+
 def tv_grad(x, eps=1e-8):
     """Gradient of TV_eps(x) = sum_j sqrt(|D x_j|^2 + eps) with forward differences on a unit grid
     and zero difference at the last index of each axis (Neumann boundary)."""

@@ -480,6 +480,47 @@ def test_sart_matches_dense_per_angle_update(orc):
     assert r[1] < r[0] and r[2] < r[1] and r[3] < r[2], r
 
 
+def test_os_sart_matches_dense_subset_update(orc):
+    """OS-SART against explicit subset matrices: subsets of 4 angles (the last one of 2), one subset
+    of all 6 angles (a SIRT step), and block = 1 equal to SART."""
+    geo = _geo(orc, nVoxel=(8, 8, 8), nDetector=(10, 10), dDetector=(1.6, 1.6))
+    angles = inputs.uniform_angles(6)
+    nvox = 512
+    rng = np.random.default_rng(52)
+    xt = rng.uniform(0, 1, geo.vol_shape)
+    b = orc.siddon_fwd(geo, angles, xt)
+    A_t, B_t = [], []
+    for t in range(6):
+        cols = []
+        for j in range(nvox):
+            e = np.zeros(nvox)
+            e[j] = 1
+            cols.append(orc.siddon_fwd(geo, angles[t:t + 1], e.reshape(geo.vol_shape)).ravel())
+        A_t.append(np.stack(cols, 1))
+        rows = []
+        for p in range(100):
+            e = np.zeros(100)
+            e[p] = 1
+            rows.append(orc.bp(geo, angles[t:t + 1], e.reshape(1, 10, 10), orc.W_FDK).ravel())
+        B_t.append(np.stack(rows, 1))
+    for block in (4, 6):
+        x = np.zeros(nvox)
+        for it in range(2):
+            for s0 in range(0, 6, block):
+                S = range(s0, min(6, s0 + block))
+                A_S = np.concatenate([A_t[t] for t in S], 0)
+                B_S = np.concatenate([B_t[t] for t in S], 1)
+                bS = np.concatenate([b[t].ravel() for t in S])
+                c = A_S @ np.ones(nvox)
+                W = np.where(c > 1e-2 * 1.0, 1 / np.where(c > 0, c, 1), 0)
+                V = B_S @ np.ones(len(bS))
+                num = B_S @ (W * (bS - A_S @ x))
+                x = x + 0.8 * np.where(V > 1e-6, num / np.where(V > 0, V, 1), 0)
+        got = orc.os_sart(geo, angles, b, 2, block, lam=0.8)
+        np.testing.assert_allclose(got.ravel(), x, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(orc.os_sart(geo, angles, b, 2, 1), orc.sart(geo, angles, b, 2))
+
+
 # --------------------------------------------------------------------------------------------
 # C8 TV: T1 finite differences, T2 constant, T3 1-D step edge, T4 descent
 
