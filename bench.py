@@ -50,9 +50,8 @@ def recorded_traffic(kernel_key):
     return rec
 
 
-def A_sart_ws(plan):
-    from paper_1905_03748_amd import _abi
-    return _abi.ct_sart_workspace_bytes(plan.handle)
+def A_sart_ws(plan, block=1):
+    return plan.sart_workspace_bytes(block)
 
 
 def log(*a):
@@ -445,6 +444,9 @@ def main():
         ex["cgls_iter_ms"] = round((t4 - t1) / 3, 3)
         sws = torch.empty(A_sart_ws(plan), dtype=torch.uint8, device=dev)
         ex["sart_sweep_ms"] = round(timed(lambda: plan.sart(p, 1, x=xs.zero_(), workspace=sws), 1), 3)
+        ows = torch.empty(A_sart_ws(plan, 10), dtype=torch.uint8, device=dev)
+        ex["os_sart10_sweep_ms"] = round(timed(lambda: plan.sart(p, 1, x=xs.zero_(), block=10, workspace=ows), 1), 3)
+        del ows
         from paper_1905_03748_amd.operators import tv_steps, tv_workspace_bytes
         tws = torch.empty(tv_workspace_bytes(plan.geometry), dtype=torch.uint8, device=dev)
         xt = x.clone()

@@ -196,12 +196,17 @@ ct_status ct_cgls_host_workspace_bytes(const ct_plan *plan, uint64_t *bytes);
 ct_status ct_cgls_host(ct_plan *plan, const float *h_b, float *h_x, int32_t niter, double *resid,
                        void *h_workspace, uint64_t device_cap_bytes, ct_ooc_stats *stats);
 
-/* SART (Andersen and Kak; Section 3.2 uses its ordered-subset form) with A = CT_SIDDON and
- * B = CT_BP_FDK, one angle per update (block must be 1), angles in natural order, relaxation
- * lambda:  x += lambda B_t(W (b_t - A_t x)) / V  with W = 1/(A_t 1) for rays whose chord through
- * the grid exceeds 1e-2 min(dVoxel) (others weigh 0) and V = B_t 1, voxels with V <= 1e-6 left
- * unchanged.  d_b and d_x as ct_cgls; FP32 storage only. */
-ct_status ct_sart_workspace_bytes(const ct_plan *plan, uint64_t *bytes);
+/* OS-SART, the ordered-subset SART that Section 3.2 runs (Andersen and Kak's SART when
+ * block = 1), with A = CT_SIDDON and B = CT_BP_FDK.  The angles, in natural order, are cut into
+ * consecutive subsets of `block` angles (the last one may be shorter); each subset S makes one
+ * update with relaxation lambda:
+ *   x += lambda B_S(W (b_S - A_S x)) / V
+ * with W = 1/(A_S 1) for rays whose chord through the grid exceeds 1e-2 min(dVoxel) (others weigh
+ * 0) and V = B_S 1, voxels with V <= 1e-6 left unchanged.  block: 1 .. n_angles (n_angles gives one
+ * SIRT step per sweep).  d_b and d_x as ct_cgls; FP32 storage only.  The workspace grows with block
+ * (two projection-sized buffers per angle of a subset).  Errors: CT_ERR_ARG for a NULL pointer,
+ * niter < 0, block outside [1, n_angles] or a non-finite lambda. */
+ct_status ct_sart_workspace_bytes(const ct_plan *plan, int32_t block, uint64_t *bytes);
 ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, double lambda,
                   int32_t block, void *d_workspace, void *stream);
 

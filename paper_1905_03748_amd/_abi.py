@@ -67,7 +67,7 @@ SIGNATURES = {
     "ct_cgls": [_P, _P, _INT, _P, _INT, _I32, _P, _P, _P],
     "ct_cgls_host_workspace_bytes": [_P, C.POINTER(_U64)],
     "ct_cgls_host": [_P, _P, _P, _I32, _P, _P, _U64, C.POINTER(ct_ooc_stats)],
-    "ct_sart_workspace_bytes": [_P, C.POINTER(_U64)],
+    "ct_sart_workspace_bytes": [_P, _I32, C.POINTER(_U64)],
     "ct_sart": [_P, _P, _P, _I32, _D, _I32, _P, _P],
     "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_tv_steps": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
@@ -189,9 +189,9 @@ def ct_cgls_host(plan, h_b, h_x, niter, h_resid, h_workspace, device_cap_bytes) 
     return s
 
 
-def ct_sart_workspace_bytes(plan) -> int:
+def ct_sart_workspace_bytes(plan, block=1) -> int:
     b = _U64()
-    _check(lib().ct_sart_workspace_bytes(plan, C.byref(b)))
+    _check(lib().ct_sart_workspace_bytes(plan, block, C.byref(b)))
     return b.value
 
 

@@ -236,9 +236,11 @@ ct_status ct_cgls_host(ct_plan *plan, const float *h_b, float *h_x, int32_t nite
     return cgls_host_run(plan, h_b, h_x, niter, resid, h_workspace, device_cap_bytes, stats);
 }
 
-ct_status ct_sart_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
+ct_status ct_sart_workspace_bytes(const ct_plan *plan, int32_t block, uint64_t *bytes) {
     if (!plan || !bytes) return fail(CT_ERR_ARG, "ct_sart_workspace_bytes: null pointer");
-    *bytes = sart_workspace(plan);
+    if (block < 1 || block > (int64_t)plan->angles.size())
+        return fail(CT_ERR_ARG, "ct_sart_workspace_bytes: block must be in [1, n_angles]");
+    *bytes = sart_workspace(plan, block);
     return CT_OK;
 }
 
@@ -246,9 +248,10 @@ ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, doub
                   void *d_workspace, void *stream) {
     if (!plan || !d_b || !d_x) return fail(CT_ERR_ARG, "ct_sart: null pointer");
     if (niter < 0) return fail(CT_ERR_ARG, "ct_sart: niter must be >= 0");
-    if (block != 1) return fail(CT_ERR_ARG, "ct_sart: only block = 1 (one angle per update) is supported");
+    if (block < 1 || block > (int64_t)plan->angles.size())
+        return fail(CT_ERR_ARG, "ct_sart: block must be in [1, n_angles]");
     if (!std::isfinite(lambda)) return fail(CT_ERR_ARG, "ct_sart: lambda must be finite");
-    return sart_run(plan, d_b, d_x, niter, lambda, d_workspace, (hipStream_t)stream);
+    return sart_run(plan, d_b, d_x, niter, lambda, block, d_workspace, (hipStream_t)stream);
 }
 
 ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes) {

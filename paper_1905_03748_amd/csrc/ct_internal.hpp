@@ -126,18 +126,20 @@ size_t dot_partials_count();
 ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter,
                    double *resid, void *work, hipStream_t st);
 size_t cgls_workspace(const ct_plan *p, ct_dtype vt, ct_dtype pt);
-ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, void *work,
+ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, int32_t block, void *work,
                    hipStream_t st);
-size_t sart_workspace(const ct_plan *p);
+size_t sart_workspace(const ct_plan *p, int32_t block);
 ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work,
                  hipStream_t st);
 size_t tv_workspace(const ct_geometry &g);
 
 // SART pieces (kern_backproject.hip / kern_forward.hip)
 ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hipStream_t st);
-ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda, hipStream_t st);
-// the same update on the column-major copy (launch_zcols layout), residual rT in [u][v] layout
-ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t angle, float lambda,
+// one (OS-)SART update over the angle subset [a0, a1): r holds its weighted residuals [a1-a0][v][u]
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t a0, int64_t a1, float lambda,
+                             hipStream_t st);
+// the same update on the column-major copy (launch_zcols layout), residuals rT in [a1-a0][u][v] layout
+ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t a0, int64_t a1, float lambda,
                                  hipStream_t st);
 
 // Out-of-core (ooc.cpp)

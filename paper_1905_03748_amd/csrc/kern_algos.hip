@@ -1,6 +1,6 @@
 // Device-resident iterative algorithms built on the operators: CGLS (FP64 inner products and
 // residual recurrence, scalars kept in device memory so an iteration never waits on the host),
-// SART (one angle per update) and TV steepest descent.  Reductions use a fixed partition
+// OS-SART (SART with one angle per update when block = 1) and TV steepest descent.  Reductions use a fixed partition
 // (DOT_BLOCKS contiguous ranges, fixed wave/block trees, fixed final sum), so results are bitwise
 // repeatable regardless of what else shares the device.
 #include <cmath>
@@ -136,13 +136,19 @@ __global__ void k_sart_resid(const float *__restrict__ b, const float *__restric
     }
 }
 
-// The same residual written transposed, rT[u][v], through 32 x 32 LDS tiles
+// The same residual written transposed, rT[u][v], through 32 x 32 LDS tiles; blockIdx.z is the
+// angle within the subset (each array advances by one projection per angle)
 __global__ __launch_bounds__(256) void k_sart_resid_t(const float *__restrict__ b, const float *__restrict__ chord,
                                                       const float *__restrict__ r, float *__restrict__ rT, float thr,
                                                       int nu, int nv) {
     __shared__ float tile[32][33];
     const int u0 = blockIdx.x * 32, v0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t po = (int64_t)blockIdx.z * nu * nv;
+    b += po;
+    chord += po;
+    r += po;
+    rT += po;
 #pragma unroll
     for (int k = 0; k < 32; k += 8) {
         const int u = u0 + tx, v = v0 + ty + k;
@@ -353,24 +359,29 @@ ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
 // ---------------------------------------------------------------------------------------------
 // SART
 
-// chords of every ray, one angle's residual (and its transpose), and a column-major copy of x
+// chords of every ray, one subset's residuals (and their transposes), and a column-major copy of x
 // that the sweep projects from and updates in place (x is restored from it at the end)
-size_t sart_workspace(const ct_plan *p) {
+size_t sart_workspace(const ct_plan *p, int32_t block) {
     const ct_geometry &g = p->g;
     const size_t pix = (size_t)g.nDetector[0] * g.nDetector[1];
-    return align256(pix * p->angles.size() * 4) + 2 * align256(pix * 4) + align256((size_t)zcol_elems(g) * 4);
+    const size_t nb = (size_t)std::max<int32_t>(block, 1);
+    return align256(pix * p->angles.size() * 4) + 2 * align256(pix * nb * 4) + align256((size_t)zcol_elems(g) * 4);
 }
 
-ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, void *work, hipStream_t st) {
+// OS-SART: the angles in natural order, cut into consecutive subsets of `block` (the last one may be
+// shorter); each subset projects, forms its weighted residuals and makes one update (block = 1 is
+// SART)
+ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, int32_t block, void *work,
+                   hipStream_t st) {
     const ct_geometry &g = p->g;
     const int64_t na = (int64_t)p->angles.size();
     const int64_t pix = g.nDetector[0] * g.nDetector[1];
     Workspace ws;
-    ct_status s = ws.acquire(work, sart_workspace(p), st);
+    ct_status s = ws.acquire(work, sart_workspace(p, block), st);
     if (s != CT_OK) return s;
     float *chord = (float *)ws.take(pix * na * 4);
-    float *r = (float *)ws.take(pix * 4);
-    float *rT = (float *)ws.take(pix * 4);
+    float *r = (float *)ws.take(pix * block * 4);
+    float *rT = (float *)ws.take(pix * block * 4);
     float *xz = (float *)ws.take((size_t)zcol_elems(g) * 4);
     const float thr = (float)(1e-2 * std::fmin(g.dVoxel[0], std::fmin(g.dVoxel[1], g.dVoxel[2])));
     const int nu = (int)g.nDetector[0], nv = (int)g.nDetector[1];
@@ -379,26 +390,28 @@ ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lam
     if (zcol_ok(p, 0, na)) {
         // the sweep works on the column-major copy only
         CK(launch_zcols(x, CT_F32, xz, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
-        const dim3 tg((unsigned)((nu + 31) / 32), (unsigned)((nv + 31) / 32));
         for (int32_t it = 0; it < niter; ++it) {
-            for (int64_t t = 0; t < na; ++t) {
-                CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st, xz));
-                hipLaunchKernelGGL(k_sart_resid_t, tg, dim3(256), 0, st, (const float *)b + t * pix, chord + t * pix,
+            for (int64_t t0 = 0; t0 < na; t0 += block) {
+                const int64_t t1 = std::min<int64_t>(na, t0 + block);
+                CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t0, t1, full, st, xz));
+                const dim3 tg((unsigned)((nu + 31) / 32), (unsigned)((nv + 31) / 32), (unsigned)(t1 - t0));
+                hipLaunchKernelGGL(k_sart_resid_t, tg, dim3(256), 0, st, (const float *)b + t0 * pix, chord + t0 * pix,
                                    (const float *)r, rT, thr, nu, nv);
                 CT_HIP(hipGetLastError());
-                CK(launch_sart_update_col(p, rT, xz, t, (float)lambda, st));
+                CK(launch_sart_update_col(p, rT, xz, t0, t1, (float)lambda, st));
             }
         }
         CK(launch_zcols_inv(xz, CT_F32, x, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
         return CT_OK;
     }
     for (int32_t it = 0; it < niter; ++it) {
-        for (int64_t t = 0; t < na; ++t) {
-            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t, t + 1, full, st));
-            hipLaunchKernelGGL(k_sart_resid, dim3(ew_grid(pix)), dim3(EW_THREADS), 0, st, (const float *)b + t * pix,
-                               chord + t * pix, r, thr, pix);
+        for (int64_t t0 = 0; t0 < na; t0 += block) {
+            const int64_t t1 = std::min<int64_t>(na, t0 + block);
+            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t0, t1, full, st));
+            hipLaunchKernelGGL(k_sart_resid, dim3(ew_grid((t1 - t0) * pix)), dim3(EW_THREADS), 0, st,
+                               (const float *)b + t0 * pix, chord + t0 * pix, r, thr, (t1 - t0) * pix);
             CT_HIP(hipGetLastError());
-            CK(launch_sart_update(p, r, (float *)x, t, (float)lambda, st));
+            CK(launch_sart_update(p, r, (float *)x, t0, t1, (float)lambda, st));
         }
     }
     return CT_OK;

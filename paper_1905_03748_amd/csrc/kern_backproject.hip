@@ -628,40 +628,51 @@ __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r
     if (i >= A.nx || j >= A.ny) return;
     const float x = fmaf((float)i, A.dx, A.x0);
     const float y = fmaf((float)j, A.dy, A.y0);
-    const AngleGeo &G = A.tab[A.a0];
-    const float c = (float)G.c, s = (float)G.s;
-    const float Ld = A.DSO - (x * c + y * s);
-    const float iL = 1.0f / Ld;
-    const float m = A.DSD * iL;
-    const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
-    const float af = floorf(as);
-    const float fa = as - af;
-    const int ia = (int)af;
-    const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
-    const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
-    if (wa0 == 0.0f && wa1 == 0.0f) return;
-    const int ia0 = clampi(ia, 0, A.nu - 1), ia1 = clampi(ia + 1, 0, A.nu - 1);
-    const float q = A.DSO * iL;
-    const float w = q * q;
+    const int64_t pix = (int64_t)A.nu * A.nv;
+    // sums over the subset's angles, in angle order
+    float num[BP_NZ], V[BP_NZ];
+#pragma unroll
+    for (int k = 0; k < BP_NZ; ++k) num[k] = V[k] = 0.0f;
+    for (int t = 0; t < A.nang; ++t) {
+        const AngleGeo &G = A.tab[A.a0 + t];
+        const float c = (float)G.c, s = (float)G.s;
+        const float Ld = A.DSO - (x * c + y * s);
+        const float iL = 1.0f / Ld;
+        const float m = A.DSD * iL;
+        const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
+        const float af = floorf(as);
+        const float fa = as - af;
+        const int ia = (int)af;
+        const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
+        const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
+        if (wa0 == 0.0f && wa1 == 0.0f) continue;
+        const int ia0 = clampi(ia, 0, A.nu - 1), ia1 = clampi(ia + 1, 0, A.nu - 1);
+        const float q = A.DSO * iL;
+        const float w = q * q;
+        const float *rt = r + t * pix;
+#pragma unroll
+        for (int k = 0; k < BP_NZ; ++k) {
+            const int kk = min(kb + k, A.nz - 1);
+            const float z = fmaf((float)kk, A.dz, A.z0);
+            const float bs = fmaf(m * z, A.inv_dv, A.bv0);
+            const float bf = floorf(bs);
+            const float fb = bs - bf;
+            const int ib = (int)bf;
+            const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+            const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+            const int r0 = clampi(ib, 0, A.nv - 1) * A.nu, r1 = clampi(ib + 1, 0, A.nv - 1) * A.nu;
+            const float v0 = fmaf(wa1, rt[r0 + ia1], wa0 * rt[r0 + ia0]);
+            const float v1 = fmaf(wa1, rt[r1 + ia1], wa0 * rt[r1 + ia0]);
+            num[k] += w * fmaf(wb1, v1, wb0 * v0);
+            V[k] += w * ((wa0 + wa1) * (wb0 + wb1));
+        }
+    }
+#pragma unroll
     for (int k = 0; k < BP_NZ; ++k) {
         const int kk = kb + k;
-        if (kk >= A.nz) break;
-        const float z = fmaf((float)kk, A.dz, A.z0);
-        const float bs = fmaf(m * z, A.inv_dv, A.bv0);
-        const float bf = floorf(bs);
-        const float fb = bs - bf;
-        const int ib = (int)bf;
-        const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-        const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
-        const int r0 = clampi(ib, 0, A.nv - 1) * A.nu, r1 = clampi(ib + 1, 0, A.nv - 1) * A.nu;
-        const float v0 = fmaf(wa1, r[r0 + ia1], wa0 * r[r0 + ia0]);
-        const float v1 = fmaf(wa1, r[r1 + ia1], wa0 * r[r1 + ia0]);
-        const float num = w * fmaf(wb1, v1, wb0 * v0);
-        const float V = w * ((wa0 + wa1) * (wb0 + wb1));
-        if (V > 1e-6f) {
+        if (kk < A.nz && V[k] > 1e-6f) {
             const int64_t o = ((int64_t)kk * A.ny + j) * A.nx + i;
-            const float nv = fmaf(lambda, num / V, vol[o]);
-            vol[o] = nv;
+            vol[o] = fmaf(lambda, num[k] / V[k], vol[o]);
         }
     }
 }
@@ -687,54 +698,67 @@ __global__ __launch_bounds__(256) void k_sart_update_col(const float *__restrict
     const int i = (int)(col % A.nx), j = (int)(col / A.nx);
     const float x = fmaf((float)i, A.dx, A.x0);
     const float y = fmaf((float)j, A.dy, A.y0);
-    const AngleGeo &G = A.tab[A.a0];
-    const float c = (float)G.c, s = (float)G.s;
-    const float Ld = A.DSO - (x * c + y * s);
-    const float iL = 1.0f / Ld;
-    const float m = A.DSD * iL;
-    const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
-    const float af = floorf(as);
-    const float fa = as - af;
-    const int ia = (int)af;
-    const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
-    const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
-    if (wa0 == 0.0f && wa1 == 0.0f) return;
-    const float *r0 = rT + (int64_t)clampi(ia, 0, A.nu - 1) * A.nv;
-    const float *r1 = rT + (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
-    const float q = A.DSO * iL;
-    const float w = q * q;
-    const float wva = w * (wa0 + wa1);
-    const float mv = m * A.inv_dv;
+    const int64_t pix = (int64_t)A.nu * A.nv;
     float *vc = vz + col * (A.nz + 2) + 1;
-    // all loads of the wave's SART_R heights first (indices clamped into the column), then the
-    // updates: the loads of every height are in flight together
-    float wb0[SART_R], wb1[SART_R], t00[SART_R], t01[SART_R], t10[SART_R], t11[SART_R], xo[SART_R];
+    // the voxels' values are read first, so their loads overlap the first angle's taps
+    float xo[SART_R];
 #pragma unroll
-    for (int r = 0; r < SART_R; ++r) {
-        const int kk = min(kk0 + 64 * r, A.nz - 1);
-        const float z = fmaf((float)kk, A.dz, A.z0);
-        const float bs = fmaf(z, mv, A.bv0);
-        const float bf = floorf(bs);
-        const float fb = bs - bf;
-        const int ib = (int)bf;
-        wb0[r] = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-        wb1[r] = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
-        const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
-        t00[r] = r0[b0];
-        t10[r] = r1[b0];
-        t01[r] = r0[b1];
-        t11[r] = r1[b1];
-        xo[r] = vc[kk];
+    for (int r = 0; r < SART_R; ++r) xo[r] = vc[min(kk0 + 64 * r, A.nz - 1)];
+    // sums over the subset's angles, in angle order
+    float num[SART_R], V[SART_R];
+#pragma unroll
+    for (int r = 0; r < SART_R; ++r) num[r] = V[r] = 0.0f;
+    for (int t = 0; t < A.nang; ++t) {
+        const AngleGeo &G = A.tab[A.a0 + t];
+        const float c = (float)G.c, s = (float)G.s;
+        const float Ld = A.DSO - (x * c + y * s);
+        const float iL = 1.0f / Ld;
+        const float m = A.DSD * iL;
+        const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
+        const float af = floorf(as);
+        const float fa = as - af;
+        const int ia = (int)af;
+        const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
+        const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
+        if (wa0 == 0.0f && wa1 == 0.0f) continue;
+        const float *rt = rT + t * pix;
+        const float *r0 = rt + (int64_t)clampi(ia, 0, A.nu - 1) * A.nv;
+        const float *r1 = rt + (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
+        const float q = A.DSO * iL;
+        const float w = q * q;
+        const float wva = w * (wa0 + wa1);
+        const float mv = m * A.inv_dv;
+        // all taps of the wave's SART_R heights first (heights clamped into the column), then the sums
+        float wb0[SART_R], wb1[SART_R], t00[SART_R], t01[SART_R], t10[SART_R], t11[SART_R];
+#pragma unroll
+        for (int r = 0; r < SART_R; ++r) {
+            const int kk = min(kk0 + 64 * r, A.nz - 1);
+            const float z = fmaf((float)kk, A.dz, A.z0);
+            const float bs = fmaf(z, mv, A.bv0);
+            const float bf = floorf(bs);
+            const float fb = bs - bf;
+            const int ib = (int)bf;
+            wb0[r] = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+            wb1[r] = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+            const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
+            t00[r] = r0[b0];
+            t10[r] = r1[b0];
+            t01[r] = r0[b1];
+            t11[r] = r1[b1];
+        }
+#pragma unroll
+        for (int r = 0; r < SART_R; ++r) {
+            const float v0 = fmaf(wa1, t10[r], wa0 * t00[r]);
+            const float v1 = fmaf(wa1, t11[r], wa0 * t01[r]);
+            num[r] += w * fmaf(wb1[r], v1, wb0[r] * v0);
+            V[r] += wva * (wb0[r] + wb1[r]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < SART_R; ++r) {
         const int kk = kk0 + 64 * r;
-        const float v0 = fmaf(wa1, t10[r], wa0 * t00[r]);
-        const float v1 = fmaf(wa1, t11[r], wa0 * t01[r]);
-        const float num = w * fmaf(wb1[r], v1, wb0[r] * v0);
-        const float V = wva * (wb0[r] + wb1[r]);
         // num / V through the hardware reciprocal (within 1 ulp)
-        if (kk < A.nz && V > 1e-6f) vc[kk] = fmaf(lambda, num * __builtin_amdgcn_rcpf(V), xo[r]);
+        if (kk < A.nz && V[r] > 1e-6f) vc[kk] = fmaf(lambda, num[r] * __builtin_amdgcn_rcpf(V[r]), xo[r]);
     }
 }
 
@@ -1009,23 +1033,24 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     return CT_OK;
 }
 
-ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t angle, float lambda, hipStream_t st) {
+ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t a0, int64_t a1, float lambda,
+                             hipStream_t st) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
-    BpArgs A = make_bp_args(p, tab, angle, angle + 1, full_slab(p->g), 1);
+    BpArgs A = make_bp_args(p, tab, a0, a1, full_slab(p->g), 1);
     const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((A.nz + BP_NZ - 1) / BP_NZ));
     hipLaunchKernelGGL(k_sart_update, grid, dim3(256), 0, st, r, vol, A, lambda);
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
 
-ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t angle, float lambda,
+ct_status launch_sart_update_col(ct_plan *p, const float *rT, float *vz, int64_t a0, int64_t a1, float lambda,
                                  hipStream_t st) {
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
-    BpArgs A = make_bp_args(p, tab, angle, angle + 1, full_slab(p->g), 1);
+    BpArgs A = make_bp_args(p, tab, a0, a1, full_slab(p->g), 1);
     const int zwaves = (A.nz + 64 * SART_R - 1) / (64 * SART_R);
     const int64_t waves = (int64_t)A.nx * A.ny * zwaves;
     hipLaunchKernelGGL(k_sart_update_col, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, rT, vz, A, lambda,

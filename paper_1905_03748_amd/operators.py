@@ -153,10 +153,16 @@ class Plan:
                             cap_bytes)
         return x, resid, st.as_dict()
 
-    def sart(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, lam=1.0, workspace=None, stream=None):
+    def sart_workspace_bytes(self, block=1) -> int:
+        return A.ct_sart_workspace_bytes(self.handle, block)
+
+    def sart(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, lam=1.0, block=1, workspace=None,
+             stream=None):
+        """OS-SART in place on x (zeros if None): subsets of `block` consecutive angles, one update
+        each (block = 1 is SART)."""
         if x is None:
             x = torch.zeros(self.vol_shape, dtype=torch.float32, device=b.device)
-        A.ct_sart(self.handle, _dev(b, self.proj_shape, "b"), _dev(x, self.vol_shape, "x"), niter, lam, 1,
+        A.ct_sart(self.handle, _dev(b, self.proj_shape, "b"), _dev(x, self.vol_shape, "x"), niter, lam, block,
                   workspace.data_ptr() if workspace is not None else 0, _stream(stream))
         return x
 

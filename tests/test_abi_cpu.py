@@ -85,7 +85,9 @@ def test_calls_validate_before_device_work(lib):
                      lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 0, 5, 5),
                      lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 65),
                      lambda: A.ct_backproject(p, 9, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 64),
-                     lambda: A.ct_sart(p, 16, 16, 1, 1.0, 4),
+                     lambda: A.ct_sart(p, 16, 16, 1, 1.0, 0),
+                     lambda: A.ct_sart(p, 16, 16, 1, 1.0, 65),
+                     lambda: A.ct_sart_workspace_bytes(p, 0),
                      lambda: A.ct_cgls(p, 16, A.CT_F32, 16, A.CT_F32, -1)):
             with pytest.raises(A.CtError) as e:
                 call()

@@ -103,6 +103,26 @@ def test_sart_parity_tiny(tiny, orc):
     assert r2 < r1
 
 
+@pytest.mark.parametrize("block", [4, 7, 32])
+def test_os_sart_parity_tiny(tiny, orc, block):
+    """OS-SART with subsets of 4, 7 (the last one of 4) and all 32 angles (one SIRT step per
+    sweep), two sweeps with relaxation 0.8, against the oracle."""
+    w, geo, b, og = tiny
+    ang = w.angles[::2]
+    bb = b[::2].copy()
+    plan = Plan(geo, ang)
+    say(f"[os-sart] tiny, 32 angles, block {block}")
+    x = plan.sart(torch.from_numpy(bb).to(DEV), 2, lam=0.8, block=block).cpu().numpy()
+    xr = orc.os_sart(og, ang, bb.astype(np.float64), 2, block, lam=0.8)
+    e = rel_l2(x, xr)
+    say(f"   rel L2 {e:.3e}")
+    assert e <= 1e-4
+    # a caller workspace sized for the block gives the same result
+    ws = torch.empty(plan.sart_workspace_bytes(block), dtype=torch.uint8, device=DEV)
+    x2 = plan.sart(torch.from_numpy(bb).to(DEV), 2, lam=0.8, block=block, workspace=ws).cpu().numpy()
+    assert np.array_equal(x, x2)
+
+
 def test_tv_parity(orc):
     rng = np.random.default_rng(8)
     for shape in ((23, 17, 31), (64, 64, 64)):

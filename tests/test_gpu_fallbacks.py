@@ -64,3 +64,8 @@ def test_fallback_algorithms(orc):
     e = rel_l2(xs, orc.sart(og, w.angles, b, 1))
     say(f"[fallback wide_cone] SART-1 rel L2 {e:.3e}")
     assert e <= 1e-4
+    # ordered subsets of 5 angles (the last one shorter) through the same fallback kernels
+    xo = plan.sart(torch.from_numpy(b.astype(np.float32)).to(DEV), 2, block=5).cpu().numpy()
+    e = rel_l2(xo, orc.os_sart(og, w.angles, b, 2, 5))
+    say(f"[fallback wide_cone] OS-SART(5)-2 rel L2 {e:.3e}")
+    assert e <= 1e-4
