@@ -40,6 +40,11 @@ def _dev(t: torch.Tensor, shape, name):
     return t.data_ptr()
 
 
+def _check_workspace(ws: torch.Tensor, need: int):
+    if not ws.is_cuda or not ws.is_contiguous() or ws.numel() * ws.element_size() < need:
+        raise ValueError(f"workspace must be a contiguous device tensor of at least {need} bytes")
+
+
 class Plan:
     """A validated geometry and angle set (``ct_plan``).
 
@@ -120,6 +125,8 @@ class Plan:
         tensor of niter+1 residual norms."""
         if x is None:
             x = torch.zeros(self.vol_shape, dtype=vol_dtype or b.dtype, device=b.device)
+        if workspace is not None:
+            _check_workspace(workspace, self.cgls_workspace_bytes(x.dtype, b.dtype))
         if resid is None:
             resid = torch.empty(niter + 1, dtype=torch.float64, device=b.device)
         A.ct_cgls(self.handle, _dev(b, self.proj_shape, "b"), ct_dtype(b.dtype), _dev(x, self.vol_shape, "x"),
@@ -162,6 +169,8 @@ class Plan:
         each (block = 1 is SART)."""
         if x is None:
             x = torch.zeros(self.vol_shape, dtype=torch.float32, device=b.device)
+        if workspace is not None:
+            _check_workspace(workspace, self.sart_workspace_bytes(block))
         A.ct_sart(self.handle, _dev(b, self.proj_shape, "b"), _dev(x, self.vol_shape, "x"), niter, lam, block,
                   workspace.data_ptr() if workspace is not None else 0, _stream(stream))
         return x
@@ -174,6 +183,8 @@ def tv_steps(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps: floa
     nx, ny, nz = (int(v) for v in geometry["nVoxel"])
     if x.dtype != torch.float32:
         raise TypeError("tv_steps works on FP32 volumes")
+    if workspace is not None:
+        _check_workspace(workspace, tv_workspace_bytes(geometry))
     A.ct_tv_steps(g, _dev(x, (nz, ny, nx), "x"), nsteps, lam, eps,
                   workspace.data_ptr() if workspace is not None else 0, _stream(stream))
     return x

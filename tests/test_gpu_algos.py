@@ -123,6 +123,20 @@ def test_os_sart_parity_tiny(tiny, orc, block):
     assert np.array_equal(x, x2)
 
 
+def test_undersized_workspace_rejected(tiny):
+    """A caller workspace smaller than the query says is refused before any device work."""
+    w, geo, b, og = tiny
+    plan = Plan(geo, w.angles)
+    bt = torch.from_numpy(b).to(DEV)
+    small = torch.empty(plan.sart_workspace_bytes(1), dtype=torch.uint8, device=DEV)
+    with pytest.raises(ValueError):
+        plan.sart(bt, 1, block=8, workspace=small)
+    with pytest.raises(ValueError):
+        plan.cgls(bt, 1, workspace=small[:16])
+    with pytest.raises(ValueError):
+        tv_steps(geo, torch.zeros(plan.vol_shape, device=DEV), 1, 0.01, workspace=small[:16])
+
+
 def test_tv_parity(orc):
     rng = np.random.default_rng(8)
     for shape in ((23, 17, 31), (64, 64, 64)):
