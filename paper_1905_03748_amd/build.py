@@ -32,12 +32,12 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, verbose: bool, defines=(), tag="") -> str:
+def _compile(src: str, verbose: bool, defines=(), tag="", device_extra=()) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
     dflags = [f"-D{d}" for d in defines]
     cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON + dflags
     if src.endswith(".hip"):
-        cmd = [_hipcc(), "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE_FLAGS + dflags
+        cmd = [_hipcc(), "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE_FLAGS + list(device_extra) + dflags
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,15 +48,16 @@ def _compile(src: str, verbose: bool, defines=(), tag="") -> str:
     return obj
 
 
-def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
-    """Compile and link.  `defines` (NAME=VALUE strings) and `out` build a variant library for
-    tuning experiments; the default builds libct.so."""
+def build(verbose: bool = False, defines=(), out: str | None = None, device_extra=()) -> str:
+    """Compile and link.  `defines` (NAME=VALUE strings), `device_extra` (additional hipcc flags for
+    the HIP sources) and `out` build a variant library for tuning experiments; the default builds
+    libct.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     lib = out or LIB
     tag = "" if out is None else "." + os.path.basename(out)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, defines, tag), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, defines, tag, device_extra), srcs))
     tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
