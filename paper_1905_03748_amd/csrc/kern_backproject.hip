@@ -481,8 +481,14 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
 // kernel then orders each voxel's faces once (za, zb) instead of ordering the two parameters of
 // every row.  Rows of the other sign get an empty interval either way, so both forms give the same
 // bits.
+// at most 4 waves per SIMD: the compiler then keeps the row loads of all R voxels of a candidate
+// column in flight together instead of two at a time (more registers, fewer exposed latencies)
+#ifndef CT_ADJ_WAVES
+#define CT_ADJ_WAVES 1, 4
+#endif
+#define CT_ADJ_OCC __attribute__((amdgpu_waves_per_eu(CT_ADJ_WAVES)))
 template <typename TV, int R, int NR, bool ZC, bool ORD>
-__global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
+__global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
                                                  int zgroups, int xblocks) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -580,6 +586,8 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
             const float t0 = fmaf(s0, iL, dotp * (iL * iL));
             const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
             const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
+            // the rows of all R voxels are loaded first, so their loads are in flight together
+            float2 wv[R][NR];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]: the lowest
@@ -590,8 +598,13 @@ __global__ __launch_bounds__(256) void k_adj_col(const float2 *__restrict__ yq, 
                 // uniform column base plus an unsigned 32-bit byte offset of row bl
                 const float2 *cb = (const float2 *)((const char *)col + (uint32_t)((int)bl + 1) * 8u);
 #pragma unroll
+                for (int q = 0; q < NR; ++q) wv[r][q] = cb[q];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
                 for (int q = 0; q < NR; ++q) {
-                    const float2 w = cb[q];
+                    const float2 w = wv[r][q];
                     // parameters relative to t0 (one rounding each), clipped to [0, T]: a row that
                     // stays inside the voxel gets exactly T
                     const float tA = fmaf(za[r], w.y, -t0), tB = fmaf(zb[r], w.y, -t0);
