@@ -11,16 +11,17 @@ Operators (plain C in ``ct_oracle.c``, loaded with ctypes):
   interp_fwd / interp_rays         trilinear-interpolated projector (Chou 2011, Section 2.1)
   bp / bp_voxels                   voxel-driven backprojection, FDK or pseudo-matched weights
                                    (Jia 2011, Section 2.2)
-Algorithms (``algos.py``, numpy over the operators): CGLS, SART, TV steepest descent.
+Algorithms (``algos.py``, numpy over the operators): CGLS, SART and OS-SART, TV steepest descent,
+FDK reconstruction (cosine weight, ramp filter, FDK-weighted backprojection).
 """
 from .core import (Geometry, W_FDK, W_PM, bp, bp_coverage, bp_transpose, bp_voxels, get_threads,
                    interp_fwd, interp_ray, interp_rays, ray_endpoints, set_threads, siddon_adj,
                    siddon_adj_voxels, siddon_fwd, siddon_ray, siddon_rays, load)
-from .algos import cgls, os_sart, sart, tv_grad, tv_value, tv_steps
+from .algos import cgls, fdk, fdk_filter, os_sart, ramp_taps, sart, tv_grad, tv_value, tv_steps
 
 __all__ = [
     "Geometry", "W_FDK", "W_PM", "bp", "bp_coverage", "bp_transpose", "bp_voxels", "get_threads",
     "interp_fwd", "interp_ray", "interp_rays", "ray_endpoints", "set_threads", "siddon_adj",
-    "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "load", "cgls", "os_sart", "sart",
-    "tv_grad", "tv_value", "tv_steps",
+    "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "load", "cgls", "fdk", "fdk_filter",
+    "os_sart", "ramp_taps", "sart", "tv_grad", "tv_value", "tv_steps",
 ]

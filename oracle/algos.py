@@ -153,3 +153,53 @@ def tv_steps(x, nsteps, lam, eps=1e-8):
         if ng > 0.0:
             x = x - alpha * g / ng
     return x
+
+
+def ramp_taps(nu):
+    """Band-limited ramp filter (Ram-Lak) sampled at integer offsets m = -(nu-1) .. nu-1, in units
+    of 1/ds^2 for detector spacing ds: the inverse discrete-time Fourier transform of |f| cut off at
+    the Nyquist frequency (Kak & Slaney, Ch. 3), which is 1/4 at m = 0, 0 at even m and
+    -1/(pi m)^2 at odd m.  Returned as an array indexed by m + nu - 1."""
+    m = np.arange(-(nu - 1), nu)
+    h = np.zeros(2 * nu - 1)
+    h[m == 0] = 0.25
+    odd = (m % 2) != 0
+    h[odd] = -1.0 / (np.pi * m[odd]) ** 2
+    return h
+
+
+def fdk_filter(geo: core.Geometry, angles, proj):
+    """Weighting and filtering of the FDK reconstruction (Feldkamp, Davis & Kress 1984; the FDK
+    algorithm that Section 2.2's FDK-weighted backprojector serves) for a full circular scan.
+
+    Steps, for every projection and detector row:
+      1. cosine weight: each pixel times DSD / |P - S|, with |P - S| = sqrt(DSD^2 + u^2 + v^2) for
+         the pixel's detector coordinates (u, v) measured from the central ray;
+      2. ramp filter along the row: q[a] = ds * sum_a' h((a - a') ds) p_w[a'] with h the band-limited
+         ramp of `ramp_taps` and ds = du * DSO / DSD the pixel spacing scaled to the rotation axis
+         (the linear convolution over the whole row, no periodic wrap);
+      3. scale by dtheta / 2 with dtheta = 2 pi / N_angles (the 1/2 because every line is measured
+         twice over a full turn).
+    The reconstruction is then the FDK-weighted backprojection of q, see `fdk`.
+    """
+    angles = np.asarray(angles, dtype=np.float64)
+    proj = np.asarray(proj, dtype=np.float64)
+    nu, nv = geo.nDetector
+    du, dv = geo.dDetector
+    u = (np.arange(nu) - (nu - 1) / 2.0) * du + geo.offDetector[0]
+    v = (np.arange(nv) - (nv - 1) / 2.0) * dv + geo.offDetector[1]
+    w = geo.DSD / np.sqrt(geo.DSD ** 2 + u[None, :] ** 2 + v[:, None] ** 2)
+    ds = du * geo.DSO / geo.DSD
+    h = ramp_taps(nu)
+    a = np.arange(nu)
+    H = h[a[None, :] - a[:, None] + nu - 1]          # H[a', a] = h(a - a')
+    pw = (proj * w[None]).reshape(-1, nu)
+    q = (pw @ H) / ds
+    dtheta = 2.0 * np.pi / len(angles)
+    return (q * (dtheta / 2.0)).reshape(proj.shape)
+
+
+def fdk(geo: core.Geometry, angles, proj):
+    """FDK reconstruction: the FDK-weighted voxel backprojection (weight (DSO/L)^2, Section 2.2) of
+    the weighted, filtered projections of `fdk_filter`."""
+    return core.bp(geo, angles, fdk_filter(geo, angles, proj), core.W_FDK)

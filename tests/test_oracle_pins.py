@@ -587,3 +587,74 @@ def test_fp32_input_samplers_equal_fp64_on_widened_data(orc):
                                       orc.bp_voxels(geo, angles, proj.astype(np.float64), vox, kind))
     np.testing.assert_array_equal(orc.siddon_adj_voxels(geo, angles, proj, vox),
                                   orc.siddon_adj_voxels(geo, angles, proj.astype(np.float64), vox))
+
+
+# --- FDK reconstruction (Feldkamp, Davis & Kress 1984, the algorithm behind Section 2.2's FDK weight)
+
+def test_F1_ramp_filter_response_to_a_cosine(orc):
+    """The discrete ramp filter's response is |omega| / (2 pi) at every frequency below Nyquist:
+    1/4 - (2/pi^2) sum_{odd m} cos(m w)/m^2 = |w|/(2 pi), from the Fourier series
+    sum_{odd m} cos(m w)/m^2 = (pi/8)(pi - 2|w|).  With DSD so large that the cosine weight is 1 to
+    1e-8, `fdk_filter` of the row cos(w a + phi) must be (dtheta/2)(1/ds)(|w|/2pi) cos(w a + phi)
+    away from the row ends, where the truncated tail of the taps is below 1/(pi^2 * 127).  A shifted,
+    mis-scaled or mis-signed tap set, or a wrong ds, fails this."""
+    nu, nv, na = 512, 3, 8
+    DSD, DSO, du = 1e7, 6e6, 0.7
+    geo = orc.Geometry(DSO, DSD, (4, 4, 4), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), (nu, nv), (du, 1.0),
+                       (0.0, 0.0), 0.5)
+    angles = inputs.uniform_angles(na)
+    a = np.arange(nu)
+    ds = du * DSO / DSD
+    for wfreq, phi in ((0.3 * np.pi, 0.4), (0.75 * np.pi, -1.1), (0.05 * np.pi, 2.0)):
+        row = np.cos(wfreq * a + phi)
+        proj = np.broadcast_to(row, (na, nv, nu)).copy()
+        q = orc.fdk_filter(geo, angles, proj)
+        want = (2 * np.pi / na / 2) / ds * (wfreq / (2 * np.pi)) * row
+        amp = (2 * np.pi / na / 2) / ds
+        inner = slice(nu // 4, 3 * nu // 4)
+        np.testing.assert_allclose(q[:, :, inner] / amp, np.broadcast_to(want[inner] / amp, q[:, :, inner].shape),
+                                   atol=1.5e-3)
+
+
+def _fdk_pin_case(nv, n_angles=64):
+    # a short source distance so that the fan reaches 28 degrees and the weights matter
+    return inputs.Workload("fdk_pin", (64, 64, 64), (1.0, 1.0, 1.0), (128, nv), (1.0, 1.0), n_angles, 0, 0,
+                           DSO=60.0, DSD=90.0)
+
+
+def test_F2_fdk_reconstructs_a_centred_sphere(orc):
+    """In the mid-plane FDK is fan-beam filtered backprojection, exact for band-limited data: the
+    reconstruction of a unit-density sphere of radius 28 mm from its exact line integrals is 1
+    inside (here within 0.5 % at every voxel at least 6 mm from the surface in the two middle
+    slices; measured 0.17 %).  Without the cosine weight the error is 5.6 %; without the 1/2, or
+    with ds left at the detector pitch, it is 100 % and 33 %."""
+    w = _fdk_pin_case(128)
+    ells = [inputs.Ellipsoid(np.zeros(3), np.array([28.0] * 3), 1.0, np.eye(3))]
+    geo = orc.Geometry.from_dict(w.geometry_dict())
+    p = inputs.analytic_projections(w, ells, dtype=np.float64)
+    rec = orc.fdk(geo, w.angles, p)
+    c = inputs.voxel_centres_1d(64, 1.0, 0.0)
+    zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+    m = (np.sqrt(xx ** 2 + yy ** 2 + zz ** 2) < 22.0) & (np.abs(zz) <= 1.0)
+    assert m.sum() > 2000
+    assert np.max(np.abs(rec[m] - 1.0)) <= 5e-3
+
+
+def test_F3_fdk_exact_for_an_axially_invariant_object(orc):
+    """FDK is exact for objects that do not vary along the rotation axis: a ray at elevation kappa
+    crosses such an object along 1/cos(kappa) times the in-plane chord, which the cosine weight's v
+    term cancels, so every detector row carries the mid-plane data and every slice is reconstructed
+    as the mid-plane.  A cylinder of radius 24 mm (an ellipsoid with a 1e7 mm axis, its line
+    integrals not clipped to the grid) comes back as 1 inside, within 0.3 % at every voxel at least
+    6 mm from its surface in every slice (measured 0.08 %).  Without the v term of the cosine
+    weight the error is 17 %.  The detector is tall enough that every voxel projects onto it."""
+    w = _fdk_pin_case(160)
+    ells = [inputs.Ellipsoid(np.zeros(3), np.array([24.0, 24.0, 1e7]), 1.0, np.eye(3))]
+    geo = orc.Geometry.from_dict(w.geometry_dict())
+    p = inputs.analytic_projections(w, ells, clip_to_grid=False, dtype=np.float64)
+    rec = orc.fdk(geo, w.angles, p)
+    c = inputs.voxel_centres_1d(64, 1.0, 0.0)
+    zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+    m = np.sqrt(xx ** 2 + yy ** 2) < 18.0
+    assert m.sum() > 60000
+    assert np.max(np.abs(rec[m] - 1.0)) <= 3e-3
