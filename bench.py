@@ -457,6 +457,10 @@ def main():
         tws = torch.empty(tv_workspace_bytes(plan.geometry), dtype=torch.uint8, device=dev)
         xt = x.clone()
         ex["tv_5steps_ms"] = round(timed(lambda: tv_steps(plan.geometry, xt, 5, 0.01, workspace=tws), 1), 3)
+        fq = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
+        ex["fdk_filter_ms"] = round(timed(lambda: plan.fdk_filter(p, out=fq), 2), 3)
+        ex["fdk_recon_ms"] = round(timed(lambda: plan.fdk(p, out=v, workspace=fq.view(torch.uint8)), 2), 3)
+        del fq
         out["ops"].update(ex)
 
     if not args.no_serving:

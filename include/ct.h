@@ -210,6 +210,29 @@ ct_status ct_sart_workspace_bytes(const ct_plan *plan, int32_t block, uint64_t *
 ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, double lambda,
                   int32_t block, void *d_workspace, void *stream);
 
+/* FDK reconstruction (Feldkamp, Davis and Kress 1984, the algorithm that Section 2.2's
+ * FDK-weighted backprojector belongs to) for a full circular scan with uniformly spaced angles.
+ * ct_fdk_filter weights and filters the projections of the angles [angle_begin, angle_end):
+ * every pixel is multiplied by DSD / sqrt(DSD^2 + u^2 + v^2), (u, v) its detector coordinates
+ * from the central ray, and every detector row is convolved (linearly, zero-extended, over the
+ * whole row) with the band-limited ramp filter sampled at ds = du DSO / DSD: taps 1/(4 ds^2) at
+ * offset 0, 0 at even offsets, -1/(pi n ds)^2 at odd offsets n, times ds.  The result is scaled by
+ * dtheta / 2 with dtheta = 2 pi / n_angles of the plan.  FP32 arithmetic, taps summed from the
+ * centre outwards.
+ * d_proj: device, (angle_end - angle_begin) projections of Nv*Nu elements of proj_dtype, projection
+ * 0 of d_proj being angle angle_begin (read only).  d_q: device FP32 array of the same shape,
+ * written (may not alias d_proj).  Stream-ordered.
+ * ct_fdk runs ct_fdk_filter over all angles into d_workspace, then ct_backproject(CT_BP_FDK) of
+ * the filtered projections into d_vol (overwritten, vol_dtype).  d_workspace: device memory of at
+ * least ct_fdk_workspace_bytes bytes (n_angles*Nv*Nu FP32), or NULL for stream-ordered scratch.
+ * Errors: CT_ERR_ARG for a NULL pointer, a bad angle range or detector rows longer than 4096
+ * pixels, CT_ERR_DTYPE for an unknown dtype, CT_ERR_HIP for a launch failure. */
+ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, float *d_q,
+                        int64_t angle_begin, int64_t angle_end, void *stream);
+ct_status ct_fdk_workspace_bytes(const ct_plan *plan, uint64_t *bytes);
+ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype,
+                 void *d_workspace, void *stream);
+
 /* TV steepest descent (Section 2.3, gradient-descent form): nsteps steps of
  * x <- x - alpha g / ||g||_2, g = grad TV_eps(x) with forward differences on a unit grid and zero
  * difference at the last index of each axis, TV_eps(x) = sum_j sqrt(|D x_j|^2 + eps), and

@@ -69,6 +69,9 @@ SIGNATURES = {
     "ct_cgls_host": [_P, _P, _P, _I32, _P, _P, _U64, C.POINTER(ct_ooc_stats)],
     "ct_sart_workspace_bytes": [_P, _I32, C.POINTER(_U64)],
     "ct_sart": [_P, _P, _P, _I32, _D, _I32, _P, _P],
+    "ct_fdk_filter": [_P, _P, _INT, _P, _I64, _I64, _P],
+    "ct_fdk_workspace_bytes": [_P, C.POINTER(_U64)],
+    "ct_fdk": [_P, _P, _INT, _P, _INT, _P, _P],
     "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_tv_steps": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
     "ct_dot": [_P, _P, _INT, _I64, _P, _P],
@@ -197,6 +200,20 @@ def ct_sart_workspace_bytes(plan, block=1) -> int:
 
 def ct_sart(plan, d_b, d_x, niter, lam=1.0, block=1, d_workspace=0, stream=0):
     return _check(lib().ct_sart(plan, d_b, d_x, niter, float(lam), block, d_workspace or None, stream or None))
+
+
+def ct_fdk_filter(plan, d_proj, proj_dtype, d_q, angle_begin, angle_end, stream=0):
+    return _check(lib().ct_fdk_filter(plan, d_proj, proj_dtype, d_q, angle_begin, angle_end, stream or None))
+
+
+def ct_fdk_workspace_bytes(plan) -> int:
+    b = _U64()
+    _check(lib().ct_fdk_workspace_bytes(plan, C.byref(b)))
+    return b.value
+
+
+def ct_fdk(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace=0, stream=0):
+    return _check(lib().ct_fdk(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace or None, stream or None))
 
 
 def ct_tv_workspace_bytes(geometry: ct_geometry) -> int:

@@ -254,6 +254,28 @@ ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, doub
     return sart_run(plan, d_b, d_x, niter, lambda, block, d_workspace, (hipStream_t)stream);
 }
 
+ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, float *d_q, int64_t angle_begin,
+                        int64_t angle_end, void *stream) {
+    if (!plan || !d_proj || !d_q) return fail(CT_ERR_ARG, "ct_fdk_filter: null pointer");
+    if (!dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_filter: unknown dtype");
+    ct_status st = check_range(plan, angle_begin, angle_end, "ct_fdk_filter");
+    if (st != CT_OK) return st;
+    return fdk_filter(plan, d_proj, proj_dtype, d_q, angle_begin, angle_end, (hipStream_t)stream);
+}
+
+ct_status ct_fdk_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
+    if (!plan || !bytes) return fail(CT_ERR_ARG, "ct_fdk_workspace_bytes: null pointer");
+    *bytes = fdk_workspace(plan);
+    return CT_OK;
+}
+
+ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype,
+                 void *d_workspace, void *stream) {
+    if (!plan || !d_proj || !d_vol) return fail(CT_ERR_ARG, "ct_fdk: null pointer");
+    if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk: unknown dtype");
+    return fdk_run(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace, (hipStream_t)stream);
+}
+
 ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes) {
     if (!geometry || !bytes) return fail(CT_ERR_ARG, "ct_tv_workspace_bytes: null pointer");
     *bytes = tv_workspace(*geometry);

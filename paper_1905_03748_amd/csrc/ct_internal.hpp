@@ -132,6 +132,12 @@ size_t sart_workspace(const ct_plan *p, int32_t block);
 ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work,
                  hipStream_t st);
 size_t tv_workspace(const ct_geometry &g);
+// FDK reconstruction (kern_fdk.hip): weighted, ramp-filtered FP32 rows of the angles [a0, a1)
+// (proj and q hold those angles from projection 0), and the whole reconstruction through a
+// workspace of fdk_workspace bytes (stream-ordered scratch when work is null)
+ct_status fdk_filter(ct_plan *p, const void *proj, ct_dtype pt, float *q, int64_t a0, int64_t a1, hipStream_t st);
+ct_status fdk_run(ct_plan *p, const void *proj, ct_dtype pt, void *vol, ct_dtype vt, void *work, hipStream_t st);
+size_t fdk_workspace(const ct_plan *p);
 
 // SART pieces (kern_backproject.hip / kern_forward.hip)
 ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hipStream_t st);

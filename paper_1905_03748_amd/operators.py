@@ -175,6 +175,34 @@ class Plan:
                   workspace.data_ptr() if workspace is not None else 0, _stream(stream))
         return x
 
+    def fdk_filter(self, proj: torch.Tensor, out: torch.Tensor | None = None, angle_begin=0, angle_end=None,
+                   stream=None) -> torch.Tensor:
+        """Cosine-weighted, ramp-filtered FP32 projections of the angles [angle_begin, angle_end)."""
+        angle_end = self.n_angles if angle_end is None else angle_end
+        shape = (angle_end - angle_begin,) + self.proj_shape[1:]
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=proj.device)
+        if out.dtype != torch.float32:
+            raise TypeError("filtered projections are FP32")
+        A.ct_fdk_filter(self.handle, _dev(proj, shape, "proj"), ct_dtype(proj.dtype), _dev(out, shape, "q"),
+                        angle_begin, angle_end, _stream(stream))
+        return out
+
+    def fdk_workspace_bytes(self) -> int:
+        return A.ct_fdk_workspace_bytes(self.handle)
+
+    def fdk(self, proj: torch.Tensor, out: torch.Tensor | None = None, out_dtype=None, workspace=None,
+            stream=None) -> torch.Tensor:
+        """FDK reconstruction of a full circular scan (filter, then FDK-weighted backprojection)."""
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=out_dtype or torch.float32, device=proj.device)
+        if workspace is not None:
+            _check_workspace(workspace, self.fdk_workspace_bytes())
+        A.ct_fdk(self.handle, _dev(proj, self.proj_shape, "proj"), ct_dtype(proj.dtype),
+                 _dev(out, self.vol_shape, "vol"), ct_dtype(out.dtype),
+                 workspace.data_ptr() if workspace is not None else 0, _stream(stream))
+        return out
+
 
 def tv_steps(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps: float = 1e-8, workspace=None,
              stream=None) -> torch.Tensor:
