@@ -941,6 +941,12 @@ FwdArgs make_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const
     return A;
 }
 
+// Angles per launch: a dispatch holds its grid size in work-items as a 32-bit count, so one launch
+// stays below 2^31 work-items and longer angle ranges go in several launches.
+int64_t angles_per_launch(int64_t blocks_per_angle, int64_t threads_per_block) {
+    return std::max<int64_t>(1, (int64_t(1) << 31) / std::max<int64_t>(1, blocks_per_angle * threads_per_block));
+}
+
 unsigned fwd_grid(const FwdArgs &A) {
     const int64_t vb = (A.nv + FWD_TV - 1) / FWD_TV;
     return (unsigned)((int64_t)A.ublocks * A.nang * vb);
@@ -1064,7 +1070,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
             const int rows = cblocks * (a1 - a0) * ((nv + 127) / 128) >= 4096 ? 2 : 1;
 #endif
             const int64_t rgroups = (nv + 64 * rows - 1) / (64 * rows);
-            const int64_t max_ang = std::max<int64_t>(1, (int64_t(1) << 30) / (cblocks * rgroups));
+            const int64_t max_ang = angles_per_launch(cblocks * rgroups, 64 * ZC_COLS);
             const size_t proj_angle = (size_t)nu * nv * dtype_size(pt);
             for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
                 const int64_t c1 = std::min(a1, c0 + max_ang);
@@ -1110,7 +1116,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
             const int64_t cblocks = (nu + ZC_COLS - 1) / ZC_COLS;
             const int rows = cblocks * (a1 - a0) * ((nv + 127) / 128) >= 4096 ? 2 : 1;
             const int64_t rgroups = (nv + 64 * rows - 1) / (64 * rows);
-            const int64_t max_ang = std::max<int64_t>(1, (int64_t(1) << 30) / (cblocks * rgroups));
+            const int64_t max_ang = angles_per_launch(cblocks * rgroups, 64 * ZC_COLS);
             const size_t proj_angle = (size_t)nu * nv * dtype_size(pt);
             for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
                 const int64_t c1 = std::min(a1, c0 + max_ang);
@@ -1159,10 +1165,9 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
     }
     // 32-bit signed byte offsets: volumes (or slabs) below 2 GiB
     const bool buf = (uint64_t)vbytes < (uint64_t(1) << 31);
-    // launch in pieces of at most 2^30 blocks' worth of angles
     const int64_t vb = (g.nDetector[1] + FWD_TV - 1) / FWD_TV;
     const int64_t ub = (g.nDetector[0] + FWD_TU - 1) / FWD_TU;
-    const int64_t max_ang = std::max<int64_t>(1, (int64_t(1) << 30) / (vb * ub));
+    const int64_t max_ang = angles_per_launch(vb * ub, FWD_TU * FWD_TV);
     const size_t proj_angle = (size_t)g.nDetector[0] * g.nDetector[1] * dtype_size(pt);
     for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
         const int64_t c1 = std::min(a1, c0 + max_ang);
@@ -1197,9 +1202,18 @@ ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hip
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
-    FwdArgs A = make_args(p, tab, a0, a1, full_slab(p->g), 0);
-    hipLaunchKernelGGL(k_ray_chord, dim3(fwd_grid(A)), dim3(FWD_TU * FWD_TV), 0, st, chord, A);
-    CT_HIP(hipGetLastError());
+    const ct_geometry &g = p->g;
+    const int64_t vb = (g.nDetector[1] + FWD_TV - 1) / FWD_TV;
+    const int64_t ub = (g.nDetector[0] + FWD_TU - 1) / FWD_TU;
+    const int64_t max_ang = angles_per_launch(vb * ub, FWD_TU * FWD_TV);
+    const size_t pix = (size_t)g.nDetector[0] * g.nDetector[1];
+    for (int64_t c0 = a0; c0 < a1; c0 += max_ang) {
+        const int64_t c1 = std::min(a1, c0 + max_ang);
+        FwdArgs A = make_args(p, tab, c0, c1, full_slab(g), 0);
+        hipLaunchKernelGGL(k_ray_chord, dim3(fwd_grid(A)), dim3(FWD_TU * FWD_TV), 0, st, chord + (size_t)(c0 - a0) * pix,
+                           A);
+        CT_HIP(hipGetLastError());
+    }
     return CT_OK;
 }
 
