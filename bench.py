@@ -291,7 +291,7 @@ def ooc_bench(dev, cap_gib=32):
     """3072^3 FP32 volume (108 GiB) and 3072 projections of 3072^2 (108 GiB) in pageable host memory
     (the streamer stages it through its pinned ring; a single 108 GiB pinned allocation is refused
     on the GPU machines), device memory capped at cap_gib GiB: one out-of-core Siddon Ax and one FDK
-    A^T y."""
+    A^T y, then the FDK reconstruction of the same projections."""
     import torch
     from paper_1905_03748_amd import inputs
     from paper_1905_03748_amd.operators import Plan
@@ -327,6 +327,19 @@ def ooc_bench(dev, cap_gib=32):
     out["backprojection"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
     out["backprojection"]["h2d_gbs"] = round(st["bytes_h2d"] / st["t_total_s"] / 1e9, 1)
     log(f"[ooc] backprojection done: {out['backprojection']}")
+    log("[ooc] FDK reconstruction")
+    st = plan.fdk_host(proj, vol, cap_bytes=cap)
+    out["fdk_reconstruction"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    out["fdk_reconstruction"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
+    # how close the reconstruction of the phantom's own projections comes to the phantom, in the 8
+    # middle slices (where the cone angle vanishes); a property of FDK, not a parity figure
+    z0 = nz // 2 - 4
+    ws = inputs.Workload("mid", (w.nvox[0], w.nvox[1], 8), w.dvox, w.ndet, w.ddet, 1, 0, 0,
+                         off_origin=(0.0, 0.0, (z0 + 4 - nz / 2.0) * w.dvox[2]))
+    ph = inputs.voxelize_torch(ws, ells, device=dev).double()
+    rec = vol[z0:z0 + 8].to(dev).double()
+    out["fdk_reconstruction"]["mid_slices_rel_l2_vs_phantom"] = round(float((rec - ph).norm() / ph.norm()), 4)
+    log(f"[ooc] FDK reconstruction done: {out['fdk_reconstruction']}")
     del vol, proj
     return out
 

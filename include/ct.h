@@ -143,7 +143,8 @@ typedef struct {
  * direction: 0 = forward (3 projection chunk buffers), 1 = FDK or pseudo-matched backprojection
  * (2 buffers), 2 = exact-adjoint backprojection (2 buffers plus the kernel's transposed FP32 copy
  * of one chunk, 8 (Nv + 2) Nu bytes per angle; chunks of up to 128 angles, because each chunk
- * re-reads the slab's accumulators).  projector matters for direction 0 only.
+ * re-reads the slab's accumulators), 3 = FDK reconstruction (ct_fdk_host: 2 buffers plus one
+ * filtered FP32 chunk, 4 Nv Nu bytes per angle).  projector matters for direction 0 only.
  * Errors: CT_ERR_ARG, CT_ERR_DTYPE, CT_ERR_CAP. */
 ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
                       ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out);
@@ -230,6 +231,14 @@ ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, doub
 ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, float *d_q,
                         int64_t angle_begin, int64_t angle_end, void *stream);
 ct_status ct_fdk_workspace_bytes(const ct_plan *plan, uint64_t *bytes);
+/* Out-of-core FDK reconstruction: Algorithm 2's slab/chunk streaming of ct_backproject_host with
+ * CT_BP_FDK, each projection chunk weighted and filtered on the device (as ct_fdk_filter) right
+ * after its upload and before its backprojection.  The filter runs once per chunk and slab.
+ * h_proj, h_vol, device_cap_bytes and stats as ct_backproject_host; the plan is ct_ooc_plan's
+ * direction 3.  Errors: as ct_backproject_host, and CT_ERR_ARG for detector rows longer than
+ * 4096 pixels. */
+ct_status ct_fdk_host(ct_plan *plan, const void *h_proj, ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
+                      uint64_t device_cap_bytes, ct_ooc_stats *stats);
 ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype,
                  void *d_workspace, void *stream);
 

@@ -71,6 +71,7 @@ SIGNATURES = {
     "ct_sart": [_P, _P, _P, _I32, _D, _I32, _P, _P],
     "ct_fdk_filter": [_P, _P, _INT, _P, _I64, _I64, _P],
     "ct_fdk_workspace_bytes": [_P, C.POINTER(_U64)],
+    "ct_fdk_host": [_P, _P, _INT, _P, _INT, _U64, C.POINTER(ct_ooc_stats)],
     "ct_fdk": [_P, _P, _INT, _P, _INT, _P, _P],
     "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_tv_steps": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
@@ -210,6 +211,12 @@ def ct_fdk_workspace_bytes(plan) -> int:
     b = _U64()
     _check(lib().ct_fdk_workspace_bytes(plan, C.byref(b)))
     return b.value
+
+
+def ct_fdk_host(plan, h_proj, proj_dtype, h_vol, vol_dtype, device_cap_bytes) -> ct_ooc_stats:
+    s = ct_ooc_stats()
+    _check(lib().ct_fdk_host(plan, h_proj, proj_dtype, h_vol, vol_dtype, int(device_cap_bytes), C.byref(s)))
+    return s
 
 
 def ct_fdk(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace=0, stream=0):

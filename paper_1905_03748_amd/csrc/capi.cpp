@@ -183,7 +183,7 @@ ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const vo
 ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
                       ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out) {
     if (!plan || !out) return fail(CT_ERR_ARG, "ct_ooc_plan: null pointer");
-    if (direction < 0 || direction > 2) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0, 1 or 2");
+    if (direction < 0 || direction > 3) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0, 1, 2 or 3");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_ooc_plan: unknown dtype");
     return ooc_plan(plan, direction, projector, vol_dtype, proj_dtype, device_cap_bytes, out);
 }
@@ -261,6 +261,15 @@ ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, 
     ct_status st = check_range(plan, angle_begin, angle_end, "ct_fdk_filter");
     if (st != CT_OK) return st;
     return fdk_filter(plan, d_proj, proj_dtype, d_q, angle_begin, angle_end, (hipStream_t)stream);
+}
+
+ct_status ct_fdk_host(ct_plan *plan, const void *h_proj, ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
+                      uint64_t device_cap_bytes, ct_ooc_stats *stats) {
+    if (!plan || !h_proj || !h_vol) return fail(CT_ERR_ARG, "ct_fdk_host: null pointer");
+    if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_host: unknown dtype");
+    if (plan->g.nDetector[0] > 4096)
+        return fail(CT_ERR_ARG, "ct_fdk_host: detector rows longer than 4096 pixels are not supported");
+    return ooc_backproject(plan, CT_BP_FDK, h_proj, proj_dtype, h_vol, vol_dtype, device_cap_bytes, stats, true);
 }
 
 ct_status ct_fdk_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {

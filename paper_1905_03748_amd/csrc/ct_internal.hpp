@@ -153,8 +153,10 @@ ct_status ooc_plan(const ct_plan *p, int direction, ct_projector proj, ct_dtype 
                    uint64_t cap, ct_ooc_stats *out);
 ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype vt, void *h_proj,
                       ct_dtype pt, uint64_t cap, ct_ooc_stats *stats);
+// fdk_filtered: the FDK reconstruction, each projection chunk weighted and ramp-filtered on the
+// device before its FDK-weighted backprojection (kind is then CT_BP_FDK)
 ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj, ct_dtype pt, void *h_vol,
-                          ct_dtype vt, uint64_t cap, ct_ooc_stats *stats);
+                          ct_dtype vt, uint64_t cap, ct_ooc_stats *stats, bool fdk_filtered = false);
 
 // Out-of-core CGLS (ooc_cgls.cpp): host workspace r, q, s, p in FP32
 size_t cgls_host_workspace(const ct_plan *p);

@@ -127,7 +127,7 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     // with its transposed projection copy.
     const uint64_t pix = (uint64_t)g.nDetector[0] * g.nDetector[1];
     int64_t K = direction == 0 ? (int64_t)std::max<uint64_t>(1, (8ull << 20) / std::max<uint64_t>(pix, 1))
-                               : (direction == 1 ? 32 : 128);
+                               : (direction == 2 ? 128 : 32);
     K = std::min<int64_t>(K, na);
     K = std::max<int64_t>(K, 1);
     // fewest slabs wins (the image is split as little as possible); among equal counts the larger
@@ -135,8 +135,10 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     const int64_t kmin = std::max<int64_t>(1, K / 8);
     bool found = false;
     for (int64_t k = K; k >= 1; k = (k == 1 ? 0 : std::max<int64_t>(1, k / 2))) {
-        const uint64_t bufs =
-            nbuf * (uint64_t)k * pangle + (direction == 2 ? (uint64_t)k * adj_chunk_bytes_per_angle(g) : 0);
+        // the FDK reconstruction (direction 3) also holds the filtered FP32 copy of a chunk
+        const uint64_t bufs = nbuf * (uint64_t)k * pangle +
+                              (direction == 2 ? (uint64_t)k * adj_chunk_bytes_per_angle(g) : 0) +
+                              (direction == 3 ? (uint64_t)k * pix * sizeof(float) : 0);
         int64_t h = 0;
         if (cap > RESERVE + bufs) h = (int64_t)((cap - RESERVE - bufs) / slice) - extra;
         if (h >= 1) {
@@ -352,11 +354,12 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
 }
 
 ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj, ct_dtype pt, void *h_vol, ct_dtype vt,
-                          uint64_t cap, ct_ooc_stats *stats) {
+                          uint64_t cap, ct_ooc_stats *stats, bool fdk_filtered) {
     const auto t_start = clk::now();
     const ct_geometry &g = p->g;
     Layout L;
-    ct_status s = layout_for(p, kind == CT_BP_ADJOINT ? 2 : 1, CT_SIDDON, vt, pt, cap, L);
+    if (fdk_filtered) kind = CT_BP_FDK;
+    ct_status s = layout_for(p, fdk_filtered ? 3 : (kind == CT_BP_ADJOINT ? 2 : 1), CT_SIDDON, vt, pt, cap, L);
     if (s != CT_OK) return s;
     ct_ooc_stats st;
     std::memset(&st, 0, sizeof(st));
@@ -379,12 +382,15 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     // the exact adjoint accumulates into a column-major slab (its lanes run down the columns), which
     // goes out through a stage of ZSTAGE slices
     const bool zcol = kind == CT_BP_ADJOINT && adj_col_ok(p);
-    DevBuf slab, dbuf[2], adj, stage;
+    DevBuf slab, dbuf[2], adj, stage, filt;
     CT_HIP(hipMalloc(&slab.p, L.h * slice));
     if (zcol) CT_HIP(hipMalloc(&stage.p, ZSTAGE * slice));
     for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
     const size_t adj_bytes = (size_t)L.K * adj_chunk_bytes_per_angle(g);  // one transposed copy per chunk
     if (kind == CT_BP_ADJOINT) CT_HIP(hipMalloc(&adj.p, adj_bytes));
+    // FDK reconstruction: each chunk is weighted and filtered into an FP32 buffer, which the
+    // backprojection reads (both on the compute stream, so the buffer is reused in order)
+    if (fdk_filtered) CT_HIP(hipMalloc(&filt.p, (size_t)L.K * g.nDetector[0] * g.nDetector[1] * sizeof(float)));
     HostBuf sin[2], svol[2];
     if (!proj_pinned)
         for (auto &b : sin) CT_HIP(hipHostMalloc(&b.p, chunk_bytes, hipHostMallocDefault));
@@ -432,7 +438,14 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
             st.bytes_h2d += (double)bytes;
             CT_HIP(hipStreamWaitEvent(S.comp, ev_h2d.e[j], 0));
             CT_HIP(hipEventRecord(tk0.e[c], S.comp));
-            if ((s = launch_backproject(p, kind, dbuf[j].p, pt, slab.p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp, adj.p,
+            const void *bp_in = dbuf[j].p;
+            ct_dtype bp_t = pt;
+            if (fdk_filtered) {
+                if ((s = fdk_filter(p, dbuf[j].p, pt, (float *)filt.p, a0, a1, S.comp)) != CT_OK) return s;
+                bp_in = filt.p;
+                bp_t = CT_F32;
+            }
+            if ((s = launch_backproject(p, kind, bp_in, bp_t, slab.p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp, adj.p,
                                         adj.p ? adj_bytes : 0)) != CT_OK)
                 return s;
             CT_HIP(hipEventRecord(tk1.e[c], S.comp));

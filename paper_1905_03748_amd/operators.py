@@ -110,6 +110,16 @@ class Plan:
                                   ct_dtype(out.dtype), cap_bytes)
         return s.as_dict()
 
+    def fdk_host(self, proj: torch.Tensor, out: torch.Tensor, cap_bytes=32 << 30) -> dict:
+        """Out-of-core FDK reconstruction of host projections into the host volume `out`."""
+        assert proj.device.type == "cpu" and out.device.type == "cpu" and proj.is_contiguous() and out.is_contiguous()
+        if tuple(proj.shape) != self.proj_shape or tuple(out.shape) != self.vol_shape:
+            raise ValueError(f"shapes {tuple(proj.shape)}, {tuple(out.shape)}; expected {self.proj_shape}, "
+                             f"{self.vol_shape}")
+        s = A.ct_fdk_host(self.handle, proj.data_ptr(), ct_dtype(proj.dtype), out.data_ptr(), ct_dtype(out.dtype),
+                          cap_bytes)
+        return s.as_dict()
+
     def ooc_plan(self, direction=0, projector="siddon", vol_dtype=torch.float32, proj_dtype=torch.float32,
                  cap_bytes=32 << 30) -> dict:
         return A.ct_ooc_plan(self.handle, direction, _PROJ[projector], ct_dtype(vol_dtype), ct_dtype(proj_dtype),

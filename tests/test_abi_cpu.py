@@ -137,15 +137,24 @@ def test_ooc_planner_equal_slabs_and_halo(lib):
         for nslices in (1, 5, 13, 40, 64, 100):
             cap = reserve + 3 * 64 * pangle + nslices * slice_b
             for kind, halo in ((A.CT_SIDDON, 0), (A.CT_INTERP, 1)):
-                for direction, nbuf in ((0, 3), (1, 2), (2, 2)):
+                for direction, nbuf in ((0, 3), (1, 2), (2, 2), (3, 2)):
                     s = A.ct_ooc_plan(p, direction, kind, A.CT_F32, A.CT_F32, cap)
                     h = halo if direction == 0 else 0
                     adj = s.chunk_angles * 64 * 66 * 8 if direction == 2 else 0
+                    filt = s.chunk_angles * 64 * 64 * 4 if direction == 3 else 0   # FDK's filtered chunk
                     assert s.n_slabs * s.slab_slices >= 64
                     assert s.slab_slices == -(-64 // s.n_slabs)            # equal slabs
                     assert (s.n_slabs - 1) * s.slab_slices < 64
-                    assert reserve + (s.slab_slices + 2 * h) * slice_b + nbuf * s.chunk_angles * pangle + adj <= cap
+                    assert (reserve + (s.slab_slices + 2 * h) * slice_b + nbuf * s.chunk_angles * pangle + adj + filt
+                            <= cap)
                     assert s.n_chunks == -(-64 // s.chunk_angles)
+                # the filtered chunk costs room: never fewer slabs than the plain FDK backprojection
+                assert (A.ct_ooc_plan(p, 3, kind, A.CT_F32, A.CT_F32, cap).n_slabs
+                        >= A.ct_ooc_plan(p, 1, kind, A.CT_F32, A.CT_F32, cap).n_slabs)
+            for bad in (-1, 4):
+                with pytest.raises(A.CtError) as e:
+                    A.ct_ooc_plan(p, bad, A.CT_SIDDON, A.CT_F32, A.CT_F32, cap)
+                assert e.value.status == A.CT_ERR_ARG
             # with room for the whole volume and full chunks: one slab
             if nslices >= 64:
                 assert A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F32, A.CT_F32, cap).n_slabs == 1

@@ -102,6 +102,21 @@ def test_fdk_reconstructs_a_centred_sphere(orc):
     assert rel_l2(v, orc.fdk(og, w.angles, p.astype(np.float64))) <= TOL_BP
 
 
+@pytest.mark.parametrize("nu", [700, 2049, 3072, 4096])
+def test_fdk_filter_wide_rows(orc, nu):
+    """Rows of up to 4096 pixels (the filter's limit; 3072 is the splitting workload's detector):
+    one row per block of up to 512 threads instead of several rows per block."""
+    w = inputs.Workload("fdk_wide", (16, 16, 8), (1.0, 1.0, 1.0), (nu, 5), (0.1, 1.0), 6, 0, 0,
+                        off_detector=(0.37, 0.0))
+    p = inputs.random_array((6, 5, nu), 60 + nu, kind="uniform")
+    plan, og, pt = _case(w, p, orc)
+    say(f"[fdk] filter, rows of {nu} pixels")
+    q = plan.fdk_filter(pt).cpu().numpy()
+    e = rel_l2(q, orc.fdk_filter(og, w.angles, p.astype(np.float64)))
+    say(f"   rel L2 {e:.3e}")
+    assert e <= TOL_PROJ
+
+
 def test_fdk_medium_sampled(orc):
     """512^3, 360 angles, 512^2 detector (the benchmark's size, in the launch the benchmark times):
     filtered rows at 2000 sampled pixels, and the reconstruction at 400 sampled voxels against the
@@ -121,6 +136,43 @@ def test_fdk_medium_sampled(orc):
     vox = inputs.sample_indices(512 ** 3, 400, 52)
     ref = orc.bp_voxels(og, w.angles, qref, vox, orc.W_FDK)
     e = rel_l2(v[vox], ref)
+    say(f"   reconstruction rel L2 (sampled) {e:.3e}")
+    assert e <= TOL_BP
+
+
+def test_fdk_splitting_geometry_sampled(orc):
+    """The splitting workload's geometry (3072^3 of 256/3072 mm, 3072^2 detector of 0.8*512/3072 mm)
+    at 4 of its angles, resident (a 108 GiB FP32 volume in device memory), on the exact line
+    integrals of 6 of its phantom's ellipsoids: the filtered rows, and the reconstruction at 400
+    sampled voxels against the oracle's FDK-weighted backprojection of its own filtered rows.
+
+    The backprojector interpolates at an FP32 detector coordinate, whose spacing is 2.4e-4 pixels
+    above 2048: on data that changes by its full size from pixel to pixel (ramp-filtered white
+    noise) that alone gives 2.2e-4 relative L2 at this detector size.  Projections of objects are
+    smooth between their edges, and that is the data used here."""
+    base = inputs.workload("ooc")
+    w = inputs.Workload("ooc_4", base.nvox, base.dvox, base.ndet, base.ddet, 4, 6, base.seed,
+                        angles=np.asarray(base.angles)[[0, 768, 1536, 2304]])
+    say("[fdk] 3072^3 geometry, 4 angles: exact line integrals of 6 ellipsoids")
+    y = inputs.analytic_projections(w, inputs.ellipsoids(w))
+    geo = w.geometry_dict()
+    plan = Plan(geo, w.angles)
+    og = orc.Geometry.from_dict(geo)
+    say("[fdk] 3072^3 geometry: oracle filter")
+    qref = orc.fdk_filter(og, w.angles, y)
+    say("[fdk] 3072^3 geometry: GPU reconstruction")
+    yt = torch.from_numpy(y).to(DEV)
+    q = plan.fdk_filter(yt).cpu().numpy()
+    e = rel_l2(q, qref)
+    say(f"   filter rel L2 {e:.3e}")
+    assert e <= TOL_PROJ
+    vol = plan.fdk(yt)
+    vox = inputs.sample_indices(3072 ** 3, 400, 405)
+    got = vol.view(-1)[torch.from_numpy(vox).to(DEV)].cpu().numpy()
+    del vol
+    torch.cuda.empty_cache()
+    ref = orc.bp_voxels(og, w.angles, qref, vox, orc.W_FDK)
+    e = rel_l2(got, ref)
     say(f"   reconstruction rel L2 (sampled) {e:.3e}")
     assert e <= TOL_BP
 

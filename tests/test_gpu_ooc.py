@@ -18,19 +18,21 @@ RESERVE = 64 << 20
 def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=torch.float32):
     """A cap that leaves exactly `slices` slices next to the planner's smallest chunk buffers (the
     planner shrinks chunks down to an eighth of its target when that gives fewer slabs).
-    direction 0: forward; 1: FDK or pseudo-matched backprojection; 2: exact adjoint."""
+    direction 0: forward; 1: FDK or pseudo-matched backprojection; 2: exact adjoint; 3: FDK
+    reconstruction."""
     nz, ny, nx = plan.vol_shape
     na, nv, nu = plan.proj_shape
     slice_b = nx * ny * torch.empty(0, dtype=dt).element_size()
     pangle = nu * nv * torch.empty(0, dtype=pdt).element_size()
     nbuf = 3 if direction == 0 else 2
     halo = 1 if (direction == 0 and projector == "interp") else 0
-    k = min(na, max(1, (8 << 20) // (nu * nv))) if direction == 0 else min(32 if direction == 1 else 128, na)
+    k = min(na, max(1, (8 << 20) // (nu * nv))) if direction == 0 else min(128 if direction == 2 else 32, na)
     kmin = max(1, k // 8)
     # the exact adjoint also holds its transposed FP32 copy of each chunk and an 8-slice stage for
     # its column-major slab; a Siddon forward holds its slab column-major (two zero slots per
     # column) and an 8-slice stage
     adj = kmin * nu * (nv + 2) * 8 if direction == 2 else 0
+    adj += kmin * nu * nv * 4 if direction == 3 else 0   # the FDK reconstruction's filtered chunk
     extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0) + (8 if direction == 2 else 0)
     return RESERVE + nbuf * kmin * pangle + adj + (slices + extra) * slice_b
 
@@ -86,6 +88,39 @@ def test_backprojection_split_bitwise(case, orc, slices, pinned):
         assert torch.equal(out, res), (kind, st, float((out - res).abs().max()))
     og = orc.Geometry.from_dict(w.geometry_dict())
     assert rel_l2(out.numpy(), orc.siddon_adj(og, w.angles, y.astype(np.float64))) <= TOL_BP
+
+
+@pytest.mark.parametrize("slices", [37, 10, 1])
+def test_fdk_reconstruction_split_bitwise(case, orc, slices):
+    """Out-of-core FDK reconstruction: each chunk is weighted and filtered on the device after its
+    upload, row by row as in the resident filter, and the chunked backprojection is exact, so the
+    result equals the resident ct_fdk bit for bit."""
+    w, vol, y = case
+    plan = Plan(w.geometry_dict(), w.angles)
+    cap = _cap_for(plan, slices, 3)
+    info = plan.ooc_plan(3, cap_bytes=cap)
+    say(f"[ooc fdk reconstruction] slices={slices} plan={info}")
+    out = torch.full(plan.vol_shape, -7.0)
+    st = plan.fdk_host(torch.from_numpy(y), out, cap_bytes=cap)
+    assert st["n_slabs"] == info["n_slabs"] == -(-37 // slices), (info, st)
+    res = plan.fdk(torch.from_numpy(y).to(DEV)).cpu()
+    assert torch.equal(out, res), (st, float((out - res).abs().max()))
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    assert rel_l2(out.numpy(), orc.fdk(og, w.angles, y.astype(np.float64))) <= TOL_BP
+
+
+def test_fdk_reconstruction_16bit_projections(case, orc):
+    w, vol, y = case
+    plan = Plan(w.geometry_dict(), w.angles)
+    yh = torch.from_numpy(y).half()
+    cap = _cap_for(plan, 9, 3, pdt=torch.float16)
+    say("[ooc fdk reconstruction] FP16 projections")
+    out = torch.zeros(plan.vol_shape)
+    st = plan.fdk_host(yh, out, cap_bytes=cap)
+    assert st["n_slabs"] > 1
+    assert torch.equal(out, plan.fdk(yh.to(DEV)).cpu())
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    assert rel_l2(out.numpy(), orc.fdk(og, w.angles, yh.float().numpy().astype(np.float64))) <= TOL_BP
 
 
 def test_ooc_16bit_storage(case, orc):
