@@ -250,6 +250,19 @@ ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d
 ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes);
 ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, double lambda,
                       double eps, void *d_workspace, void *stream);
+/* The same TV steps on an image in host memory (Section 2.3's regularisation of images larger
+ * than device memory), under device_cap_bytes.  The image is cut into equal slabs of axial slices;
+ * each is uploaded with one halo slice on either side, because the gradient at slice z reads
+ * slices z - 1 .. z + 1.  A step makes two passes over the slabs: the first sums ||g||^2 (and, at
+ * the first step, ||x_in||^2) in FP64, slab by slab, in slab order; the second recomputes each
+ * slab's gradient and applies the update, with the lower halo taken from the slice below as it was
+ * before the step.  The result equals ct_tv_steps up to the order of those FP64 sums (bitwise
+ * equal with one slab).  h_x: host FP32 volume of the geometry's nVoxel shape, in: x, out: result
+ * (pageable or pinned).  stats (may be NULL): n_slabs, slab_slices, bytes moved, t_total_s.
+ * Synchronous.  Errors: as ct_tv_steps, and CT_ERR_CAP for a cap below one slice with its halos
+ * and buffers (64 MiB reserve). */
+ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nsteps, double lambda, double eps,
+                           uint64_t device_cap_bytes, ct_ooc_stats *stats);
 
 /* ---------------------------------------------------------------------------------------------
  * Small device utilities used by the algorithms, exported for callers that compose their own. */

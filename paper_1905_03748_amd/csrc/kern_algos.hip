@@ -3,7 +3,9 @@
 // OS-SART (SART with one angle per update when block = 1) and TV steepest descent.  Reductions use a fixed partition
 // (DOT_BLOCKS contiguous ranges, fixed wave/block trees, fixed final sum), so results are bitwise
 // repeatable regardless of what else shares the device.
+#include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "dev_common.hpp"
 
@@ -167,14 +169,17 @@ __global__ __launch_bounds__(256) void k_sart_resid_t(const float *__restrict__ 
 }
 
 // TV_eps gradient with forward differences, unit spacing, zero difference at the last index.
+// Slice z = blockIdx.z + kg0 of the volume (nz slices in all); x holds slices from kx0 on (at
+// least z - 1 .. z + 1 where they exist) and g from kg0 on.  A whole resident volume has
+// kx0 = kg0 = 0.
 __global__ __launch_bounds__(256) void k_tv_grad(const float *__restrict__ x, float *__restrict__ g, int nx, int ny,
-                                                 int nz, float eps) {
+                                                 int nz, float eps, int64_t kx0, int64_t kg0) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int k = blockIdx.z;
+    const int64_t k = blockIdx.z + kg0;
     if (i >= nx || j >= ny) return;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const int64_t o = k * sz + (int64_t)j * sy + i;
+    const int64_t o = (k - kx0) * sz + (int64_t)j * sy + i;
     auto X = [&](int di, int dj, int dk) { return x[o + dk * sz + dj * sy + di]; };
     const float xc = X(0, 0, 0);
     // differences at j
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float *__restrict__ x, fl
         const float c = xc - xm;
         gv += c / sqrtf(a * a + b * b + c * c + eps);
     }
-    g[o] = gv;
+    g[(k - kg0) * sz + (int64_t)j * sy + i] = gv;
 }
 
 // TV scalars: [0] = ||x_in||^2, [1] = alpha, [2] = ||g||^2
@@ -439,7 +444,8 @@ ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, d
     CT_HIP(hipGetLastError());
     const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz);
     for (int32_t k = 0; k < nsteps; ++k) {
-        hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, st, (const float *)x, gbuf, nx, ny, nz, (float)eps);
+        hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, st, (const float *)x, gbuf, nx, ny, nz, (float)eps,
+                           (int64_t)0, (int64_t)0);
         CT_HIP(hipGetLastError());
         CK(dot_f64(gbuf, gbuf, CT_F32, nv, scal + 2, parts, st));
         hipLaunchKernelGGL(k_tv_update, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (float *)x, (const float *)gbuf, scal, nv);
@@ -447,6 +453,132 @@ ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, d
     }
     return CT_OK;
 #undef CK
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// TV steepest descent out of core: the image in host memory, slabs of axial slices under a device
+// memory cap.  The gradient at slice z needs slices z - 1 .. z + 1, so each slab is uploaded with a
+// halo slice on either side.  A step is two passes over the slabs: the first sums ||g||^2 (and,
+// at the first step, ||x_in||^2) slab by slab in FP64, in slab order; the second recomputes each
+// slab's gradient and applies x -= alpha g / ||g||.  In the second pass the slab below has already
+// been updated, so its last slice is kept on the device as it was before that update and replaces
+// the uploaded lower halo: every gradient of a step sees the image from before the step.
+
+namespace {
+
+constexpr uint64_t TV_RESERVE = 64ull << 20;
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+}  // namespace
+
+ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, uint64_t cap,
+                      ct_ooc_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1];
+    const int64_t nz = g.nVoxel[2];
+    const int64_t slice = (int64_t)nx * ny;
+    const uint64_t sb = (uint64_t)slice * sizeof(float);
+    const uint64_t fixed = TV_RESERVE + align256(DOT_BLOCKS * 8) + align256(4 * 8);
+    // device: the slab with two halo slices, its gradient, one saved slice
+    if (cap <= fixed || (cap - fixed) / sb < 5)
+        return fail(CT_ERR_CAP, "device memory cap is below one slab slice plus halos and buffers");
+    int64_t h = (int64_t)(((cap - fixed) / sb - 3) / 2);
+    h = std::max<int64_t>(1, std::min<int64_t>(h, nz));
+    const int64_t nsp = (nz + h - 1) / h;
+    h = (nz + nsp - 1) / nsp;
+    ct_ooc_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.n_slabs = (int32_t)nsp;
+    st.slab_slices = (int32_t)h;
+    OwnStream S;
+    CT_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
+    DevMem xb, gb, saved, parts, scal;
+    CT_HIP(hipMalloc(&xb.p, (size_t)(h + 2) * sb));
+    CT_HIP(hipMalloc(&gb.p, (size_t)h * sb));
+    CT_HIP(hipMalloc(&saved.p, (size_t)sb));
+    CT_HIP(hipMalloc(&parts.p, DOT_BLOCKS * 8));
+    CT_HIP(hipMalloc(&scal.p, 4 * 8));
+    float *xbuf = (float *)xb.p, *gbuf = (float *)gb.p;
+    double *dscal = (double *)scal.p;
+    const hipStream_t s = S.s;
+    auto bounds = [&](int64_t n, int64_t &o0, int64_t &o1, int64_t &m0, int64_t &m1) {
+        o0 = n * h;
+        o1 = std::min(nz, o0 + h);
+        m0 = std::max<int64_t>(0, o0 - 1);
+        m1 = std::min(nz, o1 + 1);
+    };
+    auto grad = [&](int64_t m0, int64_t o0, int64_t o1) -> ct_status {
+        const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)(o1 - o0));
+        hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, (const float *)xbuf, gbuf, nx, ny, (int)nz, (float)eps,
+                           m0, o0);
+        CT_HIP(hipGetLastError());
+        return CT_OK;
+    };
+    auto dot_host = [&](const float *a, int64_t n, double &out) -> ct_status {
+        ct_status e = dot_f64(a, a, CT_F32, n, dscal + 3, (double *)parts.p, s);
+        if (e != CT_OK) return e;
+        CT_HIP(hipMemcpyAsync(&out, dscal + 3, 8, hipMemcpyDeviceToHost, s));
+        CT_HIP(hipStreamSynchronize(s));
+        return CT_OK;
+    };
+    double alpha = 0.0;
+    ct_status e = CT_OK;
+    for (int32_t step = 0; step < nsteps; ++step) {
+        double gg = 0.0, xx = 0.0;
+        for (int64_t n = 0; n < nsp; ++n) {  // pass 1: norms
+            int64_t o0, o1, m0, m1;
+            bounds(n, o0, o1, m0, m1);
+            CT_HIP(hipMemcpyAsync(xbuf, hx + m0 * slice, (size_t)(m1 - m0) * sb, hipMemcpyHostToDevice, s));
+            st.bytes_h2d += (double)(m1 - m0) * sb;
+            if ((e = grad(m0, o0, o1)) != CT_OK) return e;
+            double d = 0.0;
+            if ((e = dot_host(gbuf, (o1 - o0) * slice, d)) != CT_OK) return e;
+            gg += d;
+            if (step == 0) {
+                if ((e = dot_host(xbuf + (o0 - m0) * slice, (o1 - o0) * slice, d)) != CT_OK) return e;
+                xx += d;
+            }
+        }
+        if (step == 0) alpha = lambda * std::sqrt(xx);
+        const double hs[4] = {xx, alpha, gg, 0.0};
+        CT_HIP(hipMemcpyAsync(dscal, hs, sizeof(hs), hipMemcpyHostToDevice, s));
+        for (int64_t n = 0; n < nsp; ++n) {  // pass 2: update
+            int64_t o0, o1, m0, m1;
+            bounds(n, o0, o1, m0, m1);
+            CT_HIP(hipMemcpyAsync(xbuf, hx + m0 * slice, (size_t)(m1 - m0) * sb, hipMemcpyHostToDevice, s));
+            st.bytes_h2d += (double)(m1 - m0) * sb;
+            if (n > 0) CT_HIP(hipMemcpyAsync(xbuf, saved.p, (size_t)sb, hipMemcpyDeviceToDevice, s));
+            if (n + 1 < nsp)
+                CT_HIP(hipMemcpyAsync(saved.p, xbuf + (o1 - 1 - m0) * slice, (size_t)sb, hipMemcpyDeviceToDevice, s));
+            if ((e = grad(m0, o0, o1)) != CT_OK) return e;
+            const int64_t nown = (o1 - o0) * slice;
+            hipLaunchKernelGGL(k_tv_update, dim3(ew_grid(nown)), dim3(EW_THREADS), 0, s, xbuf + (o0 - m0) * slice,
+                               (const float *)gbuf, (const double *)dscal, nown);
+            CT_HIP(hipGetLastError());
+            CT_HIP(hipMemcpyAsync(hx + o0 * slice, xbuf + (o0 - m0) * slice, (size_t)nown * 4, hipMemcpyDeviceToHost,
+                                  s));
+            CT_HIP(hipStreamSynchronize(s));
+            st.bytes_d2h += (double)nown * 4;
+        }
+    }
+    CT_HIP(hipStreamSynchronize(s));
+    st.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = st;
+    return CT_OK;
 }
 
 }  // namespace ct
