@@ -5,6 +5,8 @@
 // repeatable regardless of what else shares the device.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "dev_common.hpp"
@@ -476,6 +478,15 @@ struct DevMem {
     }
 };
 
+// CT_OOC_VERBOSE=1 reports each finished pass on stderr (long out-of-core runs)
+bool tv_verbose() {
+    static const bool v = [] {
+        const char *e = std::getenv("CT_OOC_VERBOSE");
+        return e && e[0] && e[0] != '0';
+    }();
+    return v;
+}
+
 struct OwnStream {
     hipStream_t s = nullptr;
     ~OwnStream() {
@@ -554,6 +565,11 @@ ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double la
             }
         }
         if (step == 0) alpha = lambda * std::sqrt(xx);
+        if (tv_verbose()) {
+            std::fprintf(stderr, "[ct ooc tv] step %d: norms done at %.1f s\n", step + 1,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+            std::fflush(stderr);
+        }
         const double hs[4] = {xx, alpha, gg, 0.0};
         CT_HIP(hipMemcpyAsync(dscal, hs, sizeof(hs), hipMemcpyHostToDevice, s));
         for (int64_t n = 0; n < nsp; ++n) {  // pass 2: update
@@ -573,6 +589,11 @@ ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double la
                                   s));
             CT_HIP(hipStreamSynchronize(s));
             st.bytes_d2h += (double)nown * 4;
+        }
+        if (tv_verbose()) {
+            std::fprintf(stderr, "[ct ooc tv] step %d: update done at %.1f s\n", step + 1,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+            std::fflush(stderr);
         }
     }
     CT_HIP(hipStreamSynchronize(s));
