@@ -17,11 +17,11 @@ FDK reconstruction (cosine weight, ramp filter, FDK-weighted backprojection).
 from .core import (Geometry, W_FDK, W_PM, bp, bp_coverage, bp_transpose, bp_voxels, get_threads,
                    interp_fwd, interp_ray, interp_rays, ray_endpoints, set_threads, siddon_adj,
                    siddon_adj_voxels, siddon_fwd, siddon_ray, siddon_rays, load)
-from .algos import cgls, fdk, fdk_filter, os_sart, ramp_taps, sart, tv_grad, tv_value, tv_steps
+from .algos import cgls, fdk, fdk_filter, os_sart, ramp_taps, sart, tv_grad, tv_value, tv_steps, tv_steps_split
 
 __all__ = [
     "Geometry", "W_FDK", "W_PM", "bp", "bp_coverage", "bp_transpose", "bp_voxels", "get_threads",
     "interp_fwd", "interp_ray", "interp_rays", "ray_endpoints", "set_threads", "siddon_adj",
     "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "load", "cgls", "fdk", "fdk_filter",
-    "os_sart", "ramp_taps", "sart", "tv_grad", "tv_value", "tv_steps",
+    "os_sart", "ramp_taps", "sart", "tv_grad", "tv_value", "tv_steps", "tv_steps_split",
 ]

@@ -658,3 +658,20 @@ def test_F3_fdk_exact_for_an_axially_invariant_object(orc):
     m = np.sqrt(xx ** 2 + yy ** 2) < 18.0
     assert m.sum() > 60000
     assert np.max(np.abs(rec[m] - 1.0)) <= 3e-3
+
+
+def test_T5_split_tv_reproduces_whole_image_steps(orc):
+    """Section 2.3's splitting with halos `depth` deep: with the exact image norm substituted for the
+    per-slab estimate, every slab height and depth gives the whole-image steps (the halo keeps each
+    slab's own slices exact for `depth` steps); with one slab the per-slab norm is the image norm.
+    A halo too shallow for its round, or a stale copy of a neighbour, fails this."""
+    rng = np.random.default_rng(4)
+    x0 = (rng.uniform(0, 1, (29, 17, 13)) > 0.7) * 0.8 + 0.05 * rng.standard_normal((29, 17, 13))
+    ref = orc.tv_steps(x0, 7, 0.01)
+    for slab, depth in ((10, 3), (5, 2), (1, 4), (7, 7), (4, 1), (3, 10)):
+        got = orc.tv_steps_split(x0, 7, 0.01, slab, depth, norm="global")
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(orc.tv_steps_split(x0, 7, 0.01, 29, 3), ref, rtol=0, atol=1e-13)
+    # the per-slab norm is an approximation: close to, not equal to, the whole-image steps
+    e = np.linalg.norm(orc.tv_steps_split(x0, 7, 0.01, 5, 2) - ref) / np.linalg.norm(ref)
+    assert 1e-6 < e < 1e-2
