@@ -346,7 +346,8 @@ def ooc_bench(dev, cap_gib=32):
 
 def ooc_tv_bench(dev, cap_gib=32, nsteps=2):
     """TV steepest descent on the 3072^3 FP32 phantom (108 GiB, pageable host memory) under a
-    cap_gib GiB device cap: slabs with halo slices, two passes over the image per step."""
+    cap_gib GiB device cap: the exact form (slabs with one halo slice, two passes over the image per
+    step), then the halo splitting with depths 8 and 60 (one pass per round of that many steps)."""
     import torch
     from paper_1905_03748_amd import inputs
     from paper_1905_03748_amd.operators import tv_steps_host
@@ -362,13 +363,18 @@ def ooc_tv_bench(dev, cap_gib=32, nsteps=2):
                              off_origin=(0.0, 0.0, (z0 + h / 2.0 - nz / 2.0) * w.dvox[2]))
         vol[z0:z0 + h].copy_(inputs.voxelize_torch(ws, ells, device=dev))
         torch.cuda.synchronize()
-    log(f"[ooc tv] {nsteps} steps")
-    st = tv_steps_host(w.geometry_dict(), vol, nsteps, 0.01, cap_bytes=cap_gib << 30)
-    out = {"workload": "3072^3 FP32 (108 GiB) phantom, pageable host memory", "cap_gib": cap_gib, "steps": nsteps}
-    out.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()
-                if k in ("n_slabs", "slab_slices", "bytes_h2d", "bytes_d2h", "t_total_s")})
-    out["s_per_step"] = round(st["t_total_s"] / nsteps, 2)
-    out["host_link_gbs"] = round((st["bytes_h2d"] + st["bytes_d2h"]) / st["t_total_s"] / 1e9, 2)
+    out = {"workload": "3072^3 FP32 (108 GiB) phantom, pageable host memory", "cap_gib": cap_gib}
+    # exact steps (two passes per step), then the halo splitting at depth 8 and at the paper's 60
+    for depth, steps in ((0, nsteps), (8, 8), (60, 60)):
+        log(f"[ooc tv] halo depth {depth}: {steps} steps")
+        st = tv_steps_host(w.geometry_dict(), vol, steps, 0.01, cap_bytes=cap_gib << 30, halo_depth=depth)
+        r = {"steps": steps}
+        r.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()
+                  if k in ("n_slabs", "slab_slices", "bytes_h2d", "bytes_d2h", "t_total_s")})
+        r["s_per_step"] = round(st["t_total_s"] / steps, 2)
+        r["host_link_gbs"] = round((st["bytes_h2d"] + st["bytes_d2h"]) / st["t_total_s"] / 1e9, 2)
+        out["exact" if depth == 0 else f"halo_{depth}"] = r
+        log(f"[ooc tv] {r}")
     del vol
     return out
 

@@ -259,10 +259,15 @@ ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, do
  * before the step.  The result equals ct_tv_steps up to the order of those FP64 sums (bitwise
  * equal with one slab).  h_x: host FP32 volume of the geometry's nVoxel shape, in: x, out: result
  * (pageable or pinned).  stats (may be NULL): n_slabs, slab_slices, bytes moved, t_total_s.
- * Synchronous.  Errors: as ct_tv_steps, and CT_ERR_CAP for a cap below one slice with its halos
- * and buffers (64 MiB reserve). */
+ * halo_depth = 0 selects that exact form.  halo_depth = d >= 1 selects the splitting of Section
+ * 2.3 instead: each slab carries d halo slices on either side and takes up to d steps on its own
+ * copy before writing back (one upload and one download of the image per d steps); each step's
+ * ||g||^2 is the slab's own sum scaled by (Nz / slab slices), the paper's uniform-distribution
+ * estimate, so results differ slightly from the exact form (alpha is exact).
+ * Synchronous.  Errors: as ct_tv_steps, CT_ERR_ARG for halo_depth outside [0, 4096], and
+ * CT_ERR_CAP for a cap below one slice with its halos and buffers (64 MiB reserve). */
 ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nsteps, double lambda, double eps,
-                           uint64_t device_cap_bytes, ct_ooc_stats *stats);
+                           int32_t halo_depth, uint64_t device_cap_bytes, ct_ooc_stats *stats);
 
 /* ---------------------------------------------------------------------------------------------
  * Small device utilities used by the algorithms, exported for callers that compose their own. */

@@ -75,7 +75,7 @@ SIGNATURES = {
     "ct_fdk": [_P, _P, _INT, _P, _INT, _P, _P],
     "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_tv_steps": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
-    "ct_tv_steps_host": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _U64, C.POINTER(ct_ooc_stats)],
+    "ct_tv_steps_host": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _I32, _U64, C.POINTER(ct_ooc_stats)],
     "ct_dot": [_P, _P, _INT, _I64, _P, _P],
     "ct_convert": [_P, _INT, _P, _INT, _I64, _P],
     "ct_last_error": [],
@@ -235,10 +235,10 @@ def ct_tv_steps(geometry: ct_geometry, d_x, nsteps, lam, eps=1e-8, d_workspace=0
                                     stream or None))
 
 
-def ct_tv_steps_host(geometry: ct_geometry, h_x, nsteps, lam, eps, device_cap_bytes) -> ct_ooc_stats:
+def ct_tv_steps_host(geometry: ct_geometry, h_x, nsteps, lam, eps, halo_depth, device_cap_bytes) -> ct_ooc_stats:
     s = ct_ooc_stats()
-    _check(lib().ct_tv_steps_host(C.byref(geometry), h_x, nsteps, float(lam), float(eps), int(device_cap_bytes),
-                                  C.byref(s)))
+    _check(lib().ct_tv_steps_host(C.byref(geometry), h_x, nsteps, float(lam), float(eps), int(halo_depth),
+                                  int(device_cap_bytes), C.byref(s)))
     return s
 
 

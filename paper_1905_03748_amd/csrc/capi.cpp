@@ -302,13 +302,14 @@ ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, do
 }
 
 ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nsteps, double lambda, double eps,
-                           uint64_t device_cap_bytes, ct_ooc_stats *stats) {
+                           int32_t halo_depth, uint64_t device_cap_bytes, ct_ooc_stats *stats) {
     if (!geometry || !h_x) return fail(CT_ERR_ARG, "ct_tv_steps_host: null pointer");
     if (nsteps < 0) return fail(CT_ERR_ARG, "ct_tv_steps_host: nsteps must be >= 0");
+    if (halo_depth < 0 || halo_depth > 4096) return fail(CT_ERR_ARG, "ct_tv_steps_host: halo_depth must be in [0, 4096]");
     if (!(eps > 0) || !std::isfinite(lambda)) return fail(CT_ERR_ARG, "ct_tv_steps_host: need eps > 0 and finite lambda");
     for (int a = 0; a < 3; ++a)
         if (geometry->nVoxel[a] <= 0) return fail(CT_ERR_GEOMETRY, "ct_tv_steps_host: voxel counts must be positive");
-    return tv_host_run(*geometry, h_x, nsteps, lambda, eps, device_cap_bytes, stats);
+    return tv_host_run(*geometry, h_x, nsteps, lambda, eps, halo_depth, device_cap_bytes, stats);
 }
 
 ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out, void *stream) {

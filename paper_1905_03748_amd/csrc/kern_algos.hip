@@ -496,8 +496,14 @@ struct OwnStream {
 
 }  // namespace
 
-ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, uint64_t cap,
-                      ct_ooc_stats *stats) {
+__global__ void k_scale_entry(double *p, double f) { *p *= f; }
+
+ct_status tv_host_run_halo(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, int32_t depth,
+                           uint64_t cap, ct_ooc_stats *stats);
+
+ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, int32_t depth,
+                      uint64_t cap, ct_ooc_stats *stats) {
+    if (depth > 0) return tv_host_run_halo(g, hx, nsteps, lambda, eps, depth, cap, stats);
     const auto t_start = std::chrono::steady_clock::now();
     const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1];
     const int64_t nz = g.nVoxel[2];
@@ -597,6 +603,110 @@ ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double la
         }
     }
     CT_HIP(hipStreamSynchronize(s));
+    st.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = st;
+    return CT_OK;
+}
+
+
+// The splitting of Section 2.3: each slab carries `depth` halo slices of its neighbours on either
+// side and takes up to `depth` steps on its own copy before the slabs exchange anything.  A halo
+// slice stops being exact one step after its outer neighbour, so the gradient is computed on a
+// region that shrinks by a slice per step at each inner boundary and always covers the slab's own
+// slices.  Each step's ||g||^2 is the slab's own sum scaled by (image slices / slab slices), the
+// uniform-distribution estimate, so no norm is exchanged; alpha = lambda ||x_in|| comes from one
+// pass over the whole image first.  In a round every slab starts from the image as it stood at the
+// round's start: the lower halo is a device copy of the slices below, taken before their update.
+ct_status tv_host_run_halo(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, int32_t depth,
+                           uint64_t cap, ct_ooc_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1];
+    const int64_t nz = g.nVoxel[2];
+    const int64_t d = depth;
+    const int64_t slice = (int64_t)nx * ny;
+    const uint64_t sb = (uint64_t)slice * sizeof(float);
+    const uint64_t fixed = TV_RESERVE + align256(DOT_BLOCKS * 8) + align256(4 * 8);
+    // device: the slab with its halos, the gradient of the same, `depth` saved slices
+    if (cap <= fixed || (cap - fixed) / sb < (uint64_t)(5 * d + 2))
+        return fail(CT_ERR_CAP, "device memory cap is below one slab slice plus halos and buffers");
+    int64_t h = (int64_t)(((cap - fixed) / sb - 5 * d) / 2);
+    h = std::max<int64_t>(1, std::min<int64_t>(h, nz));
+    const int64_t nsp = (nz + h - 1) / h;
+    h = (nz + nsp - 1) / nsp;
+    ct_ooc_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.n_slabs = (int32_t)nsp;
+    st.slab_slices = (int32_t)h;
+    OwnStream S;
+    CT_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
+    DevMem xb, gb, saved, parts, scal;
+    CT_HIP(hipMalloc(&xb.p, (size_t)(h + 2 * d) * sb));
+    CT_HIP(hipMalloc(&gb.p, (size_t)(h + 2 * d) * sb));
+    CT_HIP(hipMalloc(&saved.p, (size_t)d * sb));
+    CT_HIP(hipMalloc(&parts.p, DOT_BLOCKS * 8));
+    CT_HIP(hipMalloc(&scal.p, 4 * 8));
+    float *xbuf = (float *)xb.p, *gbuf = (float *)gb.p, *sbuf = (float *)saved.p;
+    double *dscal = (double *)scal.p;
+    const hipStream_t s = S.s;
+    ct_status e = CT_OK;
+    // alpha from ||x_in||, summed slab by slab in FP64
+    double xx = 0.0;
+    for (int64_t n = 0; n < nsp; ++n) {
+        const int64_t o0 = n * h, o1 = std::min(nz, o0 + h);
+        CT_HIP(hipMemcpyAsync(xbuf, hx + o0 * slice, (size_t)(o1 - o0) * sb, hipMemcpyHostToDevice, s));
+        st.bytes_h2d += (double)(o1 - o0) * sb;
+        if ((e = dot_f64(xbuf, xbuf, CT_F32, (o1 - o0) * slice, dscal + 3, (double *)parts.p, s)) != CT_OK) return e;
+        double v = 0.0;
+        CT_HIP(hipMemcpyAsync(&v, dscal + 3, 8, hipMemcpyDeviceToHost, s));
+        CT_HIP(hipStreamSynchronize(s));
+        xx += v;
+    }
+    const double hs[4] = {xx, lambda * std::sqrt(xx), 0.0, 0.0};
+    CT_HIP(hipMemcpyAsync(dscal, hs, sizeof(hs), hipMemcpyHostToDevice, s));
+    CT_HIP(hipStreamSynchronize(s));
+    for (int32_t done = 0; done < nsteps;) {
+        const int64_t k = std::min<int64_t>(d, nsteps - done);
+        for (int64_t n = 0; n < nsp; ++n) {
+            const int64_t o0 = n * h, o1 = std::min(nz, o0 + h);
+            const int64_t m0 = std::max<int64_t>(0, o0 - d), m1 = std::min(nz, o1 + d);
+            CT_HIP(hipMemcpyAsync(xbuf + (o0 - m0) * slice, hx + o0 * slice, (size_t)(m1 - o0) * sb,
+                                  hipMemcpyHostToDevice, s));
+            st.bytes_h2d += (double)(m1 - o0) * sb;
+            if (o0 > m0) CT_HIP(hipMemcpyAsync(xbuf, sbuf, (size_t)(o0 - m0) * sb, hipMemcpyDeviceToDevice, s));
+            if (n + 1 < nsp) {  // the next slab's lower halo, as it stands at the round's start
+                const int64_t n0 = std::max<int64_t>(0, o1 - d);
+                CT_HIP(hipMemcpyAsync(sbuf, xbuf + (n0 - m0) * slice, (size_t)(o1 - n0) * sb, hipMemcpyDeviceToDevice,
+                                      s));
+            }
+            const int64_t nown = (o1 - o0) * slice;
+            for (int64_t i = 0; i < k; ++i) {
+                const int64_t r0 = m0 == 0 ? 0 : m0 + i + 1, r1 = m1 == nz ? nz : m1 - i - 1;
+                const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)(r1 - r0));
+                hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, (const float *)xbuf, gbuf, nx, ny, (int)nz,
+                                   (float)eps, m0, r0);
+                CT_HIP(hipGetLastError());
+                if ((e = dot_f64(gbuf + (o0 - r0) * slice, gbuf + (o0 - r0) * slice, CT_F32, nown, dscal + 2,
+                                 (double *)parts.p, s)) != CT_OK)
+                    return e;
+                hipLaunchKernelGGL(k_scale_entry, dim3(1), dim3(1), 0, s, dscal + 2, (double)nz / (double)(o1 - o0));
+                CT_HIP(hipGetLastError());
+                const int64_t nr = (r1 - r0) * slice;
+                hipLaunchKernelGGL(k_tv_update, dim3(ew_grid(nr)), dim3(EW_THREADS), 0, s, xbuf + (r0 - m0) * slice,
+                                   (const float *)gbuf, (const double *)dscal, nr);
+                CT_HIP(hipGetLastError());
+            }
+            CT_HIP(hipMemcpyAsync(hx + o0 * slice, xbuf + (o0 - m0) * slice, (size_t)nown * 4, hipMemcpyDeviceToHost,
+                                  s));
+            CT_HIP(hipStreamSynchronize(s));
+            st.bytes_d2h += (double)nown * 4;
+        }
+        done += (int32_t)k;
+        if (tv_verbose()) {
+            std::fprintf(stderr, "[ct ooc tv] %d of %d steps done at %.1f s\n", done, nsteps,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+            std::fflush(stderr);
+        }
+    }
     st.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     if (stats) *stats = st;
     return CT_OK;

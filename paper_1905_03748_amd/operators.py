@@ -229,12 +229,14 @@ def tv_steps(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps: floa
 
 
 def tv_steps_host(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps: float = 1e-8,
-                  cap_bytes=32 << 30) -> dict:
-    """TV steepest descent in place on the FP32 host volume x, under a device memory cap."""
+                  cap_bytes=32 << 30, halo_depth=0) -> dict:
+    """TV steepest descent in place on the FP32 host volume x, under a device memory cap:
+    exact (halo_depth 0) or split with halos halo_depth deep and per-slab norm estimates."""
     nx, ny, nz = (int(v) for v in geometry["nVoxel"])
     if x.device.type != "cpu" or not x.is_contiguous() or x.dtype != torch.float32 or tuple(x.shape) != (nz, ny, nx):
         raise ValueError(f"x must be a contiguous FP32 host tensor of shape {(nz, ny, nx)}")
-    return A.ct_tv_steps_host(A.make_geometry(geometry), x.data_ptr(), nsteps, lam, eps, cap_bytes).as_dict()
+    return A.ct_tv_steps_host(A.make_geometry(geometry), x.data_ptr(), nsteps, lam, eps, halo_depth,
+                              cap_bytes).as_dict()
 
 
 def tv_workspace_bytes(geometry: dict) -> int:

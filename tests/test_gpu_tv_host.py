@@ -63,3 +63,22 @@ def test_tv_host_edge_cases():
     assert e.value.status == CT_ERR_CAP
     with pytest.raises(ValueError):
         tv_steps_host(geo, x.double(), 1, 0.01)
+
+
+@pytest.mark.parametrize("h,d", [(29, 3), (10, 3), (5, 2), (1, 4), (3, 10)])
+def test_tv_host_halo_split_matches_oracle(orc, h, d):
+    """The splitting of Section 2.3 (halos d deep, d steps per exchange, per-slab norm estimates):
+    against the oracle's form of the same scheme with the slab height the planner chose."""
+    nz, ny, nx = 29, 17, 31
+    rng = np.random.default_rng(82)
+    x0 = (rng.uniform(0, 1, (nz, ny, nx)) > 0.7).astype(np.float32) * 0.8 + \
+        0.05 * rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    say(f"[tv host halo] slab height {h}, depth {d}")
+    x = torch.from_numpy(x0.copy())
+    # the slab and its gradient with d halo slices each side, and d saved slices
+    st = tv_steps_host(_geo(nx, ny, nz), x, 7, 0.01, cap_bytes=FIXED + (2 * h + 5 * d) * nx * ny * 4, halo_depth=d)
+    assert st["n_slabs"] == -(-nz // h), st
+    ref = orc.tv_steps_split(x0.astype(np.float64), 7, 0.01, st["slab_slices"], d, norm="split")
+    e = rel_l2(x.numpy(), ref)
+    say(f"   rel L2 vs oracle {e:.3e}")
+    assert e <= 1e-5
