@@ -117,6 +117,18 @@ def test_fdk_filter_wide_rows(orc, nu):
     assert e <= TOL_PROJ
 
 
+@pytest.mark.parametrize("nu", [1, 2, 3, 9])
+def test_fdk_degenerate_rows(orc, nu):
+    """Rows of 1 to 9 pixels: no odd offset at all (1), a single tap pair, and a row shorter than
+    one thread's 8 outputs; the reconstruction too."""
+    w = inputs.Workload("fdk_short", (6, 5, 4), (1.0, 1.0, 1.0), (nu, 2), (1.3, 1.1), 3, 0, 0)
+    p = inputs.random_array((3, 2, nu), 90 + nu, kind="uniform")
+    plan, og, pt = _case(w, p, orc)
+    say(f"[fdk] rows of {nu} pixels")
+    assert rel_l2(plan.fdk_filter(pt).cpu().numpy(), orc.fdk_filter(og, w.angles, p.astype(np.float64))) <= TOL_PROJ
+    assert rel_l2(plan.fdk(pt).cpu().numpy(), orc.fdk(og, w.angles, p.astype(np.float64))) <= TOL_BP
+
+
 def test_fdk_medium_sampled(orc):
     """512^3, 360 angles, 512^2 detector (the benchmark's size, in the launch the benchmark times):
     filtered rows at 2000 sampled pixels, and the reconstruction at 400 sampled voxels against the

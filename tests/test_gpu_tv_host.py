@@ -82,3 +82,14 @@ def test_tv_host_halo_split_matches_oracle(orc, h, d):
     e = rel_l2(x.numpy(), ref)
     say(f"   rel L2 vs oracle {e:.3e}")
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("d", [0, 1, 3])
+def test_tv_host_single_slice(orc, d):
+    """A one-slice image: no halo on either side, in the exact form and the split form."""
+    ny, nx = 19, 23
+    x0 = np.random.default_rng(83).uniform(0, 1, (1, ny, nx)).astype(np.float32)
+    x = torch.from_numpy(x0.copy())
+    st = tv_steps_host(_geo(nx, ny, 1), x, 4, 0.01, cap_bytes=FIXED + (2 + 5 * max(d, 1)) * nx * ny * 4, halo_depth=d)
+    assert st["n_slabs"] == 1
+    assert rel_l2(x.numpy(), orc.tv_steps(x0.astype(np.float64), 4, 0.01)) <= 1e-5
