@@ -251,3 +251,49 @@ def tv_steps_split(x, nsteps, lam, slab, depth, eps=1e-8, norm="split"):
             x[o0:o1] = loc[o0 - m0:o1 - m0]
         done += k
     return x
+
+
+def grad3(u):
+    """Forward differences on a unit grid along each axis, zero at the last index (the gradient of
+    the TV and ROF models); returns an array of shape (3,) + u.shape, axis order of u."""
+    u = np.asarray(u, dtype=np.float64)
+    g = np.zeros((3,) + u.shape)
+    for a in range(3):
+        d = np.diff(u, axis=a)
+        sl = [slice(None)] * 3
+        sl[a] = slice(0, u.shape[a] - 1)
+        g[a][tuple(sl)] = d
+    return g
+
+
+def div3(p):
+    """Discrete divergence, minus the adjoint of `grad3`: along each axis p_i - p_{i-1} inside,
+    p_0 at the first index and -p_{n-2} at the last (Chambolle 2004, Section 2)."""
+    p = np.asarray(p, dtype=np.float64)
+    out = np.zeros(p.shape[1:])
+    for a in range(3):
+        q = np.moveaxis(p[a], a, 0)
+        n = q.shape[0]
+        d = np.zeros_like(q)
+        if n == 1:
+            d[0] = 0.0
+        else:
+            d[0] = q[0]
+            d[1:n - 1] = q[1:n - 1] - q[0:n - 2]
+            d[n - 1] = -q[n - 2]
+        out += np.moveaxis(d, 0, a)
+    return out
+
+
+def rof_chambolle(f, lam, niter, tau=1.0 / 12.0):
+    """The ROF model min_u ||u - f||^2 / (2 lam) + sum_j |(grad u)_j| (Rudin, Osher & Fatemi 1992,
+    the second TV minimiser of Section 2.3), solved by Chambolle's dual projection iteration
+    (Chambolle 2004): from p = 0,
+        w = div p - f / lam,   p <- (p + tau grad w) / (1 + tau |grad w|),
+    and u = f - lam div p.  tau <= 1/12 converges in 3D (||div||^2 <= 12)."""
+    f = np.asarray(f, dtype=np.float64)
+    p = np.zeros((3,) + f.shape)
+    for _ in range(niter):
+        g = grad3(div3(p) - f / lam)
+        p = (p + tau * g) / (1.0 + tau * np.sqrt(np.sum(g * g, axis=0)))
+    return f - lam * div3(p)

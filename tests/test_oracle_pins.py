@@ -675,3 +675,38 @@ def test_T5_split_tv_reproduces_whole_image_steps(orc):
     # the per-slab norm is an approximation: close to, not equal to, the whole-image steps
     e = np.linalg.norm(orc.tv_steps_split(x0, 7, 0.01, 5, 2) - ref) / np.linalg.norm(ref)
     assert 1e-6 < e < 1e-2
+
+
+# --- ROF model by Chambolle's projection (the second TV minimiser of Section 2.3)
+
+def test_R1_divergence_is_minus_the_adjoint_of_the_gradient(orc):
+    """<grad u, p> = -<u, div p> for any u and p, the identity Chambolle's iteration rests on; a
+    wrong boundary row of either operator breaks it."""
+    rng = np.random.default_rng(1)
+    for shape in ((5, 6, 7), (1, 4, 9), (2, 1, 1)):
+        u = rng.standard_normal(shape)
+        p = rng.standard_normal((3,) + shape)
+        lhs = np.sum(orc.grad3(u) * p)
+        assert abs(lhs + np.sum(u * orc.div3(p))) <= 1e-12 * (np.abs(u).sum() * np.abs(p).sum())
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_R2_rof_of_a_step_has_the_closed_form(orc, axis):
+    """A step of height h between two runs of n samples: the ROF solution keeps the step and moves
+    each level by lam / n towards the other (minimise n a^2 + n (b - h)^2 over 2 lam + |b - a|),
+    when h > 2 lam / n.  Along each axis in turn."""
+    n, h, lam = 8, 1.0, 2.0
+    shape = [1, 1, 1]
+    shape[axis] = 2 * n
+    idx = np.arange(2 * n).reshape(shape)
+    f = np.where(idx >= n, h, 0.0)
+    u = orc.rof_chambolle(f, lam, 5000)
+    want = np.where(idx < n, lam / n, h - lam / n)
+    np.testing.assert_allclose(u, want, rtol=0, atol=1e-8)
+
+
+def test_R3_rof_keeps_the_mean_and_constant_images(orc):
+    rng = np.random.default_rng(2)
+    x0 = rng.uniform(0, 1, (9, 8, 7))
+    assert abs(orc.rof_chambolle(x0, 0.1, 50).mean() - x0.mean()) <= 1e-14
+    np.testing.assert_array_equal(orc.rof_chambolle(np.full((4, 5, 6), 0.3), 0.1, 20), np.full((4, 5, 6), 0.3))
