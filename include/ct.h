@@ -269,6 +269,21 @@ ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, do
 ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nsteps, double lambda, double eps,
                            int32_t halo_depth, uint64_t device_cap_bytes, ct_ooc_stats *stats);
 
+/* The ROF model (Rudin, Osher and Fatemi; the second TV minimiser of Section 2.3):
+ *   min_u ||u - f||^2 / (2 lambda) + sum_j |(grad u)_j|
+ * with forward differences on a unit grid, zero at the last index of each axis, solved by
+ * Chambolle's projection iteration (2004): from p = 0, niter times
+ *   w = div p - f / lambda,   p <- (p + tau grad w) / (1 + tau |grad w|),
+ * then u = f - lambda div p, div being minus the adjoint of grad.  tau <= 1/12 converges in 3D.
+ * FP32 throughout.  d_x: device FP32 volume of the geometry's nVoxel shape, in: f, out: u.
+ * d_workspace: device memory of at least ct_rof_workspace_bytes bytes (p and w: four volumes), or
+ * NULL for stream-ordered scratch.  Stream-ordered.  Errors: CT_ERR_ARG for a NULL pointer,
+ * niter < 0, lambda or tau not finite and positive, or more than 65535 slices; CT_ERR_GEOMETRY
+ * for a non-positive voxel count. */
+ct_status ct_rof_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes);
+ct_status ct_rof(const ct_geometry *geometry, void *d_x, int32_t niter, double lambda, double tau, void *d_workspace,
+                 void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Small device utilities used by the algorithms, exported for callers that compose their own. */
 

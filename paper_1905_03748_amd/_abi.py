@@ -76,6 +76,8 @@ SIGNATURES = {
     "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_tv_steps": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
     "ct_tv_steps_host": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _I32, _U64, C.POINTER(ct_ooc_stats)],
+    "ct_rof_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
+    "ct_rof": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
     "ct_dot": [_P, _P, _INT, _I64, _P, _P],
     "ct_convert": [_P, _INT, _P, _INT, _I64, _P],
     "ct_last_error": [],
@@ -240,6 +242,17 @@ def ct_tv_steps_host(geometry: ct_geometry, h_x, nsteps, lam, eps, halo_depth, d
     _check(lib().ct_tv_steps_host(C.byref(geometry), h_x, nsteps, float(lam), float(eps), int(halo_depth),
                                   int(device_cap_bytes), C.byref(s)))
     return s
+
+
+def ct_rof_workspace_bytes(geometry: ct_geometry) -> int:
+    b = _U64()
+    _check(lib().ct_rof_workspace_bytes(C.byref(geometry), C.byref(b)))
+    return b.value
+
+
+def ct_rof(geometry: ct_geometry, d_x, niter, lam, tau, d_workspace=0, stream=0):
+    return _check(lib().ct_rof(C.byref(geometry), d_x, niter, float(lam), float(tau), d_workspace or None,
+                               stream or None))
 
 
 def ct_dot(d_a, d_b, dtype, n, d_out, stream=0):

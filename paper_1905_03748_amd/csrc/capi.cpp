@@ -312,6 +312,24 @@ ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nste
     return tv_host_run(*geometry, h_x, nsteps, lambda, eps, halo_depth, device_cap_bytes, stats);
 }
 
+ct_status ct_rof_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes) {
+    if (!geometry || !bytes) return fail(CT_ERR_ARG, "ct_rof_workspace_bytes: null pointer");
+    *bytes = rof_workspace(*geometry);
+    return CT_OK;
+}
+
+ct_status ct_rof(const ct_geometry *geometry, void *d_x, int32_t niter, double lambda, double tau, void *d_workspace,
+                 void *stream) {
+    if (!geometry || !d_x) return fail(CT_ERR_ARG, "ct_rof: null pointer");
+    if (niter < 0) return fail(CT_ERR_ARG, "ct_rof: niter must be >= 0");
+    if (!(lambda > 0) || !std::isfinite(lambda) || !(tau > 0) || !std::isfinite(tau))
+        return fail(CT_ERR_ARG, "ct_rof: need finite lambda > 0 and tau > 0");
+    for (int a = 0; a < 3; ++a)
+        if (geometry->nVoxel[a] <= 0) return fail(CT_ERR_GEOMETRY, "ct_rof: voxel counts must be positive");
+    if (geometry->nVoxel[2] > 65535) return fail(CT_ERR_ARG, "ct_rof: more than 65535 slices");
+    return rof_run(*geometry, d_x, niter, lambda, tau, d_workspace, (hipStream_t)stream);
+}
+
 ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out, void *stream) {
     if (!d_a || !d_b || !d_out) return fail(CT_ERR_ARG, "ct_dot: null pointer");
     if (n < 0) return fail(CT_ERR_ARG, "ct_dot: negative length");

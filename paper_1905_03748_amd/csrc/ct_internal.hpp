@@ -132,6 +132,8 @@ size_t sart_workspace(const ct_plan *p, int32_t block);
 ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work,
                  hipStream_t st);
 size_t tv_workspace(const ct_geometry &g);
+ct_status rof_run(const ct_geometry &g, void *x, int32_t niter, double lambda, double tau, void *work, hipStream_t st);
+size_t rof_workspace(const ct_geometry &g);
 ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, int32_t depth,
                       uint64_t cap, ct_ooc_stats *stats);
 // FDK reconstruction (kern_fdk.hip): weighted, ramp-filtered FP32 rows of the angles [a0, a1)

@@ -213,6 +213,70 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float *__restrict__ x, fl
     g[(k - kg0) * sz + (int64_t)j * sy + i] = gv;
 }
 
+// ROF model by Chambolle's projection.  The dual field p = (px, py, pz) holds one FP32 volume per
+// axis.  Divergence, minus the adjoint of the forward-difference gradient: along each axis
+// p_i - p_{i-1} inside, p_0 at the first index, -p_{n-2} at the last, 0 for an axis of one voxel.
+__device__ __forceinline__ float rof_div(const float *__restrict__ px, const float *__restrict__ py,
+                                         const float *__restrict__ pz, int i, int j, int k, int nx, int ny, int nz,
+                                         int64_t o, int64_t sy, int64_t sz) {
+    float d = 0.0f;
+    if (nz > 1) d += k == 0 ? pz[o] : (k == nz - 1 ? -pz[o - sz] : pz[o] - pz[o - sz]);
+    if (ny > 1) d += j == 0 ? py[o] : (j == ny - 1 ? -py[o - sy] : py[o] - py[o - sy]);
+    if (nx > 1) d += i == 0 ? px[o] : (i == nx - 1 ? -px[o - 1] : px[o] - px[o - 1]);
+    return d;
+}
+
+// w = div p - f / lam
+__global__ __launch_bounds__(256) void k_rof_w(const float *__restrict__ f, const float *__restrict__ px,
+                                               const float *__restrict__ py, const float *__restrict__ pz,
+                                               float *__restrict__ w, int nx, int ny, int nz, float inv_lam) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t o = k * sz + (int64_t)j * sy + i;
+    w[o] = rof_div(px, py, pz, i, j, k, nx, ny, nz, o, sy, sz) - f[o] * inv_lam;
+}
+
+// p <- (p + tau grad w) / (1 + tau |grad w|), forward differences, zero at the last index
+__global__ __launch_bounds__(256) void k_rof_p(const float *__restrict__ w, float *__restrict__ px,
+                                               float *__restrict__ py, float *__restrict__ pz, int nx, int ny, int nz,
+                                               float tau) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t o = k * sz + (int64_t)j * sy + i;
+    const float wc = w[o];
+    const float gx = i < nx - 1 ? w[o + 1] - wc : 0.0f;
+    const float gy = j < ny - 1 ? w[o + sy] - wc : 0.0f;
+    const float gz = k < nz - 1 ? w[o + sz] - wc : 0.0f;
+    const float den = 1.0f + tau * sqrtf(gx * gx + gy * gy + gz * gz);
+    px[o] = (px[o] + tau * gx) / den;
+    py[o] = (py[o] + tau * gy) / den;
+    pz[o] = (pz[o] + tau * gz) / den;
+}
+
+// u = f - lam div p, in place over f (each voxel reads only its own f)
+__global__ __launch_bounds__(256) void k_rof_u(float *__restrict__ x, const float *__restrict__ px,
+                                               const float *__restrict__ py, const float *__restrict__ pz, int nx,
+                                               int ny, int nz, float lam) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= nx || j >= ny) return;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t o = k * sz + (int64_t)j * sy + i;
+    x[o] = fmaf(-lam, rof_div(px, py, pz, i, j, k, nx, ny, nz, o, sy, sz), x[o]);
+}
+
+__global__ void k_fill_zero(float *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
 // TV scalars: [0] = ||x_in||^2, [1] = alpha, [2] = ||g||^2
 __global__ void k_tv_alpha(double *scal, double lambda) { scal[1] = lambda * sqrt(scal[0]); }
 
@@ -457,6 +521,38 @@ ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, d
 #undef CK
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// ROF model (Chambolle's projection): workspace px, py, pz, w
+
+size_t rof_workspace(const ct_geometry &g) {
+    const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
+    return 4 * align256(nv * 4);
+}
+
+ct_status rof_run(const ct_geometry &g, void *x, int32_t niter, double lambda, double tau, void *work, hipStream_t st) {
+    const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1], nz = (int)g.nVoxel[2];
+    const int64_t nv = (int64_t)nx * ny * nz;
+    Workspace ws;
+    ct_status s = ws.acquire(work, rof_workspace(g), st);
+    if (s != CT_OK) return s;
+    float *px = (float *)ws.take(nv * 4), *py = (float *)ws.take(nv * 4), *pz = (float *)ws.take(nv * 4);
+    float *w = (float *)ws.take(nv * 4);
+    hipLaunchKernelGGL(k_fill_zero, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, px, nv);
+    hipLaunchKernelGGL(k_fill_zero, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, py, nv);
+    hipLaunchKernelGGL(k_fill_zero, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, pz, nv);
+    CT_HIP(hipGetLastError());
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz);
+    for (int32_t it = 0; it < niter; ++it) {
+        hipLaunchKernelGGL(k_rof_w, grid, dim3(256), 0, st, (const float *)x, px, py, pz, w, nx, ny, nz,
+                           (float)(1.0 / lambda));
+        hipLaunchKernelGGL(k_rof_p, grid, dim3(256), 0, st, (const float *)w, px, py, pz, nx, ny, nz, (float)tau);
+        CT_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_rof_u, grid, dim3(256), 0, st, (float *)x, px, py, pz, nx, ny, nz, (float)lambda);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
 
 // ---------------------------------------------------------------------------------------------
 // TV steepest descent out of core: the image in host memory, slabs of axial slices under a device

@@ -239,6 +239,23 @@ def tv_steps_host(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps:
                               cap_bytes).as_dict()
 
 
+def rof(geometry: dict, x: torch.Tensor, niter: int, lam: float, tau: float = 1.0 / 12.0, workspace=None,
+        stream=None) -> torch.Tensor:
+    """ROF denoising in place on the FP32 device volume x (Chambolle's projection, niter iterations)."""
+    nx, ny, nz = (int(v) for v in geometry["nVoxel"])
+    if x.dtype != torch.float32:
+        raise TypeError("rof works on FP32 volumes")
+    if workspace is not None:
+        _check_workspace(workspace, rof_workspace_bytes(geometry))
+    A.ct_rof(A.make_geometry(geometry), _dev(x, (nz, ny, nx), "x"), niter, lam, tau,
+             workspace.data_ptr() if workspace is not None else 0, _stream(stream))
+    return x
+
+
+def rof_workspace_bytes(geometry: dict) -> int:
+    return A.ct_rof_workspace_bytes(A.make_geometry(geometry))
+
+
 def tv_workspace_bytes(geometry: dict) -> int:
     return A.ct_tv_workspace_bytes(A.make_geometry(geometry))
 

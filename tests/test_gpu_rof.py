@@ -1,0 +1,66 @@
+"""The ROF model by Chambolle's projection (ct_rof) against the FP64 oracle: a noisy phantom, the
+closed-form step along each axis, constant images, no iterations, caller workspace and errors."""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import rel_l2, say
+from paper_1905_03748_amd.operators import rof, rof_workspace_bytes
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _geo(nx, ny, nz):
+    return dict(DSO=1000.0, DSD=1500.0, nVoxel=(nx, ny, nz), dVoxel=(1.0, 1.0, 1.0), offOrigin=(0, 0, 0),
+                nDetector=(8, 8), dDetector=(1.0, 1.0), offDetector=(0, 0), accuracy=0.5)
+
+
+def test_rof_parity(orc):
+    nz, ny, nx = 23, 17, 31
+    rng = np.random.default_rng(84)
+    f = (rng.uniform(0, 1, (nz, ny, nx)) > 0.7).astype(np.float32) * 0.8 + \
+        0.05 * rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    say("[rof] 23 x 17 x 31, 40 iterations")
+    x = torch.from_numpy(f).to(DEV)
+    rof(_geo(nx, ny, nz), x, 40, 0.1)
+    ref = orc.rof_chambolle(f.astype(np.float64), 0.1, 40)
+    e = rel_l2(x.cpu().numpy(), ref)
+    say(f"   rel L2 vs oracle {e:.3e}")
+    assert e <= 1e-5
+    ws = torch.empty(rof_workspace_bytes(_geo(nx, ny, nz)), dtype=torch.uint8, device=DEV)
+    x2 = torch.from_numpy(f).to(DEV)
+    rof(_geo(nx, ny, nz), x2, 40, 0.1, workspace=ws)
+    assert torch.equal(x, x2)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_rof_step_closed_form(axis):
+    """Each level of a step moves by lam / n towards the other (the oracle's R2 pin), on the GPU."""
+    n, h, lam = 8, 1.0, 2.0
+    shape = [1, 1, 1]
+    shape[axis] = 2 * n
+    idx = np.arange(2 * n).reshape(shape)
+    f = np.where(idx >= n, h, 0.0).astype(np.float32)
+    x = torch.from_numpy(f).to(DEV)
+    rof(_geo(shape[2], shape[1], shape[0]), x, 5000, lam)
+    want = np.where(idx < n, lam / n, h - lam / n)
+    assert np.max(np.abs(x.cpu().numpy() - want)) <= 1e-4
+
+
+def test_rof_edge_cases():
+    g = _geo(7, 5, 6)
+    x = torch.full((6, 5, 7), 0.3, device=DEV)
+    rof(g, x, 20, 0.1)
+    assert float((x - 0.3).abs().max()) == 0.0
+    y = torch.rand((6, 5, 7), device=DEV)
+    y0 = y.clone()
+    rof(g, y, 0, 0.1)
+    assert torch.equal(y, y0)
+    from paper_1905_03748_amd._abi import CT_ERR_ARG, CtError
+    for lam, tau, it in ((0.0, 0.08, 1), (0.1, 0.0, 1), (float("nan"), 0.08, 1), (0.1, 0.08, -1)):
+        with pytest.raises(CtError) as e:
+            rof(g, y, it, lam, tau)
+        assert e.value.status == CT_ERR_ARG
+    with pytest.raises(ValueError):
+        rof(g, y, 1, 0.1, workspace=torch.empty(16, dtype=torch.uint8, device=DEV))
