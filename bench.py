@@ -509,6 +509,10 @@ def main():
         tws = torch.empty(tv_workspace_bytes(plan.geometry), dtype=torch.uint8, device=dev)
         xt = x.clone()
         ex["tv_5steps_ms"] = round(timed(lambda: tv_steps(plan.geometry, xt, 5, 0.01, workspace=tws), 1), 3)
+        from paper_1905_03748_amd.operators import rof, rof_workspace_bytes
+        rws = torch.empty(rof_workspace_bytes(plan.geometry), dtype=torch.uint8, device=dev)
+        ex["rof_10iter_ms"] = round(timed(lambda: rof(plan.geometry, xt, 10, 0.05, workspace=rws), 1), 3)
+        del rws
         fq = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
         ex["fdk_filter_ms"] = round(timed(lambda: plan.fdk_filter(p, out=fq), 2), 3)
         ex["fdk_recon_ms"] = round(timed(lambda: plan.fdk(p, out=v, workspace=fq.view(torch.uint8)), 2), 3)
