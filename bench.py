@@ -7,7 +7,7 @@ then v = B p (voxel-driven FDK backprojection), inputs resident in HBM.  value =
 
 The roofline entry is for the dominant kernel of the step, with algorithmic bytes under the
 gather model (bytes each unit of work must read if nothing were reused):
-  Siddon forward      segments * 4 B, 1.132 segments per voxel.proj at this workload
+  Siddon forward      segments * 4 B, 1.133 segments per voxel.proj at this workload
   FDK backprojection  4 bilinear taps * 4 B = 16 B per voxel.proj
 divided by the kernel's average duration measured with HIP events on its stream.
 """
@@ -25,9 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Siddon pieces per voxel.proj for the 512^3 / 360 / 512^2 workload (oracle count over a seeded
-# sample of 20000 rays, scaled)
-SIDDON_SEG_PER_VP = 1.132
+# Siddon pieces per voxel.proj for the 512^3 / 360 / 512^2 workload: the oracle's count over a seeded
+# sample of rays, stored by tests/golden/make_siddon_segments.py (and re-checked by the CPU tests)
+SIDDON_SEG_PER_VP = json.load(open(os.path.join(ROOT, "tests", "golden", "siddon_segments.json")))["pieces_per_voxel_proj"]
 BYTES_PER_VP = {"siddon": 4.0 * SIDDON_SEG_PER_VP, "fdk": 16.0}
 
 

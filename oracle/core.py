@@ -85,6 +85,7 @@ def load():
             "orc_interp_ray": (d, [g, pd, pd, pd, pi]),
             "orc_siddon_fwd": (None, [g, pd, i64, pd, pd, pi]),
             "orc_siddon_rays": (None, [g, pd, pi, i64, pd, pd]),
+            "orc_siddon_segments": (None, [g, pd, pi, i64, pi]),
             "orc_siddon_adj": (None, [g, pd, i64, pd, pd]),
             "orc_siddon_adj_voxels": (None, [g, pd, i64, pd, pi, i64, pd]),
             "orc_interp_fwd": (None, [g, pd, i64, pd, pd, pi]),
@@ -94,7 +95,6 @@ def load():
             "orc_siddon_rays_f32": (None, [g, pd, pi, i64, C.POINTER(C.c_float), pd]),
             "orc_bp_voxels_f32": (None, [g, pd, i64, C.POINTER(C.c_float), C.c_int, pi, i64, pd]),
             "orc_siddon_adj_voxels_f32": (None, [g, pd, i64, C.POINTER(C.c_float), pi, i64, pd]),
-            "orc_bp_coverage": (None, [g, d, pd]),
             "orc_bp_transpose": (None, [g, pd, i64, pd, C.c_int, pd]),
         }
         for name, (res, args) in sig.items():
@@ -172,6 +172,15 @@ def siddon_rays(geo: Geometry, angles, ray_idx, vol):
     return out
 
 
+def siddon_segments(geo: Geometry, angles, ray_idx):
+    """Number of Siddon pieces of selected rays (flat indices as siddon_rays)."""
+    angles = _f64(angles)
+    idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
+    out = np.zeros(len(idx), dtype=np.int64)
+    load().orc_siddon_segments(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx), _pi(out))
+    return out
+
+
 def siddon_adj(geo: Geometry, angles, proj):
     angles, proj = _f64(angles), _f64(proj)
     out = np.zeros(geo.vol_shape)
@@ -231,12 +240,6 @@ def bp_voxels(geo: Geometry, angles, proj, vox_idx, kind=W_FDK):
     proj = _f64(proj)
     load().orc_bp_voxels(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), int(kind), _pi(idx),
                          len(idx), _pd(out))
-    return out
-
-
-def bp_coverage(geo: Geometry, theta: float):
-    out = np.zeros(geo.vol_shape)
-    load().orc_bp_coverage(C.byref(geo.c()), float(theta), _pd(out))
     return out
 
 

@@ -383,6 +383,30 @@ void orc_siddon_rays(const orc_geom *g, const double *angles, const int64_t *ray
     }
 }
 
+/* Number of Siddon pieces (non-empty segments between consecutive plane crossings) of selected
+ * rays, ray_idx as orc_siddon_rays: the count of voxel reads a ray costs. */
+void orc_siddon_segments(const orc_geom *g, const double *angles, const int64_t *ray_idx, int64_t n,
+                         int64_t *out) {
+    const int64_t nu = g->ndet[0], nv = g->ndet[1];
+#pragma omp parallel
+    {
+        scratch_t sc;
+        scratch_init(&sc, g);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t q = 0; q < n; ++q) {
+            int64_t r = ray_idx[q];
+            int64_t a = r % nu, b = (r / nu) % nv, t = r / (nu * nv);
+            double S[3], P[3];
+            int64_t ns = 0;
+            source_pos(g, angles[t], S);
+            pixel_pos(g, angles[t], (double)a, (double)b, P);
+            siddon_core(g, S, P, NULL, NULL, NULL, 0.0, -1, &ns, &sc);
+            out[q] = ns;
+        }
+        free(sc.buf);
+    }
+}
+
 /* Exact transpose of orc_siddon_fwd: vol = sum over rays of y_ray * (piece lengths), scattered.
  * Threads scatter into private volumes that are summed at the end. */
 void orc_siddon_adj(const orc_geom *g, const double *angles, int64_t na, const double *proj,
@@ -578,32 +602,6 @@ void orc_bp_voxels_f32(const orc_geom *g, const double *angles, int64_t na, cons
     for (int64_t q = 0; q < n; ++q) {
         int64_t lin = vox_idx[q];
         out[q] = bp_voxel(g, angles, na, NULL, proj, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
-    }
-}
-
-/* Bilinear coverage of one voxel at one angle: the bilinear interpolation of an all-ones detector
- * (zero outside), i.e. the sum of the in-detector bilinear weights. */
-void orc_bp_coverage(const orc_geom *g, double th, double *cov) {
-    const int64_t nx = g->nvox[0], ny = g->nvox[1], nz = g->nvox[2];
-    const int64_t nu = g->ndet[0], nv = g->ndet[1];
-#pragma omp parallel for schedule(static)
-    for (int64_t r = 0; r < nz * ny; ++r) {
-        int64_t k = r / ny, j = r % ny;
-        for (int64_t i = 0; i < nx; ++i) {
-            double X[3], as, bs, w;
-            voxel_centre(g, i, j, k, X);
-            project_voxel(g, th, X, ORC_W_FDK, &as, &bs, &w);
-            double a0 = floor(as), b0 = floor(bs), fa = as - a0, fb = bs - b0;
-            int64_t ia = (int64_t)a0, ib = (int64_t)b0;
-            double c = 0.0;
-            for (int db = 0; db < 2; ++db)
-                for (int da = 0; da < 2; ++da) {
-                    int64_t aa = ia + da, bb = ib + db;
-                    if (aa < 0 || bb < 0 || aa >= nu || bb >= nv) continue;
-                    c += (da ? fa : 1 - fa) * (db ? fb : 1 - fb);
-                }
-            cov[(k * ny + j) * nx + i] = c;
-        }
     }
 }
 

@@ -589,6 +589,102 @@ def test_fp32_input_samplers_equal_fp64_on_widened_data(orc):
                                   orc.siddon_adj_voxels(geo, angles, proj.astype(np.float64), vox))
 
 
+# --- the sampled entry points (used by every large-size parity test and the CPU baseline)
+
+def _pixel_ray_by_convention(geo, th, a, b):
+    """Source and pixel centre of ray (th, a, b), written out from the stated conventions: source
+    DSO (cos, sin, 0), detector centre -(DSD - DSO)(cos, sin, 0), e_u = (-sin, cos, 0), e_v = z."""
+    c, s = math.cos(th), math.sin(th)
+    u = (a - (geo.nDetector[0] - 1) / 2) * geo.dDetector[0] + geo.offDetector[0]
+    v = (b - (geo.nDetector[1] - 1) / 2) * geo.dDetector[1] + geo.offDetector[1]
+    S = np.array([geo.DSO * c, geo.DSO * s, 0.0])
+    C = -(geo.DSD - geo.DSO) * np.array([c, s, 0.0])
+    return S, C + u * np.array([-s, c, 0.0]) + v * np.array([0.0, 0.0, 1.0])
+
+
+def _ragged_case(orc, seed):
+    geo = _geo(orc, nVoxel=(11, 9, 7), dVoxel=(1.1, 0.9, 1.3), offOrigin=(0.3, -0.2, 0.4),
+               nDetector=(13, 10), dDetector=(1.5, 1.7), offDetector=(0.4, -0.3))
+    rng = np.random.default_rng(seed)
+    angles = rng.uniform(0, 2 * np.pi, 5)
+    vol = rng.uniform(0, 1, geo.vol_shape)
+    return geo, angles, vol, rng
+
+
+def test_sampled_rays_equal_the_whole_array_projectors(orc):
+    """siddon_rays / interp_rays decode a flat index as (t Nv + b) Nu + a.  On a ragged geometry
+    with volume and detector offsets and a 13 x 10 detector they must return, bit for bit, the
+    whole-array projectors' values at those indices, for every index in a shuffled order; a decode
+    with a and b (or the angle) swapped reads another pixel, and the data tell them apart."""
+    geo, angles, vol, rng = _ragged_case(orc, 41)
+    idx = rng.permutation(len(angles) * 10 * 13)
+    for whole, sampled in ((orc.siddon_fwd, orc.siddon_rays), (orc.interp_fwd, orc.interp_rays)):
+        full = whole(geo, angles, vol)
+        assert full.shape == (5, 10, 13)
+        np.testing.assert_array_equal(sampled(geo, angles, idx, vol), full.ravel()[idx])
+        # the decodes a plausible mistake would make give other values on these data
+        t, rem = np.divmod(idx, 10 * 13)
+        b, a = np.divmod(rem, 13)
+        ok = (a < 10) & (b < 13) & (a != b)
+        swapped = full[t[ok], a[ok], b[ok]]
+        assert np.mean(swapped != full.ravel()[idx[ok]]) > 0.8
+    # the FP32 reader of the Siddon sampler, on FP32-representable data
+    v32 = vol.astype(np.float32)
+    np.testing.assert_array_equal(orc.siddon_rays(geo, angles, idx, v32),
+                                  orc.siddon_fwd(geo, angles, v32.astype(np.float64)).ravel()[idx])
+
+
+def test_whole_array_projectors_follow_the_pixel_convention(orc):
+    """Every pixel of siddon_fwd and interp_fwd equals the single-ray projectors (themselves pinned
+    by P1-P4 and I1-I2) on the ray whose endpoints are written out here from the conventions, so
+    the pixel loops' angle, row and column decode and their pixel positions are pinned."""
+    geo, angles, vol, _ = _ragged_case(orc, 42)
+    fs = orc.siddon_fwd(geo, angles, vol)
+    fi = orc.interp_fwd(geo, angles, vol)
+    for t, th in enumerate(angles):
+        for b in range(10):
+            for a in range(13):
+                S, P = _pixel_ray_by_convention(geo, th, a, b)
+                rs, _ = orc.siddon_ray(geo, S, P, vol)
+                ri, _ = orc.interp_ray(geo, S, P, vol)
+                assert abs(fs[t, b, a] - rs) <= 1e-12 * max(abs(rs), 1.0), (t, b, a)
+                assert abs(fi[t, b, a] - ri) <= 1e-12 * max(abs(ri), 1.0), (t, b, a)
+
+
+def test_sampled_voxels_equal_the_whole_array_backprojectors(orc):
+    """bp_voxels and siddon_adj_voxels decode a flat voxel index as (k Ny + j) Nx + i and must agree
+    with the whole-volume backprojectors at every voxel (bitwise for the voxel-driven ones, which
+    run the same per-voxel sum; to rounding for the exact transpose, whose whole-volume form adds
+    the scattered pieces in another order)."""
+    geo, angles, _, rng = _ragged_case(orc, 43)
+    proj = rng.uniform(-1, 1, geo.proj_shape(len(angles)))
+    idx = rng.permutation(11 * 9 * 7)
+    for kind in (orc.W_FDK, orc.W_PM):
+        np.testing.assert_array_equal(orc.bp_voxels(geo, angles, proj, idx, kind),
+                                      orc.bp(geo, angles, proj, kind).ravel()[idx])
+    full = orc.siddon_adj(geo, angles, proj).ravel()
+    np.testing.assert_allclose(orc.siddon_adj_voxels(geo, angles, proj, idx), full[idx],
+                               rtol=1e-12, atol=1e-12 * np.abs(full).max())
+
+
+def test_siddon_segment_count_is_the_piece_count(orc):
+    """siddon_segments counts a ray's pieces: an axis-aligned ray through the middle of an n-voxel
+    row crosses n - 1 inner planes, so it has n pieces; the count matches siddon_ray's own."""
+    geo, angles, vol, rng = _ragged_case(orc, 44)
+    idx = rng.choice(5 * 10 * 13, 60, replace=False)
+    got = orc.siddon_segments(geo, angles, idx)
+    for q, r in enumerate(idx):
+        t, rem = divmod(int(r), 130)
+        b, a = divmod(rem, 13)
+        S, P = _pixel_ray_by_convention(geo, angles[t], a, b)
+        _, ns = orc.siddon_ray(geo, S, P, vol)
+        assert got[q] == ns
+    # theta = 0 and the central pixel of an odd detector: the ray runs along x through y = z = 0,
+    # which lies inside one voxel row of a grid with odd Ny and Nz and no offset
+    g2 = _geo(orc, nVoxel=(6, 5, 3), nDetector=(3, 3))
+    assert orc.siddon_segments(g2, np.array([0.0]), np.array([4]))[0] == 6
+
+
 # --- FDK reconstruction (Feldkamp, Davis & Kress 1984, the algorithm behind Section 2.2's FDK weight)
 
 def test_F1_ramp_filter_response_to_a_cosine(orc):
@@ -710,3 +806,20 @@ def test_R3_rof_keeps_the_mean_and_constant_images(orc):
     x0 = rng.uniform(0, 1, (9, 8, 7))
     assert abs(orc.rof_chambolle(x0, 0.1, 50).mean() - x0.mean()) <= 1e-14
     np.testing.assert_array_equal(orc.rof_chambolle(np.full((4, 5, 6), 0.3), 0.1, 20), np.full((4, 5, 6), 0.3))
+
+
+def test_stored_siddon_piece_count_reproduces():
+    """The stored gather-model unit of the Siddon projector (pieces per voxel-projection at the
+    512^3 / 360 / 512^2 workload) is reproduced by the oracle on an independent seeded sample of
+    rays, within four standard errors of the two estimates."""
+    sys_path = os.path.join(os.path.dirname(__file__), "golden")
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_siddon_segments",
+                                                  os.path.join(sys_path, "make_siddon_segments.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    stored = json.load(open(os.path.join(sys_path, "siddon_segments.json")))
+    fresh = mod.count(20000, seed=stored["seed"] + 1)
+    err = math.hypot(stored["stderr_pieces_per_voxel_proj"], fresh["stderr_pieces_per_voxel_proj"])
+    assert abs(fresh["pieces_per_voxel_proj"] - stored["pieces_per_voxel_proj"]) <= 4 * err
+    assert 1.0 < stored["pieces_per_voxel_proj"] < 1.3
