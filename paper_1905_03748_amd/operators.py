@@ -40,6 +40,20 @@ def _dev(t: torch.Tensor, shape, name):
     return t.data_ptr()
 
 
+def _host(t: torch.Tensor, shape, name):
+    """Pointer of a host tensor that must hold exactly `shape` elements of a storage dtype: the
+    library reads and writes through the raw pointer, so a short buffer would be overrun."""
+    if t.device.type != "cpu":
+        raise ValueError(f"{name} must be a host tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype not in _TORCH_DT:
+        raise ValueError(f"{name} has unsupported dtype {t.dtype}")
+    return t.data_ptr()
+
+
 def _check_workspace(ws: torch.Tensor, need: int):
     if not ws.is_cuda or not ws.is_contiguous() or ws.numel() * ws.element_size() < need:
         raise ValueError(f"workspace must be a contiguous device tensor of at least {need} bytes")
@@ -99,25 +113,21 @@ class Plan:
 
     # -- out-of-core operators (host tensors) ---------------------------------------------------
     def forward_host(self, vol: torch.Tensor, out: torch.Tensor, projector="siddon", cap_bytes=32 << 30) -> dict:
-        assert vol.device.type == "cpu" and out.device.type == "cpu" and vol.is_contiguous() and out.is_contiguous()
-        s = A.ct_forward_host(self.handle, _PROJ[projector], vol.data_ptr(), ct_dtype(vol.dtype), out.data_ptr(),
-                              ct_dtype(out.dtype), cap_bytes)
+        pv, po = _host(vol, self.vol_shape, "vol"), _host(out, self.proj_shape, "out")
+        s = A.ct_forward_host(self.handle, _PROJ[projector], pv, ct_dtype(vol.dtype), po, ct_dtype(out.dtype),
+                              cap_bytes)
         return s.as_dict()
 
     def backproject_host(self, proj: torch.Tensor, out: torch.Tensor, kind="fdk", cap_bytes=32 << 30) -> dict:
-        assert proj.device.type == "cpu" and out.device.type == "cpu" and proj.is_contiguous() and out.is_contiguous()
-        s = A.ct_backproject_host(self.handle, _BP[kind], proj.data_ptr(), ct_dtype(proj.dtype), out.data_ptr(),
-                                  ct_dtype(out.dtype), cap_bytes)
+        pp, po = _host(proj, self.proj_shape, "proj"), _host(out, self.vol_shape, "out")
+        s = A.ct_backproject_host(self.handle, _BP[kind], pp, ct_dtype(proj.dtype), po, ct_dtype(out.dtype),
+                                  cap_bytes)
         return s.as_dict()
 
     def fdk_host(self, proj: torch.Tensor, out: torch.Tensor, cap_bytes=32 << 30) -> dict:
         """Out-of-core FDK reconstruction of host projections into the host volume `out`."""
-        assert proj.device.type == "cpu" and out.device.type == "cpu" and proj.is_contiguous() and out.is_contiguous()
-        if tuple(proj.shape) != self.proj_shape or tuple(out.shape) != self.vol_shape:
-            raise ValueError(f"shapes {tuple(proj.shape)}, {tuple(out.shape)}; expected {self.proj_shape}, "
-                             f"{self.vol_shape}")
-        s = A.ct_fdk_host(self.handle, proj.data_ptr(), ct_dtype(proj.dtype), out.data_ptr(), ct_dtype(out.dtype),
-                          cap_bytes)
+        pp, po = _host(proj, self.proj_shape, "proj"), _host(out, self.vol_shape, "out")
+        s = A.ct_fdk_host(self.handle, pp, ct_dtype(proj.dtype), po, ct_dtype(out.dtype), cap_bytes)
         return s.as_dict()
 
     def ooc_plan(self, direction=0, projector="siddon", vol_dtype=torch.float32, proj_dtype=torch.float32,
@@ -261,6 +271,10 @@ def tv_workspace_bytes(geometry: dict) -> int:
 
 
 def dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
+    if a.numel() != b.numel() or a.dtype != b.dtype:
+        raise ValueError("dot needs two tensors of the same size and dtype")
+    _dev(a, a.shape, "a")
+    _dev(b, b.shape, "b")
     out = torch.empty(1, dtype=torch.float64, device=a.device)
     A.ct_dot(a.data_ptr(), b.data_ptr(), ct_dtype(a.dtype), a.numel(), out.data_ptr(), _stream(stream))
     return out

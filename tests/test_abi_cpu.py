@@ -160,3 +160,32 @@ def test_ooc_planner_equal_slabs_and_halo(lib):
                 assert A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F32, A.CT_F32, cap).n_slabs == 1
     finally:
         A.ct_plan_destroy(p)
+
+
+def test_host_operators_reject_wrong_shapes_before_the_library(lib):
+    """The out-of-core wrappers pass raw host pointers: a tensor of the wrong shape, device, layout
+    or dtype is refused with ValueError (also under python -O) before anything reaches the library."""
+    import torch
+    from paper_1905_03748_amd.operators import Plan
+    w = inputs.workload("tiny")
+    plan = Plan(w.geometry_dict(), w.angles)
+    vol = torch.zeros(plan.vol_shape)
+    proj = torch.zeros(plan.proj_shape)
+    short_proj = torch.zeros((plan.n_angles - 1,) + plan.proj_shape[1:])
+    short_vol = torch.zeros((plan.vol_shape[0] - 1,) + plan.vol_shape[1:])
+    bad = [
+        lambda: plan.forward_host(vol, short_proj),
+        lambda: plan.forward_host(short_vol, proj),
+        lambda: plan.forward_host(vol, proj.view(-1)),                  # right size, wrong shape
+        lambda: plan.forward_host(vol, torch.zeros(plan.proj_shape[::-1]).transpose(0, 2)),   # not contiguous
+        lambda: plan.forward_host(vol.double(), proj),
+        lambda: plan.backproject_host(short_proj, vol),
+        lambda: plan.backproject_host(proj, short_vol),
+        lambda: plan.backproject_host(proj, vol.to(torch.int32)),
+        lambda: plan.fdk_host(proj, short_vol),
+        lambda: plan.fdk_host(short_proj, vol),
+    ]
+    for k, call in enumerate(bad):
+        with pytest.raises(ValueError):
+            call()
+    plan.close()
