@@ -52,86 +52,187 @@ struct BpArgs {
     // exact adjoint (FP64 set-up)
     double ddx, ddy, ddz, dx0, dy0, dz0;
     double dDSO, dDSD, du, dv, cu, cv, offu, offv;
+    double dau0, dbv0;      // au0, bv0 in FP64
+    double idu, idv;        // 1 / du, 1 / dv in FP64
 };
+
+// 1 / d in FP64 without a division: the FP32 reciprocal (about 1 ulp) refined by one Newton step,
+// which squares its relative error (to ~1e-14) for the positive, moderate d used here.
+__device__ __forceinline__ double rcp_f64(double d) {
+    const double r = (double)__builtin_amdgcn_rcpf((float)d);
+    return r * fma(-d, r, 2.0);
+}
+
+// Detector coordinates of the voxels of a tile, relative to a reference point of the tile.
+//
+// At a detector of more than 2048 pixels an FP32 coordinate a* ~ 3000 is only resolved to
+// 2.4e-4 pixel, and the FP32 chain that forms it from mm-sized quantities (products of ~1e3 mm
+// depths, a reciprocal) loses a few ulps more; on ramp-filtered data that shows as 2e-4 relative
+// error of the backprojection.  Instead the tile's reference point (x_r, y_r, z_r) is projected
+// once per angle in FP64 and each voxel adds a small FP32 offset:
+//   with N = y c - x s and D = DSO - (x c + y s) (transverse position and depth of the voxel),
+//   a* - a*_r = DSD / du * (N / D - N_r / D_r) = Ka (dN D_r - N_r dD) / D,  Ka = DSD / (du D_r)
+//   b* - b*_r = DSD / dv * (z / D - z_r / D_r) = (z - z_r) m / dv + Kb dD / D,
+//                                                    Kb = -DSD z_r / (dv D_r),  m = DSD / D
+// where dN, dD, z - z_r are the voxel's offsets from the reference (a tile width or less), so every
+// FP32 quantity is a few pixels in size.  Aloc, Bloc: the reference's coordinates minus an integer
+// origin (the staging window's corner, or the floor of the reference coordinate).
+struct TileRef {
+    float c, s;      // cos, sin of the angle
+    float Dr, Nr;    // depth and transverse position of the reference point, mm
+    float Ka, Kb;
+    float Aloc, Bloc;
+};
+
+// FP64 projection of the reference point (xr, yr, zr) (mm) under the angle (c, s); returns a*_r, b*_r
+// and fills the FP32 factors (Aloc / Bloc are left to the caller).
+__device__ __forceinline__ void tile_ref(const BpArgs &A, double c, double s, double xr, double yr, double zr,
+                                         TileRef &R, double &ar, double &br) {
+    const double N = yr * c - xr * s, D = A.dDSO - (xr * c + yr * s);
+    const double iD = rcp_f64(D);
+    const double ka = A.dDSD * iD * A.idu, kb = A.dDSD * iD * A.idv;
+    ar = fma(ka, N, A.dau0);
+    br = fma(kb, zr, A.dbv0);
+    R.c = (float)c;
+    R.s = (float)s;
+    R.Dr = (float)D;
+    R.Nr = (float)N;
+    R.Ka = (float)ka;
+    R.Kb = (float)(-kb * zr);
+}
+
+// Per-voxel part: the voxel's offset (lx, ly) (mm) from the reference gives the local column
+// coordinate as, the row coordinate at the reference height bq (add zl * mv for a height zl above
+// it) and 1 / D.
+__device__ __forceinline__ void tile_local(const TileRef &R, float lx, float ly, float DSD, float inv_dv, float &as,
+                                           float &bq, float &mv, float &iL) {
+    const float dN = fmaf(ly, R.c, -lx * R.s);
+    const float dD = -fmaf(lx, R.c, ly * R.s);
+    iL = __builtin_amdgcn_rcpf(R.Dr + dD);
+    const float T = fmaf(dN, R.Dr, -R.Nr * dD);
+    as = fmaf(R.Ka * T, iL, R.Aloc);
+    bq = fmaf(R.Kb * dD, iL, R.Bloc);
+    mv = DSD * iL * inv_dv;
+}
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Reference point of a tile: the centre of its columns that lie in the grid and of its run of
+// slices clipped to the grid.  It depends only on the tile and the run, not on the slab or launch,
+// so a voxel's arithmetic is the same however the volume is cut; and it lies inside the volume box,
+// so its depth is positive.
+__device__ __forceinline__ float tile_mid(int first, int len, int n) { return 0.5f * (float)(first + min(first + len, n) - 1); }
+
+// Runs of nrun slices start at absolute multiples of nrun (the first run of a slab may begin below
+// own_lo; those voxels are neither read nor written).
+__device__ __forceinline__ int run_base(const BpArgs &A, int nrun) { return (A.own_lo / nrun + (int)blockIdx.z) * nrun; }
+
 template <int W, typename TP, typename TV>
 __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, TV *__restrict__ vol, BpArgs A) {
-    const int i = blockIdx.x * BP_TX + (threadIdx.x % BP_TX);
-    const int j = blockIdx.y * BP_TY + (threadIdx.x / BP_TX);
-    const int kb = A.own_lo + blockIdx.z * BP_NZ;
-    if (i >= A.nx || j >= A.ny) return;
+    __shared__ TileRef ref[64];
+    __shared__ float iref[64][2];
+    const int i0 = blockIdx.x * BP_TX, j0 = blockIdx.y * BP_TY;
+    const int i = i0 + (threadIdx.x % BP_TX);
+    const int j = j0 + (threadIdx.x / BP_TX);
+    const int kb = run_base(A, BP_NZ);
+    const bool live = i < A.nx && j < A.ny;
+    const float ir = tile_mid(i0, BP_TX, A.nx), jr = tile_mid(j0, BP_TY, A.ny), kr = tile_mid(kb, BP_NZ, A.nz);
+    const float lx = ((float)i - ir) * A.dx, ly = ((float)j - jr) * A.dy;
     const float x = fmaf((float)i, A.dx, A.x0);
     const float y = fmaf((float)j, A.dy, A.y0);
-    float zk[BP_NZ];
+    float zk[BP_NZ], zl[BP_NZ];
 #pragma unroll
-    for (int k = 0; k < BP_NZ; ++k) zk[k] = fmaf((float)(kb + k), A.dz, A.z0);
+    for (int k = 0; k < BP_NZ; ++k) {
+        zk[k] = fmaf((float)(kb + k), A.dz, A.z0);
+        zl[k] = ((float)(kb + k) - kr) * A.dz;
+    }
     // with accumulate the sums start from the stored values, so a sequence of launches over
     // consecutive angle ranges performs exactly the additions of one launch over all of them
     float acc[BP_NZ];
 #pragma unroll
     for (int k = 0; k < BP_NZ; ++k) {
         const int kk = kb + k;
-        acc[k] = (A.accumulate && kk < A.own_hi) ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i]) : 0.0f;
+        acc[k] = (live && A.accumulate && kk >= A.own_lo && kk < A.own_hi)
+                     ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i])
+                     : 0.0f;
     }
     const int64_t psz = (int64_t)A.nu * A.nv;
     constexpr int ES = (int)sizeof(TP);
     const int rowb = A.nu * ES;
-    for (int t = 0; t < A.nang; ++t) {
-        const AngleGeo &G = A.tab[A.a0 + t];
-        const float c = (float)G.c, s = (float)G.s;
-        const float Ld = A.DSO - (x * c + y * s);
-        const float iL = __builtin_amdgcn_rcpf(Ld);
-        const float m = A.DSD * iL;
-        const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
-        const float af = floorf(as);
-        const float fa = as - af;
-        const int ia = (int)af;
-        const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
-        const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
-        if (wa0 == 0.0f && wa1 == 0.0f) continue;
-        const int ca0 = clampi(ia, 0, A.nu - 1) * ES;
-        const int dca = (clampi(ia + 1, 0, A.nu - 1) - clampi(ia, 0, A.nu - 1)) * ES;
-        const float mv = m * A.inv_dv;
-        float w = 0.0f, rxy2 = 0.0f, wpm = 0.0f;
-        if (W == CT_BP_FDK) {
-            const float q = A.DSO * iL;
-            w = q * q;
-        } else {
-            const float sx = x - A.DSO * c, sy = y - A.DSO * s;
-            rxy2 = sx * sx + sy * sy;
-            wpm = A.pm_const * iL * iL * iL;
+    const float amax = (float)A.nu + 1.0f, bmax = (float)A.nv + 1.0f;
+    for (int t0 = 0; t0 < A.nang; t0 += 64) {
+        const int nk = min(64, A.nang - t0);
+        __syncthreads();  // the previous chunk's references have been read
+        if ((int)threadIdx.x < nk) {
+            const AngleGeo &G = A.tab[A.a0 + t0 + threadIdx.x];
+            TileRef R;
+            double ar, br;
+            tile_ref(A, G.c, G.s, A.dx0 + (double)ir * A.ddx, A.dy0 + (double)jr * A.ddy, A.dz0 + (double)kr * A.ddz, R,
+                     ar, br);
+            // integer origins (clamped far outside the detector, where every tap is zero anyway)
+            const double fa = fmin(fmax(floor(ar), -16777216.0), 16777216.0);
+            const double fbr = fmin(fmax(floor(br), -16777216.0), 16777216.0);
+            R.Aloc = (float)(ar - fa);
+            R.Bloc = (float)(br - fbr);
+            ref[threadIdx.x] = R;
+            iref[threadIdx.x][0] = (float)fa;
+            iref[threadIdx.x][1] = (float)fbr;
         }
-        const __amdgpu_buffer_rsrc_t R = proj_rsrc(proj + (int64_t)t * psz, psz * ES);
-        // all taps of the column are issued before any is used, so they are in flight together
-        float p[BP_NZ][4], fb[BP_NZ];
+        __syncthreads();
+        if (!live) continue;
+        for (int q = 0; q < nk; ++q) {
+            const TileRef R = ref[q];
+            float as, bq, mv, iL;
+            tile_local(R, lx, ly, A.DSD, A.inv_dv, as, bq, mv, iL);
+            const float af = floorf(as);
+            const float fa = as - af;
+            const int ia = (int)__builtin_amdgcn_fmed3f(iref[q][0] + af, -2.0f, amax);
+            const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
+            const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
+            if (wa0 == 0.0f && wa1 == 0.0f) continue;
+            const int ca0 = clampi(ia, 0, A.nu - 1) * ES;
+            const int dca = (clampi(ia + 1, 0, A.nu - 1) - clampi(ia, 0, A.nu - 1)) * ES;
+            const float ob = iref[q][1];
+            float w = 0.0f, rxy2 = 0.0f, wpm = 0.0f;
+            if (W == CT_BP_FDK) {
+                const float qq = A.DSO * iL;
+                w = qq * qq;
+            } else {
+                const float sx = x - A.DSO * R.c, sy = y - A.DSO * R.s;
+                rxy2 = sx * sx + sy * sy;
+                wpm = A.pm_const * iL * iL * iL;
+            }
+            const __amdgpu_buffer_rsrc_t Rs = proj_rsrc(proj + (int64_t)(t0 + q) * psz, psz * ES);
+            // all taps of the column are issued before any is used, so they are in flight together
+            float p[BP_NZ][4], fb[BP_NZ];
 #pragma unroll
-        for (int k = 0; k < BP_NZ; ++k) {
-            // each voxel's row coordinate comes from its own absolute height, so a voxel's value
-            // does not depend on how the volume is cut into launches or slabs
-            const float bs = fmaf(zk[k], mv, A.bv0);
-            const float bf = floorf(bs);
-            fb[k] = bs - bf;
-            const int o00 = (int)bf * rowb + ca0;  // rows outside the detector read 0
-            p[k][0] = bload(R, o00, (TP *)nullptr);
-            p[k][1] = bload(R, o00 + dca, (TP *)nullptr);
-            p[k][2] = bload(R, o00 + rowb, (TP *)nullptr);
-            p[k][3] = bload(R, o00 + rowb + dca, (TP *)nullptr);
-        }
+            for (int k = 0; k < BP_NZ; ++k) {
+                const float bs = fmaf(zl[k], mv, bq);
+                const float bf = floorf(bs);
+                fb[k] = bs - bf;
+                // rows outside the detector read 0 (negative offsets wrap past the buffer's end)
+                const int o00 = (int)__builtin_amdgcn_fmed3f(ob + bf, -2.0f, bmax) * rowb + ca0;
+                p[k][0] = bload(Rs, o00, (TP *)nullptr);
+                p[k][1] = bload(Rs, o00 + dca, (TP *)nullptr);
+                p[k][2] = bload(Rs, o00 + rowb, (TP *)nullptr);
+                p[k][3] = bload(Rs, o00 + rowb + dca, (TP *)nullptr);
+            }
 #pragma unroll
-        for (int k = 0; k < BP_NZ; ++k) {
-            const float v0 = fmaf(wa1, p[k][1], wa0 * p[k][0]);
-            const float v1 = fmaf(wa1, p[k][3], wa0 * p[k][2]);
-            const float v = fmaf(fb[k], v1 - v0, v0);
-            float wk = w;
-            if (W != CT_BP_FDK) wk = wpm * sqrtf(fmaf(zk[k], zk[k], rxy2));
-            acc[k] = fmaf(wk, v, acc[k]);
+            for (int k = 0; k < BP_NZ; ++k) {
+                const float v0 = fmaf(wa1, p[k][1], wa0 * p[k][0]);
+                const float v1 = fmaf(wa1, p[k][3], wa0 * p[k][2]);
+                const float v = fmaf(fb[k], v1 - v0, v0);
+                float wk = w;
+                if (W != CT_BP_FDK) wk = wpm * sqrtf(fmaf(zk[k], zk[k], rxy2));
+                acc[k] = fmaf(wk, v, acc[k]);
+            }
         }
     }
+    if (!live) return;
 #pragma unroll
     for (int k = 0; k < BP_NZ; ++k) {
         const int kk = kb + k;
+        if (kk < A.own_lo) continue;
         if (kk >= A.own_hi) break;
         const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
         vol[o] = from_f<TV>(acc[k]);
@@ -165,42 +266,57 @@ constexpr int BPL_PN = CT_BPL_PITCH;       // row pitch of narrow windows (the c
 
 // PITCH: LDS row pitch (floats) of a window, a compile-time constant so that both rows of a
 // bilinear tap pair are one base address with immediate offsets.
+constexpr int BPL_G = 64;  // angles per group of tile references
+static_assert(BPL_NZ * 256 <= BPL_FLOATS, "the staging window parks the accumulators");
+
+// at least 7 waves per SIMD: the taps are LDS reads one after another, so latency is hidden by the
+// other waves rather than by reads kept in flight in one wave (which the compiler would otherwise
+// schedule, at 4 waves per SIMD)
+#ifndef CT_BPL_WAVES
+#define CT_BPL_WAVES 7
+#endif
+#ifndef CT_BPL_WAVES_PM
+#define CT_BPL_WAVES_PM 6
+#endif
 template <int W, int PITCH, typename TP, typename TV>
-__global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV *__restrict__ vol, BpArgs A, int WW,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W == CT_BP_FDK ? CT_BPL_WAVES : CT_BPL_WAVES_PM))) void k_bp_lds(const TP *__restrict__ proj, TV *__restrict__ vol, BpArgs A, int WW,
                                                 int HW, int K) {
     __shared__ float win[BPL_FLOATS];
-    __shared__ int org[BPL_K][2];
+    __shared__ TileRef ref[BPL_G];
+    __shared__ int org[BPL_G][2];
     const int i0 = blockIdx.x * BP_TX, j0 = blockIdx.y * BP_TY;
     const int i = i0 + (threadIdx.x % BP_TX);
     const int j = j0 + (threadIdx.x / BP_TX);
-    const int kb = A.own_lo + blockIdx.z * BPL_NZ;
+    const int kb = run_base(A, BPL_NZ);
     const bool live = i < A.nx && j < A.ny;
-    const float x = fmaf((float)i, A.dx, A.x0);
-    const float y = fmaf((float)j, A.dy, A.y0);
-    float zk[BPL_NZ];
-#pragma unroll
-    for (int k = 0; k < BPL_NZ; ++k) zk[k] = fmaf((float)(kb + k), A.dz, A.z0);
-    float acc[BPL_NZ];
-#pragma unroll
-    for (int k = 0; k < BPL_NZ; ++k) {
-        const int kk = kb + k;
-        acc[k] = (live && A.accumulate && kk < A.own_hi) ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i])
-                                                          : 0.0f;
-    }
+    const float ir = tile_mid(i0, BP_TX, A.nx), jr = tile_mid(j0, BP_TY, A.ny), kr = tile_mid(kb, BPL_NZ, A.nz);
+    const float lx = ((float)i - ir) * A.dx, ly = ((float)j - jr) * A.dy;
+    // heights of the run's first voxel relative to the reference (row coordinates) and absolute
+    // (the pseudo-matched weight); voxel k of the run adds k dz
+    const float zl0 = ((float)kb - kr) * A.dz, zk0 = fmaf((float)kb, A.dz, A.z0);
     const int64_t psz = (int64_t)A.nu * A.nv;
     const int wsz = PITCH * HW;
     const float lamax = (float)(WW - 2), lbmax = (float)(HW - 2);
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    for (int t0 = 0; t0 < A.nang; t0 += K) {
-        const int nk = min(K, A.nang - t0);
-        __syncthreads();  // the previous round's taps have been read
-        // lanes 8q' .. 8q'+7 of wave 0: the tile's corners under angle t0 + q0 + q'
-        for (int q0 = 0; wave == 0 && q0 < nk; q0 += 8) {
-            const int q = q0 + (lane >> 3), cn = lane & 7;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const int lane = tid & 63;
+    float acc[BPL_NZ];
+    for (int g0 = 0; g0 < A.nang; g0 += BPL_G) {
+        const int ng = min(BPL_G, A.nang - g0);
+        if (g0 > 0) {
+            // park the sums in the window while the group's references are formed, so the FP64
+            // set-up does not hold registers next to them
+            __syncthreads();  // the last round's taps have been read
+#pragma unroll
+            for (int k = 0; k < BPL_NZ; ++k) win[k * 256 + tid] = acc[k];
+        }
+        // threads 8q' .. 8q'+7: the tile's corners under angle g0 + q0 + q' (FP32; the window has a
+        // pixel of margin), then thread 8q' projects the reference point in FP64
+        for (int q0 = 0; q0 < ng; q0 += 32) {
+            const int q = q0 + (tid >> 3), cn = tid & 7;
             float as = 0.0f, bs = 0.0f;
-            if (q < nk) {
-                const AngleGeo &G = A.tab[A.a0 + t0 + q];
+            if (q < ng) {
+                const AngleGeo &G = A.tab[A.a0 + g0 + q];
                 const float c = (float)G.c, s = (float)G.s;
                 const float xc = fmaf((float)(i0 + ((cn & 1) ? BP_TX - 1 : 0)), A.dx, A.x0);
                 const float yc = fmaf((float)(j0 + ((cn & 2) ? BP_TY - 1 : 0)), A.dy, A.y0);
@@ -216,79 +332,110 @@ __global__ __launch_bounds__(256) void k_bp_lds(const TP *__restrict__ proj, TV 
                 amin = fminf(amin, __shfl_xor(amin, off, 64));
                 bmin = fminf(bmin, __shfl_xor(bmin, off, 64));
             }
-            if (cn == 0 && q < nk) {
-                org[q][0] = (int)floorf(amin) - 1;
-                org[q][1] = (int)floorf(bmin) - 1;
+            if (cn == 0 && q < ng) {
+                const int oa = (int)floorf(amin) - 1, ob = (int)floorf(bmin) - 1;
+                org[q][0] = oa;
+                org[q][1] = ob;
+                const AngleGeo &G = A.tab[A.a0 + g0 + q];
+                TileRef R;
+                double ar, br;
+                tile_ref(A, G.c, G.s, A.dx0 + (double)ir * A.ddx, A.dy0 + (double)jr * A.ddy, A.dz0 + (double)kr * A.ddz,
+                         R, ar, br);
+                R.Aloc = (float)(ar - oa);
+                R.Bloc = (float)(br - ob);
+                ref[q] = R;
             }
         }
         __syncthreads();
-        // stage: wave w copies rows w, w + 4, ... of every window; lane = window column
-        for (int q = 0; q < nk; ++q) {
-            const int u = org[q][0] + lane;
-            const bool uok = lane < WW && (unsigned)u < (unsigned)A.nu;
-            const TP *pq = proj + (int64_t)(t0 + q) * psz + u;
-            float *wq = win + q * wsz + lane;
-            for (int r = wave; r < HW; r += 4) {
-                const int v = org[q][1] + r;
-                float val = 0.0f;
-                if (uok && (unsigned)v < (unsigned)A.nv) val = to_f(pq[(int64_t)v * A.nu]);
-                if (lane < WW) wq[r * PITCH] = val;
-            }
-        }
-        __syncthreads();
-        if (!live) continue;
-        for (int q = 0; q < nk; ++q) {
-            const AngleGeo &G = A.tab[A.a0 + t0 + q];
-            const float c = (float)G.c, s = (float)G.s;
-            const float Ld = A.DSO - (x * c + y * s);
-            const float iL = __builtin_amdgcn_rcpf(Ld);
-            const float m = A.DSD * iL;
-            const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
-            const float af = floorf(as);
-            const float fa = as - af;
-            const float wa0 = 1.0f - fa, wa1 = fa;  // taps off the detector are zeros in the window
-            // window-local column and row (exact integers in FP32), clamped into the window
-            const float la = __builtin_amdgcn_fmed3f(af - (float)org[q][0], 0.0f, lamax);
-            const float ob = (float)org[q][1];
-            const float mv = m * A.inv_dv;
-            float w = 0.0f, rxy2 = 0.0f, wpm = 0.0f;
-            if (W == CT_BP_FDK) {
-                const float qq = A.DSO * iL;
-                w = qq * qq;
-            } else {
-                const float sx = x - A.DSO * c, sy = y - A.DSO * s;
-                rxy2 = sx * sx + sy * sy;
-                wpm = A.pm_const * iL * iL * iL;
-            }
-            // LDS byte offset of the window column (exact in FP32), rebased so that the absolute row
-            // index can be used directly; the clamp keeps rows 0 .. HW - 2 of the window
-            const float cb = fmaf(la, 4.0f, (float)(q * wsz * 4));
-            const float cbr = fmaf(-ob, (float)(4 * PITCH), cb), cbmax = fmaf(lbmax, (float)(4 * PITCH), cb);
+        if (g0 == 0) {
+            // one base address, slices a uniform stride apart (the stride is hidden from the
+            // compiler so the 16 addresses are not kept live until the stores at the end)
+            int64_t sl = (int64_t)A.nx * A.ny;
+            asm volatile("" : "+s"(sl));
+            const TV *vb = vol + ((int64_t)(kb - A.mem_lo) * A.ny + j) * A.nx + i;
 #pragma unroll
             for (int k = 0; k < BPL_NZ; ++k) {
-                // the row coordinate comes from the voxel's absolute height (independent of the
-                // tile and slab the voxel is processed in)
-                const float bs = fmaf(zk[k], mv, A.bv0);
-                const float bf = floorf(bs);
-                const float fb = bs - bf;
-                const float off = __builtin_amdgcn_fmed3f(fmaf(bf, (float)(4 * PITCH), cbr), cb, cbmax);
-                const float *t = (const float *)((const char *)win + (int)off);
-                const float v0 = fmaf(wa1, t[1], wa0 * t[0]);
-                const float v1 = fmaf(wa1, t[PITCH + 1], wa0 * t[PITCH]);
-                const float v = fmaf(fb, v1 - v0, v0);
-                float wk = w;
-                if (W != CT_BP_FDK) wk = wpm * sqrtf(fmaf(zk[k], zk[k], rxy2));
-                acc[k] = fmaf(wk, v, acc[k]);
+                const int kk = kb + k;
+                acc[k] = (live && A.accumulate && kk >= A.own_lo && kk < A.own_hi) ? to_f(vb[k * sl]) : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < BPL_NZ; ++k) acc[k] = win[k * 256 + tid];
+        }
+        for (int t0 = 0; t0 < ng; t0 += K) {
+            const int nk = min(K, ng - t0);
+            __syncthreads();  // the window is free (parked sums read back, or the last round's taps read)
+            // stage: wave w copies rows w, w + 4, ... of every window; lane = window column
+            for (int q = 0; q < nk; ++q) {
+                const int u = org[t0 + q][0] + lane;
+                const bool uok = lane < WW && (unsigned)u < (unsigned)A.nu;
+                const TP *pq = proj + (int64_t)(g0 + t0 + q) * psz + u;
+                float *wq = win + q * wsz + lane;
+                const int ob = org[t0 + q][1];
+                for (int r = wave; r < HW; r += 4) {
+                    const int v = ob + r;
+                    float val = 0.0f;
+                    if (uok && (unsigned)v < (unsigned)A.nv) val = to_f(pq[(int64_t)v * A.nu]);
+                    if (lane < WW) wq[r * PITCH] = val;
+                }
+            }
+            __syncthreads();
+            if (!live) continue;
+            for (int q = 0; q < nk; ++q) {
+                const TileRef R = ref[t0 + q];
+                // window-local column coordinate, row coordinate at the reference height
+                float as, bq, mv, iL;
+                tile_local(R, lx, ly, A.DSD, A.inv_dv, as, bq, mv, iL);
+                const float af = floorf(as);
+                const float fa = as - af;
+                const float wa0 = 1.0f - fa, wa1 = fa;  // taps off the detector are zeros in the window
+                // window column clamped into the window (an exact integer in FP32)
+                const float la = __builtin_amdgcn_fmed3f(af, 0.0f, lamax);
+                float w = 0.0f, rxy2 = 0.0f, wpm = 0.0f;
+                if (W == CT_BP_FDK) {
+                    const float qq = A.DSO * iL;
+                    w = qq * qq;
+                } else {
+                    const float sx = fmaf(-A.DSO, R.c, fmaf((float)i, A.dx, A.x0));
+                    const float sy = fmaf(-A.DSO, R.s, fmaf((float)j, A.dy, A.y0));
+                    rxy2 = sx * sx + sy * sy;
+                    wpm = A.pm_const * iL * iL * iL;
+                }
+                // LDS byte offset of the window column (exact in FP32); the clamp keeps rows 0 .. HW - 2
+                const float cb = fmaf(la, 4.0f, (float)(q * wsz * 4));
+                const float cbmax = fmaf(lbmax, (float)(4 * PITCH), cb);
+                // row coordinate of voxel k of the run: b0 + k db, with db a few pixels at most
+                const float b0 = fmaf(zl0, mv, bq), db = A.dz * mv;
+#pragma unroll
+                for (int k = 0; k < BPL_NZ; ++k) {
+                    const float bs = fmaf((float)k, db, b0);
+                    const float bf = floorf(bs);
+                    const float fb = bs - bf;
+                    const float off = __builtin_amdgcn_fmed3f(fmaf(bf, (float)(4 * PITCH), cb), cb, cbmax);
+                    const float *t = (const float *)((const char *)win + (int)off);
+                    const float v0 = fmaf(wa1, t[1], wa0 * t[0]);
+                    const float v1 = fmaf(wa1, t[PITCH + 1], wa0 * t[PITCH]);
+                    const float v = fmaf(fb, v1 - v0, v0);
+                    float wk = w;
+                    if (W != CT_BP_FDK) {
+                        const float zk = fmaf((float)k, A.dz, zk0);
+                        wk = wpm * sqrtf(fmaf(zk, zk, rxy2));
+                    }
+                    acc[k] = fmaf(wk, v, acc[k]);
+                }
             }
         }
     }
-    if (!live) return;
+    if (!live || A.nang <= 0) return;
+    int64_t sl = (int64_t)A.nx * A.ny;
+    asm volatile("" : "+s"(sl));
+    TV *vs = vol + ((int64_t)(kb - A.mem_lo) * A.ny + j) * A.nx + i;
 #pragma unroll
     for (int k = 0; k < BPL_NZ; ++k) {
         const int kk = kb + k;
+        if (kk < A.own_lo) continue;
         if (kk >= A.own_hi) break;
-        const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
-        vol[o] = from_f<TV>(acc[k]);
+        vs[k * sl] = from_f<TV>(acc[k]);
     }
 }
 
@@ -314,12 +461,12 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
     const int tid = threadIdx.x;
     const int i = blockIdx.x * BP_TX + (tid % BP_TX);
     const int j = blockIdx.y * BP_TY + (tid / BP_TX);
-    const int kb = A.own_lo + blockIdx.z * ADJ_NZ;
+    const int kb = run_base(A, ADJ_NZ);  // heights are taken relative to the run's lowest face
     const bool live = i < A.nx && j < A.ny;
 #pragma unroll
     for (int k = 0; k < ADJ_NZ; ++k) {
         const int kk = kb + k;
-        accs[k * 256 + tid] = (live && A.accumulate && kk < A.own_hi)
+        accs[k * 256 + tid] = (live && A.accumulate && kk >= A.own_lo && kk < A.own_hi)
                                   ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i])
                                   : 0.0f;
     }
@@ -331,7 +478,9 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
     const float dz = A.dz, idz = 1.0f / A.dz;
     const int nzr = min(ADJ_NZ, A.own_hi - kb);
     const float zl0 = fmaf((float)kb, dz, zface0), zr_hi = fmaf((float)(kb + nzr), dz, zface0);
-    const float v0 = (float)(A.offv - A.cv * A.dv), dv = (float)A.dv, idv = 1.0f / dv;
+    const double v0d = A.offv - A.cv * A.dv;       // height of row 0 at the detector
+    const double zl0d = A.dz0 + (kb - 0.5) * A.ddz;  // lower face of the run's first voxel
+    const float v0 = (float)v0d, dv = (float)A.dv, idv = 1.0f / dv;
     const float aum = (float)(A.cu - A.offu / A.du), iau = (float)(1.0 / A.du);
     const int64_t psz = (int64_t)A.nu * A.nv;
     constexpr int ES = (int)sizeof(TP);
@@ -359,7 +508,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
             // (x, y) direction of the rays of column a: P - S = -DSD (c, s) + ua (-s, c)
             const double Dx = -A.dDSD * c - ua * s, Dy = -A.dDSD * s + ua * c;
             const float cross = (float)(Wx * Dy - Wy * Dx);   // = |D| * signed distance
-            const float dotp = (float)(Wx * Dx + Wy * Dy);    // = |D|^2 * t of the closest point
+            const double dotd = Wx * Dx + Wy * Dy;            // = |D|^2 * t of the closest point
             const float fDx = (float)Dx, fDy = (float)Dy;
             const float L2 = fmaf(fDx, fDx, fDy * fDy);
             const float iL = __builtin_amdgcn_rsqf(L2);
@@ -387,7 +536,11 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
             }
             if (!(s0 < s1)) continue;
             const float T = (s1 - s0) * iL;                       // t-length inside the column
-            const float t0 = fmaf(s0, iL, dotp * (iL * iL));      // t where the trace enters
+            // t where the trace enters, in FP64 (one Newton step on the FP32 reciprocal of |D|^2)
+            const double L2d = Dx * Dx + Dy * Dy;
+            const double rl = (double)__builtin_amdgcn_rcpf((float)L2d);
+            const double t0d = fma(dotd, rl * fma(-L2d, rl, 2.0), (double)(s0 * iL));
+            const float t0 = (float)t0d;
             const float t1 = t0 + T;
             // rows whose height range inside the column meets the thread's z run [zl0, zr_hi]
             const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t1);
@@ -397,13 +550,16 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
             int off = blo * rowb + a * ES;
             for (int b = blo; b <= bhi; ++b, off += rowb) {
                 const float y = bload(R, off, (TP *)nullptr);
-                const float vb = fmaf((float)b, dv, v0);
-                const float za = t0 * vb;            // height where the row enters the column
+                const double vbd = fma((double)b, A.dv, v0d);
+                const float vb = (float)vbd;
+                // height where the row enters the column, relative to the run's lowest face (a
+                // difference of heights of up to the volume's half height, formed in FP64)
+                const float za = (float)fma(t0d, vbd, -zl0d);
                 const float ext = T * vb;            // signed height change across the column
                 const float lo = fminf(za, za + ext), hi = fmaxf(za, za + ext);
                 const float full = T * sqrtf(fmaf(vb, vb, L2));   // chord inside the column
-                const int klo = (int)floorf((lo - zface0) * idz) - kb;
-                const int khi = (int)floorf((hi - zface0) * idz) - kb;
+                const int klo = (int)floorf(lo * idz);
+                const int khi = (int)floorf(hi * idz);
                 if (klo == khi) {
                     // the row stays inside one voxel
                     if ((unsigned)klo < (unsigned)nzr) accs[klo * 256 + tid] = fmaf(full, y, accs[klo * 256 + tid]);
@@ -411,7 +567,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
                     const float iext = __builtin_amdgcn_rcpf(hi - lo);
                     const int ke = min(khi, nzr - 1);
                     for (int k = max(klo, 0); k <= ke; ++k) {
-                        const float zl = fmaf((float)(kb + k), dz, zface0);
+                        const float zl = (float)k * dz;
                         const float ov = fmaxf(fminf(hi, zl + dz) - fmaxf(lo, zl), 0.0f);
                         accs[k * 256 + tid] = fmaf(full * (ov * iext), y, accs[k * 256 + tid]);
                     }
@@ -422,6 +578,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
 #pragma unroll
     for (int k = 0; k < ADJ_NZ; ++k) {
         const int kk = kb + k;
+        if (kk < A.own_lo) continue;
         if (kk >= A.own_hi) break;
         const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
         vol[o] = from_f<TV>(accs[k * 256 + tid]);
@@ -467,7 +624,7 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
                 const double ua = (u - A.cu) * A.du + A.offu, vb = (b - A.cv) * A.dv + A.offv;
                 // |P - S| (mm per unit t) is the same for every angle in a circular orbit
                 q.x = (float)(tile[tx][ty + k] * sqrt(A.dDSD * A.dDSD + ua * ua + vb * vb));
-                q.y = vb != 0.0 ? (float)(1.0 / vb) : 1e30f;
+                q.y = vb != 0.0 ? (float)(A.ddz / vb) : 1e30f;  // parameter step across one voxel height
             }
             yq[((int64_t)t * A.nu + u) * nvp + r] = q;
         }
@@ -481,10 +638,10 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
 // kernel then orders each voxel's faces once (za, zb) instead of ordering the two parameters of
 // every row.  Rows of the other sign get an empty interval either way, so both forms give the same
 // bits.
-// at most 4 waves per SIMD: the compiler then keeps the row loads of all R voxels of a candidate
+// exactly 4 waves per SIMD: the compiler then keeps the row loads of all R voxels of a candidate
 // column in flight together instead of two at a time (more registers, fewer exposed latencies)
 #ifndef CT_ADJ_WAVES
-#define CT_ADJ_WAVES 1, 4
+#define CT_ADJ_WAVES 4, 4
 #endif
 #define CT_ADJ_OCC __attribute__((amdgpu_waves_per_eu(CT_ADJ_WAVES)))
 template <typename TV, int R, int NR, bool ZC, bool ORD>
@@ -516,24 +673,34 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
                   : ((int64_t)(k - A.mem_lo) * A.ny + j) * A.nx + i;
     };
     // za, zb: the voxel's faces in the order its rows reach them (lower face first unless ORD and
-    // the voxel lies below the source plane)
-    float acc[R], za[R], zb[R];
+    // the voxel lies below the source plane), for choosing the candidate rows.
+    // kA, sg: index of the face that rows of the voxel's side of the source plane reach first (the
+    // upper face for a voxel below the plane), an exact integer, and the direction of the other
+    // face.  They are the same with and without ORD, so both forms give the same bits.
+    float acc[R], za[R], zb[R], kA[R], sg[R];
     bool kin[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
         kin[r] = k < A.own_hi;
         const float zl = fmaf((float)k, dz, zface0), zh = fmaf((float)(k + 1), dz, zface0);
-        const bool flip = ORD && zh <= 0.0f;
+        const bool below = zh <= 0.0f;
+        const bool flip = ORD && below;
         za[r] = flip ? zh : zl;
         zb[r] = flip ? zl : zh;
+        kA[r] = (float)(below ? k + 1 : k);
+        sg[r] = below ? -1.0f : 1.0f;
         const int64_t o = vidx(k);
         acc[r] = (kin[r] && A.accumulate) ? to_f(vol[o]) : 0.0f;
     }
     const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;  // column centre (mm)
     const float hx = 0.5f * A.dx, hy = 0.5f * A.dy;
     const float fxc = (float)xc, fyc = (float)yc;
-    const float v0 = (float)(A.offv - A.cv * A.dv), idv = 1.0f / (float)A.dv;
+    const double v0d = A.offv - A.cv * A.dv;  // height of row 0 at the detector
+    // heights in voxel units above the lower face of voxel 0: row b enters the square at height
+    // H0 + b S with H0 = (t0 v0 - zface0) / dz and S = t0 dv / dz
+    const double v0dz = v0d / A.ddz, zf0dz = (A.dz0 - 0.5 * A.ddz) / A.ddz, dvdz = A.dv / A.ddz;
+    const float v0 = (float)v0d, idv = 1.0f / (float)A.dv;
     const float nv0 = -v0 * idv;
     const float bmax = (float)(A.nv + 1 - NR);
     const float aum = (float)(A.cu - A.offu / A.du), iau = (float)(1.0 / A.du);
@@ -557,7 +724,7 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
             const double ua = (a - A.cu) * A.du + A.offu;
             const double Dx = -A.dDSD * c - ua * s, Dy = -A.dDSD * s + ua * c;
             const float cross = (float)(Wx * Dy - Wy * Dx);
-            const float dotp = (float)(Wx * Dx + Wy * Dy);
+            const double dotd = Wx * Dx + Wy * Dy;
             const float fDx = (float)Dx, fDy = (float)Dy;
             const float L2 = fmaf(fDx, fDx, fDy * fDy);
             const float iL = __builtin_amdgcn_rsqf(L2);
@@ -583,20 +750,45 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
             }
             if (!(s0 < s1)) continue;
             const float T = (s1 - s0) * iL;
-            const float t0 = fmaf(s0, iL, dotp * (iL * iL));
+            // t where the trace enters the square, in FP64: the foot point's parameter W.D / |D|^2
+            // (one Newton step on the FP32 reciprocal) plus the small FP32 clip offset
+            const double L2d = Dx * Dx + Dy * Dy;
+            const double rl = (double)__builtin_amdgcn_rcpf((float)L2d);
+            const double t0d = fma(dotd, rl * fma(-L2d, rl, 2.0), (double)(s0 * iL));
+            const float t0 = (float)t0d;
+            // H0 = H0h + H0l with H0h on a grid of 2^-7 (adding and removing 1.5 * 2^16 rounds to
+            // it for |H0| < 2^15), S = Sh + Sr with Sh holding 10 significant bits: then for face
+            // index kA (an integer) and row b (|b| < 2^14) kA - H0h and b Sh are exact FP32 values
+            // and so is their difference, which is a few voxels for the candidate rows; only the
+            // small terms b Sr + H0l are rounded
+            const double H0d = fma(t0d, v0dz, -zf0dz), Sd = t0d * dvdz;
+            const float H0h = ((float)H0d + 98304.0f) - 98304.0f;
+            const float H0l = (float)(H0d - (double)H0h);
+            const float Sf = (float)Sd;
+            const float Sh = __uint_as_float(__float_as_uint(Sf) & 0xFFFFC000u);
+            const float Sr = (float)(Sd - (double)Sh);
             const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
             const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
-            // the rows of all R voxels are loaded first, so their loads are in flight together
             float2 wv[R][NR];
+            float bl[R], E[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]: the lowest
                 // v = z / t over the lower face and t in [t0, t1] (with ORD, za * it1 for voxels
                 // above the plane and zb * it0 for voxels below)
                 const float vlo = ORD ? fminf(za[r] * it1, zb[r] * it0) : fminf(za[r] * it0, za[r] * it1);
-                const float bl = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
+                bl[r] = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
+                // the height of face A above row bl where the row enters the square, in voxel
+                // units (kA - H0 - bl S: a difference of heights of up to the volume's height,
+                // formed exactly up to the small terms)
+                const float d = (kA[r] - H0h) - bl[r] * Sh;
+                E[r] = d - fmaf(bl[r], Sr, H0l);
+            }
+            // the rows of all R voxels are loaded before any is used, so they are in flight together
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
                 // uniform column base plus an unsigned 32-bit byte offset of row bl
-                const float2 *cb = (const float2 *)((const char *)col + (uint32_t)((int)bl + 1) * 8u);
+                const float2 *cb = (const float2 *)((const char *)col + (uint32_t)((int)bl[r] + 1) * 8u);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) wv[r][q] = cb[q];
             }
@@ -605,9 +797,11 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
                     const float2 w = wv[r][q];
-                    // parameters relative to t0 (one rounding each), clipped to [0, T]: a row that
-                    // stays inside the voxel gets exactly T
-                    const float tA = fmaf(za[r], w.y, -t0), tB = fmaf(zb[r], w.y, -t0);
+                    // parameters relative to t0 of the row's crossings of faces A and B (its
+                    // height below face A in voxels times dz / v_b, and one step dz / v_b more),
+                    // clipped to [0, T]: a row that stays inside the voxel gets exactly T
+                    const float Eq = q == 0 ? E[r] : fmaf(-(float)q, Sf, E[r]);
+                    const float tA = Eq * w.y, tB = fmaf(sg[r], w.y, tA);
                     float len;
                     if (ORD) {
                         // tA <= tB for the rows that can meet the voxel; rows of the other sign have
@@ -635,51 +829,75 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
 //   x_j += lambda * (w_j * bilinear(r)) / (w_j * bilinear(1))   where w_j * bilinear(1) > 1e-6
 __global__ __launch_bounds__(256) void k_sart_update(const float *__restrict__ r, float *__restrict__ vol,
                                                      BpArgs A, float lambda) {
-    const int i = blockIdx.x * BP_TX + (threadIdx.x % BP_TX);
-    const int j = blockIdx.y * BP_TY + (threadIdx.x / BP_TX);
+    __shared__ TileRef ref[64];
+    __shared__ float iref[64][2];
+    const int i0 = blockIdx.x * BP_TX, j0 = blockIdx.y * BP_TY;
+    const int i = i0 + (threadIdx.x % BP_TX);
+    const int j = j0 + (threadIdx.x / BP_TX);
     const int kb = blockIdx.z * BP_NZ;
-    if (i >= A.nx || j >= A.ny) return;
-    const float x = fmaf((float)i, A.dx, A.x0);
-    const float y = fmaf((float)j, A.dy, A.y0);
+    const bool live = i < A.nx && j < A.ny;
+    // detector coordinates relative to the tile's reference point (see TileRef)
+    const float ir = tile_mid(i0, BP_TX, A.nx), jr = tile_mid(j0, BP_TY, A.ny), kr = tile_mid(kb, BP_NZ, A.nz);
+    const float lx = ((float)i - ir) * A.dx, ly = ((float)j - jr) * A.dy;
     const int64_t pix = (int64_t)A.nu * A.nv;
+    const float amax = (float)A.nu + 1.0f, bmax = (float)A.nv + 1.0f;
     // sums over the subset's angles, in angle order
     float num[BP_NZ], V[BP_NZ];
 #pragma unroll
     for (int k = 0; k < BP_NZ; ++k) num[k] = V[k] = 0.0f;
-    for (int t = 0; t < A.nang; ++t) {
-        const AngleGeo &G = A.tab[A.a0 + t];
-        const float c = (float)G.c, s = (float)G.s;
-        const float Ld = A.DSO - (x * c + y * s);
-        const float iL = 1.0f / Ld;
-        const float m = A.DSD * iL;
-        const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
-        const float af = floorf(as);
-        const float fa = as - af;
-        const int ia = (int)af;
-        const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
-        const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
-        if (wa0 == 0.0f && wa1 == 0.0f) continue;
-        const int ia0 = clampi(ia, 0, A.nu - 1), ia1 = clampi(ia + 1, 0, A.nu - 1);
-        const float q = A.DSO * iL;
-        const float w = q * q;
-        const float *rt = r + t * pix;
+    for (int t0 = 0; t0 < A.nang; t0 += 64) {
+        const int nk = min(64, A.nang - t0);
+        __syncthreads();
+        if ((int)threadIdx.x < nk) {
+            const AngleGeo &G = A.tab[A.a0 + t0 + threadIdx.x];
+            TileRef R;
+            double ar, br;
+            tile_ref(A, G.c, G.s, A.dx0 + (double)ir * A.ddx, A.dy0 + (double)jr * A.ddy, A.dz0 + (double)kr * A.ddz, R,
+                     ar, br);
+            const double fa = fmin(fmax(floor(ar), -16777216.0), 16777216.0);
+            const double fbr = fmin(fmax(floor(br), -16777216.0), 16777216.0);
+            R.Aloc = (float)(ar - fa);
+            R.Bloc = (float)(br - fbr);
+            ref[threadIdx.x] = R;
+            iref[threadIdx.x][0] = (float)fa;
+            iref[threadIdx.x][1] = (float)fbr;
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int q = 0; q < nk; ++q) {
+            const TileRef R = ref[q];
+            float as, bq, mv, iL;
+            tile_local(R, lx, ly, A.DSD, A.inv_dv, as, bq, mv, iL);
+            const float af = floorf(as);
+            const float fa = as - af;
+            const int ia = (int)__builtin_amdgcn_fmed3f(iref[q][0] + af, -2.0f, amax);
+            const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
+            const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
+            if (wa0 == 0.0f && wa1 == 0.0f) continue;
+            const int ia0 = clampi(ia, 0, A.nu - 1), ia1 = clampi(ia + 1, 0, A.nu - 1);
+            const float qq = A.DSO * iL;
+            const float w = qq * qq;
+            const float *rt = r + (t0 + q) * pix;
+            const float ob = iref[q][1];
 #pragma unroll
-        for (int k = 0; k < BP_NZ; ++k) {
-            const int kk = min(kb + k, A.nz - 1);
-            const float z = fmaf((float)kk, A.dz, A.z0);
-            const float bs = fmaf(m * z, A.inv_dv, A.bv0);
-            const float bf = floorf(bs);
-            const float fb = bs - bf;
-            const int ib = (int)bf;
-            const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-            const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
-            const int r0 = clampi(ib, 0, A.nv - 1) * A.nu, r1 = clampi(ib + 1, 0, A.nv - 1) * A.nu;
-            const float v0 = fmaf(wa1, rt[r0 + ia1], wa0 * rt[r0 + ia0]);
-            const float v1 = fmaf(wa1, rt[r1 + ia1], wa0 * rt[r1 + ia0]);
-            num[k] += w * fmaf(wb1, v1, wb0 * v0);
-            V[k] += w * ((wa0 + wa1) * (wb0 + wb1));
+            for (int k = 0; k < BP_NZ; ++k) {
+                // heights past the top of the volume are clamped to the last slice (and not written)
+                const float zlk = ((float)min(kb + k, A.nz - 1) - kr) * A.dz;
+                const float bs = fmaf(zlk, mv, bq);
+                const float bf = floorf(bs);
+                const float fb = bs - bf;
+                const int ib = (int)__builtin_amdgcn_fmed3f(ob + bf, -2.0f, bmax);
+                const float wb0 = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+                const float wb1 = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+                const int r0 = clampi(ib, 0, A.nv - 1) * A.nu, r1 = clampi(ib + 1, 0, A.nv - 1) * A.nu;
+                const float v0 = fmaf(wa1, rt[r0 + ia1], wa0 * rt[r0 + ia0]);
+                const float v1 = fmaf(wa1, rt[r1 + ia1], wa0 * rt[r1 + ia0]);
+                num[k] += w * fmaf(wb1, v1, wb0 * v0);
+                V[k] += w * ((wa0 + wa1) * (wb0 + wb1));
+            }
         }
     }
+    if (!live) return;
 #pragma unroll
     for (int k = 0; k < BP_NZ; ++k) {
         const int kk = kb + k;
@@ -703,70 +921,103 @@ constexpr int SART_R = CT_SART_R;  // voxels per lane of the column update
 // column-major copy.
 __global__ __launch_bounds__(256) void k_sart_update_col(const float *__restrict__ rT, float *__restrict__ vz,
                                                          BpArgs A, float lambda, int zwaves) {
+    // per wave and angle: the column's detector coordinate a* (origin and fraction), FDK weight and
+    // row step per mm; per height group r, the row coordinate of the group's reference height
+    // (origin and fraction).  All from FP64, so the FP32 per-height parts are a few pixels in size.
+    struct ColRef {
+        float fa, w, mv, ia;
+    };
+    __shared__ ColRef hdr[4][64];
+    __shared__ float2 bref[4][64][SART_R];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t col = gw / zwaves;
-    if (col >= (int64_t)A.nx * A.ny) return;
-    const int kk0 = (int)(gw % zwaves) * 64 * SART_R + (threadIdx.x & 63);
+    const int64_t ncol = (int64_t)A.nx * A.ny;
+    const bool live = gw / zwaves < ncol;
+    const int64_t col = live ? gw / zwaves : ncol - 1;  // a wave past the last column writes nothing
+    const int zbase = (int)(gw % zwaves) * 64 * SART_R;
+    const int kk0 = zbase + lane;
     const int i = (int)(col % A.nx), j = (int)(col / A.nx);
-    const float x = fmaf((float)i, A.dx, A.x0);
-    const float y = fmaf((float)j, A.dy, A.y0);
     const int64_t pix = (int64_t)A.nu * A.nv;
     float *vc = vz + col * (A.nz + 2) + 1;
     // the voxels' values are read first, so their loads overlap the first angle's taps
-    float xo[SART_R];
+    float xo[SART_R], kref[SART_R], zl[SART_R];
 #pragma unroll
-    for (int r = 0; r < SART_R; ++r) xo[r] = vc[min(kk0 + 64 * r, A.nz - 1)];
+    for (int r = 0; r < SART_R; ++r) {
+        const int kk = min(kk0 + 64 * r, A.nz - 1);
+        xo[r] = vc[kk];
+        kref[r] = tile_mid(min(zbase + 64 * r, A.nz - 1), 64, A.nz);
+        zl[r] = ((float)kk - kref[r]) * A.dz;
+    }
+    const double xc = A.dx0 + i * A.ddx, yc = A.dy0 + j * A.ddy;
+    const float amax = (float)A.nu + 1.0f, bmax = (float)A.nv + 1.0f;
     // sums over the subset's angles, in angle order
     float num[SART_R], V[SART_R];
 #pragma unroll
     for (int r = 0; r < SART_R; ++r) num[r] = V[r] = 0.0f;
-    for (int t = 0; t < A.nang; ++t) {
-        const AngleGeo &G = A.tab[A.a0 + t];
-        const float c = (float)G.c, s = (float)G.s;
-        const float Ld = A.DSO - (x * c + y * s);
-        const float iL = 1.0f / Ld;
-        const float m = A.DSD * iL;
-        const float as = fmaf(m * (y * c - x * s), A.inv_du, A.au0);
-        const float af = floorf(as);
-        const float fa = as - af;
-        const int ia = (int)af;
-        const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
-        const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
-        if (wa0 == 0.0f && wa1 == 0.0f) continue;
-        const float *rt = rT + t * pix;
-        const float *r0 = rt + (int64_t)clampi(ia, 0, A.nu - 1) * A.nv;
-        const float *r1 = rt + (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
-        const float q = A.DSO * iL;
-        const float w = q * q;
-        const float wva = w * (wa0 + wa1);
-        const float mv = m * A.inv_dv;
-        // all taps of the wave's SART_R heights first (heights clamped into the column), then the sums
-        float wb0[SART_R], wb1[SART_R], t00[SART_R], t01[SART_R], t10[SART_R], t11[SART_R];
-#pragma unroll
-        for (int r = 0; r < SART_R; ++r) {
-            const int kk = min(kk0 + 64 * r, A.nz - 1);
-            const float z = fmaf((float)kk, A.dz, A.z0);
-            const float bs = fmaf(z, mv, A.bv0);
-            const float bf = floorf(bs);
-            const float fb = bs - bf;
-            const int ib = (int)bf;
-            wb0[r] = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
-            wb1[r] = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
-            const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
-            t00[r] = r0[b0];
-            t10[r] = r1[b0];
-            t01[r] = r0[b1];
-            t11[r] = r1[b1];
+    for (int t0 = 0; t0 < A.nang; t0 += 64) {
+        const int nk = min(64, A.nang - t0);
+        __syncthreads();
+        // lane = (angle, height group) pair, so a launch of one angle (SART) costs one pass
+        for (int p0 = 0; p0 < nk * SART_R; p0 += 64) {
+            const int q = (p0 + lane) / SART_R, r = (p0 + lane) % SART_R;
+            if (q < nk) {
+                const AngleGeo &G = A.tab[A.a0 + t0 + q];
+                const double D = A.dDSO - (xc * G.c + yc * G.s), iD = rcp_f64(D);
+                const double kv = A.dDSD * iD * A.idv;
+                if (r == 0) {
+                    const double ar = fma(A.dDSD * iD * A.idu, yc * G.c - xc * G.s, A.dau0);
+                    const double fa = fmin(fmax(floor(ar), -16777216.0), 16777216.0);
+                    const double w = A.dDSO * iD;
+                    hdr[wave][q] = ColRef{(float)(ar - fa), (float)(w * w), (float)kv, (float)fa};
+                }
+                const float kr = tile_mid(min(zbase + 64 * r, A.nz - 1), 64, A.nz);
+                const double br = fma(kv, A.dz0 + (double)kr * A.ddz, A.dbv0);
+                const double fb = fmin(fmax(floor(br), -16777216.0), 16777216.0);
+                bref[wave][q][r] = make_float2((float)fb, (float)(br - fb));
+            }
         }
+        __syncthreads();
+        if (!live) continue;
+        for (int q = 0; q < nk; ++q) {
+            const ColRef H = hdr[wave][q];
+            const int ia = (int)__builtin_amdgcn_fmed3f(H.ia, -2.0f, amax);
+            const float fa = H.fa;
+            const float wa0 = ((unsigned)ia < (unsigned)A.nu) ? 1.0f - fa : 0.0f;
+            const float wa1 = ((unsigned)(ia + 1) < (unsigned)A.nu) ? fa : 0.0f;
+            if (wa0 == 0.0f && wa1 == 0.0f) continue;
+            const float *rt = rT + (t0 + q) * pix;
+            const float *r0 = rt + (int64_t)clampi(ia, 0, A.nu - 1) * A.nv;
+            const float *r1 = rt + (int64_t)clampi(ia + 1, 0, A.nu - 1) * A.nv;
+            const float w = H.w;
+            const float wva = w * (wa0 + wa1);
+            // all taps of the wave's SART_R heights first (heights clamped into the column), then the sums
+            float wb0[SART_R], wb1[SART_R], t00[SART_R], t01[SART_R], t10[SART_R], t11[SART_R];
 #pragma unroll
-        for (int r = 0; r < SART_R; ++r) {
-            const float v0 = fmaf(wa1, t10[r], wa0 * t00[r]);
-            const float v1 = fmaf(wa1, t11[r], wa0 * t01[r]);
-            num[r] += w * fmaf(wb1[r], v1, wb0[r] * v0);
-            V[r] += wva * (wb0[r] + wb1[r]);
+            for (int r = 0; r < SART_R; ++r) {
+                const float2 B = bref[wave][q][r];
+                const float bs = fmaf(zl[r], H.mv, B.y);
+                const float bf = floorf(bs);
+                const float fb = bs - bf;
+                const int ib = (int)__builtin_amdgcn_fmed3f(B.x + bf, -2.0f, bmax);
+                wb0[r] = ((unsigned)ib < (unsigned)A.nv) ? 1.0f - fb : 0.0f;
+                wb1[r] = ((unsigned)(ib + 1) < (unsigned)A.nv) ? fb : 0.0f;
+                const int b0 = clampi(ib, 0, A.nv - 1), b1 = clampi(ib + 1, 0, A.nv - 1);
+                t00[r] = r0[b0];
+                t10[r] = r1[b0];
+                t01[r] = r0[b1];
+                t11[r] = r1[b1];
+            }
+#pragma unroll
+            for (int r = 0; r < SART_R; ++r) {
+                const float v0 = fmaf(wa1, t10[r], wa0 * t00[r]);
+                const float v1 = fmaf(wa1, t11[r], wa0 * t01[r]);
+                num[r] += w * fmaf(wb1[r], v1, wb0[r] * v0);
+                V[r] += wva * (wb0[r] + wb1[r]);
+            }
         }
     }
+    if (!live) return;
 #pragma unroll
     for (int r = 0; r < SART_R; ++r) {
         const int kk = kk0 + 64 * r;
@@ -859,8 +1110,12 @@ BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, con
     A.offv = g.offDetector[1];
     A.inv_du = (float)(1.0 / g.dDetector[0]);
     A.inv_dv = (float)(1.0 / g.dDetector[1]);
-    A.au0 = (float)(A.cu - g.offDetector[0] / g.dDetector[0]);
-    A.bv0 = (float)(A.cv - g.offDetector[1] / g.dDetector[1]);
+    A.dau0 = A.cu - g.offDetector[0] / g.dDetector[0];
+    A.dbv0 = A.cv - g.offDetector[1] / g.dDetector[1];
+    A.au0 = (float)A.dau0;
+    A.bv0 = (float)A.dbv0;
+    A.idu = 1.0 / g.dDetector[0];
+    A.idv = 1.0 / g.dDetector[1];
     A.DSO = (float)g.DSO;
     A.DSD = (float)g.DSD;
     A.dDSO = g.DSO;
@@ -899,15 +1154,17 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     if (slab.zcol && (kind != CT_BP_ADJOINT || !adj_col_ok(p)))
         return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's column kernel");
     BpArgs A = make_bp_args(p, tab, a0, a1, slab, accumulate);
-    const int nzrun = kind == CT_BP_ADJOINT ? ADJ_NZ : BP_NZ;
-    const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((nzown + nzrun - 1) / nzrun));
+    // voxel-driven kernels: runs of slices aligned to absolute multiples of the run length
+    auto runs = [&](int n) { return (unsigned)((slab.own_hi - 1) / n - slab.own_lo / n + 1); };
+    const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY,
+                    kind == CT_BP_ADJOINT ? runs(ADJ_NZ) : runs(BP_NZ));
     const dim3 block(256);
     int WW = 0, HW = 0;
 #ifndef CT_NO_BP_LDS
     if (kind != CT_BP_ADJOINT && bp_window(p->g, WW, HW)) {
         const bool narrow = WW <= BPL_PN;
         const int K = std::min(BPL_K, BPL_FLOATS / ((narrow ? BPL_PN : 64) * HW));
-        const dim3 lgrid(grid.x, grid.y, (unsigned)((nzown + BPL_NZ - 1) / BPL_NZ));
+        const dim3 lgrid(grid.x, grid.y, runs(BPL_NZ));
 #define CT_BPL(KIND, PITCH)                                                                                      \
     CT_DISPATCH2(pt, TP, vt, TV,                                                                                 \
                  hipLaunchKernelGGL((k_bp_lds<KIND, PITCH, TP, TV>), lgrid, block, 0, st, (const TP *)proj,        \

@@ -157,11 +157,7 @@ def test_fdk_splitting_geometry_sampled(orc):
     at 4 of its angles, resident (a 108 GiB FP32 volume in device memory), on the exact line
     integrals of 6 of its phantom's ellipsoids: the filtered rows, and the reconstruction at 400
     sampled voxels against the oracle's FDK-weighted backprojection of its own filtered rows.
-
-    The backprojector interpolates at an FP32 detector coordinate, whose spacing is 2.4e-4 pixels
-    above 2048: on data that changes by its full size from pixel to pixel (ramp-filtered white
-    noise) that alone gives 2.2e-4 relative L2 at this detector size.  Projections of objects are
-    smooth between their edges, and that is the data used here."""
+    (Ramp-filtered noise at the same geometry: test_backprojectors_3072_detector_ramp_noise.)"""
     base = inputs.workload("ooc")
     w = inputs.Workload("ooc_4", base.nvox, base.dvox, base.ndet, base.ddet, 4, 6, base.seed,
                         angles=np.asarray(base.angles)[[0, 768, 1536, 2304]])
@@ -187,6 +183,50 @@ def test_fdk_splitting_geometry_sampled(orc):
     e = rel_l2(got, ref)
     say(f"   reconstruction rel L2 (sampled) {e:.3e}")
     assert e <= TOL_BP
+
+
+def test_backprojectors_3072_detector_ramp_noise(orc):
+    """The splitting workload's geometry (3072^3 voxels of 256/3072 mm, 3072^2 detector) at 4 of its
+    angles on ramp-filtered uniform noise: data that changes by its full size from pixel to pixel,
+    which is what the FDK reconstruction feeds the backprojector.  Every detector coordinate is
+    above 2048 pixels from the edge somewhere, where an FP32 coordinate is resolved to only 2.4e-4
+    pixel; the kernels form each voxel's coordinate as a small offset from a tile reference
+    projected in FP64.  FDK-weighted, pseudo-matched and exact-adjoint backprojections of the same
+    FP32 rows, each at 600 sampled voxels against the oracle (1e-4), then the whole FDK
+    reconstruction of the noise."""
+    base = inputs.workload("ooc")
+    w = inputs.Workload("ooc_4", base.nvox, base.dvox, base.ndet, base.ddet, 4, 6, base.seed,
+                        angles=np.asarray(base.angles)[[0, 769, 1536, 2305]])
+    geo = w.geometry_dict()
+    plan = Plan(geo, w.angles)
+    og = orc.Geometry.from_dict(geo)
+    noise = inputs.random_array(plan.proj_shape, 406, kind="uniform")
+    say("[bp3072] oracle ramp filter of 4 x 3072^2 uniform noise")
+    y64 = orc.fdk_filter(og, w.angles, noise.astype(np.float64))
+    y = y64.astype(np.float32)
+    yt = torch.from_numpy(y).to(DEV)
+    vox = inputs.sample_indices(3072 ** 3, 600, 407)
+    vt = torch.from_numpy(vox).to(DEV)
+    vol = torch.empty(plan.vol_shape, dtype=torch.float32, device=DEV)
+    refs = {"fdk": lambda: orc.bp_voxels(og, w.angles, y, vox, orc.W_FDK),
+            "pm": lambda: orc.bp_voxels(og, w.angles, y, vox, orc.W_PM),
+            "adjoint": lambda: orc.siddon_adj_voxels(og, w.angles, y, vox)}
+    errs = {}
+    for kind, ref_fn in refs.items():
+        say(f"[bp3072] {kind} backprojection, 3072^3 x 4 angles, resident")
+        plan.backproject(yt, kind, out=vol)
+        got = vol.view(-1)[vt].cpu().numpy()
+        errs[kind] = rel_l2(got, ref_fn())
+        say(f"   {kind} rel L2 (600 sampled voxels) {errs[kind]:.3e}")
+    say("[bp3072] FDK reconstruction of the noise")
+    plan.fdk(torch.from_numpy(noise).to(DEV), out=vol)
+    got = vol.view(-1)[vt].cpu().numpy()
+    del vol
+    torch.cuda.empty_cache()
+    errs["fdk_recon"] = rel_l2(got, orc.bp_voxels(og, w.angles, y64, vox, orc.W_FDK))
+    say(f"   reconstruction rel L2 (sampled) {errs['fdk_recon']:.3e}")
+    for kind, e in errs.items():
+        assert e <= TOL_BP, (kind, e)
 
 
 def test_fdk_rejects_bad_arguments(tiny):

@@ -231,7 +231,7 @@ def test_medium_backprojection_sampled(medium, orc):
     idx = inputs.sample_indices(512 ** 3, 600, 32)
     for kind, n, fn in (("fdk", 600, lambda i: orc.bp_voxels(og, w.angles, y64, i, orc.W_FDK)),
                         ("pm", 600, lambda i: orc.bp_voxels(og, w.angles, y64, i, orc.W_PM)),
-                        ("adjoint", 48, lambda i: orc.siddon_adj_voxels(og, w.angles, y64, i))):
+                        ("adjoint", 300, lambda i: orc.siddon_adj_voxels(og, w.angles, y64, i))):
         say(f"[medium backprojection sampled] kind={kind}")
         v = plan.backproject(yt, kind).cpu().numpy().ravel()[idx[:n]]
         e = rel_l2(v, fn(idx[:n]))
