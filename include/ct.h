@@ -53,8 +53,11 @@ typedef enum {
 } ct_status;
 
 /* Storage type of a volume or projection array.  Arithmetic is always FP32 (accumulation along
- * every ray and over every voxel's angles); CGLS inner products and norms are FP64. */
-typedef enum { CT_F32 = 0, CT_F16 = 1, CT_BF16 = 2 } ct_dtype;
+ * every ray and over every voxel's angles); CGLS inner products and norms are FP64.
+ * CT_F64 is not a storage type of the operators or algorithms (they refuse it with CT_ERR_DTYPE):
+ * FP64 arrays are accepted by ct_convert, to bring FP64 data to a storage type on the device (to
+ * FP32 with one rounding, to FP16/BF16 through FP32), and by ct_dot. */
+typedef enum { CT_F32 = 0, CT_F16 = 1, CT_BF16 = 2, CT_F64 = 3 } ct_dtype;
 
 /* Forward projectors (Section 2.1). */
 typedef enum {
@@ -137,6 +140,8 @@ typedef struct {
     double t_compute_s;     /* time the compute stream was busy (kernels, incl. overlapped copies) */
     double t_stage_s;       /* host time spent copying between caller memory and pinned staging */
     double t_other_mem_s;   /* allocation, freeing and copies not overlapped with kernels */
+    double t_pin_s;         /* allocating the pinned staging buffers (hipHostMalloc; part of
+                               t_other_mem_s; 0 when the caller's arrays are pinned) */
 } ct_ooc_stats;
 
 /* Pure host planner used by the *_host calls: slab height and chunk size for a cap.
@@ -204,12 +209,14 @@ ct_status ct_cgls_host(ct_plan *plan, const float *h_b, float *h_x, int32_t nite
  *   x += lambda B_S(W (b_S - A_S x)) / V
  * with W = 1/(A_S 1) for rays whose chord through the grid exceeds 1e-2 min(dVoxel) (others weigh
  * 0) and V = B_S 1, voxels with V <= 1e-6 left unchanged.  block: 1 .. n_angles (n_angles gives one
- * SIRT step per sweep).  d_b and d_x as ct_cgls; FP32 storage only.  The workspace grows with block
- * (two projection-sized buffers per angle of a subset).  Errors: CT_ERR_ARG for a NULL pointer,
- * niter < 0, block outside [1, n_angles] or a non-finite lambda. */
+ * SIRT step per sweep).  d_b (proj_dtype) and d_x (vol_dtype) as ct_cgls: the sweeps update an FP32
+ * copy of x, so a 16-bit x is rounded once, when the result is written back; b is read in its
+ * storage type.  The workspace grows with block (two projection-sized buffers per angle of a
+ * subset) and does not depend on the dtypes.  Errors: CT_ERR_ARG for a NULL pointer, niter < 0,
+ * block outside [1, n_angles] or a non-finite lambda; CT_ERR_DTYPE. */
 ct_status ct_sart_workspace_bytes(const ct_plan *plan, int32_t block, uint64_t *bytes);
-ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, double lambda,
-                  int32_t block, void *d_workspace, void *stream);
+ct_status ct_sart(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype,
+                  int32_t niter, double lambda, int32_t block, void *d_workspace, void *stream);
 
 /* FDK reconstruction (Feldkamp, Davis and Kress 1984, the algorithm that Section 2.2's
  * FDK-weighted backprojector belongs to) for a full circular scan with uniformly spaced angles.
@@ -245,10 +252,14 @@ ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d
 /* TV steepest descent (Section 2.3, gradient-descent form): nsteps steps of
  * x <- x - alpha g / ||g||_2, g = grad TV_eps(x) with forward differences on a unit grid and zero
  * difference at the last index of each axis, TV_eps(x) = sum_j sqrt(|D x_j|^2 + eps), and
- * alpha = lambda ||x_in||_2 fixed for the call.  Norms are FP64.  d_x: device volume (FP32) of
- * the geometry's nVoxel shape. */
-ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes);
-ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, double lambda,
+ * alpha = lambda ||x_in||_2 fixed for the call.  Norms are FP64.  d_x: device volume of the
+ * geometry's nVoxel shape, stored in dtype; a 16-bit image is stepped in an FP32 copy in the
+ * workspace (one more FP32 volume) and rounded once at the end.  d_workspace: at least
+ * ct_tv_workspace_bytes(geometry, dtype) bytes, or NULL for stream-ordered scratch.
+ * Errors: CT_ERR_ARG (NULL pointer, nsteps < 0, eps <= 0, non-finite lambda), CT_ERR_DTYPE,
+ * CT_ERR_GEOMETRY (a voxel count <= 0). */
+ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, ct_dtype dtype, uint64_t *bytes);
+ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, ct_dtype dtype, int32_t nsteps, double lambda,
                       double eps, void *d_workspace, void *stream);
 /* The same TV steps on an image in host memory (Section 2.3's regularisation of images larger
  * than device memory), under device_cap_bytes.  The image is cut into equal slabs of axial slices;
@@ -288,10 +299,11 @@ ct_status ct_rof(const ct_geometry *geometry, void *d_x, int32_t niter, double l
  * Small device utilities used by the algorithms, exported for callers that compose their own. */
 
 /* out[0] = sum_i a[i] * b[i] in FP64 with a fixed reduction order (bitwise repeatable).
- * a, b: device arrays of n elements of dtype; out: device double. */
+ * a, b: device arrays of n elements of dtype (any ct_dtype, CT_F64 included); out: device double. */
 ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out,
                  void *stream);
-/* Storage conversion: dst[i] = (dst_dtype) src[i] (round to nearest even). */
+/* Storage conversion: dst[i] = (dst_dtype) src[i] (round to nearest even; from CT_F64 to the 16-bit
+ * types through FP32).  Any ct_dtype, CT_F64 included. */
 ct_status ct_convert(const void *d_src, ct_dtype src_dtype, void *d_dst, ct_dtype dst_dtype, int64_t n,
                      void *stream);
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libct.so")
 
 CT_OK, CT_ERR_ARG, CT_ERR_GEOMETRY, CT_ERR_DTYPE, CT_ERR_OOM, CT_ERR_CAP, CT_ERR_HIP, CT_ERR_STATE = \
     0, -1, -2, -3, -4, -5, -6, -7
-CT_F32, CT_F16, CT_BF16 = 0, 1, 2
+CT_F32, CT_F16, CT_BF16, CT_F64 = 0, 1, 2, 3
 CT_SIDDON, CT_INTERP = 0, 1
 CT_BP_FDK, CT_BP_PSEUDO_MATCHED, CT_BP_ADJOINT = 0, 1, 2
 
@@ -40,7 +40,7 @@ class ct_ooc_stats(C.Structure):
     _fields_ = [("n_slabs", C.c_int32), ("slab_slices", C.c_int32), ("chunk_angles", C.c_int32),
                 ("n_chunks", C.c_int32), ("bytes_h2d", C.c_double), ("bytes_d2h", C.c_double),
                 ("t_total_s", C.c_double), ("t_compute_s", C.c_double), ("t_stage_s", C.c_double),
-                ("t_other_mem_s", C.c_double)]
+                ("t_other_mem_s", C.c_double), ("t_pin_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,13 +68,13 @@ SIGNATURES = {
     "ct_cgls_host_workspace_bytes": [_P, C.POINTER(_U64)],
     "ct_cgls_host": [_P, _P, _P, _I32, _P, _P, _U64, C.POINTER(ct_ooc_stats)],
     "ct_sart_workspace_bytes": [_P, _I32, C.POINTER(_U64)],
-    "ct_sart": [_P, _P, _P, _I32, _D, _I32, _P, _P],
+    "ct_sart": [_P, _P, _INT, _P, _INT, _I32, _D, _I32, _P, _P],
     "ct_fdk_filter": [_P, _P, _INT, _P, _I64, _I64, _P],
     "ct_fdk_workspace_bytes": [_P, C.POINTER(_U64)],
     "ct_fdk_host": [_P, _P, _INT, _P, _INT, _U64, C.POINTER(ct_ooc_stats)],
     "ct_fdk": [_P, _P, _INT, _P, _INT, _P, _P],
-    "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
-    "ct_tv_steps": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
+    "ct_tv_workspace_bytes": [C.POINTER(ct_geometry), _INT, C.POINTER(_U64)],
+    "ct_tv_steps": [C.POINTER(ct_geometry), _P, _INT, _I32, _D, _D, _P, _P],
     "ct_tv_steps_host": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _I32, _U64, C.POINTER(ct_ooc_stats)],
     "ct_rof_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_rof": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
@@ -202,8 +202,9 @@ def ct_sart_workspace_bytes(plan, block=1) -> int:
     return b.value
 
 
-def ct_sart(plan, d_b, d_x, niter, lam=1.0, block=1, d_workspace=0, stream=0):
-    return _check(lib().ct_sart(plan, d_b, d_x, niter, float(lam), block, d_workspace or None, stream or None))
+def ct_sart(plan, d_b, proj_dtype, d_x, vol_dtype, niter, lam=1.0, block=1, d_workspace=0, stream=0):
+    return _check(lib().ct_sart(plan, d_b, proj_dtype, d_x, vol_dtype, niter, float(lam), block, d_workspace or None,
+                                stream or None))
 
 
 def ct_fdk_filter(plan, d_proj, proj_dtype, d_q, angle_begin, angle_end, stream=0):
@@ -226,14 +227,14 @@ def ct_fdk(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace=0, stream=0):
     return _check(lib().ct_fdk(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace or None, stream or None))
 
 
-def ct_tv_workspace_bytes(geometry: ct_geometry) -> int:
+def ct_tv_workspace_bytes(geometry: ct_geometry, dtype=CT_F32) -> int:
     b = _U64()
-    _check(lib().ct_tv_workspace_bytes(C.byref(geometry), C.byref(b)))
+    _check(lib().ct_tv_workspace_bytes(C.byref(geometry), dtype, C.byref(b)))
     return b.value
 
 
-def ct_tv_steps(geometry: ct_geometry, d_x, nsteps, lam, eps=1e-8, d_workspace=0, stream=0):
-    return _check(lib().ct_tv_steps(C.byref(geometry), d_x, nsteps, float(lam), float(eps), d_workspace or None,
+def ct_tv_steps(geometry: ct_geometry, d_x, dtype, nsteps, lam, eps=1e-8, d_workspace=0, stream=0):
+    return _check(lib().ct_tv_steps(C.byref(geometry), d_x, dtype, nsteps, float(lam), float(eps), d_workspace or None,
                                     stream or None))
 
 

@@ -22,8 +22,9 @@ ct_status hip_fail(hipError_t e, const char *what) {
     return CT_ERR_HIP;
 }
 
-size_t dtype_size(ct_dtype t) { return t == CT_F32 ? 4 : 2; }
+size_t dtype_size(ct_dtype t) { return t == CT_F64 ? 8 : t == CT_F32 ? 4 : 2; }
 bool dtype_ok(int t) { return t == CT_F32 || t == CT_F16 || t == CT_BF16; }
+bool dtype_ok_any(int t) { return dtype_ok(t) || t == CT_F64; }
 
 static ct_status validate(const ct_geometry &g) {
     if (!(g.DSO > 0) || !(g.DSD > g.DSO) || !std::isfinite(g.DSD))
@@ -160,7 +161,7 @@ ct_status ct_forward(ct_plan *plan, ct_projector projector, const void *d_vol, c
                      int64_t angle_end, void *stream) {
     if (!plan || !d_vol || !d_proj) return fail(CT_ERR_ARG, "ct_forward: null pointer");
     if (projector != CT_SIDDON && projector != CT_INTERP) return fail(CT_ERR_ARG, "ct_forward: unknown projector");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward: dtype must be CT_F32, CT_F16 or CT_BF16");
     ct_status st = check_range(plan, angle_begin, angle_end, "ct_forward");
     if (st != CT_OK) return st;
     return launch_forward(plan, projector, d_vol, vol_dtype, d_proj, proj_dtype, accumulate, angle_begin,
@@ -173,7 +174,7 @@ ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const vo
     if (!plan || !d_vol || !d_proj) return fail(CT_ERR_ARG, "ct_backproject: null pointer");
     if (backprojector != CT_BP_FDK && backprojector != CT_BP_PSEUDO_MATCHED && backprojector != CT_BP_ADJOINT)
         return fail(CT_ERR_ARG, "ct_backproject: unknown backprojector");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject: dtype must be CT_F32, CT_F16 or CT_BF16");
     ct_status st = check_range(plan, angle_begin, angle_end, "ct_backproject");
     if (st != CT_OK) return st;
     return launch_backproject(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, accumulate,
@@ -184,7 +185,7 @@ ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector
                       ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out) {
     if (!plan || !out) return fail(CT_ERR_ARG, "ct_ooc_plan: null pointer");
     if (direction < 0 || direction > 3) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0, 1, 2 or 3");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_ooc_plan: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_ooc_plan: dtype must be CT_F32, CT_F16 or CT_BF16");
     return ooc_plan(plan, direction, projector, vol_dtype, proj_dtype, device_cap_bytes, out);
 }
 
@@ -193,7 +194,7 @@ ct_status ct_forward_host(ct_plan *plan, ct_projector projector, const void *h_v
                           ct_ooc_stats *stats) {
     if (!plan || !h_vol || !h_proj) return fail(CT_ERR_ARG, "ct_forward_host: null pointer");
     if (projector != CT_SIDDON && projector != CT_INTERP) return fail(CT_ERR_ARG, "ct_forward_host: unknown projector");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward_host: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward_host: dtype must be CT_F32, CT_F16 or CT_BF16");
     return ooc_forward(plan, projector, h_vol, vol_dtype, h_proj, proj_dtype, device_cap_bytes, stats);
 }
 
@@ -203,14 +204,14 @@ ct_status ct_backproject_host(ct_plan *plan, ct_backprojector backprojector, con
     if (!plan || !h_vol || !h_proj) return fail(CT_ERR_ARG, "ct_backproject_host: null pointer");
     if (backprojector != CT_BP_FDK && backprojector != CT_BP_PSEUDO_MATCHED && backprojector != CT_BP_ADJOINT)
         return fail(CT_ERR_ARG, "ct_backproject_host: unknown backprojector");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject_host: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject_host: dtype must be CT_F32, CT_F16 or CT_BF16");
     return ooc_backproject(plan, backprojector, h_proj, proj_dtype, h_vol, vol_dtype, device_cap_bytes, stats);
 }
 
 ct_status ct_cgls_workspace_bytes(const ct_plan *plan, ct_dtype vol_dtype, ct_dtype proj_dtype,
                                   uint64_t *bytes) {
     if (!plan || !bytes) return fail(CT_ERR_ARG, "ct_cgls_workspace_bytes: null pointer");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls_workspace_bytes: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls_workspace_bytes: dtype must be CT_F32, CT_F16 or CT_BF16");
     *bytes = cgls_workspace(plan, vol_dtype, proj_dtype);
     return CT_OK;
 }
@@ -219,7 +220,7 @@ ct_status ct_cgls(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x
                   int32_t niter, double *d_resid, void *d_workspace, void *stream) {
     if (!plan || !d_b || !d_x) return fail(CT_ERR_ARG, "ct_cgls: null pointer");
     if (niter < 0) return fail(CT_ERR_ARG, "ct_cgls: niter must be >= 0");
-    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls: unknown dtype");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_cgls: dtype must be CT_F32, CT_F16 or CT_BF16");
     return cgls_run(plan, d_b, proj_dtype, d_x, vol_dtype, niter, d_resid, d_workspace, (hipStream_t)stream);
 }
 
@@ -244,20 +245,21 @@ ct_status ct_sart_workspace_bytes(const ct_plan *plan, int32_t block, uint64_t *
     return CT_OK;
 }
 
-ct_status ct_sart(ct_plan *plan, const void *d_b, void *d_x, int32_t niter, double lambda, int32_t block,
-                  void *d_workspace, void *stream) {
+ct_status ct_sart(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x, ct_dtype vol_dtype, int32_t niter,
+                  double lambda, int32_t block, void *d_workspace, void *stream) {
     if (!plan || !d_b || !d_x) return fail(CT_ERR_ARG, "ct_sart: null pointer");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_sart: unsupported dtype");
     if (niter < 0) return fail(CT_ERR_ARG, "ct_sart: niter must be >= 0");
     if (block < 1 || block > (int64_t)plan->angles.size())
         return fail(CT_ERR_ARG, "ct_sart: block must be in [1, n_angles]");
     if (!std::isfinite(lambda)) return fail(CT_ERR_ARG, "ct_sart: lambda must be finite");
-    return sart_run(plan, d_b, d_x, niter, lambda, block, d_workspace, (hipStream_t)stream);
+    return sart_run(plan, d_b, proj_dtype, d_x, vol_dtype, niter, lambda, block, d_workspace, (hipStream_t)stream);
 }
 
 ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, float *d_q, int64_t angle_begin,
                         int64_t angle_end, void *stream) {
     if (!plan || !d_proj || !d_q) return fail(CT_ERR_ARG, "ct_fdk_filter: null pointer");
-    if (!dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_filter: unknown dtype");
+    if (!dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_filter: dtype must be CT_F32, CT_F16 or CT_BF16");
     ct_status st = check_range(plan, angle_begin, angle_end, "ct_fdk_filter");
     if (st != CT_OK) return st;
     return fdk_filter(plan, d_proj, proj_dtype, d_q, angle_begin, angle_end, (hipStream_t)stream);
@@ -266,7 +268,7 @@ ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, 
 ct_status ct_fdk_host(ct_plan *plan, const void *h_proj, ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
                       uint64_t device_cap_bytes, ct_ooc_stats *stats) {
     if (!plan || !h_proj || !h_vol) return fail(CT_ERR_ARG, "ct_fdk_host: null pointer");
-    if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_host: unknown dtype");
+    if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_host: dtype must be CT_F32, CT_F16 or CT_BF16");
     if (plan->g.nDetector[0] > 4096)
         return fail(CT_ERR_ARG, "ct_fdk_host: detector rows longer than 4096 pixels are not supported");
     return ooc_backproject(plan, CT_BP_FDK, h_proj, proj_dtype, h_vol, vol_dtype, device_cap_bytes, stats, true);
@@ -281,24 +283,26 @@ ct_status ct_fdk_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
 ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype,
                  void *d_workspace, void *stream) {
     if (!plan || !d_proj || !d_vol) return fail(CT_ERR_ARG, "ct_fdk: null pointer");
-    if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk: unknown dtype");
+    if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk: dtype must be CT_F32, CT_F16 or CT_BF16");
     return fdk_run(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace, (hipStream_t)stream);
 }
 
-ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes) {
+ct_status ct_tv_workspace_bytes(const ct_geometry *geometry, ct_dtype dtype, uint64_t *bytes) {
     if (!geometry || !bytes) return fail(CT_ERR_ARG, "ct_tv_workspace_bytes: null pointer");
-    *bytes = tv_workspace(*geometry);
+    if (!dtype_ok(dtype)) return fail(CT_ERR_DTYPE, "ct_tv_workspace_bytes: unsupported dtype");
+    *bytes = tv_workspace(*geometry, dtype);
     return CT_OK;
 }
 
-ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, int32_t nsteps, double lambda, double eps,
+ct_status ct_tv_steps(const ct_geometry *geometry, void *d_x, ct_dtype dtype, int32_t nsteps, double lambda, double eps,
                       void *d_workspace, void *stream) {
     if (!geometry || !d_x) return fail(CT_ERR_ARG, "ct_tv_steps: null pointer");
+    if (!dtype_ok(dtype)) return fail(CT_ERR_DTYPE, "ct_tv_steps: unsupported dtype");
     if (nsteps < 0) return fail(CT_ERR_ARG, "ct_tv_steps: nsteps must be >= 0");
     if (!(eps > 0) || !std::isfinite(lambda)) return fail(CT_ERR_ARG, "ct_tv_steps: need eps > 0 and finite lambda");
     for (int a = 0; a < 3; ++a)
         if (geometry->nVoxel[a] <= 0) return fail(CT_ERR_GEOMETRY, "ct_tv_steps: voxel counts must be positive");
-    return tv_run(*geometry, d_x, nsteps, lambda, eps, d_workspace, (hipStream_t)stream);
+    return tv_run(*geometry, d_x, dtype, nsteps, lambda, eps, d_workspace, (hipStream_t)stream);
 }
 
 ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nsteps, double lambda, double eps,
@@ -333,7 +337,7 @@ ct_status ct_rof(const ct_geometry *geometry, void *d_x, int32_t niter, double l
 ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out, void *stream) {
     if (!d_a || !d_b || !d_out) return fail(CT_ERR_ARG, "ct_dot: null pointer");
     if (n < 0) return fail(CT_ERR_ARG, "ct_dot: negative length");
-    if (!dtype_ok(dtype)) return fail(CT_ERR_DTYPE, "ct_dot: unknown dtype");
+    if (!dtype_ok_any(dtype)) return fail(CT_ERR_DTYPE, "ct_dot: unknown dtype");
     return dot_f64(d_a, d_b, dtype, n, d_out, nullptr, (hipStream_t)stream);
 }
 
@@ -341,7 +345,7 @@ ct_status ct_convert(const void *d_src, ct_dtype src_dtype, void *d_dst, ct_dtyp
                      void *stream) {
     if (!d_src || !d_dst) return fail(CT_ERR_ARG, "ct_convert: null pointer");
     if (n < 0) return fail(CT_ERR_ARG, "ct_convert: negative length");
-    if (!dtype_ok(src_dtype) || !dtype_ok(dst_dtype)) return fail(CT_ERR_DTYPE, "ct_convert: unknown dtype");
+    if (!dtype_ok_any(src_dtype) || !dtype_ok_any(dst_dtype)) return fail(CT_ERR_DTYPE, "ct_convert: unknown dtype");
     return convert(d_src, src_dtype, d_dst, dst_dtype, n, (hipStream_t)stream);
 }
 

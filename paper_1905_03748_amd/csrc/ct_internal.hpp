@@ -36,7 +36,8 @@ ct_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 size_t dtype_size(ct_dtype t);
-bool dtype_ok(int t);
+bool dtype_ok(int t);      // a storage type of the operators and algorithms (FP32, FP16, BF16)
+bool dtype_ok_any(int t);  // also FP64 (conversion and inner products)
 
 }  // namespace ct
 
@@ -99,6 +100,10 @@ ct_status launch_zcols(const void *vol, ct_dtype vt, void *vz, int64_t nx, int64
 // zero slot 0 / nzp - 1
 ct_status launch_zcols_piece(const void *src, ct_dtype vt, void *vz, int64_t nx, int64_t ny, int64_t nz, int64_t nzp,
                              int64_t slot0, int pads, hipStream_t st);
+// the same copy converted to FP32 (vz: FP32), and its inverse back to the volume's type
+ct_status launch_zcols_f32(const void *vol, ct_dtype vt, float *vz, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
+ct_status launch_zcols_inv_f32(const float *vz, void *vol, ct_dtype vt, int64_t nx, int64_t ny, int64_t nz,
+                               hipStream_t st);
 // inverse: column-major slots -> [z][y][x]
 ct_status launch_zcols_inv(const void *vz, ct_dtype vt, void *vol, int64_t nx, int64_t ny, int64_t nz, hipStream_t st);
 // slots [slot0, slot0 + zn) of column-major columns of nzp slots -> [zn][ny][nx]
@@ -126,12 +131,12 @@ size_t dot_partials_count();
 ct_status cgls_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter,
                    double *resid, void *work, hipStream_t st);
 size_t cgls_workspace(const ct_plan *p, ct_dtype vt, ct_dtype pt);
-ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, int32_t block, void *work,
-                   hipStream_t st);
+ct_status sart_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter, double lambda,
+                   int32_t block, void *work, hipStream_t st);
 size_t sart_workspace(const ct_plan *p, int32_t block);
-ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work,
+ct_status tv_run(const ct_geometry &g, void *x, ct_dtype vt, int32_t nsteps, double lambda, double eps, void *work,
                  hipStream_t st);
-size_t tv_workspace(const ct_geometry &g);
+size_t tv_workspace(const ct_geometry &g, ct_dtype vt);
 ct_status rof_run(const ct_geometry &g, void *x, int32_t niter, double lambda, double tau, void *work, hipStream_t st);
 size_t rof_workspace(const ct_geometry &g);
 ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, int32_t depth,

@@ -43,6 +43,24 @@ __device__ __forceinline__ float ldf(const T *p, int64_t i) {
     return to_f(p[i]);
 }
 
+// FP64 values (conversion and inner products only): widened exactly, narrowed to FP32 with one
+// rounding and to the 16-bit types through FP32
+__device__ __forceinline__ double to_d(double x) { return x; }
+template <typename T>
+__device__ __forceinline__ double to_d(T x) { return (double)to_f(x); }
+template <typename TD>
+__device__ __forceinline__ TD from_d(double x) {
+    // the FP32 value is kept (the compiler would otherwise fold the two narrowings to FP16 into
+    // one), so both 16-bit types are rounded from the FP32 rounding
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return from_f<TD>(f);
+}
+template <>
+__device__ __forceinline__ float from_d<float>(double x) { return (float)x; }
+template <>
+__device__ __forceinline__ double from_d<double>(double x) { return x; }
+
 // Buffer loads (CDNA raw buffer instructions with 32-bit byte offsets).  The hardware range check
 // returns 0 for offsets at or beyond the resource size (negative offsets wrap to huge unsigned
 // values), which the backprojectors use as the detector's zero padding; it also keeps addresses
@@ -102,3 +120,15 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     }
 
 #define CT_DISPATCH2(d1, T1, d2, T2, ...) CT_DISPATCH1(d1, T1, CT_DISPATCH1(d2, T2, __VA_ARGS__))
+
+// The same over every type including FP64 (conversion and inner products)
+#define CT_DISPATCH1_ANY(dt, T, ...)              \
+    switch (dt) {                                 \
+        case CT_F64: {                            \
+            using T = double;                     \
+            __VA_ARGS__;                          \
+        } break;                                  \
+        default:                                  \
+            CT_DISPATCH1(dt, T, __VA_ARGS__);     \
+            break;                                \
+    }

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dot_partial(const T *__restrict
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     double s = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)ldf(a, i) * (double)ldf(b, i);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += to_d(a[i]) * to_d(b[i]);
     s = block_sum(s, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(DOT_THREADS) void k_sum_partials(const double *__re
 template <typename TS, typename TD>
 __global__ void k_convert(const TS *__restrict__ s, TD *__restrict__ d, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        d[i] = from_f<TD>(ldf(s, i));
+        d[i] = from_d<TD>(to_d(s[i]));
 }
 
 // r (FP32) = b - r, b in its storage type
@@ -131,18 +131,20 @@ __global__ void k_cgls_beta(double *scal) {
     scal[S_GAMMA] = gnew;
 }
 
-// SART residual for one angle: r = (b - r) / chord where chord > thr, else 0
-__global__ void k_sart_resid(const float *__restrict__ b, const float *__restrict__ chord, float *__restrict__ r,
+// SART residual for one angle: r = (b - r) / chord where chord > thr, else 0 (b in its storage type)
+template <typename TP>
+__global__ void k_sart_resid(const TP *__restrict__ b, const float *__restrict__ chord, float *__restrict__ r,
                              float thr, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float c = chord[i];
-        r[i] = c > thr ? (b[i] - r[i]) / c : 0.0f;
+        r[i] = c > thr ? (to_f(b[i]) - r[i]) / c : 0.0f;
     }
 }
 
 // The same residual written transposed, rT[u][v], through 32 x 32 LDS tiles; blockIdx.z is the
 // angle within the subset (each array advances by one projection per angle)
-__global__ __launch_bounds__(256) void k_sart_resid_t(const float *__restrict__ b, const float *__restrict__ chord,
+template <typename TP>
+__global__ __launch_bounds__(256) void k_sart_resid_t(const TP *__restrict__ b, const float *__restrict__ chord,
                                                       const float *__restrict__ r, float *__restrict__ rT, float thr,
                                                       int nu, int nv) {
     __shared__ float tile[32][33];
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void k_sart_resid_t(const float *__restrict__ 
         if (u < nu && v < nv) {
             const int64_t i = (int64_t)v * nu + u;
             const float c = chord[i];
-            tile[ty + k][tx] = c > thr ? (b[i] - r[i]) / c : 0.0f;
+            tile[ty + k][tx] = c > thr ? (to_f(b[i]) - r[i]) / c : 0.0f;
         }
     }
     __syncthreads();
@@ -325,9 +327,9 @@ ct_status dot_f64(const void *a, const void *b, ct_dtype t, int64_t n, double *o
         if (s != CT_OK) return s;
         partials = (double *)ws.take(DOT_BLOCKS * sizeof(double));
     }
-    CT_DISPATCH1(t, T,
-                 hipLaunchKernelGGL((k_dot_partial<T>), dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, st, (const T *)a,
-                                    (const T *)b, n, partials));
+    CT_DISPATCH1_ANY(t, T,
+                     hipLaunchKernelGGL((k_dot_partial<T>), dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, st, (const T *)a,
+                                        (const T *)b, n, partials));
     CT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(DOT_THREADS), 0, st, partials, DOT_BLOCKS, out);
     CT_HIP(hipGetLastError());
@@ -336,9 +338,10 @@ ct_status dot_f64(const void *a, const void *b, ct_dtype t, int64_t n, double *o
 
 ct_status convert(const void *src, ct_dtype s_t, void *dst, ct_dtype d_t, int64_t n, hipStream_t st) {
     if (n == 0) return CT_OK;
-    CT_DISPATCH2(s_t, TS, d_t, TD,
-                 hipLaunchKernelGGL((k_convert<TS, TD>), dim3(ew_grid(n)), dim3(EW_THREADS), 0, st, (const TS *)src,
-                                    (TD *)dst, n));
+    CT_DISPATCH1_ANY(s_t, TS,
+                     CT_DISPATCH1_ANY(d_t, TD,
+                                      hipLaunchKernelGGL((k_convert<TS, TD>), dim3(ew_grid(n)), dim3(EW_THREADS), 0, st,
+                                                         (const TS *)src, (TD *)dst, n)));
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
@@ -442,11 +445,13 @@ size_t sart_workspace(const ct_plan *p, int32_t block) {
 // OS-SART: the angles in natural order, cut into consecutive subsets of `block` (the last one may be
 // shorter); each subset projects, forms its weighted residuals and makes one update (block = 1 is
 // SART)
-ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lambda, int32_t block, void *work,
-                   hipStream_t st) {
+ct_status sart_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt, int32_t niter, double lambda,
+                   int32_t block, void *work, hipStream_t st) {
     const ct_geometry &g = p->g;
     const int64_t na = (int64_t)p->angles.size();
     const int64_t pix = g.nDetector[0] * g.nDetector[1];
+    const int64_t nvox = g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
+    const size_t pe = dtype_size(pt);
     Workspace ws;
     ct_status s = ws.acquire(work, sart_workspace(p, block), st);
     if (s != CT_OK) return s;
@@ -458,53 +463,71 @@ ct_status sart_run(ct_plan *p, const void *b, void *x, int32_t niter, double lam
     const int nu = (int)g.nDetector[0], nv = (int)g.nDetector[1];
     CK(launch_ray_chord(p, chord, 0, na, st));
     const Slab full = full_slab(g);
+    // the sweep updates an FP32 image: the column-major copy, or (other geometries) x itself when
+    // it is stored in FP32, else an FP32 copy of it; a 16-bit x is rounded once, at the end
     if (zcol_ok(p, 0, na)) {
-        // the sweep works on the column-major copy only
-        CK(launch_zcols(x, CT_F32, xz, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
+        CK(launch_zcols_f32(x, vt, xz, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
         for (int32_t it = 0; it < niter; ++it) {
             for (int64_t t0 = 0; t0 < na; t0 += block) {
                 const int64_t t1 = std::min<int64_t>(na, t0 + block);
-                CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t0, t1, full, st, xz));
+                CK(launch_forward(p, CT_SIDDON, xz, CT_F32, r, CT_F32, 0, t0, t1, full, st, xz));
                 const dim3 tg((unsigned)((nu + 31) / 32), (unsigned)((nv + 31) / 32), (unsigned)(t1 - t0));
-                hipLaunchKernelGGL(k_sart_resid_t, tg, dim3(256), 0, st, (const float *)b + t0 * pix, chord + t0 * pix,
-                                   (const float *)r, rT, thr, nu, nv);
+                const void *bt = (const char *)b + t0 * pix * pe;
+                CT_DISPATCH1(pt, TP,
+                             hipLaunchKernelGGL((k_sart_resid_t<TP>), tg, dim3(256), 0, st, (const TP *)bt,
+                                                chord + t0 * pix, (const float *)r, rT, thr, nu, nv));
                 CT_HIP(hipGetLastError());
                 CK(launch_sart_update_col(p, rT, xz, t0, t1, (float)lambda, st));
             }
         }
-        CK(launch_zcols_inv(xz, CT_F32, x, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
+        CK(launch_zcols_inv_f32(xz, x, vt, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
         return CT_OK;
+    }
+    float *xf = (float *)x;
+    if (vt != CT_F32) {
+        xf = xz;
+        CK(convert(x, vt, xf, CT_F32, nvox, st));
     }
     for (int32_t it = 0; it < niter; ++it) {
         for (int64_t t0 = 0; t0 < na; t0 += block) {
             const int64_t t1 = std::min<int64_t>(na, t0 + block);
-            CK(launch_forward(p, CT_SIDDON, x, CT_F32, r, CT_F32, 0, t0, t1, full, st));
-            hipLaunchKernelGGL(k_sart_resid, dim3(ew_grid((t1 - t0) * pix)), dim3(EW_THREADS), 0, st,
-                               (const float *)b + t0 * pix, chord + t0 * pix, r, thr, (t1 - t0) * pix);
+            CK(launch_forward(p, CT_SIDDON, xf, CT_F32, r, CT_F32, 0, t0, t1, full, st));
+            const void *bt = (const char *)b + t0 * pix * pe;
+            CT_DISPATCH1(pt, TP,
+                         hipLaunchKernelGGL((k_sart_resid<TP>), dim3(ew_grid((t1 - t0) * pix)), dim3(EW_THREADS), 0, st,
+                                            (const TP *)bt, chord + t0 * pix, r, thr, (t1 - t0) * pix));
             CT_HIP(hipGetLastError());
-            CK(launch_sart_update(p, r, (float *)x, t0, t1, (float)lambda, st));
+            CK(launch_sart_update(p, r, xf, t0, t1, (float)lambda, st));
         }
     }
+    if (vt != CT_F32) CK(convert(xf, CT_F32, x, vt, nvox, st));
     return CT_OK;
 }
 
 // ---------------------------------------------------------------------------------------------
 // TV steepest descent
 
-size_t tv_workspace(const ct_geometry &g) {
+size_t tv_workspace(const ct_geometry &g, ct_dtype vt) {
     const size_t nv = (size_t)g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2];
-    return align256(nv * 4) + align256(DOT_BLOCKS * 8) + align256(4 * 8);
+    // a 16-bit image is stepped in an FP32 copy
+    return align256(nv * 4) * (vt == CT_F32 ? 1 : 2) + align256(DOT_BLOCKS * 8) + align256(4 * 8);
 }
 
-ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, double eps, void *work, hipStream_t st) {
+ct_status tv_run(const ct_geometry &g, void *xs, ct_dtype vt, int32_t nsteps, double lambda, double eps, void *work,
+                 hipStream_t st) {
     const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1], nz = (int)g.nVoxel[2];
     const int64_t nv = (int64_t)nx * ny * nz;
     Workspace ws;
-    ct_status s = ws.acquire(work, tv_workspace(g), st);
+    ct_status s = ws.acquire(work, tv_workspace(g, vt), st);
     if (s != CT_OK) return s;
     float *gbuf = (float *)ws.take(nv * 4);
     double *parts = (double *)ws.take(DOT_BLOCKS * 8);
     double *scal = (double *)ws.take(4 * 8);
+    void *x = xs;
+    if (vt != CT_F32) {
+        x = ws.take(nv * 4);
+        CK(convert(xs, vt, x, CT_F32, nv, st));
+    }
     CK(dot_f64(x, x, CT_F32, nv, scal + 0, parts, st));
     hipLaunchKernelGGL(k_tv_alpha, dim3(1), dim3(1), 0, st, scal, lambda);
     CT_HIP(hipGetLastError());
@@ -517,6 +540,7 @@ ct_status tv_run(const ct_geometry &g, void *x, int32_t nsteps, double lambda, d
         hipLaunchKernelGGL(k_tv_update, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (float *)x, (const float *)gbuf, scal, nv);
         CT_HIP(hipGetLastError());
     }
+    if (vt != CT_F32) CK(convert(x, CT_F32, xs, vt, nv, st));
     return CT_OK;
 #undef CK
 }

@@ -555,51 +555,52 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
 
 // [z][y][x] -> column-major slots: slices [0, nz) of src go to slots slot0 + z of columns of nzp
 // slots ([y][x][slot]); pads: bit 0 zeroes slot 0, bit 1 zeroes slot nzp - 1.  32 x 32 (z, x) tiles.
-template <typename T>
-__global__ __launch_bounds__(256) void k_zcols(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz,
+// Values pass through FP32 (exact for the storage types), so the copy may also change the type.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_zcols(const TS *__restrict__ src, TD *__restrict__ dst, int nx, int ny, int nz,
                                                int64_t nzp, int slot0, int pads) {
-    __shared__ T tile[32][33];
+    __shared__ float tile[32][33];
     const int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int x = x0 + tx, z = z0 + ty + r;
-        if (x < nx && z < nz) tile[ty + r][tx] = src[((int64_t)z * ny + y) * nx + x];
+        if (x < nx && z < nz) tile[ty + r][tx] = to_f(src[((int64_t)z * ny + y) * nx + x]);
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int z = z0 + tx, x = x0 + ty + r;
-        if (x < nx && z < nz) dst[((int64_t)y * nx + x) * nzp + slot0 + z] = tile[tx][ty + r];
+        if (x < nx && z < nz) dst[((int64_t)y * nx + x) * nzp + slot0 + z] = from_f<TD>(tile[tx][ty + r]);
     }
     if (threadIdx.x < 32) {
         const int x = x0 + threadIdx.x;
         if (x < nx) {
             const int64_t c = ((int64_t)y * nx + x) * nzp;
-            if ((pads & 1) && blockIdx.y == 0) dst[c] = from_f<T>(0.0f);
-            if ((pads & 2) && blockIdx.y == gridDim.y - 1) dst[c + nzp - 1] = from_f<T>(0.0f);
+            if ((pads & 1) && blockIdx.y == 0) dst[c] = from_f<TD>(0.0f);
+            if ((pads & 2) && blockIdx.y == gridDim.y - 1) dst[c + nzp - 1] = from_f<TD>(0.0f);
         }
     }
 }
 
 // column-major slots -> [z][y][x]: slots slot0 .. slot0 + nz - 1 of columns of nzp slots go to
 // slices 0 .. nz - 1 of dst
-template <typename T>
-__global__ __launch_bounds__(256) void k_zcols_inv(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny, int nz,
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_zcols_inv(const TS *__restrict__ src, TD *__restrict__ dst, int nx, int ny, int nz,
                                                    int64_t nzp, int slot0) {
-    __shared__ T tile[32][33];
+    __shared__ float tile[32][33];
     const int x0 = blockIdx.x * 32, z0 = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int z = z0 + tx, x = x0 + ty + r;
-        if (x < nx && z < nz) tile[ty + r][tx] = src[((int64_t)y * nx + x) * nzp + slot0 + z];
+        if (x < nx && z < nz) tile[ty + r][tx] = to_f(src[((int64_t)y * nx + x) * nzp + slot0 + z]);
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int x = x0 + tx, z = z0 + ty + r;
-        if (x < nx && z < nz) dst[((int64_t)z * ny + y) * nx + x] = tile[tx][ty + r];
+        if (x < nx && z < nz) dst[((int64_t)z * ny + y) * nx + x] = from_f<TD>(tile[tx][ty + r]);
     }
 }
 
@@ -971,8 +972,27 @@ ct_status launch_zcols_piece(const void *src, ct_dtype vt, void *vz, int64_t nx,
                              int64_t slot0, int pads, hipStream_t st) {
     const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
     CT_DISPATCH1(vt, T,
-                 hipLaunchKernelGGL((k_zcols<T>), tg, dim3(256), 0, st, (const T *)src, (T *)vz, (int)nx, (int)ny,
+                 hipLaunchKernelGGL((k_zcols<T, T>), tg, dim3(256), 0, st, (const T *)src, (T *)vz, (int)nx, (int)ny,
                                     (int)nz, nzp, (int)slot0, pads));
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+ct_status launch_zcols_f32(const void *vol, ct_dtype vt, float *vz, int64_t nx, int64_t ny, int64_t nz, hipStream_t st) {
+    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
+    CT_DISPATCH1(vt, T,
+                 hipLaunchKernelGGL((k_zcols<T, float>), tg, dim3(256), 0, st, (const T *)vol, vz, (int)nx, (int)ny,
+                                    (int)nz, nz + 2, 1, 3));
+    CT_HIP(hipGetLastError());
+    return CT_OK;
+}
+
+ct_status launch_zcols_inv_f32(const float *vz, void *vol, ct_dtype vt, int64_t nx, int64_t ny, int64_t nz,
+                               hipStream_t st) {
+    const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((nz + 31) / 32), (unsigned)ny);
+    CT_DISPATCH1(vt, T,
+                 hipLaunchKernelGGL((k_zcols_inv<float, T>), tg, dim3(256), 0, st, vz, (T *)vol, (int)nx, (int)ny,
+                                    (int)nz, nz + 2, 1));
     CT_HIP(hipGetLastError());
     return CT_OK;
 }
@@ -987,7 +1007,7 @@ ct_status launch_zcols_inv_piece(const void *vz, ct_dtype vt, void *dst, int64_t
     if (slot0 < 0 || slot0 + zn > nzp) return fail(CT_ERR_ARG, "column-major piece outside its columns");
     const dim3 tg((unsigned)((nx + 31) / 32), (unsigned)((zn + 31) / 32), (unsigned)ny);
     CT_DISPATCH1(vt, T,
-                 hipLaunchKernelGGL((k_zcols_inv<T>), tg, dim3(256), 0, st, (const T *)vz, (T *)dst, (int)nx, (int)ny,
+                 hipLaunchKernelGGL((k_zcols_inv<T, T>), tg, dim3(256), 0, st, (const T *)vz, (T *)dst, (int)nx, (int)ny,
                                     (int)zn, nzp, (int)slot0));
     CT_HIP(hipGetLastError());
     return CT_OK;

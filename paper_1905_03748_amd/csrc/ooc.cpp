@@ -202,6 +202,7 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
     if (L.col) CT_HIP(hipMalloc(&stage.p, ZSTAGE * slice));
     for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
     HostBuf sin[3], sout[3], svol[2];
+    const auto tp = clk::now();
     if (!proj_pinned)
         for (int j = 0; j < 3; ++j) {
             CT_HIP(hipHostMalloc(&sin[j].p, chunk_bytes, hipHostMallocDefault));
@@ -209,6 +210,7 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
         }
     if (!vol_pinned)
         for (auto &b : svol) CT_HIP(hipHostMalloc(&b.p, STAGE_PIECE, hipHostMallocDefault));
+    st.t_pin_s += secs(tp, clk::now());
     Events ev_h2d, ev_k, ev_d2h, ev_vol, tk0, tk1;
     if ((s = ev_h2d.make(3)) != CT_OK || (s = ev_k.make(3)) != CT_OK || (s = ev_d2h.make(3)) != CT_OK ||
         (s = ev_vol.make(2)) != CT_OK)
@@ -392,10 +394,12 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     // backprojection reads (both on the compute stream, so the buffer is reused in order)
     if (fdk_filtered) CT_HIP(hipMalloc(&filt.p, (size_t)L.K * g.nDetector[0] * g.nDetector[1] * sizeof(float)));
     HostBuf sin[2], svol[2];
+    const auto tp = clk::now();
     if (!proj_pinned)
         for (auto &b : sin) CT_HIP(hipHostMalloc(&b.p, chunk_bytes, hipHostMallocDefault));
     if (!vol_pinned)
         for (auto &b : svol) CT_HIP(hipHostMalloc(&b.p, STAGE_PIECE, hipHostMallocDefault));
+    st.t_pin_s += secs(tp, clk::now());
     Events ev_h2d, ev_k, ev_vol, tk0, tk1;
     if ((s = ev_h2d.make(2)) != CT_OK || (s = ev_k.make(2)) != CT_OK || (s = ev_vol.make(2)) != CT_OK) return s;
     tk0.e.resize(nchunks, nullptr);

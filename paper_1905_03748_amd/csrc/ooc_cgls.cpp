@@ -136,6 +136,7 @@ void add_stats(ct_ooc_stats &t, const ct_ooc_stats &s) {
     t.t_compute_s += s.t_compute_s;
     t.t_stage_s += s.t_stage_s;
     t.t_other_mem_s += s.t_other_mem_s;
+    t.t_pin_s += s.t_pin_s;
 }
 
 }  // namespace

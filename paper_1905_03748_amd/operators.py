@@ -24,6 +24,11 @@ def ct_dtype(t: torch.dtype) -> int:
         raise TypeError(f"unsupported storage dtype {t}") from None
 
 
+def _ct_dtype_any(t: torch.dtype) -> int:
+    """ct_dtype, or CT_F64 for float64 (ct_dot and ct_convert only)."""
+    return A.CT_F64 if t == torch.float64 else ct_dtype(t)
+
+
 def _stream(stream=None) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -186,13 +191,14 @@ class Plan:
     def sart(self, b: torch.Tensor, niter: int, x: torch.Tensor | None = None, lam=1.0, block=1, workspace=None,
              stream=None):
         """OS-SART in place on x (zeros if None): subsets of `block` consecutive angles, one update
-        each (block = 1 is SART)."""
+        each (block = 1 is SART).  b and x may be stored in FP32, FP16 or BF16."""
         if x is None:
             x = torch.zeros(self.vol_shape, dtype=torch.float32, device=b.device)
         if workspace is not None:
             _check_workspace(workspace, self.sart_workspace_bytes(block))
-        A.ct_sart(self.handle, _dev(b, self.proj_shape, "b"), _dev(x, self.vol_shape, "x"), niter, lam, block,
-                  workspace.data_ptr() if workspace is not None else 0, _stream(stream))
+        A.ct_sart(self.handle, _dev(b, self.proj_shape, "b"), ct_dtype(b.dtype), _dev(x, self.vol_shape, "x"),
+                  ct_dtype(x.dtype), niter, lam, block, workspace.data_ptr() if workspace is not None else 0,
+                  _stream(stream))
         return x
 
     def fdk_filter(self, proj: torch.Tensor, out: torch.Tensor | None = None, angle_begin=0, angle_end=None,
@@ -226,14 +232,13 @@ class Plan:
 
 def tv_steps(geometry: dict, x: torch.Tensor, nsteps: int, lam: float, eps: float = 1e-8, workspace=None,
              stream=None) -> torch.Tensor:
-    """TV steepest descent in place on the FP32 device volume x."""
+    """TV steepest descent in place on the device volume x (FP32, FP16 or BF16 storage)."""
     g = A.make_geometry(geometry)
     nx, ny, nz = (int(v) for v in geometry["nVoxel"])
-    if x.dtype != torch.float32:
-        raise TypeError("tv_steps works on FP32 volumes")
+    dt = ct_dtype(x.dtype)
     if workspace is not None:
-        _check_workspace(workspace, tv_workspace_bytes(geometry))
-    A.ct_tv_steps(g, _dev(x, (nz, ny, nx), "x"), nsteps, lam, eps,
+        _check_workspace(workspace, tv_workspace_bytes(geometry, x.dtype))
+    A.ct_tv_steps(g, _dev(x, (nz, ny, nx), "x"), dt, nsteps, lam, eps,
                   workspace.data_ptr() if workspace is not None else 0, _stream(stream))
     return x
 
@@ -266,8 +271,8 @@ def rof_workspace_bytes(geometry: dict) -> int:
     return A.ct_rof_workspace_bytes(A.make_geometry(geometry))
 
 
-def tv_workspace_bytes(geometry: dict) -> int:
-    return A.ct_tv_workspace_bytes(A.make_geometry(geometry))
+def tv_workspace_bytes(geometry: dict, dtype=torch.float32) -> int:
+    return A.ct_tv_workspace_bytes(A.make_geometry(geometry), ct_dtype(dtype))
 
 
 def dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
@@ -276,11 +281,13 @@ def dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
     _dev(a, a.shape, "a")
     _dev(b, b.shape, "b")
     out = torch.empty(1, dtype=torch.float64, device=a.device)
-    A.ct_dot(a.data_ptr(), b.data_ptr(), ct_dtype(a.dtype), a.numel(), out.data_ptr(), _stream(stream))
+    A.ct_dot(a.data_ptr(), b.data_ptr(), _ct_dtype_any(a.dtype), a.numel(), out.data_ptr(), _stream(stream))
     return out
 
 
 def convert(src: torch.Tensor, dtype: torch.dtype, stream=None) -> torch.Tensor:
     out = torch.empty(src.shape, dtype=dtype, device=src.device)
-    A.ct_convert(src.data_ptr(), ct_dtype(src.dtype), out.data_ptr(), ct_dtype(dtype), src.numel(), _stream(stream))
+    _dev(src, src.shape, "src")
+    A.ct_convert(src.data_ptr(), _ct_dtype_any(src.dtype), out.data_ptr(), _ct_dtype_any(dtype), src.numel(),
+                 _stream(stream))
     return out

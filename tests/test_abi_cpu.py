@@ -85,8 +85,8 @@ def test_calls_validate_before_device_work(lib):
                      lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 0, 5, 5),
                      lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 65),
                      lambda: A.ct_backproject(p, 9, 16, A.CT_F32, 16, A.CT_F32, 0, 0, 64),
-                     lambda: A.ct_sart(p, 16, 16, 1, 1.0, 0),
-                     lambda: A.ct_sart(p, 16, 16, 1, 1.0, 65),
+                     lambda: A.ct_sart(p, 16, A.CT_F32, 16, A.CT_F32, 1, 1.0, 0),
+                     lambda: A.ct_sart(p, 16, A.CT_F32, 16, A.CT_F32, 1, 1.0, 65),
                      lambda: A.ct_sart_workspace_bytes(p, 0),
                      lambda: A.ct_cgls(p, 16, A.CT_F32, 16, A.CT_F32, -1)):
             with pytest.raises(A.CtError) as e:
@@ -95,8 +95,40 @@ def test_calls_validate_before_device_work(lib):
         with pytest.raises(A.CtError) as e:
             A.ct_forward(p, A.CT_SIDDON, 16, 9, 16, A.CT_F32, 0, 0, 64)
         assert e.value.status == A.CT_ERR_DTYPE
+        # FP64 is a conversion and inner-product type only: the operators and algorithms refuse it
+        # before any device work
+        g = _geo()
+        for call in (lambda: A.ct_forward(p, A.CT_SIDDON, 16, A.CT_F64, 16, A.CT_F32, 0, 0, 64),
+                     lambda: A.ct_backproject(p, A.CT_BP_FDK, 16, A.CT_F32, 16, A.CT_F64, 0, 0, 64),
+                     lambda: A.ct_sart(p, 16, A.CT_F64, 16, A.CT_F32, 1, 1.0, 1),
+                     lambda: A.ct_sart(p, 16, A.CT_F32, 16, 5, 1, 1.0, 1),
+                     lambda: A.ct_cgls(p, 16, A.CT_F32, 16, A.CT_F64, 1),
+                     lambda: A.ct_tv_steps(g, 16, A.CT_F64, 1, 0.01),
+                     lambda: A.ct_tv_workspace_bytes(g, A.CT_F64),
+                     lambda: A.ct_convert(16, 4, 16, A.CT_F32, 1),
+                     lambda: A.ct_dot(16, 16, 4, 1, 16)):
+            with pytest.raises(A.CtError) as e:
+                call()
+            assert e.value.status == A.CT_ERR_DTYPE
     finally:
         A.ct_plan_destroy(p)
+
+
+def test_tv_workspace_grows_for_16bit_storage(lib):
+    g = _geo()
+    f32 = A.ct_tv_workspace_bytes(g, A.CT_F32)
+    # one more FP32 volume (64^3, 256-byte aligned) holds the FP32 copy of a 16-bit image
+    for dt in (A.CT_F16, A.CT_BF16):
+        assert A.ct_tv_workspace_bytes(g, dt) == f32 + 64 ** 3 * 4
+
+
+def test_ooc_stats_layout_matches_header(lib):
+    src = open(os.path.join(ROOT, "include", "ct.h")).read()
+    body = src[src.index("typedef struct {\n    int32_t n_slabs"):src.index("} ct_ooc_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(int32_t|double)\s+([a-z_0-9]+)\s*;", body)
+    assert [n for _, n in fields] == [n for n, _ in A.ct_ooc_stats._fields_]
+    assert "t_pin_s" in dict(A.ct_ooc_stats._fields_)
 
 
 def test_ooc_planner_out_of_core_config(lib):

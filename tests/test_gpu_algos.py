@@ -6,7 +6,7 @@ import torch
 
 from _helpers import rel_l2, say
 from paper_1905_03748_amd import inputs
-from paper_1905_03748_amd.operators import Plan, dot, tv_steps
+from paper_1905_03748_amd.operators import Plan, convert, dot, tv_steps, tv_workspace_bytes
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -121,6 +121,65 @@ def test_os_sart_parity_tiny(tiny, orc, block):
     ws = torch.empty(plan.sart_workspace_bytes(block), dtype=torch.uint8, device=DEV)
     x2 = plan.sart(torch.from_numpy(bb).to(DEV), 2, lam=0.8, block=block, workspace=ws).cpu().numpy()
     assert np.array_equal(x, x2)
+
+
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_sart_16bit_storage(tiny, orc, dt):
+    """SART with b and x stored in 16 bits: the sweep updates an FP32 copy of x and reads b widened
+    exactly, so the result is the FP32-storage run on the same rounded values, rounded once; and
+    that agrees with the oracle run on the rounded projections."""
+    w, geo, b, og = tiny
+    ang = w.angles[::2]
+    bb = torch.from_numpy(b[::2].copy()).to(dt)
+    plan = Plan(geo, ang)
+    say(f"[sart 16-bit] {dt}, tiny, 32 angles, OS-SART block 4")
+    x16 = torch.zeros(plan.vol_shape, dtype=dt, device=DEV)
+    plan.sart(bb.to(DEV), 1, x=x16, block=4)
+    x32 = plan.sart(bb.float().to(DEV), 1, block=4)
+    assert torch.equal(x16, x32.to(dt))
+    xr = orc.os_sart(og, ang, bb.double().numpy(), 1, 4)
+    e = rel_l2(x32.cpu().numpy(), xr)
+    say(f"   FP32 sweep on the rounded projections vs oracle: rel L2 {e:.3e}")
+    assert e <= 1e-4
+
+
+@pytest.mark.parametrize("dt", [torch.float16, torch.bfloat16])
+def test_tv_16bit_storage(orc, dt):
+    """TV steps on a 16-bit image: stepped in an FP32 copy, rounded once at the end, so the result is
+    the FP32 steps of the rounded image, rounded; and those agree with the oracle."""
+    rng = np.random.default_rng(9)
+    shape = (23, 17, 31)
+    x0 = ((rng.uniform(0, 1, shape) > 0.7) * 0.8 + 0.05 * rng.standard_normal(shape)).astype(np.float32)
+    geo = dict(DSO=1000.0, DSD=1500.0, nVoxel=(31, 17, 23), dVoxel=(1.0, 1.0, 1.0), offOrigin=(0, 0, 0),
+               nDetector=(8, 8), dDetector=(1.0, 1.0), offDetector=(0, 0), accuracy=0.5)
+    say(f"[tv 16-bit] {dt} {shape}")
+    x16 = torch.from_numpy(x0).to(dt).to(DEV)
+    x32 = x16.float()
+    ws = torch.empty(tv_workspace_bytes(geo, dt), dtype=torch.uint8, device=DEV)
+    tv_steps(geo, x16, 5, 0.01, workspace=ws)
+    tv_steps(geo, x32, 5, 0.01)
+    assert torch.equal(x16, x32.to(dt))
+    xr = orc.tv_steps(torch.from_numpy(x0).to(dt).double().numpy(), 5, 0.01)
+    assert rel_l2(x32.cpu().numpy(), xr) <= 1e-5
+    with pytest.raises(ValueError):
+        tv_steps(geo, x16, 1, 0.01, workspace=torch.empty(tv_workspace_bytes(geo), dtype=torch.uint8, device=DEV))
+
+
+def test_fp64_convert_and_dot():
+    """CT_F64 in ct_convert (to FP32 with one rounding, to the 16-bit types through FP32, and back
+    exactly) and ct_dot (FP64 products and sums)."""
+    rng = np.random.default_rng(10)
+    a = torch.from_numpy(rng.standard_normal(100_003) * 3.0).to(DEV)
+    say("[fp64] convert and dot")
+    assert torch.equal(convert(a, torch.float32), a.float())
+    for dt in (torch.float16, torch.bfloat16):
+        assert torch.equal(convert(a, dt), a.float().to(dt))
+    f = a.float()
+    assert torch.equal(convert(f, torch.float64), f.double())
+    b = torch.from_numpy(rng.standard_normal(100_003)).to(DEV)
+    got = float(dot(a, b).cpu())
+    ref = float(np.dot(a.cpu().numpy(), b.cpu().numpy()))
+    assert abs(got - ref) <= 1e-12 * abs(ref) + 1e-10
 
 
 def test_undersized_workspace_rejected(tiny):
