@@ -120,6 +120,20 @@ ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const vo
                          ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype, int accumulate,
                          int64_t angle_begin, int64_t angle_end, void *stream);
 
+/* ct_backproject for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * ct_backproject (for FP32 volumes bitwise the same), and it allocates nothing: the exact
+ * adjoint's transposed copy of the projections goes to a static device array of the library (128
+ * MiB, one per device, held from the library's load until the process ends), in sub-chunks of
+ * angles that fit it.  That array is shared by every call on a device, so calls that overlap on
+ * one device race; callers serialise them (one stream, or events).
+ * Extra errors: CT_ERR_ARG when one angle's transposed copy (8 (Nv + 2) Nu bytes) exceeds the
+ * array; CT_ERR_STATE when the plan's angle table is not yet on the current device (it is
+ * uploaded by the first allocating call with the plan on that device, e.g. ct_backproject). */
+ct_status ct_backproject_noalloc(ct_plan *plan, ct_backprojector backprojector, const void *d_proj,
+                                 ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype, int accumulate,
+                                 int64_t angle_begin, int64_t angle_end, void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Out-of-core operators: the image and projections live in host memory and the device holds at
  * most `device_cap_bytes` of working buffers (Algorithm 1 for the forward, Algorithm 2 for the

@@ -60,6 +60,7 @@ SIGNATURES = {
     "ct_plan_info": [_P, C.POINTER(ct_geometry), C.POINTER(_I64)],
     "ct_forward": [_P, _INT, _P, _INT, _P, _INT, _INT, _I64, _I64, _P],
     "ct_backproject": [_P, _INT, _P, _INT, _P, _INT, _INT, _I64, _I64, _P],
+    "ct_backproject_noalloc": [_P, _INT, _P, _INT, _P, _INT, _INT, _I64, _I64, _P],
     "ct_ooc_plan": [_P, _INT, _INT, _INT, _INT, _U64, C.POINTER(ct_ooc_stats)],
     "ct_forward_host": [_P, _INT, _P, _INT, _P, _INT, _U64, C.POINTER(ct_ooc_stats)],
     "ct_backproject_host": [_P, _INT, _P, _INT, _P, _INT, _U64, C.POINTER(ct_ooc_stats)],
@@ -150,6 +151,12 @@ def ct_backproject(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, ac
                    stream=0):
     return _check(lib().ct_backproject(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, int(accumulate),
                                        angle_begin, angle_end, stream or None))
+
+
+def ct_backproject_noalloc(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, accumulate, angle_begin,
+                           angle_end, stream=0):
+    return _check(lib().ct_backproject_noalloc(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype,
+                                               int(accumulate), angle_begin, angle_end, stream or None))
 
 
 def ct_ooc_plan(plan, direction, projector, vol_dtype, proj_dtype, device_cap_bytes) -> ct_ooc_stats:

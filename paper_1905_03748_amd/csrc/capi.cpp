@@ -99,6 +99,19 @@ ct_status plan_device_table(ct_plan *p, hipStream_t st, const AngleGeo **out) {
     return CT_OK;
 }
 
+ct_status plan_device_table_existing(ct_plan *p, hipStream_t st, const AngleGeo **out) {
+    int dev = 0;
+    CT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->dtab.find(dev);
+    if (it == p->dtab.end())
+        return fail(CT_ERR_STATE, "the plan's angle table is not on this device yet: one allocating call with the plan "
+                                  "on this device (e.g. ct_backproject) uploads it");
+    CT_HIP(hipStreamWaitEvent(st, it->second.ready, 0));
+    *out = it->second.ptr;
+    return CT_OK;
+}
+
 }  // namespace ct
 
 using namespace ct;
@@ -179,6 +192,20 @@ ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const vo
     if (st != CT_OK) return st;
     return launch_backproject(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, accumulate,
                               angle_begin, angle_end, full_slab(plan->g), (hipStream_t)stream);
+}
+
+ct_status ct_backproject_noalloc(ct_plan *plan, ct_backprojector backprojector, const void *d_proj,
+                                 ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype, int accumulate,
+                                 int64_t angle_begin, int64_t angle_end, void *stream) {
+    if (!plan || !d_vol || !d_proj) return fail(CT_ERR_ARG, "ct_backproject_noalloc: null pointer");
+    if (backprojector != CT_BP_FDK && backprojector != CT_BP_PSEUDO_MATCHED && backprojector != CT_BP_ADJOINT)
+        return fail(CT_ERR_ARG, "ct_backproject_noalloc: unknown backprojector");
+    if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype))
+        return fail(CT_ERR_DTYPE, "ct_backproject_noalloc: dtype must be CT_F32, CT_F16 or CT_BF16");
+    ct_status st = check_range(plan, angle_begin, angle_end, "ct_backproject_noalloc");
+    if (st != CT_OK) return st;
+    return backproject_noalloc(plan, backprojector, d_proj, proj_dtype, d_vol, vol_dtype, accumulate, angle_begin,
+                               angle_end, (hipStream_t)stream);
 }
 
 ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,

@@ -58,6 +58,8 @@ namespace ct {
 // Device copy of the per-angle table for the current device.  The first use uploads it in stream
 // order on `st` (no host synchronisation); later uses on any stream wait for that upload.
 ct_status plan_device_table(ct_plan *p, hipStream_t st, const AngleGeo **out);
+// The same without the upload: CT_ERR_STATE when the table is not yet on the current device.
+ct_status plan_device_table_existing(ct_plan *p, hipStream_t st, const AngleGeo **out);
 
 // Range of axial slices a launch covers and where its memory starts.
 //   own_lo/own_hi: slices whose voxels this launch owns (forward: rays are clipped to them;
@@ -69,6 +71,7 @@ struct Slab {
     bool first, last;  // the interpolated projector extends ownership to +-inf at the ends
     bool scratch_ok;   // the launch may allocate device scratch (resident calls; not under a cap)
     bool zcol = false; // exact-adjoint backprojection only: the slab is column-major, [y][x][mem_n]
+    bool no_alloc = false;  // the launch allocates nothing (the angle table must be on the device)
 };
 
 inline Slab full_slab(const ct_geometry &g) {
@@ -121,6 +124,9 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
                              hipStream_t st, void *adj_scratch = nullptr, size_t adj_bytes = 0);
 size_t adj_chunk_bytes_per_angle(const ct_geometry &g);
+// ct_backproject through the library's static device scratch (no allocation of any kind)
+ct_status backproject_noalloc(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
+                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, hipStream_t st);
 
 // Algorithm helpers (kern_algos.hip)
 ct_status dot_f64(const void *a, const void *b, ct_dtype t, int64_t n, double *out, double *partials,

@@ -14,6 +14,9 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "dev_common.hpp"
 
@@ -1148,7 +1151,7 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab, hipStream_t st,
                              void *adj_scratch, size_t adj_bytes) {
     const AngleGeo *tab = nullptr;
-    ct_status s = plan_device_table(p, st, &tab);
+    ct_status s = slab.no_alloc ? plan_device_table_existing(p, st, &tab) : plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
     const int64_t nzown = slab.own_hi - slab.own_lo;
     if (nzown <= 0) return CT_OK;
@@ -1302,6 +1305,53 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     }
     CT_HIP(hipGetLastError());
     return CT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Backprojection that allocates nothing: the exact adjoint's transposed projection copy goes to a
+// static device array (one per device, held until the process ends), filled in angle sub-chunks
+// that fit it, with the voxel sums passed between sub-chunks through the volume (FP32 volumes:
+// bitwise the same as one chunk).  The FDK and pseudo-matched kernels need no scratch.  Every
+// call on a device shares that device's array, so calls that overlap on one device race; the
+// array needs no clearing (each sub-chunk writes all of the copy it reads).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;  // one angle of a 3072^2 detector: 75.5 MB
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device id -> that device's address of `scratch`
+
+// The device address of `scratch` on the current device (the array's name in host code is only a
+// host-side handle), looked up once per device.
+ct_status scratch_address(void **out) {
+    int dev = 0;
+    CT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        CT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(CT_ERR_HIP, "no device address for the backprojection scratch");
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return CT_OK;
+}
+}  // namespace
+
+ct_status backproject_noalloc(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
+                              ct_dtype vt, int accumulate, int64_t a0, int64_t a1, hipStream_t st) {
+    if (kind == CT_BP_ADJOINT && adj_col_ok(p) && adj_chunk_bytes_per_angle(p->g) > NOALLOC_SCRATCH_BYTES)
+        return fail(CT_ERR_ARG, "ct_backproject_noalloc: one angle's transposed copy of the detector (" +
+                                    std::to_string(adj_chunk_bytes_per_angle(p->g)) + " bytes) exceeds the " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch");
+    void *scr = nullptr;
+    ct_status s = scratch_address(&scr);
+    if (s != CT_OK) return s;
+    Slab sl = full_slab(p->g);
+    sl.scratch_ok = false;
+    sl.no_alloc = true;
+    return launch_backproject(p, kind, proj, pt, vol, vt, accumulate, a0, a1, sl, st, scr, NOALLOC_SCRATCH_BYTES);
 }
 
 ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t a0, int64_t a1, float lambda,

@@ -1,0 +1,82 @@
+"""The no-allocation backprojection (ct_backproject_noalloc) through the C ABI against
+ct_backproject on the same inputs: bitwise equal for FP32 volumes (the exact adjoint's angle
+sub-chunks pass the FP32 sums through the volume unchanged), on two calls in a row, the second with
+a smaller problem; and the size and state errors, raised before any device work."""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import say
+from paper_1905_03748_amd import _abi as A
+from paper_1905_03748_amd import inputs
+from paper_1905_03748_amd.operators import Plan
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+KINDS = {"fdk": A.CT_BP_FDK, "pm": A.CT_BP_PSEUDO_MATCHED, "adjoint": A.CT_BP_ADJOINT}
+
+
+def _case(nvox, ndet, nang, seed):
+    w = inputs.Workload(f"noalloc_{nvox[0]}", nvox, (1.1, 1.0, 0.9), ndet, (1.7, 1.5), nang, 0, seed,
+                        off_origin=(0.6, -0.3, 0.4), off_detector=(0.5, -0.8))
+    plan = Plan(w.geometry_dict(), w.angles)
+    y = torch.from_numpy(inputs.random_array(plan.proj_shape, seed, kind="uniform")).to(DEV)
+    return plan, y
+
+
+def _both(plan, y, kind, accumulate=0, a0=0, a1=None):
+    a1 = plan.n_angles if a1 is None else a1
+    py = y[a0:a1].contiguous()
+    ref = torch.rand(plan.vol_shape, device=DEV, generator=torch.Generator(device=DEV).manual_seed(5))
+    got = ref.clone()
+    A.ct_backproject(plan.handle, KINDS[kind], py.data_ptr(), A.CT_F32, ref.data_ptr(), A.CT_F32, accumulate,
+                     a0, a1, 0)
+    A.ct_backproject_noalloc(plan.handle, KINDS[kind], py.data_ptr(), A.CT_F32, got.data_ptr(), A.CT_F32, accumulate,
+                             a0, a1, 0)
+    torch.cuda.synchronize()
+    return ref, got
+
+
+def test_noalloc_equals_backproject_two_calls():
+    # first call: 360 angles on a 200 x 171 detector (0.28 MB of transposed copy per angle: one
+    # sub-chunk); second call: a smaller problem
+    for nvox, ndet, nang, seed in (((72, 61, 53), (200, 171), 360, 11), ((23, 19, 17), (40, 31), 12, 12)):
+        plan, y = _case(nvox, ndet, nang, seed)
+        for kind in ("adjoint", "fdk", "pm"):
+            for acc in (0, 1):
+                say(f"[noalloc] {nvox} x {nang} angles, {kind}, accumulate={acc}")
+                ref, got = _both(plan, y, kind, acc)
+                assert torch.equal(ref, got), (kind, acc, float((ref - got).abs().max()))
+        # an angle sub-range
+        ref, got = _both(plan, y, "adjoint", 1, 3, plan.n_angles - 2)
+        assert torch.equal(ref, got)
+
+
+def test_noalloc_subchunks_match_one_chunk():
+    """A detector whose transposed copy (8 (Nv + 2) Nu bytes per angle) lets only a few angles into
+    the 128 MiB scratch, so the exact adjoint runs in many sub-chunks: still bitwise equal."""
+    plan, y = _case((64, 64, 40), (1500, 1400), 40, 13)   # 16.8 MB per angle: 7 angles per sub-chunk
+    say("[noalloc] 1500 x 1400 detector, 40 angles: adjoint in sub-chunks of 7 angles")
+    ref, got = _both(plan, y, "adjoint")
+    assert torch.equal(ref, got)
+
+
+def test_noalloc_errors_before_device_work():
+    # one angle of a 4096^2 detector needs 4096 * 4098 * 8 bytes > 128 MiB: refused.  Rows of 2 mm
+    # against 1 mm voxels keep the geometry on the column kernel (the one that uses the scratch);
+    # the buffers have their full sizes all the same
+    g = dict(inputs.workload("tiny").geometry_dict(), nDetector=(4096, 4096), dDetector=(0.05, 2.0))
+    big = Plan(g, np.array([0.0, 1.0]))
+    yb = torch.zeros(big.proj_shape, device=DEV)
+    vb = torch.zeros(big.vol_shape, device=DEV)
+    with pytest.raises(A.CtError) as e:
+        A.ct_backproject_noalloc(big.handle, A.CT_BP_ADJOINT, yb.data_ptr(), A.CT_F32, vb.data_ptr(), A.CT_F32,
+                                 0, 0, 2, 0)
+    assert e.value.status == A.CT_ERR_ARG and "scratch" in str(e.value)
+    # a plan never used on the device has no angle table there: refused, nothing uploaded
+    fresh, y = _case((23, 19, 17), (40, 31), 12, 14)
+    v = torch.empty(fresh.vol_shape, device=DEV)
+    with pytest.raises(A.CtError) as e:
+        A.ct_backproject_noalloc(fresh.handle, A.CT_BP_FDK, y.data_ptr(), A.CT_F32, v.data_ptr(), A.CT_F32, 0, 0,
+                                 fresh.n_angles, 0)
+    assert e.value.status == A.CT_ERR_STATE
