@@ -1,10 +1,16 @@
-"""Out-of-core operators at the full size of the splitting workload: a 3072^3 FP32 volume and 3072
-projections of 3072^2 (108 GiB each, in pageable host memory, which the streamer stages through its
-own pinned ring) under a 32 GiB device cap.  One Siddon A x, one FDK A^T y and one exact-adjoint A^T y
-(Algorithms 1 and 2), each checked on seeded samples of its output against the oracle, which reads
-the FP32 host arrays in place.
+"""Out-of-core operators on the splitting workload (Algorithms 1 and 2 under a device memory cap).
 
-It needs about 220 GiB of host memory and several minutes, so it runs only when CT_FULL_OOC=1."""
+test_ooc_shape_reduced: its real slice and detector shape (3072 x 3072 slices, 3072^2 detector) with
+24 slices and 16 of its angles, under caps that force 3 slabs and one-angle projection chunks: the
+split forward equals the resident one to 1e-6 and the split backprojections (FDK, exact adjoint)
+equal the resident ones bit for bit; all three match the oracle on sampled rays and voxels.
+
+test_full_size_out_of_core: the whole workload, a 3072^3 FP32 volume and 3072 projections of
+3072^2 (108 GiB each, in pageable host memory, which the streamer stages through its own pinned
+ring) under a 32 GiB device cap.  One Siddon A x and one FDK A^T y, each checked on seeded samples of
+its output against the oracle, which reads the FP32 host arrays in place.  It needs about 220 GiB of
+host memory and about three minutes.  The exact adjoint at that size
+(test_full_size_out_of_core_adjoint) takes about two minutes more and runs only with CT_FULL_OOC=1."""
 import os
 
 import numpy as np
@@ -14,12 +20,77 @@ import torch
 from _helpers import TOL_BP, TOL_PROJ, rel_l2, say
 from paper_1905_03748_amd import inputs
 from paper_1905_03748_amd.operators import Plan
+from test_gpu_ooc import _cap_for
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow,
-              pytest.mark.skipif(os.environ.get("CT_FULL_OOC") != "1",
-                                 reason="set CT_FULL_OOC=1 (needs ~220 GiB of host memory, minutes)")]
+pytestmark = [pytest.mark.gpu]
 DEV = "cuda:0"
 CAP = 32 << 30
+FULL_ADJ = pytest.mark.skipif(os.environ.get("CT_FULL_OOC") != "1",
+                              reason="set CT_FULL_OOC=1 (the 3072^3 exact adjoint adds about two minutes)")
+
+
+def test_ooc_shape_reduced(orc):
+    base = inputs.workload("ooc")
+    nz = 24
+    w = inputs.Workload("ooc_24", (3072, 3072, nz), base.dvox, base.ndet, base.ddet, 16, 0, base.seed,
+                        angles=np.asarray(base.angles)[::192])
+    plan = Plan(w.geometry_dict(), w.angles)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    say("[ooc reduced] 24 central slices of the 3072^3 phantom")
+    vol = inputs.voxelize_torch(w, inputs.ellipsoids(base), device=DEV)
+    vh = vol.cpu()
+    # forward: 3 slabs of 8 slices, one-angle chunks
+    cap = _cap_for(plan, 8, 0, "siddon")
+    info = plan.ooc_plan(0, "siddon", cap_bytes=cap)
+    assert info["n_slabs"] == 3 and info["n_chunks"] >= 4, info
+    say(f"[ooc reduced] Siddon forward, plan {info}")
+    out = torch.zeros(plan.proj_shape)
+    st = plan.forward_host(vh, out, "siddon", cap_bytes=cap)
+    res = plan.forward(vol, "siddon").cpu()
+    e = rel_l2(out.numpy(), res.numpy())
+    say(f"   split vs resident rel L2 {e:.3e}, stats {st}")
+    assert e <= 1e-6
+    # rays through the slab's rows (the others miss the 2 mm thick slab)
+    rng = np.random.default_rng(601)
+    a = rng.integers(0, 16, 400)
+    b = rng.integers(1536 - 14, 1536 + 14, 400)
+    u = rng.integers(0, 3072, 400)
+    rays = np.unique((a * 3072 + b) * 3072 + u)
+    ref = orc.siddon_rays(og, w.angles, rays, vh.numpy())
+    got = out.numpy().reshape(-1)[rays]
+    assert np.count_nonzero(ref) > 100
+    e = rel_l2(got, ref)
+    say(f"   vs oracle on {len(rays)} rays: rel L2 {e:.3e}")
+    assert e <= TOL_PROJ
+    del vol, res
+    # backprojections of uniform noise: 3 slabs, chunks of the planner's size
+    y = torch.from_numpy(inputs.random_array(plan.proj_shape, 602, kind="uniform"))
+    yd = y.to(DEV)
+    vox = inputs.sample_indices(int(np.prod(plan.vol_shape)), 300, 603)
+    for kind, direction, fn in (("fdk", 1, lambda: orc.bp_voxels(og, w.angles, y.numpy(), vox, orc.W_FDK)),
+                                ("adjoint", 2, lambda: orc.siddon_adj_voxels(og, w.angles, y.numpy(), vox))):
+        cap = _cap_for(plan, 8, direction)
+        info = plan.ooc_plan(direction, cap_bytes=cap)
+        assert info["n_slabs"] == 3, info
+        say(f"[ooc reduced] {kind} backprojection, plan {info}")
+        outv = torch.full(plan.vol_shape, -7.0)
+        plan.backproject_host(y, outv, kind, cap_bytes=cap)
+        resv = plan.backproject(yd, kind).cpu()
+        assert torch.equal(outv, resv), (kind, float((outv - resv).abs().max()))
+        e = rel_l2(outv.numpy().reshape(-1)[vox], fn())
+        say(f"   vs oracle on {len(vox)} voxels: rel L2 {e:.3e}")
+        assert e <= TOL_BP
+
+
+def _full_phantom(w, vol):
+    ells = inputs.ellipsoids(w)
+    nz = w.nvox[2]
+    for z0 in range(0, nz, 256):
+        h = min(256, nz - z0)
+        ws = inputs.Workload("slab", (w.nvox[0], w.nvox[1], h), w.dvox, w.ndet, w.ddet, 1, 0, 0,
+                             off_origin=(0.0, 0.0, (z0 + h / 2.0 - nz / 2.0) * w.dvox[2]))
+        torch.from_numpy(vol[z0:z0 + h]).copy_(inputs.voxelize_torch(ws, ells, device=DEV))
+        torch.cuda.synchronize()
 
 
 def test_full_size_out_of_core(orc):
@@ -30,44 +101,56 @@ def test_full_size_out_of_core(orc):
     proj = np.empty(plan.proj_shape, dtype=np.float32)
     say("[ooc full] phantom slab by slab")
     try:
-        ells = inputs.ellipsoids(w)
-        nz = w.nvox[2]
-        for z0 in range(0, nz, 256):
-            h = min(256, nz - z0)
-            ws = inputs.Workload("slab", (w.nvox[0], w.nvox[1], h), w.dvox, w.ndet, w.ddet, 1, 0, 0,
-                                 off_origin=(0.0, 0.0, (z0 + h / 2.0 - nz / 2.0) * w.dvox[2]))
-            torch.from_numpy(vol[z0:z0 + h]).copy_(inputs.voxelize_torch(ws, ells, device=DEV))
-            torch.cuda.synchronize()
+        _full_phantom(w, vol)
         vt, pt = torch.from_numpy(vol), torch.from_numpy(proj)
 
         say("[ooc full] Siddon forward under the cap")
         st = plan.forward_host(vt, pt, "siddon", cap_bytes=CAP)
         say(f"[ooc full] forward: {st}")
         assert st["n_slabs"] > 1
-        rays = inputs.sample_indices(proj.size, 48, 301)
+        rays = inputs.sample_indices(proj.size, 200, 301)
         ref = orc.siddon_rays(og, w.angles, rays, vol.reshape(-1))
         e = rel_l2(proj.reshape(-1)[rays].astype(np.float64), ref)
-        say(f"[ooc full] forward vs oracle on 48 rays: rel L2 {e:.3e}")
+        say(f"[ooc full] forward vs oracle on 200 rays: rel L2 {e:.3e}")
         assert e <= TOL_PROJ
 
         say("[ooc full] FDK backprojection under the cap")
         st = plan.backproject_host(pt, vt, "fdk", cap_bytes=CAP)
         say(f"[ooc full] backprojection: {st}")
         assert st["n_slabs"] > 1
-        vox = inputs.sample_indices(vol.size, 48, 302)
+        vox = inputs.sample_indices(vol.size, 200, 302)
         ref = orc.bp_voxels(og, w.angles, proj.reshape(-1), vox, orc.W_FDK)
         e = rel_l2(vol.reshape(-1)[vox].astype(np.float64), ref)
-        say(f"[ooc full] backprojection vs oracle on 48 voxels: rel L2 {e:.3e}")
+        say(f"[ooc full] backprojection vs oracle on 200 voxels: rel L2 {e:.3e}")
         assert e <= TOL_BP
+    finally:
+        del vol, proj
 
-        say("[ooc full] exact-adjoint backprojection under the cap")
-        st = plan.backproject_host(pt, vt, "adjoint", cap_bytes=CAP)
-        say(f"[ooc full] exact adjoint: {st}")
+
+@FULL_ADJ
+def test_full_size_out_of_core_adjoint(orc):
+    """The exact adjoint of 3072 projections of 3072^2 uniform noise (made on the device, angle
+    chunk by chunk) into the 3072^3 volume under the 32 GiB cap, on 64 sampled voxels."""
+    w = inputs.workload("ooc")
+    plan = Plan(w.geometry_dict(), w.angles)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    vol = np.empty(plan.vol_shape, dtype=np.float32)
+    proj = np.empty(plan.proj_shape, dtype=np.float32)
+    try:
+        say("[ooc full adjoint] noise projections")
+        g = torch.Generator(device=DEV)
+        g.manual_seed(304)
+        for a0 in range(0, proj.shape[0], 64):
+            a1 = min(proj.shape[0], a0 + 64)
+            torch.from_numpy(proj[a0:a1]).copy_(torch.rand((a1 - a0,) + proj.shape[1:], generator=g, device=DEV))
+        say("[ooc full adjoint] exact-adjoint backprojection under the cap")
+        st = plan.backproject_host(torch.from_numpy(proj), torch.from_numpy(vol), "adjoint", cap_bytes=CAP)
+        say(f"[ooc full adjoint] {st}")
         assert st["n_slabs"] > 1
-        vox = inputs.sample_indices(vol.size, 32, 303)
+        vox = inputs.sample_indices(vol.size, 64, 303)
         ref = orc.siddon_adj_voxels(og, w.angles, proj, vox)
         e = rel_l2(vol.reshape(-1)[vox].astype(np.float64), ref)
-        say(f"[ooc full] exact adjoint vs oracle on 32 voxels: rel L2 {e:.3e}")
+        say(f"[ooc full adjoint] vs oracle on 64 voxels: rel L2 {e:.3e}")
         assert e <= TOL_BP
     finally:
         del vol, proj
