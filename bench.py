@@ -392,6 +392,10 @@ def main():
     ap.add_argument("--ooc-tv", action="store_true", help="print the 3072^3 out-of-core TV report instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (ct_convert F32->F32) for HBM counter calibration")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch each resident operator of the 512^3 workload (Siddon and interpolated "
+                         "forward, FDK, pseudo-matched and exact-adjoint backprojection) --steps times after "
+                         "one warm-up, and a 1 GiB plain copy, for rocprofv3 counter runs; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the build targets single-GPU boxes (no collectives); "
@@ -420,6 +424,21 @@ def main():
     p = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
     v = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.profile_kernels:
+        from paper_1905_03748_amd.operators import convert
+        ops = [("siddon", lambda: plan.forward(x, "siddon", out=p)), ("interp", lambda: plan.forward(x, "interp", out=p)),
+               ("fdk", lambda: plan.backproject(p, "fdk", out=v)), ("pm", lambda: plan.backproject(p, "pm", out=v)),
+               ("adjoint", lambda: plan.backproject(p, "adjoint", out=v))]
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        ops.append(("copy_1gib", lambda: convert(src, torch.float32)))
+        for name, fn in ops:
+            log(f"[bench] profile {name}")
+            for _ in range(1 + args.steps):
+                fn()
+            torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": [n for n, _ in ops], "launches_each": 1 + args.steps}), flush=True)
+        return
 
     def step(ev=None):
         if ev is not None:

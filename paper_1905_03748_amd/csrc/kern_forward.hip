@@ -259,6 +259,12 @@ __global__ __launch_bounds__(FWD_TU * FWD_TV) void k_siddon(const TV *__restrict
 #ifndef CT_ZC_COLS
 #define CT_ZC_COLS 4
 #endif
+#ifndef CT_ZC_ORDER
+#define CT_ZC_ORDER 3
+#endif
+#ifndef CT_ZC_AK
+#define CT_ZC_AK 32
+#endif
 #ifndef CT_ZC_XCD_W
 #define CT_ZC_XCD_W 4
 #endif
@@ -397,10 +403,36 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restric
         if (bid < full) bid = (bid / C) * C + (bid % 8) * W + (bid % C) / 8;
     }
 #endif
-    const int cb = bid % A.cblocks;
-    const int rest = bid / A.cblocks;
-    const int ai = rest % A.nang;
-    const int rg = rest / A.nang;
+    int cb, ai, rg;
+#if CT_ZC_ORDER == 1
+    ai = bid % A.nang;
+    cb = (bid / A.nang) % A.cblocks;
+    rg = bid / A.nang / A.cblocks;
+#elif CT_ZC_ORDER == 2
+    cb = bid % A.cblocks;
+    rg = (bid / A.cblocks) % A.rgroups;
+    ai = bid / A.cblocks / A.rgroups;
+#elif CT_ZC_ORDER == 3
+    {
+        // groups of CT_ZC_AK consecutive angles: angle within the group fastest, then column block
+        constexpr int AK = CT_ZC_AK;
+        const int per = A.nang * A.cblocks, idx = bid % per, full = A.nang / AK;
+        rg = bid / per;
+        if (idx < full * AK * A.cblocks) {
+            const int r = idx % (AK * A.cblocks);
+            cb = r / AK;
+            ai = (idx / (AK * A.cblocks)) * AK + r % AK;
+        } else {
+            const int rem = A.nang - full * AK, i2 = idx - full * AK * A.cblocks;
+            cb = i2 / rem;
+            ai = full * AK + i2 % rem;
+        }
+    }
+#else
+    cb = bid % A.cblocks;
+    ai = (bid / A.cblocks) % A.nang;
+    rg = bid / A.cblocks / A.nang;
+#endif
     const int a = cb * ZC_COLS + wave;
     if (a >= A.nu) return;
     const AngleGeo &G = A.tab[A.a0 + ai];
