@@ -13,6 +13,7 @@
 // computes; pinned caller memory (hipHostMalloc) is copied directly.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -157,6 +158,56 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     return fail(CT_ERR_CAP, "device memory cap is below one slice plus the projection buffers");
 }
 
+// Detector rows [b0, b1) whose rays can meet the heights [zlo, zhi] (mm) of the volume (Section
+// 2.1's observation that a slab of the image projects to a band of the detector).  The source lies
+// in the plane z = 0 and a ray of row height v is at height t v at parameter t (t = 1 at the
+// detector); inside the volume's xy extent t lies in [(DSO - R) / DSD, (DSO + R) / DSD], R bounding
+// the distance of the volume box (grown by `grow` mm) from the axis, so the ray's v lies between
+// zlo / t and zhi / t over that range.  `margin` rows are added on either side.
+void row_band(const ct_geometry &g, double zlo, double zhi, double grow, int64_t margin, int64_t &b0, int64_t &b1) {
+    double R = 0.0;
+    for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy) {
+            const double xe = g.offOrigin[0] + (cx ? 0.5 : -0.5) * g.nVoxel[0] * g.dVoxel[0];
+            const double ye = g.offOrigin[1] + (cy ? 0.5 : -0.5) * g.nVoxel[1] * g.dVoxel[1];
+            R = std::max(R, std::sqrt(xe * xe + ye * ye));
+        }
+    R += grow;
+    const int64_t nv = g.nDetector[1];
+    b0 = 0;
+    b1 = nv;
+    if (!(g.DSO - R > 0.0)) return;
+    const double tmin = (g.DSO - R) / g.DSD, tmax = (g.DSO + R) / g.DSD;
+    const double vmin = std::min(zlo / tmin, zlo / tmax), vmax = std::max(zhi / tmin, zhi / tmax);
+    const double cv = (nv - 1) / 2.0;
+    const double bmin = (vmin - g.offDetector[1]) / g.dDetector[1] + cv;
+    const double bmax = (vmax - g.offDetector[1]) / g.dDetector[1] + cv;
+    b0 = std::max<int64_t>(0, (int64_t)std::floor(bmin) - margin);
+    b1 = std::min<int64_t>(nv, (int64_t)std::floor(bmax) + 2 + margin);
+    if (b1 < b0) b1 = b0;
+}
+
+// Height (mm) of the lower face of slice k.
+double face_z(const ct_geometry &g, int64_t k) {
+    return g.offOrigin[2] + ((double)k - 0.5 - (g.nVoxel[2] - 1) / 2.0) * g.dVoxel[2];
+}
+
+// rows [b0, b1) of each of n projections (pitch `pangle` bytes, rows of `rowb` bytes), 2-D copy
+ct_status copy_rows(void *dst, const void *src, size_t pangle, size_t rowb, int64_t b0, int64_t b1, int64_t n,
+                    hipMemcpyKind kind, hipStream_t st) {
+    if (b1 <= b0 || n <= 0) return CT_OK;
+    CT_HIP(hipMemcpy2DAsync((char *)dst + b0 * rowb, pangle, (const char *)src + b0 * rowb, pangle, (b1 - b0) * rowb, n,
+                            kind, st));
+    return CT_OK;
+}
+
+// the same between host buffers (staging), in parallel for large bands
+void host_rows(void *dst, const void *src, size_t pangle, size_t rowb, int64_t b0, int64_t b1, int64_t n) {
+    if (b1 <= b0) return;
+    for (int64_t a = 0; a < n; ++a)
+        par_memcpy((char *)dst + a * pangle + b0 * rowb, (const char *)src + a * pangle + b0 * rowb, (b1 - b0) * rowb);
+}
+
 }  // namespace
 
 ct_status ooc_plan(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt, uint64_t cap,
@@ -223,8 +274,10 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
     }
     st.t_other_mem_s += secs(t0, clk::now());
 
-    // pending output chunks waiting for their staging buffer to be drained into h_proj
-    int64_t pending[3] = {-1, -1, -1};
+    // pending output chunks (and the row band they carry) waiting for their staging buffer to be
+    // drained into h_proj
+    int64_t pending[3] = {-1, -1, -1}, pend_b0[3] = {0, 0, 0}, pend_b1[3] = {0, 0, 0};
+    const size_t rowb = (size_t)g.nDetector[0] * dtype_size(pt);
     auto drain = [&](int j) -> ct_status {
         if (pending[j] < 0) return CT_OK;
         CT_HIP(hipEventSynchronize(ev_d2h.e[j]));
@@ -232,12 +285,14 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
         const int64_t nang = std::min(L.K, na - c * L.K);
         if (!proj_pinned) {
             auto a = clk::now();
-            par_memcpy((char *)h_proj + c * chunk_bytes, sout[j].p, nang * pangle);
+            host_rows((char *)h_proj + c * chunk_bytes, sout[j].p, pangle, rowb, pend_b0[j], pend_b1[j], nang);
             st.t_stage_s += secs(a, clk::now());
         }
         pending[j] = -1;
         return CT_OK;
     };
+    // detector rows already written by earlier slabs: [0, covered)
+    int64_t covered = 0;
 
     for (int64_t n = 0; n < L.nsp; ++n) {
         const int64_t own_lo = n * L.h, own_hi = std::min(nz, own_lo + L.h);
@@ -298,11 +353,27 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
         sl.first = (n == 0);
         sl.last = (own_hi == nz);
         sl.scratch_ok = false;
+        // the rows this slab can add to (the interpolated projector's samples reach one voxel past
+        // the owned faces); the first slab's band starts at row 0 and the last one's ends at the
+        // top, so every row is written at least once.  Rows outside the band get exactly zero from
+        // this slab: they are neither sent in nor read back.
+        int64_t b0, b1;
+        {
+            const bool interp = kind == CT_INTERP;
+            const double dz = g.dVoxel[2], grow = interp ? std::max(g.dVoxel[0], g.dVoxel[1]) : 0.0;
+            row_band(g, face_z(g, own_lo) - (interp ? dz : 0.0), face_z(g, own_hi) + (interp ? dz : 0.0), grow,
+                     interp ? 2 : 1, b0, b1);
+            if (n == 0) b0 = 0;
+            if (own_hi == nz) b1 = g.nDetector[1];
+        }
+        // rows [b0, min(b1, covered)) carry partial sums of earlier slabs; [max(b0, covered), b1)
+        // start at zero here
+        const int64_t in_hi = std::min(b1, covered), new_lo = std::max(b0, covered);
         const bool acc = n > 0;
         for (int64_t c = 0; c < nchunks; ++c) {
             const int j = (int)(c % 3);
             const int64_t a0 = c * L.K, a1 = std::min(na, a0 + L.K);
-            const size_t bytes = (a1 - a0) * pangle;
+            const int64_t nang = a1 - a0;
             if ((s = drain(j)) != CT_OK) return s;
             if (acc) {
                 // partial sums of earlier slabs for this chunk come in (buffer free once its last D2H ended)
@@ -311,14 +382,19 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
                 if (!proj_pinned) {
                     CT_HIP(hipEventSynchronize(ev_h2d.e[j]));
                     auto b = clk::now();
-                    par_memcpy(sin[j].p, from, bytes);
+                    host_rows(sin[j].p, from, pangle, rowb, b0, in_hi, nang);
                     st.t_stage_s += secs(b, clk::now());
                     from = sin[j].p;
                 }
-                CT_HIP(hipMemcpyAsync(dbuf[j].p, from, bytes, hipMemcpyHostToDevice, S.h2d));
+                if ((s = copy_rows(dbuf[j].p, from, pangle, rowb, b0, in_hi, nang, hipMemcpyHostToDevice, S.h2d)) !=
+                    CT_OK)
+                    return s;
                 CT_HIP(hipEventRecord(ev_h2d.e[j], S.h2d));
                 CT_HIP(hipStreamWaitEvent(S.comp, ev_h2d.e[j], 0));
-                st.bytes_h2d += (double)bytes;
+                st.bytes_h2d += (double)(std::max<int64_t>(0, in_hi - b0) * rowb * nang);
+                if (b1 > new_lo)
+                    CT_HIP(hipMemset2DAsync((char *)dbuf[j].p + new_lo * rowb, pangle, 0, (b1 - new_lo) * rowb, nang,
+                                            S.comp));
             } else {
                 CT_HIP(hipStreamWaitEvent(S.comp, ev_d2h.e[j], 0));
             }
@@ -330,11 +406,15 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
             CT_HIP(hipEventRecord(ev_k.e[j], S.comp));
             CT_HIP(hipStreamWaitEvent(S.d2h, ev_k.e[j], 0));
             void *to = proj_pinned ? (char *)h_proj + a0 * pangle : sout[j].p;
-            CT_HIP(hipMemcpyAsync(to, dbuf[j].p, bytes, hipMemcpyDeviceToHost, S.d2h));
+            if ((s = copy_rows(to, dbuf[j].p, pangle, rowb, b0, b1, nang, hipMemcpyDeviceToHost, S.d2h)) != CT_OK)
+                return s;
             CT_HIP(hipEventRecord(ev_d2h.e[j], S.d2h));
-            st.bytes_d2h += (double)bytes;
+            st.bytes_d2h += (double)((b1 - b0) * rowb * nang);
             pending[j] = c;
+            pend_b0[j] = b0;
+            pend_b1[j] = b1;
         }
+        covered = std::max(covered, b1);
         for (int j = 0; j < 3; ++j)
             if ((s = drain(j)) != CT_OK) return s;
         CT_HIP(hipStreamSynchronize(S.comp));
@@ -421,25 +501,37 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
         sl.first = sl.last = true;
         sl.scratch_ok = false;
         sl.zcol = zcol;
+        // the detector rows the slab's voxels read (bilinear taps, or the rays that cross their
+        // boxes, with two rows to spare for the candidate rows the exact adjoint visits); the rest of
+        // each chunk buffer is zeroed once per slab and never sent
+        int64_t b0, b1;
+        row_band(g, face_z(g, own_lo), face_z(g, own_hi), 0.0, 2, b0, b1);
+        const int64_t nv = g.nDetector[1];
+        const size_t rowb = (size_t)g.nDetector[0] * dtype_size(pt);
         bool h2d_used[2] = {false, false};
         for (int64_t c = 0; c < nchunks; ++c) {
             const int j = (int)(c % 2);
             const int64_t a0 = c * L.K, a1 = std::min(na, a0 + L.K);
-            const size_t bytes = (a1 - a0) * pangle;
+            const int64_t nang = a1 - a0;
             // device buffer j is free once the kernel two chunks back has read it
             CT_HIP(hipStreamWaitEvent(S.h2d, ev_k.e[j], 0));
+            if (c < 2) {
+                if (b0 > 0) CT_HIP(hipMemset2DAsync(dbuf[j].p, pangle, 0, b0 * rowb, L.K, S.h2d));
+                if (b1 < nv) CT_HIP(hipMemset2DAsync((char *)dbuf[j].p + b1 * rowb, pangle, 0, (nv - b1) * rowb, L.K, S.h2d));
+            }
             const void *from = (const char *)h_proj + a0 * pangle;
             if (!proj_pinned) {
                 if (h2d_used[j]) CT_HIP(hipEventSynchronize(ev_h2d.e[j]));
                 auto b = clk::now();
-                par_memcpy(sin[j].p, from, bytes);
+                host_rows(sin[j].p, from, pangle, rowb, b0, b1, nang);
                 st.t_stage_s += secs(b, clk::now());
                 from = sin[j].p;
             }
-            CT_HIP(hipMemcpyAsync(dbuf[j].p, from, bytes, hipMemcpyHostToDevice, S.h2d));
+            if ((s = copy_rows(dbuf[j].p, from, pangle, rowb, b0, b1, nang, hipMemcpyHostToDevice, S.h2d)) != CT_OK)
+                return s;
             CT_HIP(hipEventRecord(ev_h2d.e[j], S.h2d));
             h2d_used[j] = true;
-            st.bytes_h2d += (double)bytes;
+            st.bytes_h2d += (double)((b1 - b0) * rowb * nang);
             CT_HIP(hipStreamWaitEvent(S.comp, ev_h2d.e[j], 0));
             CT_HIP(hipEventRecord(tk0.e[c], S.comp));
             const void *bp_in = dbuf[j].p;
