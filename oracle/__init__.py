@@ -19,13 +19,13 @@ FDK reconstruction (cosine weight, ramp filter, FDK-weighted backprojection).
 from .core import (Geometry, W_FDK, W_PM, bp, bp_transpose, bp_voxels, get_threads,
                    interp_fwd, interp_ray, interp_rays, ray_endpoints, set_threads, siddon_adj,
                    siddon_adj_voxels, siddon_fwd, siddon_ray, siddon_rays, siddon_segments, load)
-from .algos import (cgls, div3, fdk, fdk_filter, grad3, os_sart, ramp_taps, rof_chambolle, sart, tv_grad, tv_value,
-                    tv_steps, tv_steps_split)
+from .algos import (cgls, div3, fdk, fdk_filter, grad3, os_sart, ramp_taps, rof_chambolle, rof_chambolle_split, sart,
+                    tv_grad, tv_value, tv_steps, tv_steps_split)
 
 __all__ = [
     "Geometry", "W_FDK", "W_PM", "bp", "bp_transpose", "bp_voxels", "get_threads",
     "interp_fwd", "interp_ray", "interp_rays", "ray_endpoints", "set_threads", "siddon_adj",
     "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "siddon_segments", "load", "cgls", "fdk", "fdk_filter",
     "os_sart", "ramp_taps", "sart", "tv_grad", "tv_value", "tv_steps", "tv_steps_split", "grad3", "div3",
-    "rof_chambolle",
+    "rof_chambolle", "rof_chambolle_split",
 ]

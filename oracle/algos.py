@@ -253,6 +253,36 @@ def tv_steps_split(x, nsteps, lam, slab, depth, eps=1e-8, norm="split"):
     return x
 
 
+def rof_chambolle_split(f, lam, niter, slab, depth, tau=1.0 / 12.0, upper_extra=1):
+    """Chambolle's ROF iteration (rof_chambolle) run split into slabs of `slab` axial slices that
+    carry halo slices of their neighbours (Section 2.3's splitting of the TV minimisers for images
+    larger than the device): `depth` below and `depth + upper_extra` above.  Rounds of up to `depth`
+    iterations: every slab copies f and p over its slices and halo from the state at the round's
+    start, iterates on its copy with the array's ends treated as the image's ends, and writes back
+    its own slices of p.  The new p at a slice reads p one slice either side, so a wrong end value
+    spoils one more slice per iteration, and at the upper end two in the first (the forward
+    difference there reads the slice above the copy): with upper_extra = 1 the slab's own slices
+    equal the whole-image iteration after `depth` iterations, and no quantity summed over the image
+    is needed.  Then u = f - lam div p from the final p.  Axis 0 of f is the slice axis."""
+    f = np.asarray(f, dtype=np.float64)
+    nz = f.shape[0]
+    p = np.zeros((3,) + f.shape)
+    done = 0
+    while done < niter:
+        k = min(depth, niter - done)
+        start = p.copy()
+        for o0 in range(0, nz, slab):
+            o1 = min(nz, o0 + slab)
+            m0, m1 = max(0, o0 - depth), min(nz, o1 + depth + upper_extra)
+            loc, fl = start[:, m0:m1].copy(), f[m0:m1]
+            for _ in range(k):
+                g = grad3(div3(loc) - fl / lam)
+                loc = (loc + tau * g) / (1.0 + tau * np.sqrt(np.sum(g * g, axis=0)))
+            p[:, o0:o1] = loc[:, o0 - m0:o1 - m0]
+        done += k
+    return f - lam * div3(p)
+
+
 def grad3(u):
     """Forward differences on a unit grid along each axis, zero at the last index (the gradient of
     the TV and ROF models); returns an array of shape (3,) + u.shape, axis order of u."""

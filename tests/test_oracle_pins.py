@@ -808,6 +808,20 @@ def test_R3_rof_keeps_the_mean_and_constant_images(orc):
     np.testing.assert_array_equal(orc.rof_chambolle(np.full((4, 5, 6), 0.3), 0.1, 20), np.full((4, 5, 6), 0.3))
 
 
+def test_R4_split_rof_equals_the_whole_image_iteration(orc):
+    """Chambolle's step is local (p at a slice depends on p one slice either side) and needs no
+    image-wide sum, so slabs whose halos cover the iterations of a round reproduce the whole-image
+    iteration; the upper halo needs one slice more, and without it the slabs' own slices go wrong."""
+    rng = np.random.default_rng(3)
+    f = ((rng.uniform(0, 1, (23, 9, 11)) > 0.6) * 1.0 + 0.1 * rng.standard_normal((23, 9, 11)))
+    ref = orc.rof_chambolle(f, 0.2, 13)
+    for slab, depth in ((23, 13), (7, 4), (5, 1), (1, 3), (4, 13), (6, 5)):
+        np.testing.assert_allclose(orc.rof_chambolle_split(f, 0.2, 13, slab, depth), ref, rtol=0, atol=1e-14)
+    for slab, depth in ((7, 4), (5, 1)):
+        bad = orc.rof_chambolle_split(f, 0.2, 13, slab, depth, upper_extra=0)
+        assert np.abs(bad - ref).max() > 1e-7
+
+
 def test_stored_siddon_piece_count_reproduces():
     """The stored gather-model unit of the Siddon projector (pieces per voxel-projection at the
     512^3 / 360 / 512^2 workload) is reproduced by the oracle on an independent seeded sample of
