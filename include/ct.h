@@ -308,6 +308,21 @@ ct_status ct_tv_steps_host(const ct_geometry *geometry, float *h_x, int32_t nste
 ct_status ct_rof_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes);
 ct_status ct_rof(const ct_geometry *geometry, void *d_x, int32_t niter, double lambda, double tau, void *d_workspace,
                  void *stream);
+/* The same ROF iteration on an image in host memory, under device_cap_bytes (Section 2.3: the ROF
+ * minimiser holds five image copies, f, the three components of the dual field p and w, and is split
+ * through host memory when they do not fit).  The dual field p lives in h_workspace (host, pageable
+ * or pinned, at least ct_rof_host_workspace_bytes = 3 images of FP32).  Rounds of up to halo_depth
+ * iterations: each axial slab is uploaded with halo_depth halo slices below and halo_depth + 1 above
+ * (the forward difference at a slab's top reads the slice above), iterated on the device, and its
+ * own slices of p written back; a last pass forms u = f - lambda div p.  Chambolle's step needs no
+ * sum over the image, so the result equals ct_rof bit for bit for any slab height and depth.
+ * h_x: host FP32 volume of the geometry's nVoxel shape, in: f, out: u.  Synchronous.  stats (may be
+ * NULL): n_slabs, slab_slices, bytes moved, t_total_s.  Errors: as ct_rof, CT_ERR_ARG for a NULL
+ * workspace or halo_depth outside [1, 4096], CT_ERR_CAP for a cap below one slice with its halos
+ * and buffers (64 MiB reserve). */
+ct_status ct_rof_host_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes);
+ct_status ct_rof_host(const ct_geometry *geometry, float *h_x, int32_t niter, double lambda, double tau,
+                      int32_t halo_depth, void *h_workspace, uint64_t device_cap_bytes, ct_ooc_stats *stats);
 
 /* ---------------------------------------------------------------------------------------------
  * Small device utilities used by the algorithms, exported for callers that compose their own. */

@@ -79,6 +79,8 @@ SIGNATURES = {
     "ct_tv_steps_host": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _I32, _U64, C.POINTER(ct_ooc_stats)],
     "ct_rof_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
     "ct_rof": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _P, _P],
+    "ct_rof_host_workspace_bytes": [C.POINTER(ct_geometry), C.POINTER(_U64)],
+    "ct_rof_host": [C.POINTER(ct_geometry), _P, _I32, _D, _D, _I32, _P, _U64, C.POINTER(ct_ooc_stats)],
     "ct_dot": [_P, _P, _INT, _I64, _P, _P],
     "ct_convert": [_P, _INT, _P, _INT, _I64, _P],
     "ct_last_error": [],
@@ -261,6 +263,19 @@ def ct_rof_workspace_bytes(geometry: ct_geometry) -> int:
 def ct_rof(geometry: ct_geometry, d_x, niter, lam, tau, d_workspace=0, stream=0):
     return _check(lib().ct_rof(C.byref(geometry), d_x, niter, float(lam), float(tau), d_workspace or None,
                                stream or None))
+
+
+def ct_rof_host_workspace_bytes(geometry: ct_geometry) -> int:
+    b = _U64()
+    _check(lib().ct_rof_host_workspace_bytes(C.byref(geometry), C.byref(b)))
+    return b.value
+
+
+def ct_rof_host(geometry: ct_geometry, h_x, niter, lam, tau, halo_depth, h_workspace, device_cap_bytes) -> ct_ooc_stats:
+    s = ct_ooc_stats()
+    _check(lib().ct_rof_host(C.byref(geometry), h_x, niter, float(lam), float(tau), int(halo_depth), h_workspace,
+                             int(device_cap_bytes), C.byref(s)))
+    return s
 
 
 def ct_dot(d_a, d_b, dtype, n, d_out, stream=0):

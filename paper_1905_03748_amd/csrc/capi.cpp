@@ -361,6 +361,24 @@ ct_status ct_rof(const ct_geometry *geometry, void *d_x, int32_t niter, double l
     return rof_run(*geometry, d_x, niter, lambda, tau, d_workspace, (hipStream_t)stream);
 }
 
+ct_status ct_rof_host_workspace_bytes(const ct_geometry *geometry, uint64_t *bytes) {
+    if (!geometry || !bytes) return fail(CT_ERR_ARG, "ct_rof_host_workspace_bytes: null pointer");
+    *bytes = rof_host_workspace(*geometry);
+    return CT_OK;
+}
+
+ct_status ct_rof_host(const ct_geometry *geometry, float *h_x, int32_t niter, double lambda, double tau,
+                      int32_t halo_depth, void *h_workspace, uint64_t device_cap_bytes, ct_ooc_stats *stats) {
+    if (!geometry || !h_x || !h_workspace) return fail(CT_ERR_ARG, "ct_rof_host: null pointer");
+    if (niter < 0) return fail(CT_ERR_ARG, "ct_rof_host: niter must be >= 0");
+    if (!(lambda > 0) || !std::isfinite(lambda) || !(tau > 0) || !std::isfinite(tau))
+        return fail(CT_ERR_ARG, "ct_rof_host: need finite lambda > 0 and tau > 0");
+    if (halo_depth < 1 || halo_depth > 4096) return fail(CT_ERR_ARG, "ct_rof_host: halo_depth must be in [1, 4096]");
+    for (int a = 0; a < 3; ++a)
+        if (geometry->nVoxel[a] <= 0) return fail(CT_ERR_GEOMETRY, "ct_rof_host: voxel counts must be positive");
+    return rof_host_run(*geometry, h_x, niter, lambda, tau, halo_depth, (float *)h_workspace, device_cap_bytes, stats);
+}
+
 ct_status ct_dot(const void *d_a, const void *d_b, ct_dtype dtype, int64_t n, double *d_out, void *stream) {
     if (!d_a || !d_b || !d_out) return fail(CT_ERR_ARG, "ct_dot: null pointer");
     if (n < 0) return fail(CT_ERR_ARG, "ct_dot: negative length");

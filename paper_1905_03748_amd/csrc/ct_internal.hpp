@@ -145,6 +145,10 @@ ct_status tv_run(const ct_geometry &g, void *x, ct_dtype vt, int32_t nsteps, dou
 size_t tv_workspace(const ct_geometry &g, ct_dtype vt);
 ct_status rof_run(const ct_geometry &g, void *x, int32_t niter, double lambda, double tau, void *work, hipStream_t st);
 size_t rof_workspace(const ct_geometry &g);
+// the same on a host image; hp: host workspace of rof_host_workspace bytes (the dual field)
+ct_status rof_host_run(const ct_geometry &g, float *hx, int32_t niter, double lambda, double tau, int32_t depth,
+                       float *hp, uint64_t cap, ct_ooc_stats *stats);
+size_t rof_host_workspace(const ct_geometry &g);
 ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double lambda, double eps, int32_t depth,
                       uint64_t cap, ct_ooc_stats *stats);
 // FDK reconstruction (kern_fdk.hip): weighted, ramp-filtered FP32 rows of the angles [a0, a1)

@@ -832,4 +832,129 @@ ct_status tv_host_run_halo(const ct_geometry &g, float *hx, int32_t nsteps, doub
     return CT_OK;
 }
 
+// The ROF iteration of rof_run on an image in host memory (Section 2.3: the minimiser holds five
+// image copies, f, the dual field p and w, and its image splits stream through host memory).  The
+// dual field lives in the caller's host workspace (three images).  Rounds of up to `depth`
+// iterations: each slab uploads f and p over its slices with `depth` halo slices below and
+// depth + 1 above, iterates on its copy with the copy's ends treated as the image's ends, and writes
+// back its own slices of p.  A wrong end value spoils one more slice per iteration (two at the upper
+// end in the first, where the forward difference reads the slice above), so the own slices equal
+// the whole-image iteration bit for bit: the step needs no sum over the image.  In a round every
+// slab starts from the state at the round's start: its lower halo is a device copy of the slices
+// below, taken before their update.  A last pass forms u = f - lam div p slab by slab.
+size_t rof_host_workspace(const ct_geometry &g) {
+    return (size_t)3 * g.nVoxel[0] * g.nVoxel[1] * g.nVoxel[2] * sizeof(float);
+}
+
+ct_status rof_host_run(const ct_geometry &g, float *hx, int32_t niter, double lambda, double tau, int32_t depth,
+                       float *hp, uint64_t cap, ct_ooc_stats *stats) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int nx = (int)g.nVoxel[0], ny = (int)g.nVoxel[1];
+    const int64_t nz = g.nVoxel[2];
+    const int64_t d = depth;
+    const int64_t slice = (int64_t)nx * ny;
+    const int64_t nvox = slice * nz;
+    const uint64_t sb = (uint64_t)slice * sizeof(float);
+    // device: f, px, py, pz and w over the slab with its halos, and the next slab's lower halo of p
+    const uint64_t avail = cap > TV_RESERVE ? (cap - TV_RESERVE) / sb : 0;
+    if (avail < (uint64_t)(5 * (2 * d + 2) + 3 * d))
+        return fail(CT_ERR_CAP, "device memory cap is below one slab slice plus halos and buffers");
+    int64_t h = (int64_t)((avail - 3 * d) / 5) - 2 * d - 1;
+    h = std::max<int64_t>(1, std::min<int64_t>(h, nz));
+    const int64_t nsp = (nz + h - 1) / h;
+    h = (nz + nsp - 1) / nsp;
+    const int64_t L = std::min<int64_t>(nz, h + 2 * d + 1);  // slices of the largest copy
+    ct_ooc_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.n_slabs = (int32_t)nsp;
+    st.slab_slices = (int32_t)h;
+    OwnStream S;
+    CT_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
+    DevMem fm, pm[3], wm, sm;
+    CT_HIP(hipMalloc(&fm.p, (size_t)L * sb));
+    for (auto &b : pm) CT_HIP(hipMalloc(&b.p, (size_t)L * sb));
+    CT_HIP(hipMalloc(&wm.p, (size_t)L * sb));
+    CT_HIP(hipMalloc(&sm.p, (size_t)3 * d * sb));
+    float *fb = (float *)fm.p, *wb = (float *)wm.p, *sv = (float *)sm.p;
+    float *pb[3] = {(float *)pm[0].p, (float *)pm[1].p, (float *)pm[2].p};
+    const hipStream_t s = S.s;
+    auto up = [&](float *dst, const float *src, int64_t n_sl) -> ct_status {
+        if (n_sl <= 0) return CT_OK;
+        CT_HIP(hipMemcpyAsync(dst, src, (size_t)n_sl * sb, hipMemcpyHostToDevice, s));
+        st.bytes_h2d += (double)n_sl * sb;
+        return CT_OK;
+    };
+    auto down = [&](float *dst, const float *src, int64_t n_sl) -> ct_status {
+        CT_HIP(hipMemcpyAsync(dst, src, (size_t)n_sl * sb, hipMemcpyDeviceToHost, s));
+        st.bytes_d2h += (double)n_sl * sb;
+        return CT_OK;
+    };
+    ct_status e = CT_OK;
+    bool first = true;
+    for (int32_t done = 0; done < niter;) {
+        const int64_t k = std::min<int64_t>(d, niter - done);
+        for (int64_t n = 0; n < nsp; ++n) {
+            const int64_t o0 = n * h, o1 = std::min(nz, o0 + h);
+            const int64_t m0 = std::max<int64_t>(0, o0 - d), m1 = std::min(nz, o1 + d + 1), len = m1 - m0;
+            if ((e = up(fb, hx + m0 * slice, len)) != CT_OK) return e;
+            for (int c = 0; c < 3; ++c) {
+                if (first) {  // p = 0 at the start
+                    hipLaunchKernelGGL(k_fill_zero, dim3(ew_grid(len * slice)), dim3(EW_THREADS), 0, s, pb[c], len * slice);
+                    CT_HIP(hipGetLastError());
+                } else {
+                    if ((e = up(pb[c] + (o0 - m0) * slice, hp + c * nvox + o0 * slice, m1 - o0)) != CT_OK) return e;
+                    if (o0 > m0)
+                        CT_HIP(hipMemcpyAsync(pb[c], sv + c * d * slice, (size_t)(o0 - m0) * sb, hipMemcpyDeviceToDevice, s));
+                }
+                if (n + 1 < nsp) {  // the next slab's lower halo, as it stands at the round's start
+                    const int64_t n0 = std::max<int64_t>(0, o1 - d);
+                    CT_HIP(hipMemcpyAsync(sv + c * d * slice, pb[c] + (n0 - m0) * slice, (size_t)(o1 - n0) * sb,
+                                          hipMemcpyDeviceToDevice, s));
+                }
+            }
+            const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)len);
+            for (int64_t i = 0; i < k; ++i) {
+                hipLaunchKernelGGL(k_rof_w, grid, dim3(256), 0, s, (const float *)fb, pb[0], pb[1], pb[2], wb, nx, ny,
+                                   (int)len, (float)(1.0 / lambda));
+                hipLaunchKernelGGL(k_rof_p, grid, dim3(256), 0, s, (const float *)wb, pb[0], pb[1], pb[2], nx, ny,
+                                   (int)len, (float)tau);
+                CT_HIP(hipGetLastError());
+            }
+            for (int c = 0; c < 3; ++c)
+                if ((e = down(hp + c * nvox + o0 * slice, pb[c] + (o0 - m0) * slice, o1 - o0)) != CT_OK) return e;
+            CT_HIP(hipStreamSynchronize(s));
+        }
+        first = false;
+        done += (int32_t)k;
+        if (tv_verbose()) {
+            std::fprintf(stderr, "[ct ooc rof] %d of %d iterations done at %.1f s\n", done, niter,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+            std::fflush(stderr);
+        }
+    }
+    // u = f - lam div p: the divergence at a slice reads p there and one slice below, and is the
+    // interior form only below the copy's top, so each slab takes one slice either side
+    for (int64_t n = 0; n < nsp; ++n) {
+        const int64_t o0 = n * h, o1 = std::min(nz, o0 + h);
+        const int64_t m0 = std::max<int64_t>(0, o0 - 1), m1 = std::min(nz, o1 + 1), len = m1 - m0;
+        if ((e = up(fb, hx + m0 * slice, len)) != CT_OK) return e;
+        for (int c = 0; c < 3; ++c) {
+            if (niter == 0) {
+                hipLaunchKernelGGL(k_fill_zero, dim3(ew_grid(len * slice)), dim3(EW_THREADS), 0, s, pb[c], len * slice);
+                CT_HIP(hipGetLastError());
+            } else if ((e = up(pb[c], hp + c * nvox + m0 * slice, len)) != CT_OK) {
+                return e;
+            }
+        }
+        const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)len);
+        hipLaunchKernelGGL(k_rof_u, grid, dim3(256), 0, s, fb, pb[0], pb[1], pb[2], nx, ny, (int)len, (float)lambda);
+        CT_HIP(hipGetLastError());
+        if ((e = down(hx + o0 * slice, fb + (o0 - m0) * slice, o1 - o0)) != CT_OK) return e;
+        CT_HIP(hipStreamSynchronize(s));
+    }
+    st.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = st;
+    return CT_OK;
+}
+
 }  // namespace ct

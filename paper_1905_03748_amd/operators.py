@@ -267,6 +267,22 @@ def rof(geometry: dict, x: torch.Tensor, niter: int, lam: float, tau: float = 1.
     return x
 
 
+def rof_host(geometry: dict, x: torch.Tensor, niter: int, lam: float, tau: float = 1.0 / 12.0, halo_depth: int = 8,
+             cap_bytes=32 << 30, workspace: torch.Tensor | None = None) -> dict:
+    """ROF denoising in place on the FP32 host volume x under a device memory cap (slabs with halos
+    halo_depth deep, the dual field in a host workspace of three volumes, allocated if None)."""
+    nx, ny, nz = (int(v) for v in geometry["nVoxel"])
+    if x.device.type != "cpu" or not x.is_contiguous() or x.dtype != torch.float32 or tuple(x.shape) != (nz, ny, nx):
+        raise ValueError(f"x must be a contiguous FP32 host tensor of shape {(nz, ny, nx)}")
+    g = A.make_geometry(geometry)
+    need = A.ct_rof_host_workspace_bytes(g)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8)
+    if workspace.device.type != "cpu" or not workspace.is_contiguous() or workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace must be a contiguous host tensor of at least {need} bytes")
+    return A.ct_rof_host(g, x.data_ptr(), niter, lam, tau, halo_depth, workspace.data_ptr(), cap_bytes).as_dict()
+
+
 def rof_workspace_bytes(geometry: dict) -> int:
     return A.ct_rof_workspace_bytes(A.make_geometry(geometry))
 

@@ -64,3 +64,47 @@ def test_rof_edge_cases():
         assert e.value.status == CT_ERR_ARG
     with pytest.raises(ValueError):
         rof(g, y, 1, 0.1, workspace=torch.empty(16, dtype=torch.uint8, device=DEV))
+
+
+def _rof_cap(nx, ny, h, d):
+    """A device cap that leaves ct_rof_host slabs of exactly h slices at halo depth d."""
+    sb = nx * ny * 4
+    return (64 << 20) + sb * (5 * (h + 2 * d + 1) + 3 * d)
+
+
+@pytest.mark.parametrize("h,d", [(23, 13), (7, 4), (3, 1), (1, 3), (5, 13), (10, 2)])
+def test_rof_host_equals_resident(orc, h, d):
+    """ct_rof_host (dual field in host memory, slabs of h slices with halos d below and d + 1 above,
+    rounds of d iterations) equals the resident ct_rof bit for bit, for any slab height and depth."""
+    from paper_1905_03748_amd.operators import rof_host
+    nz, ny, nx = 23, 17, 31
+    rng = np.random.default_rng(85)
+    f = (rng.uniform(0, 1, (nz, ny, nx)) > 0.7).astype(np.float32) * 0.8 + \
+        0.05 * rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    geo = _geo(nx, ny, nz)
+    ref = torch.from_numpy(f).to(DEV)
+    rof(geo, ref, 13, 0.1)
+    ref = ref.cpu()
+    x = torch.from_numpy(f.copy())
+    say(f"[rof host] slabs of {h} slices, depth {d}, 13 iterations")
+    st = rof_host(geo, x, 13, 0.1, halo_depth=d, cap_bytes=_rof_cap(nx, ny, h, d))
+    assert st["n_slabs"] == -(-nz // min(h, nz)), st
+    assert torch.equal(x, ref), float((x - ref).abs().max())
+    e = rel_l2(x.numpy(), orc.rof_chambolle_split(f.astype(np.float64), 0.1, 13, h, d))
+    assert e <= 1e-5
+
+
+def test_rof_host_zero_iterations_and_errors():
+    from paper_1905_03748_amd import _abi as A
+    from paper_1905_03748_amd.operators import rof_host
+    nz, ny, nx = 6, 5, 7
+    f = np.random.default_rng(86).uniform(0, 1, (nz, ny, nx)).astype(np.float32)
+    x = torch.from_numpy(f.copy())
+    rof_host(_geo(nx, ny, nz), x, 0, 0.1, halo_depth=2, cap_bytes=_rof_cap(nx, ny, 2, 2))
+    assert torch.equal(x, torch.from_numpy(f))
+    with pytest.raises(A.CtError) as e:
+        rof_host(_geo(nx, ny, nz), x, 3, 0.1, halo_depth=0)
+    assert e.value.status == A.CT_ERR_ARG
+    with pytest.raises(A.CtError) as e:
+        rof_host(_geo(nx, ny, nz), x, 3, 0.1, halo_depth=2, cap_bytes=(64 << 20) + 10)
+    assert e.value.status == A.CT_ERR_CAP
