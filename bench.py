@@ -9,7 +9,9 @@ The roofline entry is for the dominant kernel of the step, with algorithmic byte
 gather model (bytes each unit of work must read if nothing were reused):
   Siddon forward      segments * 4 B, 1.133 segments per voxel.proj at this workload
   FDK backprojection  4 bilinear taps * 4 B = 16 B per voxel.proj
-divided by the kernel's average duration measured with HIP events on its stream.
+divided by the kernel's average duration measured with HIP events on its stream.  The model counts no
+reuse, so the caches can carry a kernel past 100 % of it; the bytes that actually leave L2, and the
+unit that the counters show busiest, are printed beside it from the committed counter record.
 """
 from __future__ import annotations
 
@@ -38,9 +40,11 @@ def kernel_source_hash(name):
 
 
 def recorded_traffic(kernel_key):
-    """HBM traffic of a kernel per launch from the committed counter runs (profiles/traffic.json):
-    FETCH_SIZE and WRITE_SIZE scaled by what the same counters read for a plain copy of known
-    size.  None when the kernel's source has changed since the counters were taken."""
+    """Counter figures of a kernel per launch from the committed counter runs (profiles/traffic.json):
+    bytes between L2 and the memory fabric summed over the size-resolved request counters
+    (32/64/128-byte reads, 32/64-byte writes), with no calibration factor, plus L2 hit rate and the
+    busy fractions of the vector ALU and the texture-address unit.  None when the kernel's source has
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -91,7 +95,16 @@ def cpu_baseline(w, vol, proj_sample_s=8.0, bp_sample_s=8.0):
         m = int(m * min(8.0, max(1.5, 1.2 * bp_sample_s / max(dt_b, 1e-3))))
     t_bp_full = dt_b * nvox_total / m
     value = 2.0 * w.voxel_proj / (t_fwd_full + t_bp_full) / 1e9
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": value, "unit": "Gvoxel·proj/s", "cores": threads, "kind": "oracle",
+            "host": {"cpu_model": cpu, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()},
             "sample": f"Siddon on {nr} seeded rays ({dt_f:.1f} s) and FDK backprojection on {m} seeded voxels "
                       f"({dt_b:.1f} s) of the 512^3/360/512^2 workload, extrapolated to one full Ax + A^T y"}
 
@@ -379,6 +392,44 @@ def ooc_tv_bench(dev, cap_gib=32, nsteps=2):
     return out
 
 
+def ooc_rof_bench(dev, cap_gib=32, n=2048):
+    """The ROF minimiser (Chambolle's projection) on an n^3 FP32 phantom in pageable host memory under
+    a cap_gib GiB device cap, its dual field in a host workspace of three volumes: halo depths 8 and
+    60 (iterations per round).  n = 2048 because at 3072^3 the image and its dual field need 432 GB
+    of host memory."""
+    import torch
+    from paper_1905_03748_amd import inputs
+    from paper_1905_03748_amd.operators import rof_host
+
+    base = inputs.workload("ooc")
+    w = inputs.scaled_workload(base, (n, n, n), (n, n), 1, name=f"rof_{n}")
+    ells = inputs.ellipsoids(base)
+    nx, ny, nz = w.nvox
+    vol = torch.from_numpy(np.empty((nz, ny, nx), dtype=np.float32))
+    log(f"[ooc rof] building the {n}^3 phantom slab by slab")
+    for z0 in range(0, nz, 256):
+        h = min(256, nz - z0)
+        ws = inputs.Workload("slab", (nx, ny, h), w.dvox, w.ndet, w.ddet, 1, 0, 0,
+                             off_origin=(0.0, 0.0, (z0 + h / 2.0 - nz / 2.0) * w.dvox[2]))
+        vol[z0:z0 + h].copy_(inputs.voxelize_torch(ws, ells, device=dev))
+        torch.cuda.synchronize()
+    work = torch.empty(3 * vol.numel() * 4, dtype=torch.uint8)
+    out = {"workload": f"{n}^3 FP32 phantom ({vol.numel() * 4 / 2**30:.0f} GiB), pageable host memory; dual field "
+                       f"in a {work.numel() / 2**30:.0f} GiB host workspace", "cap_gib": cap_gib}
+    for depth, iters in ((8, 16), (60, 60)):
+        log(f"[ooc rof] halo depth {depth}: {iters} iterations")
+        st = rof_host(w.geometry_dict(), vol, iters, 0.05, halo_depth=depth, cap_bytes=cap_gib << 30, workspace=work)
+        r = {"iterations": iters}
+        r.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()
+                  if k in ("n_slabs", "slab_slices", "bytes_h2d", "bytes_d2h", "t_total_s")})
+        r["s_per_iteration"] = round(st["t_total_s"] / iters, 3)
+        r["host_link_gbs"] = round((st["bytes_h2d"] + st["bytes_d2h"]) / st["t_total_s"] / 1e9, 2)
+        out[f"halo_{depth}"] = r
+        log(f"[ooc rof] {r}")
+    del vol, work
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +441,7 @@ def main():
     ap.add_argument("--precision", action="store_true", help="print the 16-bit storage report instead")
     ap.add_argument("--ooc", action="store_true", help="print the 3072^3 out-of-core report instead")
     ap.add_argument("--ooc-tv", action="store_true", help="print the 3072^3 out-of-core TV report instead")
+    ap.add_argument("--ooc-rof", action="store_true", help="print the 2048^3 out-of-core ROF report instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (ct_convert F32->F32) for HBM counter calibration")
     ap.add_argument("--profile-kernels", action="store_true",
@@ -415,6 +467,9 @@ def main():
         return
     if args.ooc_tv:
         print(json.dumps({"out_of_core_tv": ooc_tv_bench(dev)}), flush=True)
+        return
+    if args.ooc_rof:
+        print(json.dumps({"out_of_core_rof": ooc_rof_bench(dev)}), flush=True)
         return
     w = inputs.workload("medium")
     log(f"[bench] building phantom {w.nvox} with {w.n_ellipsoids} ellipsoids")
@@ -481,16 +536,27 @@ def main():
         "ops": {"siddon_fwd_ms": round(fwd_ms, 3), "fdk_bp_ms": round(bp_ms, 3),
                 "siddon_fwd_gvps": round(vp / (fwd_ms * 1e-3) / 1e9, 2),
                 "fdk_bp_gvps": round(vp / (bp_ms * 1e-3) / 1e9, 2)},
-        "roofline": {"bound": "hbm", "kernel": "k_siddon" if dom == "siddon" else "k_bp_voxel<FDK>",
-                     "byte_model": "gather model: %s B per voxel.proj" % round(BYTES_PER_VP[dom], 3),
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_siddon_col<float, float, 2>" if dom == "siddon" else "k_bp_lds<0, 37, float, float>",
+                     "byte_model": "gather model: %s B per voxel.proj x %.4g voxel.proj per launch"
+                                   % (round(BYTES_PER_VP[dom], 3), vp),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
     rec = recorded_traffic("siddon_fwd" if dom == "siddon" else "fdk_bp")
     if rec is not None:
-        gb = (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024 / 1e9
-        out["roofline"]["traffic"] = round(gb, 2)
-        out["roofline"]["traffic_unit"] = "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; %s)" % rec["profile"]
+        gb = (rec["read_bytes"] + rec["write_bytes"]) / 1e9
+        rl = out["roofline"]
+        rl["traffic"] = round(gb, 2)
+        rl["traffic_unit"] = ("GB per launch between L2 and the memory fabric (size-resolved TCC_EA0 read and "
+                              "write requests, no calibration factor; an upper bound on HBM bytes, since the "
+                              "last-level cache may serve some; %s)" % rec["profile"])
+        # what the counters say bounds the kernel: the busiest of the L2-miss stream (against HBM peak),
+        # the vector ALU and the texture-address unit that issues every gather
+        miss = gb / (dom_ms * 1e-3) / 1e3 / (HBM_PEAK_GBS / 1e3)
+        busy = {"texture_address_unit": rec["ta_busy"], "vector_alu": rec["valu"], "l2_miss_bytes_vs_hbm_peak": round(miss, 3)}
+        rl["limiter"] = {"unit": max(busy, key=busy.get), "busy": busy, "l2_hit": rec["l2_hit"],
+                         "counters_avg_ms": rec["avg_ms"]}
 
     if not args.no_extras:
         def timed(fn, reps=3):
