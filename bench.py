@@ -303,8 +303,8 @@ def precision_bench(dev, cgls_iters=20):
 def ooc_bench(dev, cap_gib=32):
     """3072^3 FP32 volume (108 GiB) and 3072 projections of 3072^2 (108 GiB) in pageable host memory
     (the streamer stages it through its pinned ring; a single 108 GiB pinned allocation is refused
-    on the GPU machines), device memory capped at cap_gib GiB: one out-of-core Siddon Ax and one FDK
-    A^T y, then the FDK reconstruction of the same projections."""
+    on the GPU machines), device memory capped at cap_gib GiB: one out-of-core Siddon Ax, one FDK and one
+    exact-adjoint A^T y, then the FDK reconstruction of the same projections."""
     import torch
     from paper_1905_03748_amd import inputs
     from paper_1905_03748_amd.operators import Plan
@@ -340,6 +340,11 @@ def ooc_bench(dev, cap_gib=32):
     out["backprojection"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
     out["backprojection"]["h2d_gbs"] = round(st["bytes_h2d"] / st["t_total_s"] / 1e9, 1)
     log(f"[ooc] backprojection done: {out['backprojection']}")
+    log("[ooc] exact adjoint")
+    st = plan.backproject_host(proj, vol, "adjoint", cap_bytes=cap)
+    out["adjoint"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    out["adjoint"]["gvps"] = round(w.voxel_proj / st["t_total_s"] / 1e9, 1)
+    log(f"[ooc] exact adjoint done: {out['adjoint']}")
     log("[ooc] FDK reconstruction")
     st = plan.fdk_host(proj, vol, cap_bytes=cap)
     out["fdk_reconstruction"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
