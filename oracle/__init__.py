@@ -12,18 +12,20 @@ Operators (plain C in ``ct_oracle.c``, loaded with ctypes):
   interp_fwd / interp_rays         trilinear-interpolated projector (Chou 2011, Section 2.1)
   bp / bp_voxels                   voxel-driven backprojection, FDK or pseudo-matched weights
                                    (Jia 2011, Section 2.2)
+Every operator takes the projections' views either as angles of a circular orbit or as an n x 12
+table of per-view source, detector centre and unit detector axes (C-arm, helical; Section 2.1).
 Algorithms (``algos.py``, numpy over the operators): CGLS, SART and OS-SART, TV steepest descent
 (whole and split), the ROF model by Chambolle's projection,
 FDK reconstruction (cosine weight, ramp filter, FDK-weighted backprojection).
 """
-from .core import (Geometry, W_FDK, W_PM, bp, bp_transpose, bp_voxels, get_threads,
+from .core import (Geometry, W_FDK, W_PM, bp, bp_transpose, bp_voxels, circular_views, get_threads,
                    interp_fwd, interp_ray, interp_rays, ray_endpoints, set_threads, siddon_adj,
                    siddon_adj_voxels, siddon_fwd, siddon_ray, siddon_rays, siddon_segments, load)
 from .algos import (cgls, div3, fdk, fdk_filter, grad3, os_sart, ramp_taps, rof_chambolle, rof_chambolle_split, sart,
                     tv_grad, tv_value, tv_steps, tv_steps_split)
 
 __all__ = [
-    "Geometry", "W_FDK", "W_PM", "bp", "bp_transpose", "bp_voxels", "get_threads",
+    "Geometry", "W_FDK", "W_PM", "bp", "bp_transpose", "bp_voxels", "circular_views", "get_threads",
     "interp_fwd", "interp_ray", "interp_rays", "ray_endpoints", "set_threads", "siddon_adj",
     "siddon_adj_voxels", "siddon_fwd", "siddon_ray", "siddon_rays", "siddon_segments", "load", "cgls", "fdk", "fdk_filter",
     "os_sart", "ramp_taps", "sart", "tv_grad", "tv_value", "tv_steps", "tv_steps_split", "grad3", "div3",

@@ -62,7 +62,8 @@ SART_VOXEL_MIN = 1e-6
 def sart(geo: core.Geometry, angles, b, niter, lam=1.0, x0=None):
     """SART (Andersen & Kak 1984; the OS-SART family of Section 3.2 with one angle per block).
 
-    For each sweep, for each angle t in natural order:
+    For each sweep, for each projection t in natural order (`angles`: angles of a circular orbit
+    or an n x 12 table of views, as the operators take):
         W_p = 1/(A_t 1)_p,  V_j = (B_t 1)_j,  x += lam * B_t(W * (b_t - A_t x)) / V
     with A the Siddon projector and B the FDK-weighted voxel backprojector.
     """
@@ -183,6 +184,8 @@ def fdk_filter(geo: core.Geometry, angles, proj):
     The reconstruction is then the FDK-weighted backprojection of q, see `fdk`.
     """
     angles = np.asarray(angles, dtype=np.float64)
+    if angles.ndim != 1:
+        raise ValueError("the FDK reconstruction is defined for a circular orbit: give angles, not views")
     proj = np.asarray(proj, dtype=np.float64)
     nu, nv = geo.nDetector
     du, dv = geo.dDetector

@@ -80,7 +80,8 @@ def load():
         sig = {
             "orc_set_threads": (None, [C.c_int]),
             "orc_get_threads": (C.c_int, []),
-            "orc_ray_endpoints": (None, [g, d, d, d, pd, pd]),
+            "orc_ray_endpoints": (None, [g, pd, d, d, pd, pd]),
+            "orc_circular_views": (None, [g, pd, i64, pd]),
             "orc_siddon_ray": (d, [g, pd, pd, pd, pi]),
             "orc_interp_ray": (d, [g, pd, pd, pd, pi]),
             "orc_siddon_fwd": (None, [g, pd, i64, pd, pd, pi]),
@@ -117,6 +118,25 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def circular_views(geo: Geometry, angles):
+    """The per-view table (source, detector centre, e_u, e_v; n x 12) of a circular orbit."""
+    angles = _f64(np.atleast_1d(angles))
+    out = np.zeros((len(angles), 12))
+    load().orc_circular_views(C.byref(geo.c()), _pd(angles), len(angles), _pd(out))
+    return out
+
+
+def _views(geo: Geometry, angles):
+    """Views of the projections: a 1-D array of angles (circular orbit) or an n x 12 table of
+    per-view source, detector centre and unit detector axes e_u, e_v (mm), as given."""
+    a = np.asarray(angles, dtype=np.float64)
+    if a.ndim == 2 and a.shape[1] == 12:
+        return np.ascontiguousarray(a)
+    if a.ndim != 1:
+        raise ValueError("angles must be a 1-D array of angles or an n x 12 table of views")
+    return circular_views(geo, a)
+
+
 def set_threads(n: int):
     load().orc_set_threads(int(n))
 
@@ -125,10 +145,13 @@ def get_threads() -> int:
     return int(load().orc_get_threads())
 
 
-def ray_endpoints(geo: Geometry, theta: float, a: float, b: float):
+def ray_endpoints(geo: Geometry, theta, a: float, b: float):
+    """Source and pixel centre of pixel (a, b) in one view (an angle, or a 12-vector view)."""
+    v = np.asarray(theta, dtype=np.float64)
+    view = _views(geo, v.reshape(1, 12) if v.size == 12 else v.reshape(1))[0].copy()
     S = np.zeros(3)
     P = np.zeros(3)
-    load().orc_ray_endpoints(C.byref(geo.c()), float(theta), float(a), float(b), _pd(S), _pd(P))
+    load().orc_ray_endpoints(C.byref(geo.c()), _pd(view), float(a), float(b), _pd(S), _pd(P))
     return S, P
 
 
@@ -149,102 +172,102 @@ def interp_ray(geo: Geometry, S, P, vol):
 
 
 def siddon_fwd(geo: Geometry, angles, vol, return_counts=False):
-    angles = _f64(angles)
+    views = _views(geo, angles)
     vol = _f64(vol)
-    out = np.zeros(geo.proj_shape(len(angles)))
-    cnt = np.zeros(len(angles), dtype=np.int64)
-    load().orc_siddon_fwd(C.byref(geo.c()), _pd(angles), len(angles), _pd(vol), _pd(out), _pi(cnt))
+    out = np.zeros(geo.proj_shape(len(views)))
+    cnt = np.zeros(len(views), dtype=np.int64)
+    load().orc_siddon_fwd(C.byref(geo.c()), _pd(views), len(views), _pd(vol), _pd(out), _pi(cnt))
     return (out, cnt) if return_counts else out
 
 
 def siddon_rays(geo: Geometry, angles, ray_idx, vol):
     """Selected rays.  A C-contiguous FP32 volume is read in place (widened per element), so
     volumes too large to copy to FP64 can be sampled."""
-    angles = _f64(angles)
+    views = _views(geo, angles)
     idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
     out = np.zeros(len(idx))
     if vol.dtype == np.float32 and vol.flags["C_CONTIGUOUS"]:
-        load().orc_siddon_rays_f32(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx),
+        load().orc_siddon_rays_f32(C.byref(geo.c()), _pd(views), _pi(idx), len(idx),
                                    vol.ctypes.data_as(C.POINTER(C.c_float)), _pd(out))
         return out
     vol = _f64(vol)
-    load().orc_siddon_rays(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx), _pd(vol), _pd(out))
+    load().orc_siddon_rays(C.byref(geo.c()), _pd(views), _pi(idx), len(idx), _pd(vol), _pd(out))
     return out
 
 
 def siddon_segments(geo: Geometry, angles, ray_idx):
     """Number of Siddon pieces of selected rays (flat indices as siddon_rays)."""
-    angles = _f64(angles)
+    views = _views(geo, angles)
     idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
     out = np.zeros(len(idx), dtype=np.int64)
-    load().orc_siddon_segments(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx), _pi(out))
+    load().orc_siddon_segments(C.byref(geo.c()), _pd(views), _pi(idx), len(idx), _pi(out))
     return out
 
 
 def siddon_adj(geo: Geometry, angles, proj):
-    angles, proj = _f64(angles), _f64(proj)
+    views, proj = _views(geo, angles), _f64(proj)
     out = np.zeros(geo.vol_shape)
-    load().orc_siddon_adj(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), _pd(out))
+    load().orc_siddon_adj(C.byref(geo.c()), _pd(views), len(views), _pd(proj), _pd(out))
     return out
 
 
 def siddon_adj_voxels(geo: Geometry, angles, proj, vox_idx):
     """Selected voxels.  A C-contiguous FP32 projection array is read in place."""
-    angles = _f64(angles)
+    views = _views(geo, angles)
     idx = np.ascontiguousarray(vox_idx, dtype=np.int64)
     out = np.zeros(len(idx))
     if proj.dtype == np.float32 and proj.flags["C_CONTIGUOUS"]:
-        load().orc_siddon_adj_voxels_f32(C.byref(geo.c()), _pd(angles), len(angles),
+        load().orc_siddon_adj_voxels_f32(C.byref(geo.c()), _pd(views), len(views),
                                          proj.ctypes.data_as(C.POINTER(C.c_float)), _pi(idx), len(idx),
                                          _pd(out))
         return out
     proj = _f64(proj)
-    load().orc_siddon_adj_voxels(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), _pi(idx),
+    load().orc_siddon_adj_voxels(C.byref(geo.c()), _pd(views), len(views), _pd(proj), _pi(idx),
                                  len(idx), _pd(out))
     return out
 
 
 def interp_fwd(geo: Geometry, angles, vol, return_counts=False):
-    angles, vol = _f64(angles), _f64(vol)
-    out = np.zeros(geo.proj_shape(len(angles)))
-    cnt = np.zeros(len(angles), dtype=np.int64)
-    load().orc_interp_fwd(C.byref(geo.c()), _pd(angles), len(angles), _pd(vol), _pd(out), _pi(cnt))
+    views, vol = _views(geo, angles), _f64(vol)
+    out = np.zeros(geo.proj_shape(len(views)))
+    cnt = np.zeros(len(views), dtype=np.int64)
+    load().orc_interp_fwd(C.byref(geo.c()), _pd(views), len(views), _pd(vol), _pd(out), _pi(cnt))
     return (out, cnt) if return_counts else out
 
 
 def interp_rays(geo: Geometry, angles, ray_idx, vol):
-    angles, vol = _f64(angles), _f64(vol)
+    views, vol = _views(geo, angles), _f64(vol)
     idx = np.ascontiguousarray(ray_idx, dtype=np.int64)
     out = np.zeros(len(idx))
-    load().orc_interp_rays(C.byref(geo.c()), _pd(angles), _pi(idx), len(idx), _pd(vol), _pd(out))
+    load().orc_interp_rays(C.byref(geo.c()), _pd(views), _pi(idx), len(idx), _pd(vol), _pd(out))
     return out
 
 
 def bp(geo: Geometry, angles, proj, kind=W_FDK):
-    angles, proj = _f64(angles), _f64(proj)
+    views, proj = _views(geo, angles), _f64(proj)
     out = np.zeros(geo.vol_shape)
-    load().orc_bp(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), int(kind), _pd(out))
+    load().orc_bp(C.byref(geo.c()), _pd(views), len(views), _pd(proj), int(kind), _pd(out))
     return out
 
 
 def bp_voxels(geo: Geometry, angles, proj, vox_idx, kind=W_FDK):
     """Selected voxels.  A C-contiguous FP32 projection array is read in place."""
-    angles = _f64(angles)
+    views = _views(geo, angles)
     idx = np.ascontiguousarray(vox_idx, dtype=np.int64)
     out = np.zeros(len(idx))
     if proj.dtype == np.float32 and proj.flags["C_CONTIGUOUS"]:
-        load().orc_bp_voxels_f32(C.byref(geo.c()), _pd(angles), len(angles),
+        load().orc_bp_voxels_f32(C.byref(geo.c()), _pd(views), len(views),
                                  proj.ctypes.data_as(C.POINTER(C.c_float)), int(kind), _pi(idx), len(idx),
                                  _pd(out))
         return out
     proj = _f64(proj)
-    load().orc_bp_voxels(C.byref(geo.c()), _pd(angles), len(angles), _pd(proj), int(kind), _pi(idx),
+    load().orc_bp_voxels(C.byref(geo.c()), _pd(views), len(views), _pd(proj), int(kind), _pi(idx),
                          len(idx), _pd(out))
     return out
 
 
 def bp_transpose(geo: Geometry, angles, vol, kind=W_FDK):
-    angles, vol = _f64(angles), _f64(vol)
-    out = np.zeros(geo.proj_shape(len(angles)))
-    load().orc_bp_transpose(C.byref(geo.c()), _pd(angles), len(angles), _pd(vol), int(kind), _pd(out))
+    views, vol = _views(geo, angles), _f64(vol)
+    out = np.zeros(geo.proj_shape(len(views)))
+    load().orc_bp_transpose(C.byref(geo.c()), _pd(views), len(views), _pd(vol), int(kind), _pd(out))
     return out

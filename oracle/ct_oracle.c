@@ -8,11 +8,14 @@
  *
  * Conventions (the paper gives the scanner distances but no coordinate system, so these are our
  * readings, shared with the GPU path only through this written description):
- *   rotation axis z, mm, radians; voxel (i,j,k) centre at offOrigin + ((i-(Nx-1)/2)dx, ...);
- *   source S = DSO (cos t, sin t, 0); detector centre C = -(DSD-DSO)(cos t, sin t, 0);
- *   e_u = (-sin t, cos t, 0), e_v = (0,0,1); pixel (a,b) centre C + u_a e_u + v_b e_v with
- *   u_a = (a-(Nu-1)/2) du + offU, v_b = (b-(Nv-1)/2) dv + offV; one ray per pixel centre;
- *   volume layout vol[k][j][i], projection layout proj[angle][b][a].
+ *   mm, radians; voxel (i,j,k) centre at offOrigin + ((i-(Nx-1)/2)dx, ...); volume layout
+ *   vol[k][j][i], projection layout proj[view][b][a]; one ray per pixel centre.
+ *   Every operator takes one view per projection: source S, detector centre C and the detector's
+ *   unit axes e_u, e_v (orthonormal), 12 doubles.  Pixel (a,b) has its centre at
+ *   C + u_a e_u + v_b e_v with u_a = (a-(Nu-1)/2) du + offU, v_b = (b-(Nv-1)/2) dv + offV.
+ *   The circular orbit about z (orc_circular_views) is the view of angle t:
+ *   S = DSO (cos t, sin t, 0), C = -(DSD-DSO)(cos t, sin t, 0), e_u = (-sin t, cos t, 0),
+ *   e_v = (0,0,1).  Per-view tables also describe C-arm and helical scans (Section 2.1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -38,20 +41,41 @@ enum { ORC_W_FDK = 0, ORC_W_PM = 1 };
 /* ------------------------------------------------------------------------------------------ */
 /* geometry                                                                                     */
 
-static void source_pos(const orc_geom *g, double th, double S[3]) {
-    S[0] = g->DSO * cos(th);
-    S[1] = g->DSO * sin(th);
-    S[2] = 0.0;
+typedef struct {
+    double S[3], C[3], eu[3], ev[3];
+} orc_view;
+
+static const orc_view *view_at(const double *views, int64_t t) { return (const orc_view *)(views + 12 * t); }
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-static void pixel_pos(const orc_geom *g, double th, double a, double b, double P[3]) {
-    double c = cos(th), s = sin(th);
+/* The views of a circular orbit at the given angles (conventions above). */
+void orc_circular_views(const orc_geom *g, const double *angles, int64_t na, double *views) {
+    for (int64_t t = 0; t < na; ++t) {
+        double c = cos(angles[t]), s = sin(angles[t]);
+        double k = -(g->DSD - g->DSO);
+        double *v = views + 12 * t;
+        v[0] = g->DSO * c; v[1] = g->DSO * s; v[2] = 0.0;
+        v[3] = k * c;      v[4] = k * s;      v[5] = 0.0;
+        v[6] = -s;         v[7] = c;          v[8] = 0.0;
+        v[9] = 0.0;        v[10] = 0.0;       v[11] = 1.0;
+    }
+}
+
+static void source_pos(const orc_view *v, double S[3]) {
+    for (int a = 0; a < 3; ++a) S[a] = v->S[a];
+}
+
+static void pixel_pos(const orc_geom *g, const orc_view *v, double a, double b, double P[3]) {
     double u = (a - (g->ndet[0] - 1) / 2.0) * g->ddet[0] + g->offdet[0];
-    double v = (b - (g->ndet[1] - 1) / 2.0) * g->ddet[1] + g->offdet[1];
-    double k = -(g->DSD - g->DSO);
-    P[0] = k * c - u * s;
-    P[1] = k * s + u * c;
-    P[2] = v;
+    double w = (b - (g->ndet[1] - 1) / 2.0) * g->ddet[1] + g->offdet[1];
+    for (int x = 0; x < 3; ++x) P[x] = v->C[x] + u * v->eu[x] + w * v->ev[x];
 }
 
 static void box_bounds(const orc_geom *g, double lo[3], double hi[3]) {
@@ -61,9 +85,9 @@ static void box_bounds(const orc_geom *g, double lo[3], double hi[3]) {
     }
 }
 
-void orc_ray_endpoints(const orc_geom *g, double th, double a, double b, double *S, double *P) {
-    source_pos(g, th, S);
-    pixel_pos(g, th, a, b, P);
+void orc_ray_endpoints(const orc_geom *g, const double *view, double a, double b, double *S, double *P) {
+    source_pos((const orc_view *)view, S);
+    pixel_pos(g, (const orc_view *)view, a, b, P);
 }
 
 /* Slab clip of R(t) = S + t D, t in [0,1], against [lo,hi]; axes with |D_a| < 1e-12 L are
@@ -254,29 +278,39 @@ static void voxel_centre(const orc_geom *g, int64_t i, int64_t j, int64_t k, dou
     for (int a = 0; a < 3; ++a) X[a] = g->offorig[a] + (id[a] - (g->nvox[a] - 1) / 2.0) * g->dvox[a];
 }
 
-/* continuous detector indices (a*, b*) and the weight of voxel X at angle th */
-static void project_voxel(const orc_geom *g, double th, const double X[3], int kind, double *as,
+/* Continuous detector indices (a*, b*) and the weight of voxel X in view v.  The detector normal
+ * n = e_u x e_v points from the detector towards the source; L = (S - X).n is the voxel's depth
+ * from the source, DSD_v = (S - C).n the source's distance to the detector plane, and the ray from
+ * S through X meets that plane at S + (DSD_v / L)(X - S).  FDK weight (DSO_v / L)^2 with
+ * DSO_v = S.n, the source's distance to the plane through the origin parallel to the detector
+ * (the rotation axis's distance, DSO, in a circular orbit); pseudo-matched weight
+ * (dx dy dz)/(du dv) DSD_v^2 |SX| / L^3. */
+static void project_voxel(const orc_geom *g, const orc_view *v, const double X[3], int kind, double *as,
                           double *bs, double *w) {
-    double c = cos(th), s = sin(th);
-    double Ld = g->DSO - (X[0] * c + X[1] * s);
-    double m = g->DSD / Ld;
-    double us = m * (-X[0] * s + X[1] * c);
-    double vs = m * X[2];
+    double n[3], SX[3], SC[3], P[3];
+    cross3(v->eu, v->ev, n);
+    for (int a = 0; a < 3; ++a) {
+        SX[a] = X[a] - v->S[a];
+        SC[a] = v->C[a] - v->S[a];
+    }
+    double Ld = -dot3(SX, n);
+    double DSDv = -dot3(SC, n);
+    double m = DSDv / Ld;
+    for (int a = 0; a < 3; ++a) P[a] = v->S[a] + m * SX[a] - v->C[a];
+    double us = dot3(P, v->eu), vs = dot3(P, v->ev);
     *as = (us - g->offdet[0]) / g->ddet[0] + (g->ndet[0] - 1) / 2.0;
     *bs = (vs - g->offdet[1]) / g->ddet[1] + (g->ndet[1] - 1) / 2.0;
     if (kind == ORC_W_FDK) {
-        *w = (g->DSO / Ld) * (g->DSO / Ld);
+        double DSOv = dot3(v->S, n);
+        *w = (DSOv / Ld) * (DSOv / Ld);
     } else {
-        double S[3];
-        source_pos(g, th, S);
-        double dx = X[0] - S[0], dy = X[1] - S[1], dz = X[2] - S[2];
-        double SX = sqrt(dx * dx + dy * dy + dz * dz);
-        *w = (g->dvox[0] * g->dvox[1] * g->dvox[2]) / (g->ddet[0] * g->ddet[1]) * g->DSD * g->DSD *
-             SX / (Ld * Ld * Ld);
+        double SXn = sqrt(dot3(SX, SX));
+        *w = (g->dvox[0] * g->dvox[1] * g->dvox[2]) / (g->ddet[0] * g->ddet[1]) * DSDv * DSDv * SXn /
+             (Ld * Ld * Ld);
     }
 }
 
-static double bp_voxel(const orc_geom *g, const double *angles, int64_t na, const double *proj,
+static double bp_voxel(const orc_geom *g, const double *views, int64_t na, const double *proj,
                        const float *projf, int kind, int64_t i, int64_t j, int64_t k) {
     double X[3];
     voxel_centre(g, i, j, k, X);
@@ -284,7 +318,7 @@ static double bp_voxel(const orc_geom *g, const double *angles, int64_t na, cons
     double acc = 0.0;
     for (int64_t t = 0; t < na; ++t) {
         double as, bs, w;
-        project_voxel(g, angles[t], X, kind, &as, &bs, &w);
+        project_voxel(g, view_at(views, t), X, kind, &as, &bs, &w);
         double a0 = floor(as), b0 = floor(bs);
         double fa = as - a0, fb = bs - b0;
         int64_t ia = (int64_t)a0, ib = (int64_t)b0;
@@ -332,8 +366,8 @@ double orc_interp_ray(const orc_geom *g, const double *S, const double *P, const
     return interp_ray(g, S, P, vol, nsamp);
 }
 
-/* proj[t][b][a] = Siddon(ray(angles[t], a, b)) for every pixel; optional per-angle segment counts */
-void orc_siddon_fwd(const orc_geom *g, const double *angles, int64_t na, const double *vol,
+/* proj[t][b][a] = Siddon(ray(view t, a, b)) for every pixel; optional per-view segment counts */
+void orc_siddon_fwd(const orc_geom *g, const double *views, int64_t na, const double *vol,
                     double *proj, int64_t *seg_count_per_angle) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
     if (seg_count_per_angle) memset(seg_count_per_angle, 0, sizeof(int64_t) * na);
@@ -346,10 +380,10 @@ void orc_siddon_fwd(const orc_geom *g, const double *angles, int64_t na, const d
             int64_t t = r / nv, b = r % nv;
             double S[3], P[3];
             int64_t rowsegs = 0;
-            source_pos(g, angles[t], S);
+            source_pos(view_at(views, t), S);
             for (int64_t a = 0; a < nu; ++a) {
                 int64_t ns = 0;
-                pixel_pos(g, angles[t], (double)a, (double)b, P);
+                pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
                 proj[(t * nv + b) * nu + a] = siddon_core(g, S, P, vol, NULL, NULL, 0.0, -1, &ns, &sc);
                 rowsegs += ns;
             }
@@ -363,7 +397,7 @@ void orc_siddon_fwd(const orc_geom *g, const double *angles, int64_t na, const d
 }
 
 /* Selected rays only: ray_idx[n] are flat indices (t*Nv + b)*Nu + a into the projection array. */
-void orc_siddon_rays(const orc_geom *g, const double *angles, const int64_t *ray_idx, int64_t n,
+void orc_siddon_rays(const orc_geom *g, const double *views, const int64_t *ray_idx, int64_t n,
                      const double *vol, double *out) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
 #pragma omp parallel
@@ -375,8 +409,8 @@ void orc_siddon_rays(const orc_geom *g, const double *angles, const int64_t *ray
             int64_t r = ray_idx[q];
             int64_t a = r % nu, b = (r / nu) % nv, t = r / (nu * nv);
             double S[3], P[3];
-            source_pos(g, angles[t], S);
-            pixel_pos(g, angles[t], (double)a, (double)b, P);
+            source_pos(view_at(views, t), S);
+            pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
             out[q] = siddon_core(g, S, P, vol, NULL, NULL, 0.0, -1, NULL, &sc);
         }
         free(sc.buf);
@@ -385,7 +419,7 @@ void orc_siddon_rays(const orc_geom *g, const double *angles, const int64_t *ray
 
 /* Number of Siddon pieces (non-empty segments between consecutive plane crossings) of selected
  * rays, ray_idx as orc_siddon_rays: the count of voxel reads a ray costs. */
-void orc_siddon_segments(const orc_geom *g, const double *angles, const int64_t *ray_idx, int64_t n,
+void orc_siddon_segments(const orc_geom *g, const double *views, const int64_t *ray_idx, int64_t n,
                          int64_t *out) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
 #pragma omp parallel
@@ -398,8 +432,8 @@ void orc_siddon_segments(const orc_geom *g, const double *angles, const int64_t 
             int64_t a = r % nu, b = (r / nu) % nv, t = r / (nu * nv);
             double S[3], P[3];
             int64_t ns = 0;
-            source_pos(g, angles[t], S);
-            pixel_pos(g, angles[t], (double)a, (double)b, P);
+            source_pos(view_at(views, t), S);
+            pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
             siddon_core(g, S, P, NULL, NULL, NULL, 0.0, -1, &ns, &sc);
             out[q] = ns;
         }
@@ -409,7 +443,7 @@ void orc_siddon_segments(const orc_geom *g, const double *angles, const int64_t 
 
 /* Exact transpose of orc_siddon_fwd: vol = sum over rays of y_ray * (piece lengths), scattered.
  * Threads scatter into private volumes that are summed at the end. */
-void orc_siddon_adj(const orc_geom *g, const double *angles, int64_t na, const double *proj,
+void orc_siddon_adj(const orc_geom *g, const double *views, int64_t na, const double *proj,
                     double *vol) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
     const int64_t nvox = g->nvox[0] * g->nvox[1] * g->nvox[2];
@@ -432,11 +466,11 @@ void orc_siddon_adj(const orc_geom *g, const double *angles, int64_t na, const d
         for (int64_t r = 0; r < na * nv; ++r) {
             int64_t t = r / nv, b = r % nv;
             double S[3], P[3];
-            source_pos(g, angles[t], S);
+            source_pos(view_at(views, t), S);
             for (int64_t a = 0; a < nu; ++a) {
                 double y = proj[(t * nv + b) * nu + a];
                 if (y == 0.0) continue;
-                pixel_pos(g, angles[t], (double)a, (double)b, P);
+                pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
                 siddon_core(g, S, P, NULL, NULL, mine, y, -1, NULL, &sc);
             }
         }
@@ -453,7 +487,7 @@ void orc_siddon_adj(const orc_geom *g, const double *angles, int64_t na, const d
 /* The transpose of the Siddon projector at selected voxels only: for each voxel and angle, every
  * pixel whose ray can meet the voxel (bounding box of the 8 projected corners, widened by one
  * pixel) is traversed and the length it spends in that voxel is weighted by the pixel value. */
-static void adj_voxels(const orc_geom *g, const double *angles, int64_t na, const double *proj,
+static void adj_voxels(const orc_geom *g, const double *views, int64_t na, const double *proj,
                        const float *projf, const int64_t *vox_idx, int64_t n, double *out) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
     const int64_t nx = g->nvox[0], ny = g->nvox[1];
@@ -475,7 +509,7 @@ static void adj_voxels(const orc_geom *g, const double *angles, int64_t na, cons
                     X[1] += ((c & 2) ? 0.5 : -0.5) * g->dvox[1];
                     X[2] += ((c & 4) ? 0.5 : -0.5) * g->dvox[2];
                     double as, bs, w;
-                    project_voxel(g, angles[t], X, ORC_W_FDK, &as, &bs, &w);
+                    project_voxel(g, view_at(views, t), X, ORC_W_FDK, &as, &bs, &w);
                     if (as < amin) amin = as;
                     if (as > amax) amax = as;
                     if (bs < bmin) bmin = bs;
@@ -488,13 +522,13 @@ static void adj_voxels(const orc_geom *g, const double *angles, int64_t na, cons
                 if (a1 > nu - 1) a1 = nu - 1;
                 if (b1 > nv - 1) b1 = nv - 1;
                 double S[3], P[3];
-                source_pos(g, angles[t], S);
+                source_pos(view_at(views, t), S);
                 for (int64_t b = b0; b <= b1; ++b)
                     for (int64_t a = a0; a <= a1; ++a) {
                         const int64_t o = (t * nv + b) * nu + a;
                         double y = projf ? (double)projf[o] : proj[o];
                         if (y == 0.0) continue;
-                        pixel_pos(g, angles[t], (double)a, (double)b, P);
+                        pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
                         acc += y * siddon_core(g, S, P, NULL, NULL, NULL, 0.0, lin, NULL, &sc);
                     }
             }
@@ -504,18 +538,18 @@ static void adj_voxels(const orc_geom *g, const double *angles, int64_t na, cons
     }
 }
 
-void orc_siddon_adj_voxels(const orc_geom *g, const double *angles, int64_t na, const double *proj,
+void orc_siddon_adj_voxels(const orc_geom *g, const double *views, int64_t na, const double *proj,
                            const int64_t *vox_idx, int64_t n, double *out) {
-    adj_voxels(g, angles, na, proj, NULL, vox_idx, n, out);
+    adj_voxels(g, views, na, proj, NULL, vox_idx, n, out);
 }
 
 /* The same with FP32 projections read in place (each value widened exactly to FP64). */
-void orc_siddon_adj_voxels_f32(const orc_geom *g, const double *angles, int64_t na, const float *proj,
+void orc_siddon_adj_voxels_f32(const orc_geom *g, const double *views, int64_t na, const float *proj,
                                const int64_t *vox_idx, int64_t n, double *out) {
-    adj_voxels(g, angles, na, NULL, proj, vox_idx, n, out);
+    adj_voxels(g, views, na, NULL, proj, vox_idx, n, out);
 }
 
-void orc_interp_fwd(const orc_geom *g, const double *angles, int64_t na, const double *vol,
+void orc_interp_fwd(const orc_geom *g, const double *views, int64_t na, const double *vol,
                     double *proj, int64_t *samples_per_angle) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
     if (samples_per_angle) memset(samples_per_angle, 0, sizeof(int64_t) * na);
@@ -524,10 +558,10 @@ void orc_interp_fwd(const orc_geom *g, const double *angles, int64_t na, const d
         int64_t t = r / nv, b = r % nv;
         double S[3], P[3];
         int64_t rows = 0;
-        source_pos(g, angles[t], S);
+        source_pos(view_at(views, t), S);
         for (int64_t a = 0; a < nu; ++a) {
             int64_t ns = 0;
-            pixel_pos(g, angles[t], (double)a, (double)b, P);
+            pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
             proj[(t * nv + b) * nu + a] = interp_ray(g, S, P, vol, &ns);
             rows += ns;
         }
@@ -538,7 +572,7 @@ void orc_interp_fwd(const orc_geom *g, const double *angles, int64_t na, const d
     }
 }
 
-void orc_interp_rays(const orc_geom *g, const double *angles, const int64_t *ray_idx, int64_t n,
+void orc_interp_rays(const orc_geom *g, const double *views, const int64_t *ray_idx, int64_t n,
                      const double *vol, double *out) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
 #pragma omp parallel for schedule(dynamic, 4)
@@ -546,36 +580,36 @@ void orc_interp_rays(const orc_geom *g, const double *angles, const int64_t *ray
         int64_t r = ray_idx[q];
         int64_t a = r % nu, b = (r / nu) % nv, t = r / (nu * nv);
         double S[3], P[3];
-        source_pos(g, angles[t], S);
-        pixel_pos(g, angles[t], (double)a, (double)b, P);
+        source_pos(view_at(views, t), S);
+        pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
         out[q] = interp_ray(g, S, P, vol, NULL);
     }
 }
 
 /* vol[k][j][i] = sum over angles of w * bilinear(proj_t at the voxel's projection) */
-void orc_bp(const orc_geom *g, const double *angles, int64_t na, const double *proj, int kind,
+void orc_bp(const orc_geom *g, const double *views, int64_t na, const double *proj, int kind,
             double *vol) {
     const int64_t nx = g->nvox[0], ny = g->nvox[1], nz = g->nvox[2];
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < nz * ny; ++r) {
         int64_t k = r / ny, j = r % ny;
-        for (int64_t i = 0; i < nx; ++i) vol[(k * ny + j) * nx + i] = bp_voxel(g, angles, na, proj, NULL, kind, i, j, k);
+        for (int64_t i = 0; i < nx; ++i) vol[(k * ny + j) * nx + i] = bp_voxel(g, views, na, proj, NULL, kind, i, j, k);
     }
 }
 
-void orc_bp_voxels(const orc_geom *g, const double *angles, int64_t na, const double *proj, int kind,
+void orc_bp_voxels(const orc_geom *g, const double *views, int64_t na, const double *proj, int kind,
                    const int64_t *vox_idx, int64_t n, double *out) {
     const int64_t nx = g->nvox[0], ny = g->nvox[1];
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < n; ++q) {
         int64_t lin = vox_idx[q];
-        out[q] = bp_voxel(g, angles, na, proj, NULL, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
+        out[q] = bp_voxel(g, views, na, proj, NULL, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
     }
 }
 
 /* The same samplers reading FP32 inputs (each element is widened to FP64 when read; the
  * arithmetic is that of the FP64 versions).  For inputs too large to hold twice. */
-void orc_siddon_rays_f32(const orc_geom *g, const double *angles, const int64_t *ray_idx, int64_t n,
+void orc_siddon_rays_f32(const orc_geom *g, const double *views, const int64_t *ray_idx, int64_t n,
                          const float *vol, double *out) {
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
 #pragma omp parallel
@@ -587,27 +621,27 @@ void orc_siddon_rays_f32(const orc_geom *g, const double *angles, const int64_t 
             int64_t r = ray_idx[q];
             int64_t a = r % nu, b = (r / nu) % nv, t = r / (nu * nv);
             double S[3], P[3];
-            source_pos(g, angles[t], S);
-            pixel_pos(g, angles[t], (double)a, (double)b, P);
+            source_pos(view_at(views, t), S);
+            pixel_pos(g, view_at(views, t), (double)a, (double)b, P);
             out[q] = siddon_core(g, S, P, NULL, vol, NULL, 0.0, -1, NULL, &sc);
         }
         free(sc.buf);
     }
 }
 
-void orc_bp_voxels_f32(const orc_geom *g, const double *angles, int64_t na, const float *proj, int kind,
+void orc_bp_voxels_f32(const orc_geom *g, const double *views, int64_t na, const float *proj, int kind,
                        const int64_t *vox_idx, int64_t n, double *out) {
     const int64_t nx = g->nvox[0], ny = g->nvox[1];
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < n; ++q) {
         int64_t lin = vox_idx[q];
-        out[q] = bp_voxel(g, angles, na, NULL, proj, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
+        out[q] = bp_voxel(g, views, na, NULL, proj, kind, lin % nx, (lin / nx) % ny, lin / (nx * ny));
     }
 }
 
 /* Transpose of orc_bp (a voxel-driven bilinear "splat" projector with the same weight); used only
  * to check the indexing of the backprojector by the dot-product identity. */
-void orc_bp_transpose(const orc_geom *g, const double *angles, int64_t na, const double *vol, int kind,
+void orc_bp_transpose(const orc_geom *g, const double *views, int64_t na, const double *vol, int kind,
                       double *proj) {
     const int64_t nx = g->nvox[0], ny = g->nvox[1], nz = g->nvox[2];
     const int64_t nu = g->ndet[0], nv = g->ndet[1];
@@ -622,7 +656,7 @@ void orc_bp_transpose(const orc_geom *g, const double *angles, int64_t na, const
                     if (x == 0.0) continue;
                     double X[3], as, bs, w;
                     voxel_centre(g, i, j, k, X);
-                    project_voxel(g, angles[t], X, kind, &as, &bs, &w);
+                    project_voxel(g, view_at(views, t), X, kind, &as, &bs, &w);
                     double a0 = floor(as), b0 = floor(bs), fa = as - a0, fb = bs - b0;
                     int64_t ia = (int64_t)a0, ib = (int64_t)b0;
                     for (int db = 0; db < 2; ++db)

@@ -70,6 +70,52 @@ def uniform_angles(n: int) -> np.ndarray:
     return 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
 
 
+def _rot(axis: np.ndarray, ang: float) -> np.ndarray:
+    """Rotation matrix about a unit axis (Rodrigues)."""
+    k = np.asarray(axis, dtype=np.float64)
+    k = k / np.linalg.norm(k)
+    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+    return np.eye(3) + np.sin(ang) * K + (1.0 - np.cos(ang)) * (K @ K)
+
+
+def helical_views(DSO: float, DSD: float, angles, pitch: float, z0: float = 0.0) -> np.ndarray:
+    """Per-view table (n x 12: source, detector centre, unit e_u, unit e_v, mm) of a helical scan:
+    the circular orbit's views with source and detector centre raised by z0 + pitch * theta / (2 pi)
+    (pitch in mm per turn)."""
+    th = np.asarray(angles, dtype=np.float64)
+    c, s = np.cos(th), np.sin(th)
+    z = z0 + pitch * th / (2.0 * np.pi)
+    k = -(DSD - DSO)
+    zero, one = np.zeros_like(th), np.ones_like(th)
+    return np.stack([DSO * c, DSO * s, z, k * c, k * s, z, -s, c, zero, zero, zero, one], -1)
+
+
+def carm_views(DSO: float, DSD: float, angles, seed: int, tilt_deg: float = 15.0, jitter_mm: float = 5.0,
+               orbit_tilt_deg: float = 0.0) -> np.ndarray:
+    """Per-view table (n x 12) of a C-arm-like scan: the circular orbit, tilted about the x axis by
+    orbit_tilt_deg, with each view's source and detector centre displaced by seeded offsets of up to
+    jitter_mm per axis and its detector turned about its centre by seeded rotations of up to
+    tilt_deg about e_u, e_v and the normal, in that order (e_u, e_v stay orthonormal)."""
+    th = np.asarray(angles, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    R0 = _rot(np.array([1.0, 0.0, 0.0]), np.deg2rad(orbit_tilt_deg))
+    out = np.zeros((len(th), 12))
+    for t, a in enumerate(th):
+        c, s = np.cos(a), np.sin(a)
+        S = R0 @ np.array([DSO * c, DSO * s, 0.0])
+        C = R0 @ np.array([-(DSD - DSO) * c, -(DSD - DSO) * s, 0.0])
+        eu = R0 @ np.array([-s, c, 0.0])
+        ev = R0 @ np.array([0.0, 0.0, 1.0])
+        S = S + rng.uniform(-jitter_mm, jitter_mm, 3)
+        C = C + rng.uniform(-jitter_mm, jitter_mm, 3)
+        ang = np.deg2rad(rng.uniform(-tilt_deg, tilt_deg, 3))
+        for axis, phi in ((eu, ang[0]), (ev, ang[1]), (np.cross(eu, ev), ang[2])):
+            R = _rot(axis, phi)
+            eu, ev = R @ eu, R @ ev
+        out[t] = np.concatenate([S, C, eu, ev])
+    return out
+
+
 def workload(name: str, **over) -> Workload:
     """The named synthetic problems.
 
