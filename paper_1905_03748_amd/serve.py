@@ -84,6 +84,10 @@ class Server:
         self.budget = int(hbm_budget_bytes)
         self.max_overlap_work = max_overlap_work
         self.slots = [_Slot(self.device) for _ in range(max_slots)]
+        # request buffers come from one allocation stream, so blocks freed by one request are reused
+        # by the next whatever its slot (each buffer is marked as used on its slot's stream, and the
+        # caching allocator hands it out again only after that stream's work on it has finished)
+        self.alloc_stream = torch.cuda.Stream(device=self.device)   # default priority
         self.queue: collections.deque[Request] = collections.deque()
         self.finished: list[Request] = []
         self.in_use = 0
@@ -127,18 +131,22 @@ class Server:
     def _admit(self, slot: _Slot, req: Request):
         req.t_admit = time.perf_counter()
         geo = req.geometry
-        with torch.cuda.stream(slot.stream):
-            plan = Plan(geo, req.angles)
-            b = req.b.to(self.device, non_blocking=True)
-            x = torch.zeros(plan.vol_shape, dtype=torch.float32, device=self.device)
+        plan = Plan(geo, req.angles)
+        with torch.cuda.stream(self.alloc_stream):
+            b = torch.empty(req.b.shape, dtype=torch.float32, device=self.device)
+            x = torch.empty(plan.vol_shape, dtype=torch.float32, device=self.device)
             resid = torch.empty(req.niter + 1, dtype=torch.float64, device=self.device)
             ws = torch.empty(plan.cgls_workspace_bytes(), dtype=torch.uint8, device=self.device)
+            tws = torch.empty(tv_workspace_bytes(geo), dtype=torch.uint8, device=self.device) if req.tv_steps > 0 else None
+        for t in (b, x, resid, ws, tws):
+            if t is not None:
+                t.record_stream(slot.stream)
+        with torch.cuda.stream(slot.stream):
+            b.copy_(req.b, non_blocking=True)
+            x.zero_()
             plan.cgls(b, req.niter, x=x, resid=resid, workspace=ws, stream=slot.stream)
-            if req.tv_steps > 0:
-                tws = torch.empty(tv_workspace_bytes(geo), dtype=torch.uint8, device=self.device)
+            if tws is not None:
                 tv_steps(geo, x, req.tv_steps, req.tv_lambda, req.tv_eps, workspace=tws, stream=slot.stream)
-            else:
-                tws = None
             xh = torch.empty(plan.vol_shape, dtype=torch.float32, pin_memory=True)
             rh = torch.empty(req.niter + 1, dtype=torch.float64, pin_memory=True)
             xh.copy_(x, non_blocking=True)

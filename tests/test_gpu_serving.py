@@ -57,13 +57,25 @@ def test_alone_vs_mixed_bitwise(reqs):
 def test_admission_respects_budget(reqs):
     sizes = [r.device_bytes() for r, _ in reqs]
     budget = int(sorted(sizes)[-1] + sorted(sizes)[-2] * 0.5)   # at most ~2 resident at once
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    base_alloc, base_res = torch.cuda.memory_allocated(), torch.cuda.memory_reserved()
+    torch.cuda.reset_peak_memory_stats()
     srv = Server(hbm_budget_bytes=budget, max_slots=6)
     try:
         qs = [srv.submit(_clone(r)) for r, _ in reqs]
         assert srv.drain(300)
         st = srv.stats()
-        say(f"[serve budget] budget={budget} stats={st}")
+        torch.cuda.synchronize()
+        # device memory the requests actually held (torch's allocator), not only the estimate
+        peak_alloc = torch.cuda.max_memory_allocated() - base_alloc
+        peak_res = torch.cuda.max_memory_reserved() - base_res
+        say(f"[serve budget] budget={budget} stats={st} peak allocated {peak_alloc} reserved {peak_res}")
         assert st["peak_hbm_bytes"] <= budget
+        assert peak_alloc <= budget, (peak_alloc, budget)
+        # one allocation stream: blocks freed by a request are reused by the next, so the pool
+        # grows by at most the allocator's rounding over what is allocated at once
+        assert peak_res <= budget + (64 << 20), (peak_res, budget)
         assert st["p99_s"] >= st["p50_s"] > 0
     finally:
         srv.close()
