@@ -435,6 +435,52 @@ def ooc_rof_bench(dev, cap_gib=32, n=2048):
     return out
 
 
+def views_bench(dev, reps=3):
+    """Operator times on the 512^3 workload's grid and detector with per-view geometry: a helical scan
+    (360 views over one turn, 40 mm pitch) and a C-arm scan (360 views, detectors turned by up to
+    10 degrees, sources and detectors displaced by up to 5 mm, orbit tilted by 5 degrees), against
+    the circular orbit of the same angles."""
+    import torch
+    from paper_1905_03748_amd import inputs
+    from paper_1905_03748_amd.operators import Plan
+
+    w = inputs.workload("medium")
+    vol = inputs.voxelize(w)
+    x = torch.from_numpy(vol).to(dev)
+    stream = torch.cuda.current_stream()
+    sets = {"circular": w.angles,
+            "helical": inputs.helical_views(w.DSO, w.DSD, w.angles, pitch=40.0, z0=-20.0),
+            "carm": inputs.carm_views(w.DSO, w.DSD, w.angles, 7, tilt_deg=10.0, jitter_mm=5.0, orbit_tilt_deg=5.0)}
+    out = {"workload": "512^3 volume of 0.5 mm, 360 views, 512x512 detector of 0.8 mm, DSO 1000 mm, DSD 1500 mm"}
+    for name, ang in sets.items():
+        plan = Plan(w.geometry_dict(), ang)
+        p = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
+        v = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+        r = {}
+        for op, fn in (("siddon_fwd", lambda: plan.forward(x, "siddon", out=p)),
+                       ("interp_fwd", lambda: plan.forward(x, "interp", out=p)),
+                       ("fdk_bp", lambda: plan.backproject(p, "fdk", out=v)),
+                       ("pm_bp", lambda: plan.backproject(p, "pm", out=v)),
+                       ("adjoint_bp", lambda: plan.backproject(p, "adjoint", out=v))):
+            log(f"[views] {name} {op}")
+            fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            r[op + "_ms"] = round(ms, 3)
+            r[op + "_gvps"] = round(w.voxel_proj / (ms * 1e-3) / 1e9, 1)
+        out[name] = r
+        log(f"[views] {name}: {r}")
+        del plan, p, v
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,12 +493,14 @@ def main():
     ap.add_argument("--ooc", action="store_true", help="print the 3072^3 out-of-core report instead")
     ap.add_argument("--ooc-tv", action="store_true", help="print the 3072^3 out-of-core TV report instead")
     ap.add_argument("--ooc-rof", action="store_true", help="print the 2048^3 out-of-core ROF report instead")
+    ap.add_argument("--views", action="store_true", help="print operator times with helical and C-arm views instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB copy (ct_convert F32->F32) for HBM counter calibration")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch each resident operator of the 512^3 workload (Siddon and interpolated "
-                         "forward, FDK, pseudo-matched and exact-adjoint backprojection) --steps times after "
-                         "one warm-up, and a 1 GiB plain copy, for rocprofv3 counter runs; prints nothing else")
+                         "forward, FDK, pseudo-matched and exact-adjoint backprojection, and the per-view Siddon, "
+                         "FDK and adjoint kernels on a C-arm scan) --steps times after one warm-up, and a 1 GiB "
+                         "plain copy, for rocprofv3 counter runs; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the build targets single-GPU boxes (no collectives); "
@@ -476,6 +524,9 @@ def main():
     if args.ooc_rof:
         print(json.dumps({"out_of_core_rof": ooc_rof_bench(dev)}), flush=True)
         return
+    if args.views:
+        print(json.dumps({"views": views_bench(dev)}), flush=True)
+        return
     w = inputs.workload("medium")
     log(f"[bench] building phantom {w.nvox} with {w.n_ellipsoids} ellipsoids")
     vol = inputs.voxelize(w)
@@ -490,6 +541,12 @@ def main():
         ops = [("siddon", lambda: plan.forward(x, "siddon", out=p)), ("interp", lambda: plan.forward(x, "interp", out=p)),
                ("fdk", lambda: plan.backproject(p, "fdk", out=v)), ("pm", lambda: plan.backproject(p, "pm", out=v)),
                ("adjoint", lambda: plan.backproject(p, "adjoint", out=v))]
+        # the per-view kernels on a C-arm scan of the same grid, detector and angles
+        pv = Plan(w.geometry_dict(), inputs.carm_views(w.DSO, w.DSD, w.angles, 7, tilt_deg=10.0, jitter_mm=5.0,
+                                                          orbit_tilt_deg=5.0))
+        ops += [("views_siddon", lambda: pv.forward(x, "siddon", out=p)),
+                ("views_fdk", lambda: pv.backproject(p, "fdk", out=v)),
+                ("views_adjoint", lambda: pv.backproject(p, "adjoint", out=v))]
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         ops.append(("copy_1gib", lambda: convert(src, torch.float32)))
         for name, fn in ops:

@@ -98,6 +98,22 @@ typedef struct ct_plan ct_plan;
  * Errors: CT_ERR_ARG (null pointers, n_angles <= 0), CT_ERR_GEOMETRY. */
 ct_status ct_plan_create(const ct_geometry *geometry, const double *angles, int64_t n_angles,
                          ct_plan **out);
+/* A plan over per-view geometry (Section 2.1: the projectors serve circular, C-arm and helical
+ * scans).  views (host, n_views x 12 doubles, copied): for each projection the source S, the
+ * detector centre C and the detector's unit axes e_u, e_v, in mm in the volume's frame (the frame
+ * of offOrigin).  Pixel (a, b) has its centre at C + u_a e_u + v_b e_v with u_a, v_b from nDetector,
+ * dDetector and offDetector exactly as in a circular plan; the geometry's DSO and DSD are not used
+ * (ct_plan_info reports the largest DSO_v and DSD_v over the views).  The weights of the voxel-driven
+ * backprojectors take depths L along the detector normal n = e_u x e_v: FDK (DSO_v / L)^2 with
+ * DSO_v = S.n, pseudo-matched (dx dy dz)/(du dv) DSD_v^2 |SX| / L^3 with DSD_v = (S - C).n; a
+ * circular orbit written as views reproduces ct_plan_create's operators.
+ * Validation: the grid fields as in ct_plan_create; per view: finite entries, |e_u| = |e_v| = 1
+ * and e_u.e_v = 0 to 1e-9, DSD_v > 0, and every corner of the volume box at positive depth.
+ * Every resident operator and algorithm (ct_forward, ct_backproject, ct_backproject_noalloc,
+ * ct_cgls, ct_sart) accepts such a plan; the FDK reconstruction (ct_fdk_filter, ct_fdk, ct_fdk_host)
+ * and the out-of-core calls need a circular orbit and return CT_ERR_ARG.
+ * Errors: CT_ERR_ARG (null pointers, n_views <= 0), CT_ERR_GEOMETRY. */
+ct_status ct_plan_create_views(const ct_geometry *geometry, const double *views, int64_t n_views, ct_plan **out);
 /* Release the plan.  All work that uses it must have completed (device copies are released in
  * stream order, without host synchronisation). */
 void ct_plan_destroy(ct_plan *plan);

@@ -56,6 +56,7 @@ _ST = C.c_int
 
 SIGNATURES = {
     "ct_plan_create": [C.POINTER(ct_geometry), C.POINTER(C.c_double), _I64, C.POINTER(_P)],
+    "ct_plan_create_views": [C.POINTER(ct_geometry), C.POINTER(C.c_double), _I64, C.POINTER(_P)],
     "ct_plan_destroy": [_P],
     "ct_plan_info": [_P, C.POINTER(ct_geometry), C.POINTER(_I64)],
     "ct_forward": [_P, _INT, _P, _INT, _P, _INT, _INT, _I64, _I64, _P],
@@ -130,6 +131,17 @@ def ct_plan_create(geometry: ct_geometry, angles) -> int:
     arr = (C.c_double * len(angles))(*[float(a) for a in angles])
     out = _P()
     _check(lib().ct_plan_create(C.byref(geometry), arr, len(angles), C.byref(out)))
+    return out.value
+
+
+def ct_plan_create_views(geometry: ct_geometry, views) -> int:
+    """views: n x 12 (source, detector centre, unit e_u, unit e_v per projection; mm)."""
+    flat = [float(v) for row in views for v in row]
+    if any(len(row) != 12 for row in views):
+        raise ValueError("each view has 12 entries: source, detector centre, e_u, e_v")
+    arr = (C.c_double * len(flat))(*flat)
+    out = _P()
+    _check(lib().ct_plan_create_views(C.byref(geometry), arr, len(views), C.byref(out)))
     return out.value
 
 

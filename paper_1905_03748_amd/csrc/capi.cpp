@@ -26,9 +26,8 @@ size_t dtype_size(ct_dtype t) { return t == CT_F64 ? 8 : t == CT_F32 ? 4 : 2; }
 bool dtype_ok(int t) { return t == CT_F32 || t == CT_F16 || t == CT_BF16; }
 bool dtype_ok_any(int t) { return dtype_ok(t) || t == CT_F64; }
 
-static ct_status validate(const ct_geometry &g) {
-    if (!(g.DSO > 0) || !(g.DSD > g.DSO) || !std::isfinite(g.DSD))
-        return fail(CT_ERR_GEOMETRY, "geometry: need DSD > DSO > 0");
+// the grid, detector and accuracy fields (all plans)
+static ct_status validate_grid(const ct_geometry &g) {
     for (int a = 0; a < 3; ++a) {
         if (g.nVoxel[a] <= 0 || !(g.dVoxel[a] > 0) || !std::isfinite(g.dVoxel[a]) ||
             !std::isfinite(g.offOrigin[a]))
@@ -44,6 +43,15 @@ static ct_status validate(const ct_geometry &g) {
         return fail(CT_ERR_GEOMETRY, "geometry: a dimension exceeds 2^24");
     if (!(g.accuracy >= 0.0 && g.accuracy <= 1.0))
         return fail(CT_ERR_GEOMETRY, "geometry: accuracy must be in (0, 1] (0 selects 0.5)");
+    return CT_OK;
+}
+
+// a circular orbit: also the distances
+static ct_status validate(const ct_geometry &g) {
+    if (!(g.DSO > 0) || !(g.DSD > g.DSO) || !std::isfinite(g.DSD))
+        return fail(CT_ERR_GEOMETRY, "geometry: need DSD > DSO > 0");
+    ct_status st = validate_grid(g);
+    if (st != CT_OK) return st;
     double r2 = 0;
     for (int sx = -1; sx <= 1; sx += 2)
         for (int sy = -1; sy <= 1; sy += 2) {
@@ -54,6 +62,45 @@ static ct_status validate(const ct_geometry &g) {
     if (!(r2 < g.DSO * g.DSO))
         return fail(CT_ERR_GEOMETRY, "geometry: the volume box must lie strictly inside the source orbit");
     return CT_OK;
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// The general part of a view's table entry from its source Smm, detector centre Cmm and unit axes
+// eu, ev (mm, world frame): e_v in index units, the projective map M, DSO_v and the pseudo-matched
+// constant (see AngleGeo).
+static void fill_general(const ct_geometry &g, const double *Smm, const double *Cmm, const double *eu,
+                         const double *ev, AngleGeo &t) {
+    const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2], eu[0] * ev[1] - eu[1] * ev[0]};
+    double x0[3], SC[3];
+    for (int a = 0; a < 3; ++a) {
+        t.ev[a] = ev[a] / g.dVoxel[a];
+        t.Smm[a] = Smm[a];
+        x0[a] = g.offOrigin[a] - (g.nVoxel[a] - 1) / 2.0 * g.dVoxel[a];  // centre of voxel (0, 0, 0)
+        SC[a] = Smm[a] - Cmm[a];
+    }
+    const double DSDv = dot3(SC, n);
+    t.DSOv = dot3(Smm, n);
+    t.DSDv = DSDv;
+    t.pmc = g.dVoxel[0] * g.dVoxel[1] * g.dVoxel[2] / (g.dDetector[0] * g.dDetector[1]) * DSDv * DSDv;
+    // L(X) = n.(S - X); u* L = ((S - C).e_u) L + DSD_v e_u.(X - S); a* L = u* L / du + (cu - offU / du) L
+    const double cu = (g.nDetector[0] - 1) / 2.0, cv = (g.nDetector[1] - 1) / 2.0;
+    double Lr[4], Ur[4], Vr[4];
+    Lr[3] = dot3(n, Smm) - dot3(n, x0);
+    for (int a = 0; a < 3; ++a) Lr[a] = -n[a] * g.dVoxel[a];
+    const double seu = dot3(SC, eu), sev = dot3(SC, ev);
+    for (int a = 0; a < 3; ++a) {
+        Ur[a] = seu * Lr[a] + DSDv * eu[a] * g.dVoxel[a];
+        Vr[a] = sev * Lr[a] + DSDv * ev[a] * g.dVoxel[a];
+    }
+    Ur[3] = seu * Lr[3] + DSDv * (dot3(eu, x0) - dot3(eu, Smm));
+    Vr[3] = sev * Lr[3] + DSDv * (dot3(ev, x0) - dot3(ev, Smm));
+    const double ka = cu - g.offDetector[0] / g.dDetector[0], kb = cv - g.offDetector[1] / g.dDetector[1];
+    for (int a = 0; a < 4; ++a) {
+        t.M[a] = Ur[a] / g.dDetector[0] + ka * Lr[a];
+        t.M[4 + a] = Vr[a] / g.dDetector[1] + kb * Lr[a];
+        t.M[8 + a] = Lr[a];
+    }
 }
 
 static AngleGeo angle_geo(const ct_geometry &g, double th) {
@@ -71,7 +118,45 @@ static AngleGeo angle_geo(const ct_geometry &g, double th) {
     t.eu[0] = -t.s / g.dVoxel[0];
     t.eu[1] = t.c / g.dVoxel[1];
     t.eu[2] = 0.0;
+    const double Cmm[3] = {-(g.DSD - g.DSO) * t.c, -(g.DSD - g.DSO) * t.s, 0.0};
+    const double eu[3] = {-t.s, t.c, 0.0}, ev[3] = {0.0, 0.0, 1.0};
+    fill_general(g, Smm, Cmm, eu, ev, t);
     return t;
+}
+
+// The table entry of a view (source S, detector centre C, unit axes e_u, e_v; mm).
+static AngleGeo view_geo(const ct_geometry &g, const double *v) {
+    AngleGeo t;
+    std::memset(&t, 0, sizeof(t));
+    for (int a = 0; a < 3; ++a) {
+        t.S[a] = (v[a] - g.offOrigin[a]) / g.dVoxel[a] + (g.nVoxel[a] - 1) / 2.0;
+        t.Dc[a] = (v[3 + a] - v[a]) / g.dVoxel[a];
+        t.eu[a] = v[6 + a] / g.dVoxel[a];
+    }
+    fill_general(g, v, v + 3, v + 6, v + 9, t);
+    return t;
+}
+
+// A view the kernels can serve: finite, orthonormal detector axes, the source in front of the
+// detector plane (on the side its normal points to), and every corner of the volume box at a
+// positive depth from the source.
+static ct_status validate_view(const ct_geometry &g, const double *v, int64_t i) {
+    const std::string who = "ct_plan_create_views: view " + std::to_string(i) + ": ";
+    for (int a = 0; a < 12; ++a)
+        if (!std::isfinite(v[a])) return fail(CT_ERR_GEOMETRY, who + "non-finite entry");
+    const double *eu = v + 6, *ev = v + 9;
+    if (std::fabs(dot3(eu, eu) - 1.0) > 1e-9 || std::fabs(dot3(ev, ev) - 1.0) > 1e-9 || std::fabs(dot3(eu, ev)) > 1e-9)
+        return fail(CT_ERR_GEOMETRY, who + "e_u and e_v must be orthonormal (to 1e-9)");
+    const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2], eu[0] * ev[1] - eu[1] * ev[0]};
+    const double SC[3] = {v[0] - v[3], v[1] - v[4], v[2] - v[5]};
+    if (!(dot3(SC, n) > 0.0)) return fail(CT_ERR_GEOMETRY, who + "the source must lie in front of the detector (along e_u x e_v)");
+    for (int c = 0; c < 8; ++c) {
+        double X[3];
+        for (int a = 0; a < 3; ++a) X[a] = g.offOrigin[a] + (((c >> a) & 1) ? 0.5 : -0.5) * g.nVoxel[a] * g.dVoxel[a] - v[a];
+        if (!(-dot3(X, n) > 1e-6 * std::sqrt(dot3(SC, SC))))
+            return fail(CT_ERR_GEOMETRY, who + "the volume box must lie at positive depth from the source (in front of its plane)");
+    }
+    return CT_OK;
 }
 
 ct_status plan_device_table(ct_plan *p, hipStream_t st, const AngleGeo **out) {
@@ -138,6 +223,36 @@ ct_status ct_plan_create(const ct_geometry *geometry, const double *angles, int6
     p->angles.assign(angles, angles + n_angles);
     p->tab.resize(n_angles);
     for (int64_t i = 0; i < n_angles; ++i) p->tab[i] = angle_geo(g, angles[i]);
+    *out = p;
+    return CT_OK;
+}
+
+ct_status ct_plan_create_views(const ct_geometry *geometry, const double *views, int64_t n_views, ct_plan **out) {
+    if (!geometry || !views || !out) return fail(CT_ERR_ARG, "ct_plan_create_views: null pointer");
+    if (n_views <= 0) return fail(CT_ERR_ARG, "ct_plan_create_views: n_views must be positive");
+    ct_geometry g = *geometry;
+    if (g.accuracy == 0.0) g.accuracy = 0.5;
+    ct_status st = validate_grid(g);
+    if (st != CT_OK) return st;
+    for (int64_t i = 0; i < n_views; ++i)
+        if ((st = validate_view(g, views + 12 * i, i)) != CT_OK) return st;
+    ct_plan *p = new (std::nothrow) ct_plan();
+    if (!p) return fail(CT_ERR_OOM, "ct_plan_create_views: host allocation failed");
+    p->views = true;
+    p->angles.assign((size_t)n_views, 0.0);
+    p->tab.resize(n_views);
+    double dso = 0.0, dsd = 0.0;
+    for (int64_t i = 0; i < n_views; ++i) {
+        const double *v = views + 12 * i;
+        p->vertical = p->vertical && v[8] == 0.0 && v[9] == 0.0 && v[10] == 0.0 && v[11] == 1.0 && v[5] == v[2];
+        p->tab[i] = view_geo(g, views + 12 * i);
+        dso = std::fmax(dso, p->tab[i].DSOv);
+        dsd = std::fmax(dsd, p->tab[i].DSDv);
+    }
+    // informative only (ct_plan_info): the largest distances over the views
+    g.DSO = dso;
+    g.DSD = dsd;
+    p->g = g;
     *out = p;
     return CT_OK;
 }
@@ -211,6 +326,7 @@ ct_status ct_backproject_noalloc(ct_plan *plan, ct_backprojector backprojector, 
 ct_status ct_ooc_plan(const ct_plan *plan, int direction, ct_projector projector, ct_dtype vol_dtype,
                       ct_dtype proj_dtype, uint64_t device_cap_bytes, ct_ooc_stats *out) {
     if (!plan || !out) return fail(CT_ERR_ARG, "ct_ooc_plan: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_ooc_plan: needs a circular orbit (not a plan of views)");
     if (direction < 0 || direction > 3) return fail(CT_ERR_ARG, "ct_ooc_plan: direction must be 0, 1, 2 or 3");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_ooc_plan: dtype must be CT_F32, CT_F16 or CT_BF16");
     return ooc_plan(plan, direction, projector, vol_dtype, proj_dtype, device_cap_bytes, out);
@@ -220,6 +336,7 @@ ct_status ct_forward_host(ct_plan *plan, ct_projector projector, const void *h_v
                           void *h_proj, ct_dtype proj_dtype, uint64_t device_cap_bytes,
                           ct_ooc_stats *stats) {
     if (!plan || !h_vol || !h_proj) return fail(CT_ERR_ARG, "ct_forward_host: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_forward_host: needs a circular orbit (not a plan of views)");
     if (projector != CT_SIDDON && projector != CT_INTERP) return fail(CT_ERR_ARG, "ct_forward_host: unknown projector");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_forward_host: dtype must be CT_F32, CT_F16 or CT_BF16");
     return ooc_forward(plan, projector, h_vol, vol_dtype, h_proj, proj_dtype, device_cap_bytes, stats);
@@ -229,6 +346,7 @@ ct_status ct_backproject_host(ct_plan *plan, ct_backprojector backprojector, con
                               ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
                               uint64_t device_cap_bytes, ct_ooc_stats *stats) {
     if (!plan || !h_vol || !h_proj) return fail(CT_ERR_ARG, "ct_backproject_host: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_backproject_host: needs a circular orbit (not a plan of views)");
     if (backprojector != CT_BP_FDK && backprojector != CT_BP_PSEUDO_MATCHED && backprojector != CT_BP_ADJOINT)
         return fail(CT_ERR_ARG, "ct_backproject_host: unknown backprojector");
     if (!dtype_ok(vol_dtype) || !dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_backproject_host: dtype must be CT_F32, CT_F16 or CT_BF16");
@@ -260,6 +378,7 @@ ct_status ct_cgls_host_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
 ct_status ct_cgls_host(ct_plan *plan, const float *h_b, float *h_x, int32_t niter, double *resid, void *h_workspace,
                        uint64_t device_cap_bytes, ct_ooc_stats *stats) {
     if (!plan || !h_b || !h_x || !h_workspace) return fail(CT_ERR_ARG, "ct_cgls_host: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_cgls_host: needs a circular orbit (not a plan of views)");
     if (niter < 0) return fail(CT_ERR_ARG, "ct_cgls_host: niter must be >= 0");
     return cgls_host_run(plan, h_b, h_x, niter, resid, h_workspace, device_cap_bytes, stats);
 }
@@ -286,6 +405,7 @@ ct_status ct_sart(ct_plan *plan, const void *d_b, ct_dtype proj_dtype, void *d_x
 ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, float *d_q, int64_t angle_begin,
                         int64_t angle_end, void *stream) {
     if (!plan || !d_proj || !d_q) return fail(CT_ERR_ARG, "ct_fdk_filter: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_fdk_filter: needs a circular orbit (not a plan of views)");
     if (!dtype_ok(proj_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_filter: dtype must be CT_F32, CT_F16 or CT_BF16");
     ct_status st = check_range(plan, angle_begin, angle_end, "ct_fdk_filter");
     if (st != CT_OK) return st;
@@ -295,6 +415,7 @@ ct_status ct_fdk_filter(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, 
 ct_status ct_fdk_host(ct_plan *plan, const void *h_proj, ct_dtype proj_dtype, void *h_vol, ct_dtype vol_dtype,
                       uint64_t device_cap_bytes, ct_ooc_stats *stats) {
     if (!plan || !h_proj || !h_vol) return fail(CT_ERR_ARG, "ct_fdk_host: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_fdk_host: needs a circular orbit (not a plan of views)");
     if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk_host: dtype must be CT_F32, CT_F16 or CT_BF16");
     if (plan->g.nDetector[0] > 4096)
         return fail(CT_ERR_ARG, "ct_fdk_host: detector rows longer than 4096 pixels are not supported");
@@ -310,6 +431,7 @@ ct_status ct_fdk_workspace_bytes(const ct_plan *plan, uint64_t *bytes) {
 ct_status ct_fdk(ct_plan *plan, const void *d_proj, ct_dtype proj_dtype, void *d_vol, ct_dtype vol_dtype,
                  void *d_workspace, void *stream) {
     if (!plan || !d_proj || !d_vol) return fail(CT_ERR_ARG, "ct_fdk: null pointer");
+    if (plan->views) return fail(CT_ERR_ARG, "ct_fdk: needs a circular orbit (not a plan of views)");
     if (!dtype_ok(proj_dtype) || !dtype_ok(vol_dtype)) return fail(CT_ERR_DTYPE, "ct_fdk: dtype must be CT_F32, CT_F16 or CT_BF16");
     return fdk_run(plan, d_proj, proj_dtype, d_vol, vol_dtype, d_workspace, (hipStream_t)stream);
 }

@@ -16,14 +16,25 @@ namespace ct {
 // Per-angle geometry in voxel-index space (voxel (i,j,k) centre at index coordinates (i,j,k)).
 // Double precision: the source sits ~DSO/d voxels away from the grid, so rays are set up in FP64
 // and traversed in FP32 relative to their entry point.
+//
+// Every plan fills the general part (e_v, the projective map M, DSO_v, the pseudo-matched constant),
+// so the per-view kernels run on circular plans too; c and s are meaningful for circular plans only.
+// M's rows are a* L, b* L and L as affine functions of the voxel index (i, j, k, 1), where L (mm) is
+// the voxel's depth from the source along the detector normal n = e_u x e_v and (a*, b*) the
+// continuous detector indices of the ray from the source through the voxel centre.
 struct AngleGeo {
-    double c, s;         // cos, sin of the angle
+    double c, s;         // cos, sin of the angle (circular plans)
     double S[3];         // source position, index units
     double Dc[3];        // (detector centre - source), index units
     double eu[3];        // e_u / dVoxel (index units per mm along the detector u axis)
-    double pad[5];
+    double ev[3];        // e_v / dVoxel
+    double M[12];        // projective map, row-major 3 x 4
+    double DSOv;         // FDK weight numerator: the world origin's depth (DSO in a circular orbit)
+    double pmc;          // pseudo-matched constant dx dy dz / (du dv) * DSD_v^2
+    double Smm[3];       // source position, mm
+    double DSDv;         // source to detector plane, mm (DSD in a circular orbit)
 };
-static_assert(sizeof(AngleGeo) == 128, "AngleGeo layout");
+static_assert(sizeof(AngleGeo) == 256, "AngleGeo layout");
 
 void set_error(const std::string &msg);
 ct_status fail(ct_status st, const std::string &msg);
@@ -43,7 +54,10 @@ bool dtype_ok_any(int t);  // also FP64 (conversion and inner products)
 
 struct ct_plan {
     ct_geometry g;
-    std::vector<double> angles;
+    std::vector<double> angles;  // circular plans; a plan of views holds zeros here
+    bool views = false;          // built from per-view vectors: the per-view kernels serve it
+    bool vertical = true;        // every view's e_v is +z, e_u horizontal and C at the source's
+                                 // height (circular and helical scans): the column walks apply
     std::vector<ct::AngleGeo> tab;
     std::mutex mu;
     struct DevTab {
@@ -157,6 +171,13 @@ ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double la
 ct_status fdk_filter(ct_plan *p, const void *proj, ct_dtype pt, float *q, int64_t a0, int64_t a1, hipStream_t st);
 ct_status fdk_run(ct_plan *p, const void *proj, ct_dtype pt, void *vol, ct_dtype vt, void *work, hipStream_t st);
 size_t fdk_workspace(const ct_plan *p);
+
+// Per-view kernels (kern_views.hip): every backprojector and the SART update for plans of views
+ct_status launch_backproject_views(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
+                                   ct_dtype vt, int accumulate, int64_t a0, int64_t a1, const Slab &slab,
+                                   const AngleGeo *tab, hipStream_t st);
+ct_status launch_sart_update_views(ct_plan *p, const float *r, float *vol, int64_t a0, int64_t a1, float lambda,
+                                   const AngleGeo *tab, hipStream_t st);
 
 // SART pieces (kern_backproject.hip / kern_forward.hip)
 ct_status launch_ray_chord(ct_plan *p, float *chord, int64_t a0, int64_t a1, hipStream_t st);

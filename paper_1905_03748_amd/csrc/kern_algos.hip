@@ -465,7 +465,9 @@ ct_status sart_run(ct_plan *p, const void *b, ct_dtype pt, void *x, ct_dtype vt,
     const Slab full = full_slab(g);
     // the sweep updates an FP32 image: the column-major copy, or (other geometries) x itself when
     // it is stored in FP32, else an FP32 copy of it; a 16-bit x is rounded once, at the end
-    if (zcol_ok(p, 0, na)) {
+    // the column-major sweep's update kernel is written for a circular orbit; plans of views update
+    // x through the per-view kernel
+    if (zcol_ok(p, 0, na) && !p->views) {
         CK(launch_zcols_f32(x, vt, xz, g.nVoxel[0], g.nVoxel[1], g.nVoxel[2], st));
         for (int32_t it = 0; it < niter; ++it) {
             for (int64_t t0 = 0; t0 < na; t0 += block) {

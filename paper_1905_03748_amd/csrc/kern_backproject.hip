@@ -1139,6 +1139,7 @@ bool adj_col_ok(const ct_plan *p) {
 #ifdef CT_NO_ADJ_COL
     return false;
 #else
+    if (p->views) return false;
     return std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2) <= 4;
 #endif
 }
@@ -1155,6 +1156,7 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     if (s != CT_OK) return s;
     const int64_t nzown = slab.own_hi - slab.own_lo;
     if (nzown <= 0) return CT_OK;
+    if (p->views) return launch_backproject_views(p, kind, proj, pt, vol, vt, accumulate, a0, a1, slab, tab, st);
     if (slab.zcol && (kind != CT_BP_ADJOINT || !adj_col_ok(p)))
         return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's column kernel");
     BpArgs A = make_bp_args(p, tab, a0, a1, slab, accumulate);
@@ -1359,6 +1361,7 @@ ct_status launch_sart_update(ct_plan *p, const float *r, float *vol, int64_t a0,
     const AngleGeo *tab = nullptr;
     ct_status s = plan_device_table(p, st, &tab);
     if (s != CT_OK) return s;
+    if (p->views) return launch_sart_update_views(p, r, vol, a0, a1, lambda, tab, st);
     BpArgs A = make_bp_args(p, tab, a0, a1, full_slab(p->g), 1);
     const dim3 grid((A.nx + BP_TX - 1) / BP_TX, (A.ny + BP_TY - 1) / BP_TY, (unsigned)((A.nz + BP_NZ - 1) / BP_NZ));
     hipLaunchKernelGGL(k_sart_update, grid, dim3(256), 0, st, r, vol, A, lambda);

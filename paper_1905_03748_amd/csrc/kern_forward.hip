@@ -40,6 +40,7 @@ struct FwdArgs {
     double delta;            // interpolated projector sample spacing (mm)
     int32_t ublocks;
     int32_t cblocks, rgroups;  // column Siddon: column groups per angle, row groups per column
+    int32_t gen;               // a plan of views: rays take e_v (and e_u, C - S) in all three axes
 };
 
 struct RaySetup {
@@ -57,6 +58,12 @@ __device__ __forceinline__ bool ray_clip(const AngleGeo &G, const FwdArgs &A, in
     R.D[0] = G.Dc[0] + ua * G.eu[0];
     R.D[1] = G.Dc[1] + ua * G.eu[1];
     R.D[2] = vb / A.dz;
+    if (A.gen) {
+        // pixel centre C + ua e_u + vb e_v for any detector pose
+        R.D[0] = fma(vb, G.ev[0], R.D[0]);
+        R.D[1] = fma(vb, G.ev[1], R.D[1]);
+        R.D[2] = fma(vb, G.ev[2], fma(ua, G.eu[2], G.Dc[2]));
+    }
     const double m0 = R.D[0] * A.dx, m1 = R.D[1] * A.dy, m2 = R.D[2] * A.dz;
     R.L = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
     const double mm[3] = {m0, m1, m2};
@@ -297,6 +304,44 @@ struct ZPair<bf16s> {
         __builtin_memcpy(&w, col + k, sizeof(w));
         a = __uint_as_float(w << 16);
         b = __uint_as_float(w & 0xffff0000u);
+    }
+};
+
+// Four taps of an x-paired copy: (x, z), (x + 1, z), (x, z + 1), (x + 1, z + 1) in one load
+// (16 bytes for FP32, 8 for the 16-bit types; 4- or 8-byte aligned, which global loads allow).
+template <typename TV>
+struct XQuad;
+template <>
+struct XQuad<float> {
+    static __device__ __forceinline__ void ld(const float *p, float &a, float &b, float &c, float &d) {
+        float4 v;
+        __builtin_memcpy(&v, p, sizeof(v));
+        a = v.x;
+        b = v.y;
+        c = v.z;
+        d = v.w;
+    }
+};
+template <>
+struct XQuad<f16s> {
+    static __device__ __forceinline__ void ld(const f16s *p, float &a, float &b, float &c, float &d) {
+        uint2 w;
+        __builtin_memcpy(&w, p, sizeof(w));
+        a = (float)__builtin_bit_cast(f16s, (uint16_t)(w.x & 0xffffu));
+        b = (float)__builtin_bit_cast(f16s, (uint16_t)(w.x >> 16));
+        c = (float)__builtin_bit_cast(f16s, (uint16_t)(w.y & 0xffffu));
+        d = (float)__builtin_bit_cast(f16s, (uint16_t)(w.y >> 16));
+    }
+};
+template <>
+struct XQuad<bf16s> {
+    static __device__ __forceinline__ void ld(const bf16s *p, float &a, float &b, float &c, float &d) {
+        uint2 w;
+        __builtin_memcpy(&w, p, sizeof(w));
+        a = __uint_as_float(w.x << 16);
+        b = __uint_as_float(w.x & 0xffff0000u);
+        c = __uint_as_float(w.y << 16);
+        d = __uint_as_float(w.y & 0xffff0000u);
     }
 };
 
@@ -670,12 +715,46 @@ __global__ __launch_bounds__(256) void k_pcols(const TV *__restrict__ src, TV *_
     }
 }
 
+// The same zero-padded copy with x neighbours paired: element 2 (((yp PX + xp) PZ + zp)) + e holds
+// the padded voxel (xp + e - 1, yp - 1, zp - 1), so one load brings the two z taps of two x
+// neighbours (twice the memory of k_pcols' copy, half the loads per sample).
+template <typename TV>
+__global__ __launch_bounds__(256) void k_pcols2(const TV *__restrict__ src, TV *__restrict__ dst, int nx, int ny,
+                                                int nz) {
+    __shared__ TV tile[32][34];
+    const int PX = nx + 3, PZ = nz + 3;
+    const int xp0 = blockIdx.x * 32, zp0 = blockIdx.y * 32, yp = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int y = yp - 1;
+    // tile[z][x] for padded x in [xp0, xp0 + 33) and padded z in [zp0, zp0 + 32)
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int z = zp0 + ty + r - 1;
+        for (int c = tx; c < 33; c += 32) {
+            const int x = xp0 + c - 1;
+            TV v = from_f<TV>(0.0f);
+            if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) v = src[((int64_t)z * ny + y) * nx + x];
+            tile[ty + r][c] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int zp = zp0 + tx, xp = xp0 + ty + r;
+        if (xp < PX && zp < PZ) {
+            const int64_t o = (((int64_t)yp * PX + xp) * PZ + zp) * 2;
+            dst[o] = tile[tx][ty + r];
+            dst[o + 1] = tile[tx][ty + r + 1];
+        }
+    }
+}
+
 #ifndef CT_IC_BATCH
 #define CT_IC_BATCH 4
 #endif
 constexpr int IC_B = CT_IC_BATCH;  // samples per trip
 
-template <typename TV, typename TP, int ROWS>
+template <typename TV, typename TP, int ROWS, bool XP>
 __global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restrict__ vp, TP *__restrict__ proj,
                                                              FwdArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -758,11 +837,18 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restric
                 const int y0 = (int)__builtin_amdgcn_fmed3f(fly + (float)ib[r][1], -1.0f, yhi);
                 const int z0 = (int)__builtin_amdgcn_fmed3f(flz + (float)ib[r][2], -1.0f, zhi);
                 const int64_t c = nsm[r] > 0 ? ((int64_t)(y0 + 1) * PX + (x0 + 1)) * PZ + (z0 + 1) : 0;
-                const TV *q = vp + c;
-                ZPair<TV>::ld(q, 0u, v[u][r][0], v[u][r][1]);
-                ZPair<TV>::ld(q + PZ, 0u, v[u][r][2], v[u][r][3]);
-                ZPair<TV>::ld(q + cy, 0u, v[u][r][4], v[u][r][5]);
-                ZPair<TV>::ld(q + cy + PZ, 0u, v[u][r][6], v[u][r][7]);
+                if constexpr (XP) {
+                    // (x0, z0), (x0 + 1, z0), (x0, z0 + 1), (x0 + 1, z0 + 1) of rows y0 and y0 + 1
+                    const TV *q = vp + 2 * c;
+                    XQuad<TV>::ld(q, v[u][r][0], v[u][r][2], v[u][r][1], v[u][r][3]);
+                    XQuad<TV>::ld(q + 2 * cy, v[u][r][4], v[u][r][6], v[u][r][5], v[u][r][7]);
+                } else {
+                    const TV *q = vp + c;
+                    ZPair<TV>::ld(q, 0u, v[u][r][0], v[u][r][1]);
+                    ZPair<TV>::ld(q + PZ, 0u, v[u][r][2], v[u][r][3]);
+                    ZPair<TV>::ld(q + cy, 0u, v[u][r][4], v[u][r][5]);
+                    ZPair<TV>::ld(q + cy + PZ, 0u, v[u][r][6], v[u][r][7]);
+                }
             }
         }
 #pragma unroll
@@ -971,6 +1057,7 @@ FwdArgs make_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const
     A.accumulate = accumulate;
     A.delta = g.accuracy * fmin(g.dVoxel[0], fmin(g.dVoxel[1], g.dVoxel[2]));
     A.ublocks = (A.nu + FWD_TU - 1) / FWD_TU;
+    A.gen = p->views ? 1 : 0;
     return A;
 }
 
@@ -1046,6 +1133,8 @@ ct_status launch_zcols_inv_piece(const void *vz, ct_dtype vt, void *dst, int64_t
 }
 
 bool zcol_ok(const ct_plan *p, int64_t a0, int64_t a1) {
+    // the column walk needs vertical detector columns whose rays start at the source's height
+    if (p->views && !p->vertical) return false;
     // every xy piece must climb less than one slice: |Dz| < max(|Dx|, |Dy|) for every ray.
     // max(|Dx|, |Dy|) is convex and piecewise linear in the detector coordinate u, so its minimum
     // over the detector lies at an end or where Dx, Dy or Dx +- Dy vanish.
@@ -1153,16 +1242,27 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
             return CT_OK;
         }
     }
-    // interpolated projector on a resident volume: zero-padded column-major copy
+    // interpolated projector on a resident volume: zero-padded column-major copy, x-paired when
+    // its doubled size stays modest
     if (kind == CT_INTERP && whole && slab.scratch_ok) {
         const int64_t nz = g.nVoxel[2];
         const size_t pbytes = (size_t)((nx + 3) * (ny + 3) * (nz + 3)) * dtype_size(vt);
+#ifndef CT_IC_XPAIR_MAX
+#define CT_IC_XPAIR_MAX (size_t(16) << 30)
+#endif
+        const bool xp = 2 * pbytes <= CT_IC_XPAIR_MAX;
         void *vpad = nullptr;
-        if (hipMallocAsync(&vpad, pbytes, st) == hipSuccess) {
+        if (hipMallocAsync(&vpad, xp ? 2 * pbytes : pbytes, st) == hipSuccess) {
             const dim3 tg((unsigned)((nx + 3 + 31) / 32), (unsigned)((nz + 3 + 31) / 32), (unsigned)(ny + 3));
-            CT_DISPATCH1(vt, T,
-                         hipLaunchKernelGGL((k_pcols<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)vpad, (int)nx,
-                                            (int)ny, (int)nz));
+            if (xp) {
+                CT_DISPATCH1(vt, T,
+                             hipLaunchKernelGGL((k_pcols2<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)vpad, (int)nx,
+                                                (int)ny, (int)nz));
+            } else {
+                CT_DISPATCH1(vt, T,
+                             hipLaunchKernelGGL((k_pcols<T>), tg, dim3(256), 0, st, (const T *)vol, (T *)vpad, (int)nx,
+                                                (int)ny, (int)nz));
+            }
             CT_HIP(hipGetLastError());
             const int64_t nu = g.nDetector[0], nv = g.nDetector[1];
             const int64_t cblocks = (nu + ZC_COLS - 1) / ZC_COLS;
@@ -1177,15 +1277,23 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
                 A.rgroups = (int32_t)rgroups;
                 char *pp = (char *)proj + (size_t)(c0 - a0) * proj_angle;
                 const dim3 grid((unsigned)(cblocks * (c1 - c0) * rgroups)), block(64 * ZC_COLS);
+#define CT_ICOL(R, X)                                                                                          \
+    CT_DISPATCH2(vt, TV, pt, TP,                                                                               \
+                 hipLaunchKernelGGL((k_interp_col<TV, TP, R, X>), grid, block, 0, st, (const TV *)vpad, (TP *)pp, A))
                 if (rows == 2) {
-                    CT_DISPATCH2(vt, TV, pt, TP,
-                                 hipLaunchKernelGGL((k_interp_col<TV, TP, 2>), grid, block, 0, st, (const TV *)vpad,
-                                                    (TP *)pp, A));
+                    if (xp) {
+                        CT_ICOL(2, true);
+                    } else {
+                        CT_ICOL(2, false);
+                    }
                 } else {
-                    CT_DISPATCH2(vt, TV, pt, TP,
-                                 hipLaunchKernelGGL((k_interp_col<TV, TP, 1>), grid, block, 0, st, (const TV *)vpad,
-                                                    (TP *)pp, A));
+                    if (xp) {
+                        CT_ICOL(1, true);
+                    } else {
+                        CT_ICOL(1, false);
+                    }
                 }
+#undef CT_ICOL
                 CT_HIP(hipGetLastError());
             }
             CT_HIP(hipFreeAsync(vpad, st));

@@ -69,13 +69,25 @@ class Plan:
 
     geometry: dict with DSO, DSD, nVoxel (Nx,Ny,Nz), dVoxel, offOrigin, nDetector (Nu,Nv),
     dDetector, offDetector, accuracy.  Volumes are [Nz, Ny, Nx]; projections [n_angles, Nv, Nu].
+    angles: the angles of a circular orbit, or an n x 12 array of views (per projection the
+    source, detector centre and unit detector axes e_u, e_v, mm; ``ct_plan_create_views``), for
+    C-arm and helical scans.
     """
 
     def __init__(self, geometry: dict, angles):
         self.geometry = dict(geometry)
         self.cgeom = A.make_geometry(geometry)
         self.angles = np.ascontiguousarray(angles, dtype=np.float64)
-        self.handle = A.ct_plan_create(self.cgeom, self.angles)
+        if self.angles.ndim == 2:
+            if self.angles.shape[1] != 12:
+                raise ValueError("views must be an n x 12 array")
+            self.views = True
+            self.handle = A.ct_plan_create_views(self.cgeom, self.angles.tolist())
+        elif self.angles.ndim == 1:
+            self.views = False
+            self.handle = A.ct_plan_create(self.cgeom, self.angles)
+        else:
+            raise ValueError("angles must be 1-D (circular orbit) or n x 12 (views)")
         nx, ny, nz = (int(v) for v in geometry["nVoxel"])
         nu, nv = (int(v) for v in geometry["nDetector"])
         self.vol_shape = (nz, ny, nx)

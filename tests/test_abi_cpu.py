@@ -221,3 +221,52 @@ def test_host_operators_reject_wrong_shapes_before_the_library(lib):
         with pytest.raises(ValueError):
             call()
     plan.close()
+
+
+def test_plan_of_views_validation(lib):
+    """ct_plan_create_views (per-view geometry, Section 2.1) checks every view on the host."""
+    w = inputs.workload("tiny")
+    views = inputs.carm_views(w.DSO, w.DSD, w.angles[:8], 3)
+    p = A.ct_plan_create_views(_geo(), views.tolist())
+    g, n = A.ct_plan_info(p)
+    assert n == 8 and g.DSD > g.DSO > 0
+    A.ct_plan_destroy(p)
+    helical = inputs.helical_views(w.DSO, w.DSD, w.angles, 20.0)
+    A.ct_plan_destroy(A.ct_plan_create_views(_geo(), helical.tolist()))
+
+    def bad(mutate):
+        v = views.copy()
+        mutate(v)
+        with pytest.raises(A.CtError) as e:
+            A.ct_plan_create_views(_geo(), v.tolist())
+        assert e.value.status == A.CT_ERR_GEOMETRY, A.ct_last_error()
+
+    bad(lambda v: v.__setitem__((2, 6), v[2, 6] * 1.01))          # e_u not a unit vector
+    bad(lambda v: v.__setitem__((1, slice(9, 12)), (v[1, 9:12] + 0.01 * v[1, 6:9]) / np.linalg.norm(v[1, 9:12] + 0.01 * v[1, 6:9])))  # not orthogonal
+    bad(lambda v: v.__setitem__((0, slice(6, 9)), -v[0, 6:9]))    # normal turned away from the source
+    bad(lambda v: v.__setitem__((3, slice(0, 3)), 0.0))           # source inside the volume box
+    bad(lambda v: v.__setitem__((5, 4), float("nan")))
+    with pytest.raises(A.CtError) as e:
+        A.ct_plan_create_views(_geo(), [])
+    assert e.value.status == A.CT_ERR_ARG
+    with pytest.raises(ValueError):
+        A.ct_plan_create_views(_geo(), [[0.0] * 11])
+
+
+def test_plan_of_views_refuses_the_circular_only_calls(lib):
+    """The FDK reconstruction and the out-of-core calls need a circular orbit; a plan of views is
+    refused with CT_ERR_ARG before any device work (dummy pointers are never touched)."""
+    w = inputs.workload("tiny")
+    p = A.ct_plan_create_views(_geo(), inputs.carm_views(w.DSO, w.DSD, w.angles[:4], 5).tolist())
+    try:
+        for call in (lambda: A.ct_fdk_filter(p, 16, A.CT_F32, 16, 0, 4),
+                     lambda: A.ct_fdk(p, 16, A.CT_F32, 16, A.CT_F32),
+                     lambda: A.ct_fdk_host(p, 16, A.CT_F32, 16, A.CT_F32, 1 << 30),
+                     lambda: A.ct_forward_host(p, A.CT_SIDDON, 16, A.CT_F32, 16, A.CT_F32, 1 << 30),
+                     lambda: A.ct_backproject_host(p, A.CT_BP_FDK, 16, A.CT_F32, 16, A.CT_F32, 1 << 30),
+                     lambda: A.ct_ooc_plan(p, 0, A.CT_SIDDON, A.CT_F32, A.CT_F32, 1 << 30)):
+            with pytest.raises(A.CtError) as e:
+                call()
+            assert e.value.status == A.CT_ERR_ARG and "circular" in A.ct_last_error(), A.ct_last_error()
+    finally:
+        A.ct_plan_destroy(p)

@@ -1,0 +1,215 @@
+"""GPU parity of plans of views (Section 2.1: circular, C-arm and helical scans; Section 3.2's
+algorithms on them) against the CPU FP64 oracle's per-view operators, through the C ABI.
+
+Bars as for circular plans: projections 1e-5 relative L2, backprojections 1e-4 (FP32 storage).
+The per-view kernels also run on a circular orbit written as views, where they must agree with
+the circular kernels.
+"""
+import numpy as np
+import pytest
+import torch
+
+from _helpers import TOL_BP, TOL_PROJ, rel_l2, say
+from paper_1905_03748_amd import inputs
+from paper_1905_03748_amd.operators import Plan
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _ragged():
+    return inputs.Workload("views_ragged", (37, 29, 23), (1.1, 0.9, 1.3), (45, 33), (1.7, 1.9), 13, 10, 31,
+                           off_origin=(0.6, -0.4, 0.9), off_detector=(0.37, -0.21))
+
+
+def _views(kind, w):
+    if kind == "circular":
+        return None
+    if kind == "carm":
+        return inputs.carm_views(w.DSO, w.DSD, w.angles + 0.2, 17, tilt_deg=20.0, jitter_mm=5.0, orbit_tilt_deg=12.0)
+    if kind == "helical":
+        return inputs.helical_views(w.DSO, w.DSD, w.angles + 0.1, pitch=11.0, z0=-6.0)
+    raise KeyError(kind)
+
+
+@pytest.fixture(scope="module")
+def ragged(orc):
+    w = _ragged()
+    vol = inputs.voxelize(w)
+    y = inputs.random_array((13, 33, 45), 131, kind="uniform")
+    return w, vol, y, orc.Geometry.from_dict(w.geometry_dict())
+
+
+@pytest.mark.parametrize("kind", ["carm", "helical"])
+def test_views_operators_match_the_oracle(ragged, orc, kind):
+    w, vol, y, og = ragged
+    views = _views(kind, w)
+    plan = Plan(w.geometry_dict(), views)
+    assert plan.proj_shape == (13, 33, 45)
+    x = torch.from_numpy(vol).to(DEV)
+    v64 = vol.astype(np.float64)
+    for proj, fn in (("siddon", orc.siddon_fwd), ("interp", orc.interp_fwd)):
+        say(f"[views] {kind} forward {proj}")
+        got = plan.forward(x, proj).cpu().numpy()
+        e = rel_l2(got, fn(og, views, v64))
+        say(f"   rel L2 {e:.3e}")
+        assert e <= TOL_PROJ, (kind, proj, e)
+    yd = torch.from_numpy(y).to(DEV)
+    y64 = y.astype(np.float64)
+    for bp, ref in (("fdk", lambda: orc.bp(og, views, y64, orc.W_FDK)),
+                    ("pm", lambda: orc.bp(og, views, y64, orc.W_PM)),
+                    ("adjoint", lambda: orc.siddon_adj(og, views, y64))):
+        say(f"[views] {kind} backprojection {bp}")
+        got = plan.backproject(yd, bp).cpu().numpy()
+        e = rel_l2(got, ref())
+        say(f"   rel L2 {e:.3e}")
+        assert e <= TOL_BP, (kind, bp, e)
+
+
+def test_circular_orbit_as_views_equals_the_circular_kernels(ragged, orc):
+    """The per-view kernels on a circular orbit written as views against the column walks, the LDS
+    backprojectors and the exact adjoint's column kernel of the circular plan (both FP32, so to
+    FP32 rounding), and both against the oracle."""
+    w, vol, y, og = ragged
+    views = orc.circular_views(og, w.angles)
+    pv, pc = Plan(w.geometry_dict(), views), Plan(w.geometry_dict(), w.angles)
+    x = torch.from_numpy(vol).to(DEV)
+    yd = torch.from_numpy(y).to(DEV)
+    for proj in ("siddon", "interp"):
+        say(f"[views] circular as views, forward {proj}")
+        a, b = pv.forward(x, proj).cpu().numpy(), pc.forward(x, proj).cpu().numpy()
+        assert rel_l2(a, b) <= 2e-6, (proj, rel_l2(a, b))
+    for bp in ("fdk", "pm", "adjoint"):
+        say(f"[views] circular as views, backprojection {bp}")
+        a, b = pv.backproject(yd, bp).cpu().numpy(), pc.backproject(yd, bp).cpu().numpy()
+        assert rel_l2(a, b) <= 2e-6, (bp, rel_l2(a, b))
+
+
+@pytest.mark.parametrize("kind", ["carm", "helical"])
+def test_views_adjoint_dot_product_and_accumulate(ragged, orc, kind):
+    """<A u, v> = <u, A^T v> for the Siddon pair of a plan of views (non-negative vectors, so neither
+    side cancels); angle ranges with accumulation add up to the whole call."""
+    w, vol, y, og = ragged
+    plan = Plan(w.geometry_dict(), _views(kind, w))
+    rng = np.random.default_rng(5)
+    u = torch.from_numpy(rng.uniform(0, 1, plan.vol_shape).astype(np.float32)).to(DEV)
+    v = torch.from_numpy(rng.uniform(0, 1, plan.proj_shape).astype(np.float32)).to(DEV)
+    say(f"[views] {kind} dot product")
+    lhs = float((plan.forward(u).double() * v.double()).sum())
+    rhs = float((u.double() * plan.backproject(v, "adjoint").double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+    say(f"[views] {kind} accumulate over angle ranges")
+    whole = plan.backproject(v, "adjoint")
+    part = plan.backproject(v[:6].contiguous(), "adjoint", angle_begin=0, angle_end=6)
+    plan.backproject(v[6:].contiguous(), "adjoint", out=part, accumulate=True, angle_begin=6, angle_end=13)
+    assert rel_l2(part.cpu().numpy(), whole.cpu().numpy()) <= 1e-6
+    pf = plan.forward(u)
+    pp = torch.zeros_like(pf)
+    plan.forward(u, out=pp[:5], angle_begin=0, angle_end=5)
+    plan.forward(u, out=pp[5:], angle_begin=5, angle_end=13)
+    assert torch.equal(pp, pf)
+
+
+def test_views_16bit_storage(ragged, orc):
+    w, vol, y, og = ragged
+    views = _views("carm", w)
+    plan = Plan(w.geometry_dict(), views)
+    say("[views] FP16 volume and projections")
+    xh = torch.from_numpy(vol).half().to(DEV)
+    p = plan.forward(xh, "siddon")
+    assert p.dtype == torch.float16
+    ref = orc.siddon_fwd(og, views, xh.float().cpu().numpy().astype(np.float64))
+    assert rel_l2(p.float().cpu().numpy(), ref) <= 2.0 ** -10
+    yh = torch.from_numpy(y).half().to(DEV)
+    b = plan.backproject(yh, "fdk", out_dtype=torch.float32)
+    ref = orc.bp(og, views, yh.float().cpu().numpy().astype(np.float64), orc.W_FDK)
+    assert rel_l2(b.cpu().numpy(), ref) <= TOL_BP
+
+
+def test_views_cgls_and_os_sart(orc):
+    """CGLS (Siddon and its exact adjoint) and OS-SART (subsets of 3 views) on a helical plan
+    against the oracle's iterations on the same views."""
+    w = inputs.Workload("views_alg", (24, 22, 20), (1.6, 1.6, 1.6), (36, 30), (2.4, 2.4), 12, 10, 32)
+    views = inputs.helical_views(w.DSO, w.DSD, w.angles, pitch=16.0, z0=-8.0)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    xt = inputs.voxelize(w).astype(np.float64)
+    b = orc.siddon_fwd(og, views, xt)
+    plan = Plan(w.geometry_dict(), views)
+    bt = torch.from_numpy(b.astype(np.float32)).to(DEV)
+    say("[views] CGLS 5 iterations on a helical plan")
+    x, res = plan.cgls(bt, 5)
+    A = lambda v: orc.siddon_fwd(og, views, v)
+    At = lambda v: orc.siddon_adj(og, views, v)
+    xr, rr = orc.cgls(A, At, b, 5)
+    e = rel_l2(x.cpu().numpy(), xr)
+    say(f"   x rel L2 {e:.3e}")
+    assert e <= 1e-4
+    # the residual norms come from the FP64 recurrence over FP32 operators, whose differences from
+    # the oracle (about 1e-6 of their outputs) add up in absolute terms: bounded against the first
+    # residual, the data's own norm, as rho falls by two decades here
+    np.testing.assert_allclose(res.cpu().numpy(), rr, rtol=1e-4, atol=1e-5 * rr[0])
+    say("[views] OS-SART, subsets of 3, 2 sweeps")
+    xs = plan.sart(bt, 2, block=3, lam=0.9)
+    ref = orc.os_sart(og, views, b, 2, 3, lam=0.9)
+    e = rel_l2(xs.cpu().numpy(), ref)
+    say(f"   rel L2 {e:.3e}")
+    assert e <= 1e-4
+
+
+def test_views_noalloc_equals_backproject(ragged, orc):
+    w, vol, y, og = ragged
+    plan = Plan(w.geometry_dict(), _views("carm", w))
+    yd = torch.from_numpy(y).to(DEV)
+    from paper_1905_03748_amd import _abi as A
+    kinds = {"fdk": A.CT_BP_FDK, "pm": A.CT_BP_PSEUDO_MATCHED, "adjoint": A.CT_BP_ADJOINT}
+    for kind in ("fdk", "pm", "adjoint"):
+        say(f"[views] no-alloc {kind}")
+        ref = plan.backproject(yd, kind)   # also puts the plan's table on the device
+        out = torch.full_like(ref, -3.0)
+        torch.cuda.synchronize()
+        A.ct_backproject_noalloc(plan.handle, kinds[kind], yd.data_ptr(), A.CT_F32, out.data_ptr(), A.CT_F32, 0, 0,
+                                 plan.n_angles, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), kind
+
+
+def test_views_volume_off_the_detector_gives_zeros(orc):
+    """Every ray misses the volume and every voxel projects off the detector: all zeros."""
+    w = inputs.Workload("views_off", (16, 16, 16), (1.0, 1.0, 1.0), (20, 20), (1.0, 1.0), 3, 10, 33)
+    views = orc.circular_views(orc.Geometry.from_dict(w.geometry_dict()), w.angles)
+    views[:, 3:6] += 400.0 * views[:, 6:9]   # detector slid 400 mm sideways in its own plane
+    plan = Plan(w.geometry_dict(), views)
+    x = torch.ones(plan.vol_shape, device=DEV)
+    say("[views] volume off the detector")
+    assert float(plan.forward(x).abs().max()) == 0.0
+    y = torch.ones(plan.proj_shape, device=DEV)
+    for kind in ("fdk", "pm", "adjoint"):
+        assert float(plan.backproject(y, kind).abs().max()) == 0.0, kind
+
+
+def test_views_medium_helical_sampled(orc):
+    """A helical scan of a 256^3 volume, 180 views over two turns, 256^2 detector: sampled rays and
+    voxels against the oracle, in the launch configuration of a resident call."""
+    w = inputs.Workload("views_medium", (256, 256, 256), (1.0, 1.0, 1.0), (256, 256), (1.6, 1.6), 180, 40, 34)
+    th = 4.0 * np.pi * np.arange(180) / 180
+    views = inputs.helical_views(w.DSO, w.DSD, th, pitch=60.0, z0=-60.0)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    vol = inputs.voxelize(w)
+    plan = Plan(w.geometry_dict(), views)
+    x = torch.from_numpy(vol).to(DEV)
+    say("[views] helical 256^3 x 180 forward")
+    p = plan.forward(x).cpu().numpy().ravel()
+    idx = inputs.sample_indices(p.size, 1500, 35)
+    e = rel_l2(p[idx], orc.siddon_rays(og, views, idx, vol))
+    say(f"   sampled rays rel L2 {e:.3e}")
+    assert e <= TOL_PROJ
+    y = inputs.random_array(plan.proj_shape, 36, kind="uniform")
+    yd = torch.from_numpy(y).to(DEV)
+    vidx = inputs.sample_indices(vol.size, 300, 37)
+    for kind in ("fdk", "adjoint"):
+        say(f"[views] helical 256^3 x 180 backprojection {kind}")
+        v = plan.backproject(yd, kind).cpu().numpy().ravel()
+        ref = orc.bp_voxels(og, views, y, vidx, orc.W_FDK) if kind == "fdk" else orc.siddon_adj_voxels(og, views, y, vidx)
+        e = rel_l2(v[vidx], ref)
+        say(f"   sampled voxels rel L2 {e:.3e}")
+        assert e <= TOL_BP
