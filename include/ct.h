@@ -157,6 +157,11 @@ ct_status ct_backproject_noalloc(ct_plan *plan, ct_backprojector backprojector, 
  * the projections into chunks of angles; copies run on side streams overlapped with kernels;
  * partial projections from earlier slabs are accumulated inside the projection kernel.
  * Host arrays may be pageable (staged through a pinned ring) or pinned (copied directly).
+ * Only rows of the detector that a slab's rays can meet are moved (per-slab row bands).  With the
+ * environment variable CT_OOC_SLAB_BUFFERS=2 the backprojections (and ct_fdk_host) hold two slab
+ * buffers, each half as tall for the same cap, and copy a finished slab out on a host thread of
+ * its own while the next slab accumulates (double-slab buffering); results are the same bit for
+ * bit.  The planner (ct_ooc_plan) follows the same setting.
  * Errors: CT_ERR_ARG, CT_ERR_DTYPE, CT_ERR_CAP (cap below one slice plus buffers), CT_ERR_OOM,
  * CT_ERR_HIP.  Stats may be NULL. */
 typedef struct {

@@ -1,5 +1,6 @@
 // C ABI entry points, geometry validation, per-angle tables and error reporting.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -20,6 +21,20 @@ ct_status hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     if (e == hipErrorOutOfMemory) return CT_ERR_OOM;
     return CT_ERR_HIP;
+}
+
+hipError_t fault_check() {
+    const char *e = std::getenv("CT_FAULT_ALLOC");
+    if (!e || !e[0]) return hipSuccess;
+    static std::mutex mu;
+    static std::string last;
+    static long count = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (last != e) {
+        last = e;
+        count = 0;
+    }
+    return ++count == std::strtol(e, nullptr, 10) ? hipErrorOutOfMemory : hipSuccess;
 }
 
 size_t dtype_size(ct_dtype t) { return t == CT_F64 ? 8 : t == CT_F32 ? 4 : 2; }
@@ -167,7 +182,7 @@ ct_status plan_device_table(ct_plan *p, hipStream_t st, const AngleGeo **out) {
     if (it == p->dtab.end()) {
         ct_plan::DevTab t{nullptr, nullptr};
         const size_t bytes = sizeof(AngleGeo) * p->tab.size();
-        CT_HIP(hipMallocAsync((void **)&t.ptr, bytes, st));
+        CT_HIP(CT_MALLOC_ASYNC((void **)&t.ptr, bytes, st));
         hipError_t e = hipMemcpyAsync(t.ptr, p->tab.data(), bytes, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t.ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(t.ready, st);

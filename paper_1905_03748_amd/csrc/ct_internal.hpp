@@ -40,6 +40,15 @@ void set_error(const std::string &msg);
 ct_status fail(ct_status st, const std::string &msg);
 ct_status hip_fail(hipError_t e, const char *what);
 
+// Allocation-failure injection for tests of the error paths: with CT_FAULT_ALLOC=n (optionally
+// followed by ":tag"), the n-th device or pinned allocation of the library after the variable last
+// changed fails as out-of-memory.  Unset, it costs one getenv per allocation.
+hipError_t fault_check();
+#define CT_MALLOC(p, n) (::ct::fault_check() != hipSuccess ? hipErrorOutOfMemory : hipMalloc((p), (n)))
+#define CT_MALLOC_ASYNC(p, n, s) (::ct::fault_check() != hipSuccess ? hipErrorOutOfMemory : hipMallocAsync((p), (n), (s)))
+#define CT_HOST_MALLOC(p, n) \
+    (::ct::fault_check() != hipSuccess ? hipErrorOutOfMemory : hipHostMalloc((p), (n), hipHostMallocDefault))
+
 #define CT_HIP(call)                                              \
     do {                                                          \
         hipError_t e_ = (call);                                   \

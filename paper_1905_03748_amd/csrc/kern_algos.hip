@@ -308,7 +308,7 @@ struct Workspace {
             return CT_OK;
         }
         owned = true;
-        CT_HIP(hipMallocAsync((void **)&base, bytes ? bytes : 256, s));
+        CT_HIP(CT_MALLOC_ASYNC((void **)&base, bytes ? bytes : 256, s));
         return CT_OK;
     }
     ~Workspace() {
@@ -646,11 +646,11 @@ ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double la
     OwnStream S;
     CT_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
     DevMem xb, gb, saved, parts, scal;
-    CT_HIP(hipMalloc(&xb.p, (size_t)(h + 2) * sb));
-    CT_HIP(hipMalloc(&gb.p, (size_t)h * sb));
-    CT_HIP(hipMalloc(&saved.p, (size_t)sb));
-    CT_HIP(hipMalloc(&parts.p, DOT_BLOCKS * 8));
-    CT_HIP(hipMalloc(&scal.p, 4 * 8));
+    CT_HIP(CT_MALLOC(&xb.p, (size_t)(h + 2) * sb));
+    CT_HIP(CT_MALLOC(&gb.p, (size_t)h * sb));
+    CT_HIP(CT_MALLOC(&saved.p, (size_t)sb));
+    CT_HIP(CT_MALLOC(&parts.p, DOT_BLOCKS * 8));
+    CT_HIP(CT_MALLOC(&scal.p, 4 * 8));
     float *xbuf = (float *)xb.p, *gbuf = (float *)gb.p;
     double *dscal = (double *)scal.p;
     const hipStream_t s = S.s;
@@ -762,11 +762,11 @@ ct_status tv_host_run_halo(const ct_geometry &g, float *hx, int32_t nsteps, doub
     OwnStream S;
     CT_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
     DevMem xb, gb, saved, parts, scal;
-    CT_HIP(hipMalloc(&xb.p, (size_t)(h + 2 * d) * sb));
-    CT_HIP(hipMalloc(&gb.p, (size_t)(h + 2 * d) * sb));
-    CT_HIP(hipMalloc(&saved.p, (size_t)d * sb));
-    CT_HIP(hipMalloc(&parts.p, DOT_BLOCKS * 8));
-    CT_HIP(hipMalloc(&scal.p, 4 * 8));
+    CT_HIP(CT_MALLOC(&xb.p, (size_t)(h + 2 * d) * sb));
+    CT_HIP(CT_MALLOC(&gb.p, (size_t)(h + 2 * d) * sb));
+    CT_HIP(CT_MALLOC(&saved.p, (size_t)d * sb));
+    CT_HIP(CT_MALLOC(&parts.p, DOT_BLOCKS * 8));
+    CT_HIP(CT_MALLOC(&scal.p, 4 * 8));
     float *xbuf = (float *)xb.p, *gbuf = (float *)gb.p, *sbuf = (float *)saved.p;
     double *dscal = (double *)scal.p;
     const hipStream_t s = S.s;
@@ -873,10 +873,10 @@ ct_status rof_host_run(const ct_geometry &g, float *hx, int32_t niter, double la
     OwnStream S;
     CT_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
     DevMem fm, pm[3], wm, sm;
-    CT_HIP(hipMalloc(&fm.p, (size_t)L * sb));
-    for (auto &b : pm) CT_HIP(hipMalloc(&b.p, (size_t)L * sb));
-    CT_HIP(hipMalloc(&wm.p, (size_t)L * sb));
-    CT_HIP(hipMalloc(&sm.p, (size_t)3 * d * sb));
+    CT_HIP(CT_MALLOC(&fm.p, (size_t)L * sb));
+    for (auto &b : pm) CT_HIP(CT_MALLOC(&b.p, (size_t)L * sb));
+    CT_HIP(CT_MALLOC(&wm.p, (size_t)L * sb));
+    CT_HIP(CT_MALLOC(&sm.p, (size_t)3 * d * sb));
     float *fb = (float *)fm.p, *wb = (float *)wm.p, *sv = (float *)sm.p;
     float *pb[3] = {(float *)pm[0].p, (float *)pm[1].p, (float *)pm[2].p};
     const hipStream_t s = S.s;

@@ -1210,7 +1210,7 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         void *yq = adj_scratch, *own = nullptr;
         size_t qcap = adj_scratch ? adj_bytes : 0;
         if (nr <= 4 && !yq && slab.scratch_ok) {
-            if (hipMallocAsync(&own, (size_t)(a1 - a0) * per_angle, st) == hipSuccess) {
+            if (CT_MALLOC_ASYNC(&own, (size_t)(a1 - a0) * per_angle, st) == hipSuccess) {
                 yq = own;
                 qcap = (size_t)(a1 - a0) * per_angle;
             } else {

@@ -150,7 +150,7 @@ ct_status fdk_filter(ct_plan *p, const void *proj, ct_dtype pt, float *q, int64_
 ct_status fdk_run(ct_plan *p, const void *proj, ct_dtype pt, void *vol, ct_dtype vt, void *work, hipStream_t st) {
     const int64_t na = (int64_t)p->angles.size();
     float *q = (float *)work;
-    if (!q) CT_HIP(hipMallocAsync((void **)&q, fdk_workspace(p), st));
+    if (!q) CT_HIP(CT_MALLOC_ASYNC((void **)&q, fdk_workspace(p), st));
     ct_status s = fdk_filter(p, proj, pt, q, 0, na, st);
     if (s == CT_OK) s = launch_backproject(p, CT_BP_FDK, q, CT_F32, vol, vt, 0, 0, na, full_slab(p->g), st);
     if (!work) (void)hipFreeAsync(q, st);

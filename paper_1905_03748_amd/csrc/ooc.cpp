@@ -17,6 +17,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -107,7 +109,17 @@ struct Layout {
     int64_t halo;     // extra slices each side (interpolated forward)
     bool col;         // Siddon forward: the slab is held column-major (2 zero slots per column)
                       // and uploaded through a device stage of ZSTAGE slices
+    int nbufs = 1;    // backprojection: slab buffers (2: the finished slab goes out while the next
+                      // one accumulates)
 };
+
+// Slab buffers for the backprojection: CT_OOC_SLAB_BUFFERS=2 holds two slabs (each half as tall)
+// so that a finished slab is copied out while the next one accumulates, overlapping the copy with
+// the kernels (double-slab buffering); the default 1 keeps the tallest slabs.
+int slab_buffers() {
+    const char *e = std::getenv("CT_OOC_SLAB_BUFFERS");
+    return (e && e[0] == '2') ? 2 : 1;
+}
 
 // direction: 0 forward, 1 backprojection (FDK, pseudo-matched), 2 exact-adjoint backprojection
 ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtype vt, ct_dtype pt, uint64_t cap,
@@ -122,6 +134,8 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
     // slices held besides the slab: the forward's column stage, the interpolated projector's halo,
     // or the exact adjoint's stage for turning its column-major slab back into slices
     const int64_t extra = L.col ? 2 + ZSTAGE : (direction == 2 && adj_col_ok(p) ? ZSTAGE : 2 * L.halo);
+    const int want_bufs = direction == 0 ? 1 : slab_buffers();
+    L.nbufs = 1;
     // chunk size: enough rays (forward) or angles (backprojection) per launch to fill the device.
     // The exact adjoint's lanes run down voxel columns, so its slab accumulators are read and
     // written with a stride of one slice once per launch: it takes more angles per launch, each
@@ -154,8 +168,23 @@ ct_status layout_for(const ct_plan *p, int direction, ct_projector proj, ct_dtyp
         }
         if (found && k <= kmin) break;
     }
-    if (found) return CT_OK;
-    return fail(CT_ERR_CAP, "device memory cap is below one slice plus the projection buffers");
+    if (!found) return fail(CT_ERR_CAP, "device memory cap is below one slice plus the projection buffers");
+    if (want_bufs == 2 && L.nsp > 1) {
+        // two slab buffers in the same budget, with the chunk size of the single-buffer plan (its
+        // kernels' efficiency is unchanged; only the slabs get thinner)
+        const int64_t k = L.K;
+        const uint64_t bufs = nbuf * (uint64_t)k * pangle +
+                              (direction == 2 ? (uint64_t)k * adj_chunk_bytes_per_angle(g) : 0) +
+                              (direction == 3 ? (uint64_t)k * pix * sizeof(float) : 0);
+        const int64_t h = ((int64_t)((cap - RESERVE - bufs) / slice) - 2 * extra) / 2;
+        if (h >= 1) {
+            const int64_t nsp = (g.nVoxel[2] + h - 1) / h;
+            L.nsp = nsp;
+            L.h = (g.nVoxel[2] + nsp - 1) / nsp;
+            L.nbufs = 2;
+        }
+    }
+    return CT_OK;
 }
 
 // Detector rows [b0, b1) whose rays can meet the heights [zlo, zhi] (mm) of the volume (Section
@@ -249,18 +278,18 @@ ct_status ooc_forward(ct_plan *p, ct_projector kind, const void *h_vol, ct_dtype
     CT_HIP(hipStreamCreateWithFlags(&S.h2d, hipStreamNonBlocking));
     CT_HIP(hipStreamCreateWithFlags(&S.d2h, hipStreamNonBlocking));
     DevBuf slab, stage, dbuf[3];
-    CT_HIP(hipMalloc(&slab.p, (L.h + (L.col ? 2 : 2 * L.halo)) * slice));
-    if (L.col) CT_HIP(hipMalloc(&stage.p, ZSTAGE * slice));
-    for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
+    CT_HIP(CT_MALLOC(&slab.p, (L.h + (L.col ? 2 : 2 * L.halo)) * slice));
+    if (L.col) CT_HIP(CT_MALLOC(&stage.p, ZSTAGE * slice));
+    for (auto &b : dbuf) CT_HIP(CT_MALLOC(&b.p, chunk_bytes));
     HostBuf sin[3], sout[3], svol[2];
     const auto tp = clk::now();
     if (!proj_pinned)
         for (int j = 0; j < 3; ++j) {
-            CT_HIP(hipHostMalloc(&sin[j].p, chunk_bytes, hipHostMallocDefault));
-            CT_HIP(hipHostMalloc(&sout[j].p, chunk_bytes, hipHostMallocDefault));
+            CT_HIP(CT_HOST_MALLOC(&sin[j].p, chunk_bytes));
+            CT_HIP(CT_HOST_MALLOC(&sout[j].p, chunk_bytes));
         }
     if (!vol_pinned)
-        for (auto &b : svol) CT_HIP(hipHostMalloc(&b.p, STAGE_PIECE, hipHostMallocDefault));
+        for (auto &b : svol) CT_HIP(CT_HOST_MALLOC(&b.p, STAGE_PIECE));
     st.t_pin_s += secs(tp, clk::now());
     Events ev_h2d, ev_k, ev_d2h, ev_vol, tk0, tk1;
     if ((s = ev_h2d.make(3)) != CT_OK || (s = ev_k.make(3)) != CT_OK || (s = ev_d2h.make(3)) != CT_OK ||
@@ -464,24 +493,40 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
     // the exact adjoint accumulates into a column-major slab (its lanes run down the columns), which
     // goes out through a stage of ZSTAGE slices
     const bool zcol = kind == CT_BP_ADJOINT && adj_col_ok(p);
-    DevBuf slab, dbuf[2], adj, stage, filt;
-    CT_HIP(hipMalloc(&slab.p, L.h * slice));
-    if (zcol) CT_HIP(hipMalloc(&stage.p, ZSTAGE * slice));
-    for (auto &b : dbuf) CT_HIP(hipMalloc(&b.p, chunk_bytes));
+    const int NB = L.nbufs;
+    DevBuf slab[2], dbuf[2], adj, stage[2], filt;
+    for (int k = 0; k < NB; ++k) {
+        CT_HIP(CT_MALLOC(&slab[k].p, L.h * slice));
+        if (zcol) CT_HIP(CT_MALLOC(&stage[k].p, ZSTAGE * slice));
+    }
+    for (auto &b : dbuf) CT_HIP(CT_MALLOC(&b.p, chunk_bytes));
     const size_t adj_bytes = (size_t)L.K * adj_chunk_bytes_per_angle(g);  // one transposed copy per chunk
-    if (kind == CT_BP_ADJOINT) CT_HIP(hipMalloc(&adj.p, adj_bytes));
+    if (kind == CT_BP_ADJOINT) CT_HIP(CT_MALLOC(&adj.p, adj_bytes));
     // FDK reconstruction: each chunk is weighted and filtered into an FP32 buffer, which the
     // backprojection reads (both on the compute stream, so the buffer is reused in order)
-    if (fdk_filtered) CT_HIP(hipMalloc(&filt.p, (size_t)L.K * g.nDetector[0] * g.nDetector[1] * sizeof(float)));
-    HostBuf sin[2], svol[2];
+    if (fdk_filtered) CT_HIP(CT_MALLOC(&filt.p, (size_t)L.K * g.nDetector[0] * g.nDetector[1] * sizeof(float)));
+    HostBuf sin[2], svol[2][2];
     const auto tp = clk::now();
     if (!proj_pinned)
-        for (auto &b : sin) CT_HIP(hipHostMalloc(&b.p, chunk_bytes, hipHostMallocDefault));
+        for (auto &b : sin) CT_HIP(CT_HOST_MALLOC(&b.p, chunk_bytes));
     if (!vol_pinned)
-        for (auto &b : svol) CT_HIP(hipHostMalloc(&b.p, STAGE_PIECE, hipHostMallocDefault));
+        for (int k = 0; k < NB; ++k)
+            for (auto &b : svol[k]) CT_HIP(CT_HOST_MALLOC(&b.p, STAGE_PIECE));
     st.t_pin_s += secs(tp, clk::now());
-    Events ev_h2d, ev_k, ev_vol, tk0, tk1;
-    if ((s = ev_h2d.make(2)) != CT_OK || (s = ev_k.make(2)) != CT_OK || (s = ev_vol.make(2)) != CT_OK) return s;
+    Events ev_h2d, ev_k, ev_vol[2], ev_slab, tk0, tk1;
+    if ((s = ev_h2d.make(2)) != CT_OK || (s = ev_k.make(2)) != CT_OK || (s = ev_vol[0].make(2)) != CT_OK ||
+        (s = ev_vol[1].make(2)) != CT_OK || (s = ev_slab.make(2)) != CT_OK)
+        return s;
+    // the way out for finished slabs (with two slab buffers, on a thread of its own)
+    hipStream_t s_out[2] = {nullptr, nullptr};
+    struct OutStreams {
+        hipStream_t *s;
+        ~OutStreams() {
+            for (int k = 0; k < 2; ++k)
+                if (s[k]) (void)hipStreamDestroy(s[k]);
+        }
+    } out_guard{s_out};
+    for (int k = 0; k < NB; ++k) CT_HIP(hipStreamCreateWithFlags(&s_out[k], hipStreamNonBlocking));
     tk0.e.resize(nchunks, nullptr);
     tk1.e.resize(nchunks, nullptr);
     for (int64_t c = 0; c < nchunks; ++c) {
@@ -489,10 +534,111 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
         CT_HIP(hipEventCreate(&tk1.e[c]));
     }
     st.t_other_mem_s += secs(t0, clk::now());
+    int dev = 0;
+    CT_HIP(hipGetDevice(&dev));
+
+    // Copy slab n (buffer k, slices [own_lo, own_hi)) to h_vol once its kernels have finished (event
+    // ev_slab[k]): column-major slabs through the stage, pageable memory through the pinned ring.
+    // Stages its own buffers and stream only, so it may run beside the next slab's chunk loop.
+    struct OutResult {
+        ct_status s = CT_OK;
+        std::string err;
+        double t_stage = 0.0;
+    };
+    auto slab_out = [&](int k, int64_t own_lo, int64_t own_hi, OutResult &r) {
+        auto chk = [&](hipError_t e, const char *what) {
+            if (e != hipSuccess && r.s == CT_OK) {
+                r.s = e == hipErrorOutOfMemory ? CT_ERR_OOM : CT_ERR_HIP;
+                r.err = std::string(what) + ": " + hipGetErrorString(e);
+            }
+            return e == hipSuccess;
+        };
+        if (!chk(hipSetDevice(dev), "hipSetDevice")) return;
+        hipStream_t so = s_out[k];
+        if (!chk(hipStreamWaitEvent(so, ev_slab.e[k], 0), "hipStreamWaitEvent")) return;
+        char *dst = (char *)h_vol + own_lo * slice;
+        auto download = [&](const char *src, char *hdst, size_t len_all) -> bool {
+            if (vol_pinned) {
+                return chk(hipMemcpyAsync(hdst, src, len_all, hipMemcpyDeviceToHost, so), "slab download") &&
+                       chk(hipStreamSynchronize(so), "slab download");
+            }
+            // pipelined: piece q goes D2H while piece q-1 is copied out of staging by the host
+            size_t off = 0, prev_off = 0, prev_len = 0;
+            int q = 0, prev_q = -1;
+            while (off < len_all || prev_q >= 0) {
+                int cur = -1;
+                size_t len = 0;
+                if (off < len_all) {
+                    len = std::min(STAGE_PIECE, len_all - off);
+                    if (!chk(hipMemcpyAsync(svol[k][q].p, src + off, len, hipMemcpyDeviceToHost, so), "slab download") ||
+                        !chk(hipEventRecord(ev_vol[k].e[q], so), "hipEventRecord"))
+                        return false;
+                    cur = q;
+                }
+                if (prev_q >= 0) {
+                    if (!chk(hipEventSynchronize(ev_vol[k].e[prev_q]), "hipEventSynchronize")) return false;
+                    auto b = clk::now();
+                    par_memcpy(hdst + prev_off, svol[k][prev_q].p, prev_len);
+                    r.t_stage += secs(b, clk::now());
+                }
+                prev_q = cur;
+                prev_off = off;
+                prev_len = len;
+                off += len;
+                q ^= 1;
+            }
+            return true;
+        };
+        if (zcol) {
+            const int64_t nzown = own_hi - own_lo;
+            for (int64_t z0 = 0; z0 < nzown; z0 += ZSTAGE) {
+                const int64_t zn = std::min(ZSTAGE, nzown - z0);
+                ct_status zs = launch_zcols_inv_piece(slab[k].p, vt, stage[k].p, g.nVoxel[0], g.nVoxel[1], zn, nzown, z0, so);
+                if (zs != CT_OK) {
+                    r.s = zs;
+                    r.err = "slab transpose launch failed";
+                    return;
+                }
+                if (!chk(hipStreamSynchronize(so), "slab transpose")) return;
+                if (!download((const char *)stage[k].p, dst + z0 * slice, zn * slice)) return;
+            }
+        } else {
+            download((const char *)slab[k].p, dst, (size_t)(own_hi - own_lo) * slice);
+        }
+    };
+    std::thread out_thread[2];
+    OutResult out_res[2];
+    int64_t out_lo[2] = {0, 0}, out_hi[2] = {0, 0};
+    // wait for the copy-out of buffer k (if any) and take over its result
+    auto join_out = [&](int k) -> ct_status {
+        if (!out_thread[k].joinable()) return CT_OK;
+        auto a = clk::now();
+        out_thread[k].join();
+        st.t_other_mem_s += secs(a, clk::now());
+        st.t_stage_s += out_res[k].t_stage;
+        st.bytes_d2h += (double)(out_hi[k] - out_lo[k]) * slice;
+        if (out_res[k].s != CT_OK) return fail(out_res[k].s, out_res[k].err);
+        if (verbose()) {
+            std::fprintf(stderr, "[ct ooc backprojection] slices %lld-%lld out at %.1f s\n", (long long)out_lo[k],
+                         (long long)out_hi[k] - 1, secs(t_start, clk::now()));
+            std::fflush(stderr);
+        }
+        return CT_OK;
+    };
+    struct JoinAll {
+        std::thread *t;
+        ~JoinAll() {
+            for (int k = 0; k < 2; ++k)
+                if (t[k].joinable()) t[k].join();
+        }
+    } join_guard{out_thread};
 
     for (int64_t n = 0; n < L.nsp; ++n) {
         const int64_t own_lo = n * L.h, own_hi = std::min(nz, own_lo + L.h);
         if (own_lo >= own_hi) break;
+        const int kbuf = (int)(n % NB);
+        // the buffer's previous slab must be out before it accumulates again
+        if ((s = join_out(kbuf)) != CT_OK) return s;
         Slab sl;
         sl.own_lo = own_lo;
         sl.own_hi = own_hi;
@@ -541,70 +687,35 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
                 bp_in = filt.p;
                 bp_t = CT_F32;
             }
-            if ((s = launch_backproject(p, kind, bp_in, bp_t, slab.p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp, adj.p,
-                                        adj.p ? adj_bytes : 0)) != CT_OK)
+            if ((s = launch_backproject(p, kind, bp_in, bp_t, slab[kbuf].p, vt, c > 0 ? 1 : 0, a0, a1, sl, S.comp,
+                                        adj.p, adj.p ? adj_bytes : 0)) != CT_OK)
                 return s;
             CT_HIP(hipEventRecord(tk1.e[c], S.comp));
             CT_HIP(hipEventRecord(ev_k.e[j], S.comp));
         }
-        // slab out
-        auto a = clk::now();
-        CT_HIP(hipStreamSynchronize(S.comp));
+        // slab out: after its last kernel; with two buffers on a thread of its own while the next
+        // slab accumulates in the other buffer
+        CT_HIP(hipEventRecord(ev_slab.e[kbuf], S.comp));
+        out_lo[kbuf] = own_lo;
+        out_hi[kbuf] = own_hi;
+        out_res[kbuf] = OutResult();
+        if (NB == 2) {
+            out_thread[kbuf] = std::thread(slab_out, kbuf, own_lo, own_hi, std::ref(out_res[kbuf]));
+        } else {
+            auto a = clk::now();
+            slab_out(kbuf, own_lo, own_hi, out_res[kbuf]);
+            st.t_other_mem_s += secs(a, clk::now());
+            st.t_stage_s += out_res[kbuf].t_stage;
+            st.bytes_d2h += (double)(own_hi - own_lo) * slice;
+            if (out_res[kbuf].s != CT_OK) return fail(out_res[kbuf].s, out_res[kbuf].err);
+        }
+        // the chunk kernels' times (their events are reused by the next slab)
+        CT_HIP(hipEventSynchronize(tk1.e[nchunks - 1]));
         for (int64_t c = 0; c < nchunks; ++c) {
             float ms = 0;
             CT_HIP(hipEventElapsedTime(&ms, tk0.e[c], tk1.e[c]));
             st.t_compute_s += ms * 1e-3;
         }
-        char *dst = (char *)h_vol + own_lo * slice;
-        const size_t total = (own_hi - own_lo) * slice;
-        // device bytes [src, src + len) to host hdst, through the pinned ring when pageable
-        auto download = [&](const char *src, char *hdst, size_t len_all) -> ct_status {
-            if (vol_pinned) {
-                CT_HIP(hipMemcpyAsync(hdst, src, len_all, hipMemcpyDeviceToHost, S.d2h));
-                CT_HIP(hipStreamSynchronize(S.d2h));
-                return CT_OK;
-            }
-            // pipelined: piece q goes D2H while piece q-1 is copied out of staging by the host
-            size_t off = 0, prev_off = 0, prev_len = 0;
-            int q = 0, prev_q = -1;
-            while (off < len_all || prev_q >= 0) {
-                int cur = -1;
-                size_t len = 0;
-                if (off < len_all) {
-                    len = std::min(STAGE_PIECE, len_all - off);
-                    CT_HIP(hipMemcpyAsync(svol[q].p, src + off, len, hipMemcpyDeviceToHost, S.d2h));
-                    CT_HIP(hipEventRecord(ev_vol.e[q], S.d2h));
-                    cur = q;
-                }
-                if (prev_q >= 0) {
-                    CT_HIP(hipEventSynchronize(ev_vol.e[prev_q]));
-                    auto b = clk::now();
-                    par_memcpy(hdst + prev_off, svol[prev_q].p, prev_len);
-                    st.t_stage_s += secs(b, clk::now());
-                }
-                prev_q = cur;
-                prev_off = off;
-                prev_len = len;
-                off += len;
-                q ^= 1;
-            }
-            return CT_OK;
-        };
-        if (zcol) {
-            const int64_t nzown = own_hi - own_lo;
-            for (int64_t z0 = 0; z0 < nzown; z0 += ZSTAGE) {
-                const int64_t zn = std::min(ZSTAGE, nzown - z0);
-                if ((s = launch_zcols_inv_piece(slab.p, vt, stage.p, g.nVoxel[0], g.nVoxel[1], zn, nzown, z0,
-                                                S.comp)) != CT_OK)
-                    return s;
-                CT_HIP(hipStreamSynchronize(S.comp));
-                if ((s = download((const char *)stage.p, dst + z0 * slice, zn * slice)) != CT_OK) return s;
-            }
-        } else {
-            if ((s = download((const char *)slab.p, dst, total)) != CT_OK) return s;
-        }
-        st.bytes_d2h += (double)total;
-        st.t_other_mem_s += secs(a, clk::now());
         if (verbose()) {
             std::fprintf(stderr, "[ct ooc backprojection] slab %lld/%lld (slices %lld-%lld) done at %.1f s\n",
                          (long long)n + 1, (long long)L.nsp, (long long)own_lo, (long long)own_hi - 1,
@@ -612,6 +723,8 @@ ct_status ooc_backproject(ct_plan *p, ct_backprojector kind, const void *h_proj,
             std::fflush(stderr);
         }
     }
+    for (int k = 0; k < NB; ++k)
+        if ((s = join_out(k)) != CT_OK) return s;
     st.t_total_s = secs(t_start, clk::now());
     if (stats) *stats = st;
     return CT_OK;

@@ -15,7 +15,7 @@ DEV = "cuda:0"
 RESERVE = 64 << 20
 
 
-def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=torch.float32):
+def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=torch.float32, nbufs=1):
     """A cap that leaves exactly `slices` slices next to the planner's smallest chunk buffers (the
     planner shrinks chunks down to an eighth of its target when that gives fewer slabs).
     direction 0: forward; 1: FDK or pseudo-matched backprojection; 2: exact adjoint; 3: FDK
@@ -34,7 +34,7 @@ def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=
     adj = kmin * nu * (nv + 2) * 8 if direction == 2 else 0
     adj += kmin * nu * nv * 4 if direction == 3 else 0   # the FDK reconstruction's filtered chunk
     extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0) + (8 if direction == 2 else 0)
-    return RESERVE + nbuf * kmin * pangle + adj + (slices + extra) * slice_b
+    return RESERVE + nbuf * kmin * pangle + adj + nbufs * (slices + extra) * slice_b
 
 
 @pytest.fixture(scope="module")
@@ -164,3 +164,38 @@ def test_ooc_cap_errors(case):
     with pytest.raises(CtError) as e:
         plan.forward_host(torch.from_numpy(vol), torch.zeros(plan.proj_shape), "siddon", cap_bytes=1 << 20)
     assert e.value.status == CT_ERR_CAP
+
+
+@pytest.mark.parametrize("slices", [5, 2])
+def test_backprojection_double_slab_bitwise(case, orc, slices, monkeypatch):
+    """Two slab buffers (CT_OOC_SLAB_BUFFERS=2): a finished slab is copied out on a thread of its own
+    while the next one accumulates in the other buffer (Algorithm 2 with the copy-out overlapped).
+    The planner keeps the single-buffer plan's chunk size and halves the slabs; every result is
+    still bitwise the resident one."""
+    w, vol, y = case
+    plan = Plan(w.geometry_dict(), w.angles)
+    yh = torch.from_numpy(y)
+    yd = yh.to(DEV)
+    for kind in ("fdk", "pm", "adjoint"):
+        direction = 2 if kind == "adjoint" else 1
+        cap = _cap_for(plan, slices, direction, nbufs=2)
+        monkeypatch.delenv("CT_OOC_SLAB_BUFFERS", raising=False)
+        single = plan.ooc_plan(direction, cap_bytes=cap)
+        monkeypatch.setenv("CT_OOC_SLAB_BUFFERS", "2")
+        info = plan.ooc_plan(direction, cap_bytes=cap)
+        say(f"[ooc double slab] slices={slices} kind={kind} single={single} double={info}")
+        assert single["n_slabs"] > 1 and info["slab_slices"] < single["slab_slices"]
+        assert info["chunk_angles"] == single["chunk_angles"]
+        for pinned in (False, True):
+            out = torch.full(plan.vol_shape, -7.0)
+            out = out.pin_memory() if pinned else out
+            src = yh.pin_memory() if pinned else yh.clone()
+            st = plan.backproject_host(src, out, kind, cap_bytes=cap)
+            assert st["n_slabs"] == info["n_slabs"]
+            assert torch.equal(out, plan.backproject(yd, kind).cpu()), (kind, pinned, st)
+    cap = _cap_for(plan, slices, 3, nbufs=2)
+    out = torch.full(plan.vol_shape, -7.0)
+    st = plan.fdk_host(yh, out, cap_bytes=cap)
+    say(f"[ooc double slab] fdk reconstruction {st}")
+    assert st["n_slabs"] > 1
+    assert torch.equal(out, plan.fdk(yd).cpu())
