@@ -433,6 +433,7 @@ __device__ __forceinline__ void zc_walk(const TV *__restrict__ vz, int64_t lin, 
     }
 }
 
+
 template <typename TV, typename TP, int ROWS>
 __global__ __launch_bounds__(64 * ZC_COLS) void k_siddon_col(const TV *__restrict__ vz, TP *__restrict__ proj,
                                                              FwdArgs A) {
@@ -816,8 +817,24 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restric
     for (int r = 0; r < ROWS; ++r) acc[r] = 0.0f;
     const int64_t cy = PX * PZ;
     const float xhi = (float)A.nx, yhi = (float)A.ny, zhi = (float)A.nz;
+#ifndef CT_IC_NO_REUSE
+    constexpr bool REUSE = XP;
+#else
+    constexpr bool REUSE = false;
+#endif
+    // the previous sample's cell and taps: samples half a voxel apart share a cell about half the
+    // time, and a lane that stays in its cell loads nothing
+    int64_t cprev[ROWS];
+    float vprev[ROWS][8];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        cprev[r] = -1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vprev[r][i] = 0.0f;
+    }
     for (int j0 = 0; j0 < nmax; j0 += IC_B) {
         float w[IC_B][ROWS][3], v[IC_B][ROWS][8];
+        int64_t cu[IC_B][ROWS];
 #pragma unroll
         for (int u = 0; u < IC_B; ++u) {
 #pragma unroll
@@ -837,7 +854,18 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restric
                 const int y0 = (int)__builtin_amdgcn_fmed3f(fly + (float)ib[r][1], -1.0f, yhi);
                 const int z0 = (int)__builtin_amdgcn_fmed3f(flz + (float)ib[r][2], -1.0f, zhi);
                 const int64_t c = nsm[r] > 0 ? ((int64_t)(y0 + 1) * PX + (x0 + 1)) * PZ + (z0 + 1) : 0;
-                if constexpr (XP) {
+                cu[u][r] = c;
+                if constexpr (REUSE) {
+                    const int64_t cp = u == 0 ? cprev[r] : cu[u - 1][r];
+                    if (c != cp) {
+                        const TV *q = vp + 2 * c;
+                        XQuad<TV>::ld(q, v[u][r][0], v[u][r][2], v[u][r][1], v[u][r][3]);
+                        XQuad<TV>::ld(q + 2 * cy, v[u][r][4], v[u][r][6], v[u][r][5], v[u][r][7]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) v[u][r][i] = u == 0 ? vprev[r][i] : v[u - 1][r][i];
+                    }
+                } else if constexpr (XP) {
                     // (x0, z0), (x0 + 1, z0), (x0, z0 + 1), (x0 + 1, z0 + 1) of rows y0 and y0 + 1
                     const TV *q = vp + 2 * c;
                     XQuad<TV>::ld(q, v[u][r][0], v[u][r][2], v[u][r][1], v[u][r][3]);
@@ -863,6 +891,14 @@ __global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restric
                 const float c0 = fmaf(rx, c10 - c00, c00), c1 = fmaf(rx, c11 - c01, c01);
                 const float val = fmaf(ry, c1 - c0, c0);
                 acc[r] += (j0 + u < nsm[r]) ? val : 0.0f;
+            }
+        }
+        if constexpr (REUSE) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                cprev[r] = cu[IC_B - 1][r];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) vprev[r][i] = v[IC_B - 1][r][i];
             }
         }
     }
@@ -1193,7 +1229,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
         void *own_z = nullptr;
         if (!vz) {
             const size_t zbytes = (size_t)(nx * ny * (nz + 2)) * dtype_size(vt);
-            if (hipMallocAsync(&own_z, zbytes, st) == hipSuccess) {
+            if (CT_MALLOC_ASYNC(&own_z, zbytes, st) == hipSuccess) {
                 ct_status zs = launch_zcols(vol, vt, own_z, nx, ny, nz, st);
                 if (zs != CT_OK) return zs;
                 vz = own_z;
@@ -1252,7 +1288,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
 #endif
         const bool xp = 2 * pbytes <= CT_IC_XPAIR_MAX;
         void *vpad = nullptr;
-        if (hipMallocAsync(&vpad, xp ? 2 * pbytes : pbytes, st) == hipSuccess) {
+        if (CT_MALLOC_ASYNC(&vpad, xp ? 2 * pbytes : pbytes, st) == hipSuccess) {
             const dim3 tg((unsigned)((nx + 3 + 31) / 32), (unsigned)((nz + 3 + 31) / 32), (unsigned)(ny + 3));
             if (xp) {
                 CT_DISPATCH1(vt, T,
@@ -1314,7 +1350,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
 #else
     const bool want_t = !volT && slab.scratch_ok && nx > 1 && ny > 1;
 #endif
-    if (want_t && hipMallocAsync(&own_t, vbytes, st) != hipSuccess) {
+    if (want_t && CT_MALLOC_ASYNC(&own_t, vbytes, st) != hipSuccess) {
         (void)hipGetLastError();
         own_t = nullptr;
     }
