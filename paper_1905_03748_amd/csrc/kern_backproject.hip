@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_bp_voxel(const TP *__restrict__ proj, T
                 const float v1 = fmaf(wa1, p[k][3], wa0 * p[k][2]);
                 const float v = fmaf(fb[k], v1 - v0, v0);
                 float wk = w;
-                if (W != CT_BP_FDK) wk = wpm * sqrtf(fmaf(zk[k], zk[k], rxy2));
+                if (W != CT_BP_FDK) wk = wpm * __builtin_amdgcn_sqrtf(fmaf(zk[k], zk[k], rxy2));
                 acc[k] = fmaf(wk, v, acc[k]);
             }
         }
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W == CT_BP_
                     float wk = w;
                     if (W != CT_BP_FDK) {
                         const float zk = fmaf((float)k, A.dz, zk0);
-                        wk = wpm * sqrtf(fmaf(zk, zk, rxy2));
+                        wk = wpm * __builtin_amdgcn_sqrtf(fmaf(zk, zk, rxy2));
                     }
                     acc[k] = fmaf(wk, v, acc[k]);
                 }

@@ -20,8 +20,11 @@
 // chord through the voxel box is the slab intersection about that point.  The chord equals the sum
 // of the Siddon pieces the ray leaves in the voxel; a ray that lies in a face goes to the voxel
 // above the face (a half-open slab), as in the projector.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
+#include <mutex>
 
 #include "dev_common.hpp"
 
@@ -101,8 +104,9 @@ __device__ __forceinline__ void view_ref(const VArgs &A, const AngleGeo &G, doub
     R.w0 = (float)(MODE == VM_PM ? G.pmc : MODE == VM_ADJ ? 1.0 / G.DSDv : G.DSOv);
 }
 
-// Runs of VB_NZ slices start at absolute multiples of VB_NZ.
-__device__ __forceinline__ int run_base(const VArgs &A) { return (A.own_lo / VB_NZ + (int)blockIdx.z) * VB_NZ; }
+// Runs of NZ slices start at absolute multiples of NZ.
+template <int NZ = VB_NZ>
+__device__ __forceinline__ int run_base(const VArgs &A) { return (A.own_lo / NZ + (int)blockIdx.z) * NZ; }
 
 // FDK, pseudo-matched or SART: bilinear taps at each voxel's own detector coordinates.
 template <int MODE, typename TP, typename TV>
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(256) void k_bp_views(const TP *__restrict__ proj, T
     const int i0 = blockIdx.x * VB_TX, j0 = blockIdx.y * VB_TY;
     const int i = i0 + (threadIdx.x % VB_TX);
     const int j = j0 + (threadIdx.x / VB_TX);
-    const int kb = run_base(A);
+    const int kb = run_base<>(A);
     const bool live = i < A.nx && j < A.ny;
     const double ir = tile_mid(i0, VB_TX, A.nx), jr = tile_mid(j0, VB_TY, A.ny), kr = tile_mid(kb, VB_NZ, A.nz);
     const float di = (float)((double)i - ir), dj = (float)((double)j - jr);
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bp_views(const TP *__restrict__ proj, T
                 p[k][3] = bload(Rs, o00 + rowb + dca, (TP *)nullptr);
                 if (MODE == VM_PM) {
                     const float sz = fmaf(dk[k], A.dz, R.sz);
-                    wt[k] = R.w0 * sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz))) * iw * iw * iw;
+                    wt[k] = R.w0 * __builtin_amdgcn_sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz))) * iw * iw * iw;
                 } else {
                     const float qq = R.w0 * iw;
                     wt[k] = qq * qq;
@@ -212,6 +216,209 @@ __global__ __launch_bounds__(256) void k_bp_views(const TP *__restrict__ proj, T
     }
 }
 
+// FDK and pseudo-matched backprojection with the taps staged in LDS.  For each view the block
+// projects the eight corners of its 16 x 16 x VL_NZ tile (clipped to the grid) through the local
+// form of the projective map: a perspective map with positive depth over the box sends it into the
+// convex hull of its corners' images, so the window [floor(min a*) - 1, ...] x [floor(min b*) - 1,
+// ...] holds every bilinear tap of every voxel of the tile.  Its width is at most WW columns and its
+// height at most HW rows under any tile and view (vl_window, on the host); each view's own height
+// comes from its corners, and as many views as fit (up to VL_K) are staged together, windows one
+// after another at a row pitch of PITCH floats (lanes on consecutive pixels, zeros off the
+// detector).  Taps are clamped into their view's window, so no access leaves it.  The voxels read
+// their taps there with the per-voxel arithmetic of k_bp_views; the view's constant factor of the
+// weight (DSO_v^2, or the pseudo-matched constant) is applied to the staged pixels.
+#ifndef CT_VL_NZ
+#define CT_VL_NZ 16
+#endif
+constexpr int VL_NZ = CT_VL_NZ;  // voxels per thread
+#ifndef CT_VL_FLOATS
+#define CT_VL_FLOATS 4096
+#endif
+constexpr int VL_FLOATS = CT_VL_FLOATS;  // staged floats per block
+constexpr int VL_G = 32;                 // views per group of tile references (8 corner lanes each)
+constexpr int VL_PN = 41, VL_PW = 65;    // row pitches of narrow and wide windows
+#ifndef CT_VL_K
+#define CT_VL_K 8
+#endif
+constexpr int VL_K = CT_VL_K;            // views per staging round, at most
+static_assert(VL_NZ * 256 <= VL_FLOATS, "the staging window parks the sums");
+#ifndef CT_VL_WAVES
+#define CT_VL_WAVES 6
+#endif
+
+template <int MODE, int PITCH, typename TP, typename TV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT_VL_WAVES))) void k_bp_views_lds(
+    const TP *__restrict__ proj, TV *__restrict__ vol, VArgs A, int WW, int HW) {
+    __shared__ float win[VL_FLOATS];
+    __shared__ VRef ref[VL_G];
+    __shared__ int org[VL_G][2];
+    __shared__ int hgt[VL_G];
+    const int i0 = blockIdx.x * VB_TX, j0 = blockIdx.y * VB_TY;
+    const int tid = threadIdx.x;
+    const int i = i0 + (tid % VB_TX);
+    const int j = j0 + (tid / VB_TX);
+    const int kb = run_base<VL_NZ>(A);
+    const bool live = i < A.nx && j < A.ny;
+    const double ir = tile_mid(i0, VB_TX, A.nx), jr = tile_mid(j0, VB_TY, A.ny), kr = tile_mid(kb, VL_NZ, A.nz);
+    const float di = (float)((double)i - ir), dj = (float)((double)j - jr), dk0 = (float)((double)kb - kr);
+    const int64_t psz = (int64_t)A.nu * A.nv;
+    constexpr int ROWS = VL_FLOATS / PITCH;  // rows of the staging buffer
+    const float lamax = (float)(WW - 2);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    // this thread's tile corner (offsets from the reference point, clipped to the grid)
+    const int cn = tid & 7;
+    const float cx = (float)((double)((cn & 1) ? min(i0 + VB_TX, A.nx) - 1 : i0) - ir);
+    const float cy = (float)((double)((cn & 2) ? min(j0 + VB_TY, A.ny) - 1 : j0) - jr);
+    const float cz = (float)((double)((cn & 4) ? min(kb + VL_NZ, A.nz) - 1 : kb) - kr);
+    float acc[VL_NZ];
+    for (int g0 = 0; g0 < A.nang; g0 += VL_G) {
+        const int ng = min(VL_G, A.nang - g0);
+        if (g0 > 0) {
+            // park the sums in the window while the group's references are formed in FP64
+            __syncthreads();  // the last round's taps have been read
+#pragma unroll
+            for (int k = 0; k < VL_NZ; ++k) win[k * 256 + tid] = acc[k];
+        }
+        if (tid < ng) {
+            VRef R;
+            float fa, fb;
+            view_ref<MODE>(A, A.tab[A.a0 + g0 + tid], ir, jr, kr, R, fa, fb);
+            ref[tid] = R;
+            org[tid][0] = (int)fa;
+            org[tid][1] = (int)fb;
+        }
+        __syncthreads();
+        {
+            // lanes 8q .. 8q + 7: the tile's corners under view q of the group (FP32, relative to
+            // the view's integer origin), reduced to the window's origin and height
+            const int q = tid >> 3;
+            float as = 0.0f, bs = 0.0f;
+            if (q < ng) {
+                const VRef &R = ref[q];
+                const float w = fmaf(R.mw[0], cx, fmaf(R.mw[1], cy, fmaf(R.mw[2], cz, R.wr)));
+                const float iw = __builtin_amdgcn_rcpf(w);
+                // far off the detector every tap reads zero; the clamp keeps the integers small
+                as = __builtin_amdgcn_fmed3f(fmaf(fmaf(R.ga[0], cx, fmaf(R.ga[1], cy, R.ga[2] * cz)), iw, R.Aloc),
+                                             -16777216.0f, 16777216.0f);
+                bs = __builtin_amdgcn_fmed3f(fmaf(fmaf(R.gb[0], cx, fmaf(R.gb[1], cy, R.gb[2] * cz)), iw, R.Bloc),
+                                             -16777216.0f, 16777216.0f);
+            }
+            float amin = as, bmin = bs, bmax = bs;
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                amin = fminf(amin, __shfl_xor(amin, off, 64));
+                bmin = fminf(bmin, __shfl_xor(bmin, off, 64));
+                bmax = fmaxf(bmax, __shfl_xor(bmax, off, 64));
+            }
+            __syncthreads();  // every corner has read its reference
+            if (cn == 0 && q < ng) {
+                const int wa = (int)floorf(amin) - 1, wb = (int)floorf(bmin) - 1;
+                ref[q].Aloc -= (float)wa;
+                ref[q].Bloc -= (float)wb;
+                org[q][0] += wa;
+                org[q][1] += wb;
+                // rows wb .. floor(bmax) + 2: the taps' rows with a row of margin each side
+                hgt[q] = min((int)floorf(bmax) - wb + 3, HW);
+            }
+        }
+        __syncthreads();
+        if (g0 == 0) {
+            // one base address, slices a uniform stride apart (the stride is hidden from the
+            // compiler so the addresses of all slices are not kept live from the start)
+            int64_t sl = (int64_t)A.nx * A.ny;
+            asm volatile("" : "+s"(sl));
+            const TV *vb = vol + ((int64_t)(kb - A.mem_lo) * A.ny + j) * A.nx + i;
+#pragma unroll
+            for (int k = 0; k < VL_NZ; ++k) {
+                const int kk = kb + k;
+                acc[k] = (live && A.accumulate && kk >= A.own_lo && kk < A.own_hi) ? to_f(vb[k * sl]) : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < VL_NZ; ++k) acc[k] = win[k * 256 + tid];
+        }
+        for (int t0 = 0; t0 < ng;) {
+            // the views t0 .. t1 - 1 whose windows fit the buffer together (at least one: HW <= ROWS)
+            int t1 = t0, rows = 0;
+            while (t1 < ng && t1 - t0 < VL_K && rows + hgt[t1] <= ROWS) rows += hgt[t1++];
+            __syncthreads();  // the buffer is free (parked sums read back, or the last round's taps read)
+            // stage: wave w copies rows w, w + 4, ... of every window; lane = window column
+            int rb = 0;
+            for (int q = t0; q < t1; ++q) {
+                const int h = hgt[q];
+                const int u = org[q][0] + lane;
+                const bool uok = lane < WW && (unsigned)u < (unsigned)A.nu;
+                const TP *pq = proj + (int64_t)(g0 + q) * psz + u;
+                float *wq = win + rb * PITCH + lane;
+                const int ob = org[q][1];
+                const float w0 = ref[q].w0;
+                const float sc = MODE == VM_PM ? w0 : w0 * w0;
+                for (int r = wave; r < h; r += 4) {
+                    const int v = ob + r;
+                    float val = 0.0f;
+                    if (uok && (unsigned)v < (unsigned)A.nv) val = to_f(pq[(int64_t)v * A.nu]) * sc;
+                    if (lane < WW) wq[r * PITCH] = val;
+                }
+                rb += h;
+            }
+            __syncthreads();
+            if (live) {
+                rb = 0;
+                for (int q = t0; q < t1; ++q) {
+                    const VRef R = ref[q];
+                    const int h = hgt[q];
+                    const float lbmax = (float)(h - 2);
+                    const float qb = (float)(rb * PITCH * 4);
+                    rb += h;
+                    const float wxy = fmaf(R.mw[0], di, fmaf(R.mw[1], dj, R.wr));
+                    const float axy = fmaf(R.ga[0], di, R.ga[1] * dj), bxy = fmaf(R.gb[0], di, R.gb[1] * dj);
+                    const float sx = fmaf(di, A.dx, R.sx), sy = fmaf(dj, A.dy, R.sy);
+                    const float sxy2 = fmaf(sx, sx, sy * sy);
+#pragma unroll
+                    for (int k = 0; k < VL_NZ; ++k) {
+                        const float dk = dk0 + (float)k;
+                        const float w = fmaf(R.mw[2], dk, wxy);
+                        const float iw = __builtin_amdgcn_rcpf(w);
+                        const float as = fmaf(fmaf(R.ga[2], dk, axy), iw, R.Aloc);
+                        const float bs = fmaf(fmaf(R.gb[2], dk, bxy), iw, R.Bloc);
+                        const float af = floorf(as), bf = floorf(bs);
+                        const float fa = as - af, fb = bs - bf;
+                        // LDS byte offset of the tap pair, clamped into the window (exact in FP32)
+                        const float la = __builtin_amdgcn_fmed3f(af, 0.0f, lamax);
+                        const float lb = __builtin_amdgcn_fmed3f(bf, 0.0f, lbmax);
+                        const float *t =
+                            (const float *)((const char *)win + (int)fmaf(lb, (float)(4 * PITCH), fmaf(la, 4.0f, qb)));
+                        const float v0 = fmaf(fa, t[1] - t[0], t[0]);
+                        const float v1 = fmaf(fa, t[PITCH + 1] - t[PITCH], t[PITCH]);
+                        const float v = fmaf(fb, v1 - v0, v0);
+                        float wt;
+                        if (MODE == VM_PM) {
+                            const float sz = fmaf(dk, A.dz, R.sz);
+                            wt = __builtin_amdgcn_sqrtf(fmaf(sz, sz, sxy2)) * iw * iw * iw;
+                        } else {
+                            wt = iw * iw;
+                        }
+                        acc[k] = fmaf(wt, v, acc[k]);
+                    }
+                }
+            }
+            t0 = t1;
+        }
+    }
+    if (!live || A.nang <= 0) return;
+    int64_t sl = (int64_t)A.nx * A.ny;
+    asm volatile("" : "+s"(sl));
+    TV *vs = vol + ((int64_t)(kb - A.mem_lo) * A.ny + j) * A.nx + i;
+#pragma unroll
+    for (int k = 0; k < VL_NZ; ++k) {
+        const int kk = kb + k;
+        if (kk < A.own_lo) continue;
+        if (kk >= A.own_hi) break;
+        vs[k * sl] = from_f<TV>(acc[k]);
+    }
+}
+
 // Exact adjoint of the Siddon projector for plans of views (see the header).
 template <typename TP, typename TV>
 __global__ __launch_bounds__(256) void k_adj_views(const TP *__restrict__ proj, TV *__restrict__ vol, VArgs A) {
@@ -221,7 +428,7 @@ __global__ __launch_bounds__(256) void k_adj_views(const TP *__restrict__ proj, 
     const int i0 = blockIdx.x * VB_TX, j0 = blockIdx.y * VB_TY;
     const int i = i0 + (threadIdx.x % VB_TX);
     const int j = j0 + (threadIdx.x / VB_TX);
-    const int kb = run_base(A);
+    const int kb = run_base<>(A);
     const bool live = i < A.nx && j < A.ny;
     const double ir = tile_mid(i0, VB_TX, A.nx), jr = tile_mid(j0, VB_TY, A.ny), kr = tile_mid(kb, VB_NZ, A.nz);
     const float di = (float)((double)i - ir), dj = (float)((double)j - jr);
@@ -319,7 +526,7 @@ __global__ __launch_bounds__(256) void k_adj_views(const TP *__restrict__ proj, 
                                 thi = fminf(thi, fmaxf(t1, t2));
                             }
                         }
-                        const float len = (in && thi > tlo) ? (thi - tlo) * sqrtf(fmaf(D0, D0, fmaf(D1, D1, D2 * D2))) : 0.0f;
+                        const float len = (in && thi > tlo) ? (thi - tlo) * __builtin_amdgcn_sqrtf(fmaf(D0, D0, fmaf(D1, D1, D2 * D2))) : 0.0f;
                         if (len > 0.0f) s = fmaf(bload(Rs, (b * A.nu + a) * ES, (TP *)nullptr), len, s);
                     }
                 }
@@ -366,11 +573,93 @@ VArgs make_vargs(const ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, 
     return A;
 }
 
-dim3 vgrid(const VArgs &A, const Slab &slab) {
-    const unsigned runs = (unsigned)((slab.own_hi - 1) / VB_NZ - slab.own_lo / VB_NZ + 1);
+// CT_VIEWS_BP_DIRECT=1 sends the FDK and pseudo-matched backprojections of plans of views to the
+// kernel without LDS staging (tests compare the two).
+bool direct_views_bp() {
+    const char *e = std::getenv("CT_VIEWS_BP_DIRECT");
+    return e && e[0] == '1';
+}
+
+dim3 vgrid(const VArgs &A, const Slab &slab, int nz = VB_NZ) {
+    const unsigned runs = (unsigned)((slab.own_hi - 1) / nz - slab.own_lo / nz + 1);
     return dim3((unsigned)((A.nx + VB_TX - 1) / VB_TX), (unsigned)((A.ny + VB_TY - 1) / VB_TY), runs);
 }
 
+// Detector window (columns WW, rows HW) holding the taps of any 16 x 16 x VL_NZ tile, clipped to
+// the grid, under any view of the plan; 0 x 0 when some view's is too large for the staging buffer.
+// With L = n.(S - X) the depth, p = e_u.(X - S) and a* = const + DSD_v p / (L du), two points of a
+// tile differ in a* by at most DSD_v (E_p / L_min + |p|_max E_L / L_min^2) / du, where E_p and E_L
+// bound the change of p and L over the tile's extent (the sums of |e_u| and |n| times the extent
+// along each axis), and L_min and |p|_max are taken over the corners of a box holding the tile (both
+// are affine in X).  The grid is cut into VL_NS^3 boxes, each grown by a tile's extent so that every
+// tile lies in one, and the largest bound is kept; likewise for b* with e_v.  Margins: one pixel
+// each side plus the second tap.  Computed once per plan.
+constexpr int VL_NS = 4;
+void vl_window(ct_plan *p, int &WW, int &HW) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->vl_ww >= 0) {
+        WW = p->vl_ww;
+        HW = p->vl_hw;
+        return;
+    }
+    const ct_geometry &g = p->g;
+    double x0[3], x1[3], ext[3];
+    const int64_t tn[3] = {VB_TX, VB_TY, VL_NZ};
+    for (int a = 0; a < 3; ++a) {
+        x0[a] = g.offOrigin[a] - (g.nVoxel[a] - 1) / 2.0 * g.dVoxel[a];
+        x1[a] = x0[a] + (g.nVoxel[a] - 1) * g.dVoxel[a];
+        ext[a] = (double)(std::min(tn[a], g.nVoxel[a]) - 1) * g.dVoxel[a];
+    }
+    double eu_max = 0.0, ev_max = 0.0;
+    bool ok = true;
+    for (const AngleGeo &t : p->tab) {
+        double eu[3], ev[3];
+        for (int a = 0; a < 3; ++a) {
+            eu[a] = t.eu[a] * g.dVoxel[a];
+            ev[a] = t.ev[a] * g.dVoxel[a];
+        }
+        const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2], eu[0] * ev[1] - eu[1] * ev[0]};
+        double Ep = 0.0, Eq = 0.0, EL = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            Ep += std::fabs(eu[a]) * ext[a];
+            Eq += std::fabs(ev[a]) * ext[a];
+            EL += std::fabs(n[a]) * ext[a];
+        }
+        for (int b = 0; b < VL_NS * VL_NS * VL_NS; ++b) {
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                const int s = a == 0 ? b % VL_NS : a == 1 ? (b / VL_NS) % VL_NS : b / (VL_NS * VL_NS);
+                lo[a] = std::max(x0[a] + (x1[a] - x0[a]) * s / VL_NS - ext[a], x0[a]);
+                hi[a] = std::min(x0[a] + (x1[a] - x0[a]) * (s + 1) / VL_NS + ext[a], x1[a]);
+            }
+            double Lmin = HUGE_VAL, Pu = 0.0, Pv = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                double d[3];
+                for (int a = 0; a < 3; ++a) d[a] = (((c >> a) & 1) ? hi[a] : lo[a]) - t.Smm[a];
+                Lmin = std::min(Lmin, -(n[0] * d[0] + n[1] * d[1] + n[2] * d[2]));
+                Pu = std::max(Pu, std::fabs(eu[0] * d[0] + eu[1] * d[1] + eu[2] * d[2]));
+                Pv = std::max(Pv, std::fabs(ev[0] * d[0] + ev[1] * d[1] + ev[2] * d[2]));
+            }
+            ok = ok && Lmin > 0.0;
+            if (!ok) break;
+            eu_max = std::max(eu_max, t.DSDv * (Ep / Lmin + Pu * EL / (Lmin * Lmin)) / g.dDetector[0]);
+            ev_max = std::max(ev_max, t.DSDv * (Eq / Lmin + Pv * EL / (Lmin * Lmin)) / g.dDetector[1]);
+        }
+        if (!ok || !(eu_max < 62.0 && ev_max < 1000.0)) {
+            ok = false;
+            break;
+        }
+    }
+    WW = HW = 0;
+    if (ok) {
+        WW = (int)std::ceil(eu_max) + 4;
+        HW = (int)std::ceil(ev_max) + 4;
+        // one lane per window column when staging
+        if (WW > 64 || HW > VL_FLOATS / (WW <= VL_PN ? VL_PN : VL_PW)) WW = HW = 0;
+    }
+    p->vl_ww = WW;
+    p->vl_hw = HW;
+}
 }  // namespace
 
 ct_status launch_backproject_views(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
@@ -380,6 +669,32 @@ ct_status launch_backproject_views(ct_plan *p, ct_backprojector kind, const void
     if (slab.zcol) return fail(CT_ERR_STATE, "a plan of views backprojects into [z][y][x] volumes only");
     const VArgs A = make_vargs(p, tab, a0, a1, slab, accumulate);
     const dim3 grid = vgrid(A, slab), block(256);
+    int WW = 0, HW = 0;
+    if (kind != CT_BP_ADJOINT) vl_window(p, WW, HW);
+    if (WW > 0 && !direct_views_bp()) {
+        const bool narrow = WW <= VL_PN;
+        const dim3 lgrid = vgrid(A, slab, VL_NZ);
+#define CT_VL(MODE, PITCH)                                                                                      \
+    CT_DISPATCH2(pt, TP, vt, TV,                                                                                \
+                 hipLaunchKernelGGL((k_bp_views_lds<MODE, PITCH, TP, TV>), lgrid, block, 0, st, (const TP *)proj, \
+                                    (TV *)vol, A, WW, HW))
+        if (kind == CT_BP_FDK) {
+            if (narrow) {
+                CT_VL(VM_FDK, VL_PN);
+            } else {
+                CT_VL(VM_FDK, VL_PW);
+            }
+        } else {
+            if (narrow) {
+                CT_VL(VM_PM, VL_PN);
+            } else {
+                CT_VL(VM_PM, VL_PW);
+            }
+        }
+#undef CT_VL
+        CT_HIP(hipGetLastError());
+        return CT_OK;
+    }
     if (kind == CT_BP_FDK) {
         CT_DISPATCH2(pt, TP, vt, TV,
                      hipLaunchKernelGGL((k_bp_views<VM_FDK, TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));

@@ -213,3 +213,51 @@ def test_views_medium_helical_sampled(orc):
         e = rel_l2(v[vidx], ref)
         say(f"   sampled voxels rel L2 {e:.3e}")
         assert e <= TOL_BP
+
+
+@pytest.mark.parametrize("kind", ["carm", "helical", "circular"])
+def test_views_staged_backprojection_equals_direct(ragged, orc, kind, monkeypatch):
+    """The FDK and pseudo-matched backprojections of plans of views stage each tile's detector window
+    in LDS; with CT_VIEWS_BP_DIRECT=1 they read their taps from memory instead.  The two differ only
+    in rounding (the view's weight constant is applied to the staged pixels), and both have the
+    oracle's bar.  FP32 and FP16 projections, whole calls and angle ranges with accumulation."""
+    w, vol, y, og = ragged
+    views = orc.circular_views(og, w.angles) if kind == "circular" else _views(kind, w)
+    plan = Plan(w.geometry_dict(), views)
+    for dt in (torch.float32, torch.float16):
+        yd = torch.from_numpy(y).to(DEV).to(dt)
+        for bp in ("fdk", "pm"):
+            say(f"[views] {kind} staged vs direct {bp} {dt}")
+            monkeypatch.delenv("CT_VIEWS_BP_DIRECT", raising=False)
+            a = plan.backproject(yd, bp, out_dtype=torch.float32)
+            part = plan.backproject(yd[:5].contiguous(), bp, out_dtype=torch.float32, angle_begin=0, angle_end=5)
+            plan.backproject(yd[5:].contiguous(), bp, out=part, accumulate=True, angle_begin=5, angle_end=13)
+            monkeypatch.setenv("CT_VIEWS_BP_DIRECT", "1")
+            b = plan.backproject(yd, bp, out_dtype=torch.float32)
+            monkeypatch.delenv("CT_VIEWS_BP_DIRECT")
+            assert not torch.equal(a, b), "the staged kernel did not run"
+            e = rel_l2(a.cpu().numpy(), b.cpu().numpy())
+            say(f"   rel L2 {e:.3e}")
+            assert e <= 2e-6, (kind, bp, e)
+            assert rel_l2(part.cpu().numpy(), a.cpu().numpy()) <= 1e-6
+            ref = orc.bp(og, views, yd.float().cpu().numpy().astype(np.float64), orc.W_FDK if bp == "fdk" else orc.W_PM)
+            assert rel_l2(a.cpu().numpy(), ref) <= TOL_BP
+
+
+def test_views_full_size_carm_backprojection_sampled(orc):
+    """The C-arm scan of the 512^3 workload (360 views, 512^2 detector; detectors turned by up to 10
+    degrees, sources and detectors displaced by up to 5 mm, orbit tilted by 5 degrees), backprojected
+    in the launch configuration of a resident call: sampled voxels against the oracle."""
+    w = inputs.workload("medium")
+    views = inputs.carm_views(w.DSO, w.DSD, w.angles, 7, tilt_deg=10.0, jitter_mm=5.0, orbit_tilt_deg=5.0)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    plan = Plan(w.geometry_dict(), views)
+    y = inputs.random_array(plan.proj_shape, 38, kind="uniform")
+    yd = torch.from_numpy(y).to(DEV)
+    vidx = inputs.sample_indices(int(np.prod(plan.vol_shape)), 300, 39)
+    for bp, wk in (("fdk", orc.W_FDK), ("pm", orc.W_PM)):
+        say(f"[views] C-arm 512^3 x 360 backprojection {bp}")
+        v = plan.backproject(yd, bp).cpu().numpy().ravel()
+        e = rel_l2(v[vidx], orc.bp_voxels(og, views, y, vidx, wk))
+        say(f"   sampled voxels rel L2 {e:.3e}")
+        assert e <= TOL_BP
