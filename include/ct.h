@@ -143,7 +143,7 @@ ct_status ct_backproject(ct_plan *plan, ct_backprojector backprojector, const vo
  * MiB, one per device, held from the library's load until the process ends), in sub-chunks of
  * angles that fit it.  That array is shared by every call on a device, so calls that overlap on
  * one device race; callers serialise them (one stream, or events).
- * Extra errors: CT_ERR_ARG when one angle's transposed copy (8 (Nv + 2) Nu bytes) exceeds the
+ * Extra errors: CT_ERR_ARG when one angle's transposed copy (4 (Nv + 2) Nu bytes) exceeds the
  * array; CT_ERR_STATE when the plan's angle table is not yet on the current device (it is
  * uploaded by the first allocating call with the plan on that device, e.g. ct_backproject). */
 ct_status ct_backproject_noalloc(ct_plan *plan, ct_backprojector backprojector, const void *d_proj,

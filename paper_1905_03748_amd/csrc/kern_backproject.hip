@@ -598,13 +598,23 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
 // Along the ray of row b the height is z = t v_b, so voxel [zl, zh) is met for t in
 // [zl / v_b, zh / v_b] (ordered) clipped to [t0, t1]; the rows that can meet it have v_b in
 // [min(zl / t0, zl / t1), max(zh / t0, zh / t1)], at most NR consecutive rows (NR from a host
-// bound).  The projections are read from a copy [angle][u][1 + v] of pairs (y |P - S|, 1 / v_b)
-// with a zero row below and above each column, so the rows of consecutive voxels are consecutive
-// addresses and every row costs one 8-byte load, two products and four compares.
+// bound).  The projections are read from a copy [angle][u][1 + v] of y |P - S| with a zero row
+// below and above each column, so the rows of consecutive voxels are consecutive addresses: a
+// voxel's NR candidate rows are one load of 4 NR bytes.  The parameter step dz / v_b across one
+// voxel height depends on the row alone (a circular orbit), so each block keeps the steps of all
+// rows in LDS.  Every row then costs two products and four compares.
+
+// Parameter step dz / v_b of row r = b + 1 of the padded copy (0 for the zero rows).
+__device__ __forceinline__ float adj_row_step(const BpArgs &A, int r) {
+    const int b = r - 1;
+    if (b < 0 || b >= A.nv) return 0.0f;
+    const double vb = (b - A.cv) * A.dv + A.offv;
+    return vb != 0.0 ? (float)(A.ddz / vb) : 1e30f;
+}
 
 // proj [angle][v][u] -> yq [angle][u][v + 1] (nv + 2 rows, zero first and last), 32 x 32 tiles
 template <typename TP>
-__global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, float2 *__restrict__ yq, BpArgs A) {
+__global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, float *__restrict__ yq, BpArgs A) {
     __shared__ float tile[32][33];
     const int u0 = blockIdx.x * 32, r0 = blockIdx.y * 32, t = blockIdx.z;  // r = b + 1
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -623,12 +633,11 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
         const int r = r0 + tx, u = u0 + ty + k;
         if (u < A.nu && r < nvp) {
             const int b = r - 1;
-            float2 q = make_float2(0.0f, 0.0f);
+            float q = 0.0f;
             if (b >= 0 && b < A.nv) {
                 const double ua = (u - A.cu) * A.du + A.offu, vb = (b - A.cv) * A.dv + A.offv;
                 // |P - S| (mm per unit t) is the same for every angle in a circular orbit
-                q.x = (float)(tile[tx][ty + k] * sqrt(A.dDSD * A.dDSD + ua * ua + vb * vb));
-                q.y = vb != 0.0 ? (float)(A.ddz / vb) : 1e30f;  // parameter step across one voxel height
+                q = (float)(tile[tx][ty + k] * sqrt(A.dDSD * A.dDSD + ua * ua + vb * vb));
             }
             yq[((int64_t)t * A.nu + u) * nvp + r] = q;
         }
@@ -649,10 +658,13 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
 #endif
 #define CT_ADJ_OCC __attribute__((amdgpu_waves_per_eu(CT_ADJ_WAVES)))
 template <typename TV, int R, int NR, bool ZC, bool ORD>
-__global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
+__global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
                                                  int zgroups, int xblocks) {
+    extern __shared__ float rstep[];  // nv + 2 parameter steps, one per row of the padded copy
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
+    for (int r = threadIdx.x; r < A.nv + 2; r += 256) rstep[r] = adj_row_step(A, r);
+    __syncthreads();
     int bid = blockIdx.x;
 #if CT_ADJ_XCD_W > 1
     // workgroups are dealt to the 8 XCDs in turn: give each XCD CT_ADJ_XCD_W consecutive blocks
@@ -772,8 +784,8 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
             const float Sh = __uint_as_float(__float_as_uint(Sf) & 0xFFFFC000u);
             const float Sr = (float)(Sd - (double)Sh);
             const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
-            const float2 *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
-            float2 wv[R][NR];
+            const float *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
+            float wv[R][NR];
             float bl[R], E[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -792,15 +804,16 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float2 *__rest
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 // uniform column base plus an unsigned 32-bit byte offset of row bl
-                const float2 *cb = (const float2 *)((const char *)col + (uint32_t)((int)bl[r] + 1) * 8u);
+                const float *cb = (const float *)((const char *)col + (uint32_t)((int)bl[r] + 1) * 4u);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) wv[r][q] = cb[q];
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                const float *sb = rstep + ((int)bl[r] + 1);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
-                    const float2 w = wv[r][q];
+                    const float2 w = make_float2(wv[r][q], sb[q]);
                     // parameters relative to t0 of the row's crossings of faces A and B (its
                     // height below face A in voxels times dz / v_b, and one step dz / v_b more),
                     // clipped to [0, T]: a row that stays inside the voxel gets exactly T
@@ -1135,17 +1148,20 @@ BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, con
 
 }  // namespace
 
+// rows of the padded copy whose parameter steps fit the column kernel's LDS table (64 KiB)
+constexpr int64_t ADJ_MAX_ROWS = 16384;
+
 bool adj_col_ok(const ct_plan *p) {
 #ifdef CT_NO_ADJ_COL
     return false;
 #else
-    if (p->views) return false;
+    if (p->views || p->g.nDetector[1] + 2 > ADJ_MAX_ROWS) return false;
     return std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2) <= 4;
 #endif
 }
 
 size_t adj_chunk_bytes_per_angle(const ct_geometry &g) {
-    return (size_t)g.nDetector[0] * (size_t)(g.nDetector[1] + 2) * sizeof(float2);
+    return (size_t)g.nDetector[0] * (size_t)(g.nDetector[1] + 2) * sizeof(float);
 }
 
 ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj, ct_dtype pt, void *vol,
@@ -1205,7 +1221,7 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         // voxel lanes over a transposed, pre-scaled copy of the projections, made in angle
         // sub-chunks that fit the scratch (the caller's, else stream-ordered scratch of the whole
         // range when the launch may allocate); accumulators pass between sub-chunks in FP32
-        const int nr = std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2);
+        const int nr = p->g.nDetector[1] + 2 > ADJ_MAX_ROWS ? 5 : std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2);
         const size_t per_angle = adj_chunk_bytes_per_angle(p->g);
         void *yq = adj_scratch, *own = nullptr;
         size_t qcap = adj_scratch ? adj_bytes : 0;
@@ -1246,17 +1262,18 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
             const int xblocks = (A.nx + 3) / 4;
             const dim3 ag((unsigned)((int64_t)zgroups * xblocks * A.ny));
             const size_t pangle = (size_t)A.nu * A.nv * dtype_size(pt);
+            const size_t rsbytes = (size_t)(A.nv + 2) * sizeof(float);  // the rows' parameter steps (LDS)
             for (int64_t c0 = a0; c0 < a1; c0 += kq) {
                 const int64_t c1 = std::min(a1, c0 + kq);
                 const BpArgs Ac = make_bp_args(p, tab, c0, c1, slab, c0 == a0 ? accumulate : 1);
                 const void *pc = (const char *)proj + (size_t)(c0 - a0) * pangle;
                 const dim3 pg((unsigned)((A.nu + 31) / 32), (unsigned)((A.nv + 2 + 31) / 32), (unsigned)(c1 - c0));
                 CT_DISPATCH1(pt, TP,
-                             hipLaunchKernelGGL((k_adj_prep<TP>), pg, dim3(256), 0, st, (const TP *)pc, (float2 *)yq, Ac));
+                             hipLaunchKernelGGL((k_adj_prep<TP>), pg, dim3(256), 0, st, (const TP *)pc, (float *)yq, Ac));
                 CT_HIP(hipGetLastError());
 #define CT_ADJ_L(RR, NN, Z, O)                                                                                  \
-    hipLaunchKernelGGL((k_adj_col<TV, RR, NN, Z, O>), ag, block, 0, st, (const float2 *)yq, (TV *)vol, Ac, zgroups, \
-                       xblocks)
+    hipLaunchKernelGGL((k_adj_col<TV, RR, NN, Z, O>), ag, block, rsbytes, st, (const float *)yq, (TV *)vol, Ac, \
+                       zgroups, xblocks)
 #define CT_ADJ(RR, NN)                                  \
     CT_DISPATCH1(vt, TV, if (slab.zcol) {               \
         if (ord) CT_ADJ_L(RR, NN, true, true);          \

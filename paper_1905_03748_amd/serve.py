@@ -57,7 +57,7 @@ class Request:
         vol = int(nx) * int(ny) * int(nz) * 4
         proj = int(np.prod(self.b.shape)) * 4
         nv = int(self.b.shape[1])
-        yq = proj // nv * (nv + 2) * 2                     # adjoint's transposed copy (8 B per pixel)
+        yq = proj // nv * (nv + 2)                         # adjoint's transposed copy (4 B per pixel)
         col = int(nx) * int(ny) * (int(nz) + 2) * 4        # projector's column-major copy
         # b, x, CGLS workspace (r, q: projections; s, p: volumes; the two copies), TV gradient,
         # small scalars

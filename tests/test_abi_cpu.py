@@ -172,7 +172,7 @@ def test_ooc_planner_equal_slabs_and_halo(lib):
                 for direction, nbuf in ((0, 3), (1, 2), (2, 2), (3, 2)):
                     s = A.ct_ooc_plan(p, direction, kind, A.CT_F32, A.CT_F32, cap)
                     h = halo if direction == 0 else 0
-                    adj = s.chunk_angles * 64 * 66 * 8 if direction == 2 else 0
+                    adj = s.chunk_angles * 64 * 66 * 4 if direction == 2 else 0
                     filt = s.chunk_angles * 64 * 64 * 4 if direction == 3 else 0   # FDK's filtered chunk
                     assert s.n_slabs * s.slab_slices >= 64
                     assert s.slab_slices == -(-64 // s.n_slabs)            # equal slabs

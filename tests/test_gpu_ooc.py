@@ -31,7 +31,7 @@ def _cap_for(plan, slices, direction, projector="siddon", dt=torch.float32, pdt=
     # the exact adjoint also holds its transposed FP32 copy of each chunk and an 8-slice stage for
     # its column-major slab; a Siddon forward holds its slab column-major (two zero slots per
     # column) and an 8-slice stage
-    adj = kmin * nu * (nv + 2) * 8 if direction == 2 else 0
+    adj = kmin * nu * (nv + 2) * 4 if direction == 2 else 0
     adj += kmin * nu * nv * 4 if direction == 3 else 0   # the FDK reconstruction's filtered chunk
     extra = 2 * halo + (2 + 8 if (direction == 0 and projector == "siddon") else 0) + (8 if direction == 2 else 0)
     return RESERVE + nbuf * kmin * pangle + adj + nbufs * (slices + extra) * slice_b

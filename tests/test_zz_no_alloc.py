@@ -53,19 +53,19 @@ def test_noalloc_equals_backproject_two_calls():
 
 
 def test_noalloc_subchunks_match_one_chunk():
-    """A detector whose transposed copy (8 (Nv + 2) Nu bytes per angle) lets only a few angles into
+    """A detector whose transposed copy (4 (Nv + 2) Nu bytes per angle) lets only a few angles into
     the 128 MiB scratch, so the exact adjoint runs in many sub-chunks: still bitwise equal."""
-    plan, y = _case((64, 64, 40), (1500, 1400), 40, 13)   # 16.8 MB per angle: 7 angles per sub-chunk
-    say("[noalloc] 1500 x 1400 detector, 40 angles: adjoint in sub-chunks of 7 angles")
+    plan, y = _case((64, 64, 40), (1500, 1400), 40, 13)   # 8.4 MB per angle: 15 angles per sub-chunk
+    say("[noalloc] 1500 x 1400 detector, 40 angles: adjoint in sub-chunks of 15 angles")
     ref, got = _both(plan, y, "adjoint")
     assert torch.equal(ref, got)
 
 
 def test_noalloc_errors_before_device_work():
-    # one angle of a 4096^2 detector needs 4096 * 4098 * 8 bytes > 128 MiB: refused.  Rows of 2 mm
-    # against 1 mm voxels keep the geometry on the column kernel (the one that uses the scratch);
-    # the buffers have their full sizes all the same
-    g = dict(inputs.workload("tiny").geometry_dict(), nDetector=(4096, 4096), dDetector=(0.05, 2.0))
+    # one angle of an 8192 x 4096 detector needs 8192 * 4098 * 4 bytes > 128 MiB: refused.  Rows of
+    # 2 mm against 1 mm voxels keep the geometry on the column kernel (the one that uses the
+    # scratch); the buffers have their full sizes all the same
+    g = dict(inputs.workload("tiny").geometry_dict(), nDetector=(8192, 4096), dDetector=(0.025, 2.0))
     big = Plan(g, np.array([0.0, 1.0]))
     yb = torch.zeros(big.proj_shape, device=DEV)
     vb = torch.zeros(big.vol_shape, device=DEV)
