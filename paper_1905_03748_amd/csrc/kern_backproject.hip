@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <string>
@@ -57,6 +58,7 @@ struct BpArgs {
     double dDSO, dDSD, du, dv, cu, cv, offu, offv;
     double dau0, dbv0;      // au0, bv0 in FP64
     double idu, idv;        // 1 / du, 1 / dv in FP64
+    int32_t vw;             // a plan of vertical views: the exact adjoint takes each view's S, C - S, e_u
 };
 
 // 1 / d in FP64 without a division: the FP32 reciprocal (about 1 ulp) refined by one Newton step,
@@ -636,8 +638,15 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
             float q = 0.0f;
             if (b >= 0 && b < A.nv) {
                 const double ua = (u - A.cu) * A.du + A.offu, vb = (b - A.cv) * A.dv + A.offv;
-                // |P - S| (mm per unit t) is the same for every angle in a circular orbit
-                q = (float)(tile[tx][ty + k] * sqrt(A.dDSD * A.dDSD + ua * ua + vb * vb));
+                if (A.vw) {
+                    // |P - S| of a vertical view: its horizontal part C - S + u e_u, and v_b
+                    const AngleGeo &G = A.tab[A.a0 + t];
+                    const double px = fma(ua, G.eu[0], G.Dc[0]) * A.ddx, py = fma(ua, G.eu[1], G.Dc[1]) * A.ddy;
+                    q = (float)(tile[tx][ty + k] * sqrt(px * px + py * py + vb * vb));
+                } else {
+                    // |P - S| (mm per unit t) is the same for every angle in a circular orbit
+                    q = (float)(tile[tx][ty + k] * sqrt(A.dDSD * A.dDSD + ua * ua + vb * vb));
+                }
             }
             yq[((int64_t)t * A.nu + u) * nvp + r] = q;
         }
@@ -657,9 +666,14 @@ __global__ __launch_bounds__(256) void k_adj_prep(const TP *__restrict__ proj, f
 #define CT_ADJ_WAVES 4, 4
 #endif
 #define CT_ADJ_OCC __attribute__((amdgpu_waves_per_eu(CT_ADJ_WAVES)))
-template <typename TV, int R, int NR, bool ZC, bool ORD>
+// VW: a plan of vertical views (detector columns vertical, the detector centre at the source's
+// height; circular and helical scans): each view's source, C - S and e_u replace the circular
+// orbit's, heights are taken from the view's source plane, and the faces' order is set per view
+// (VW implies !ORD and !ZC).
+template <typename TV, int R, int NR, bool ZC, bool ORD, bool VW = false>
 __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restrict__ yq, TV *__restrict__ vol, BpArgs A,
                                                  int zgroups, int xblocks) {
+    static_assert(!VW || (!ORD && !ZC), "vertical views take the general face order and [z][y][x] volumes");
     extern __shared__ float rstep[];  // nv + 2 parameter steps, one per row of the padded copy
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -700,6 +714,15 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
         const int k = A.own_lo + zg * 64 * R + 64 * r + lane;
         kin[r] = k < A.own_hi;
         const float zl = fmaf((float)k, dz, zface0), zh = fmaf((float)(k + 1), dz, zface0);
+        if (VW) {
+            // the faces in the world frame; each view takes them relative to its source
+            za[r] = zl;
+            zb[r] = zh;
+            kA[r] = (float)k;
+            sg[r] = 1.0f;
+            acc[r] = (kin[r] && A.accumulate) ? to_f(vol[vidx(k)]) : 0.0f;
+            continue;
+        }
         const bool below = zh <= 0.0f;
         const bool flip = ORD && below;
         za[r] = flip ? zh : zl;
@@ -724,21 +747,61 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
     for (int t = 0; t < A.nang; ++t) {
         const AngleGeo &G = A.tab[A.a0 + t];
         const double c = G.c, s = G.s;
-        const double Wx = xc - A.dDSO * c, Wy = yc - A.dDSO * s;  // source -> column centre
-        const float fc = (float)c, fs = (float)s;
+        double Wx, Wy;  // source -> column centre
+        double zf0v = zf0dz;  // lower face of voxel 0 above the source plane, voxel units
         float umin = FLT_MAX, umax = -FLT_MAX;
+        float szf = 0.0f;  // VW: the source's height
+        if (VW) {
+            Wx = xc - G.Smm[0];
+            Wy = yc - G.Smm[1];
+            zf0v = zf0dz - G.Smm[2] / A.ddz;
+            szf = (float)G.Smm[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float X = fxc + ((q & 1) ? hx : -hx), Y = fyc + ((q & 2) ? hy : -hy);
-            const float u = A.DSD * (Y * fc - X * fs) * __builtin_amdgcn_rcpf(A.DSO - (X * fc + Y * fs));
-            umin = fminf(umin, u);
-            umax = fmaxf(umax, u);
+            for (int r = 0; r < R; ++r) {
+                // a voxel below the source plane is met by falling rows first at its upper face
+                const bool below = zb[r] - szf <= 0.0f;
+                kA[r] = below ? (float)(A.own_lo + zg * 64 * R + 64 * r + lane + 1) : (float)(A.own_lo + zg * 64 * R + 64 * r + lane);
+                sg[r] = below ? -1.0f : 1.0f;
+            }
+            // detector coordinate u of the ray through each corner of the column's square: with
+            // X - S = Xr and C - S + u e_u parallel to it, u = (Xr x (C - S)) / (e_u x Xr)
+            const float dcx = (float)(G.Dc[0] * A.ddx), dcy = (float)(G.Dc[1] * A.ddy);
+            const float eux = (float)(G.eu[0] * A.ddx), euy = (float)(G.eu[1] * A.ddy);
+            const float fwx = (float)Wx, fwy = (float)Wy;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float X = fwx + ((q & 1) ? hx : -hx), Y = fwy + ((q & 2) ? hy : -hy);
+                const float u = (X * dcy - Y * dcx) * __builtin_amdgcn_rcpf(eux * Y - euy * X);
+                umin = fminf(umin, u);
+                umax = fmaxf(umax, u);
+            }
+        } else {
+            Wx = xc - A.dDSO * c;
+            Wy = yc - A.dDSO * s;
+            const float fc = (float)c, fs = (float)s;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float X = fxc + ((q & 1) ? hx : -hx), Y = fyc + ((q & 2) ? hy : -hy);
+                const float u = A.DSD * (Y * fc - X * fs) * __builtin_amdgcn_rcpf(A.DSO - (X * fc + Y * fs));
+                umin = fminf(umin, u);
+                umax = fmaxf(umax, u);
+            }
         }
-        const int alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - 1e-3f), 0.0f);
-        const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + 1e-3f), (float)(A.nu - 1));
+        // (a wider margin for views: their corner coordinates are formed from source-relative
+        // vectors of about a metre; a column too many is clipped away below)
+        const float um = VW ? 1e-2f : 1e-3f;
+        const int alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - um), 0.0f);
+        const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + um), (float)(A.nu - 1));
         for (int a = alo; a <= ahi; ++a) {
             const double ua = (a - A.cu) * A.du + A.offu;
-            const double Dx = -A.dDSD * c - ua * s, Dy = -A.dDSD * s + ua * c;
+            double Dx, Dy;
+            if (VW) {
+                Dx = fma(ua, G.eu[0], G.Dc[0]) * A.ddx;
+                Dy = fma(ua, G.eu[1], G.Dc[1]) * A.ddy;
+            } else {
+                Dx = -A.dDSD * c - ua * s;
+                Dy = -A.dDSD * s + ua * c;
+            }
             const float cross = (float)(Wx * Dy - Wy * Dx);
             const double dotd = Wx * Dx + Wy * Dy;
             const float fDx = (float)Dx, fDy = (float)Dy;
@@ -777,7 +840,7 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
             // index kA (an integer) and row b (|b| < 2^14) kA - H0h and b Sh are exact FP32 values
             // and so is their difference, which is a few voxels for the candidate rows; only the
             // small terms b Sr + H0l are rounded
-            const double H0d = fma(t0d, v0dz, -zf0dz), Sd = t0d * dvdz;
+            const double H0d = fma(t0d, v0dz, -zf0v), Sd = t0d * dvdz;
             const float H0h = ((float)H0d + 98304.0f) - 98304.0f;
             const float H0l = (float)(H0d - (double)H0h);
             const float Sf = (float)Sd;
@@ -792,7 +855,8 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
                 // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]: the lowest
                 // v = z / t over the lower face and t in [t0, t1] (with ORD, za * it1 for voxels
                 // above the plane and zb * it0 for voxels below)
-                const float vlo = ORD ? fminf(za[r] * it1, zb[r] * it0) : fminf(za[r] * it0, za[r] * it1);
+                const float zlo = VW ? za[r] - szf : za[r];
+                const float vlo = ORD ? fminf(za[r] * it1, zb[r] * it0) : fminf(zlo * it0, zlo * it1);
                 bl[r] = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
                 // the height of face A above row bl where the row enters the square, in voxel
                 // units (kA - H0 - bl S: a difference of heights of up to the volume's height,
@@ -1096,6 +1160,34 @@ int adj_rows(const ct_geometry &g) {
     return (int)std::floor(W * 1.001 + 1e-3) + 1;
 }
 
+// The same bound for a plan of vertical views, taken over the views: with L_min the least depth
+// (along the detector normal, which is horizontal) of the grid's corners from the view's source,
+// t_min = L_min / DSD_v, the voxel column's t extent at most sqrt(2) max(dx, dy) / DSD_v, and |z|
+// measured from the source's height.
+int adj_rows_views(const ct_plan *p) {
+    const ct_geometry &g = p->g;
+    int rows = 0;
+    for (const AngleGeo &t : p->tab) {
+        const double eu[2] = {t.eu[0] * g.dVoxel[0], t.eu[1] * g.dVoxel[1]};
+        const double n[2] = {eu[1], -eu[0]};  // e_u x e_z
+        double Lmin = HUGE_VAL, Zmax = 0.0;
+        for (int cx = 0; cx < 2; ++cx)
+            for (int cy = 0; cy < 2; ++cy) {
+                const double xe = g.offOrigin[0] + (cx ? 0.5 : -0.5) * g.nVoxel[0] * g.dVoxel[0];
+                const double ye = g.offOrigin[1] + (cy ? 0.5 : -0.5) * g.nVoxel[1] * g.dVoxel[1];
+                Lmin = std::min(Lmin, n[0] * (t.Smm[0] - xe) + n[1] * (t.Smm[1] - ye));
+            }
+        for (int cz = 0; cz < 2; ++cz)
+            Zmax = std::max(Zmax, std::fabs(g.offOrigin[2] + (cz ? 0.5 : -0.5) * g.nVoxel[2] * g.dVoxel[2] - t.Smm[2]));
+        if (!(Lmin > 0.0)) return 1 << 20;
+        const double tmin = Lmin / t.DSDv;
+        const double dt = std::sqrt(2.0) * std::max(g.dVoxel[0], g.dVoxel[1]) / t.DSDv;
+        const double W = (g.dVoxel[2] / tmin + Zmax * dt / (tmin * tmin)) / g.dDetector[1];
+        rows = std::max(rows, (int)std::floor(W * 1.001 + 1e-3) + 1);
+    }
+    return rows;
+}
+
 BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const Slab &slab, int accumulate) {
     const ct_geometry &g = p->g;
     BpArgs A;
@@ -1143,10 +1235,18 @@ BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, con
     A.mem_lo = (int32_t)slab.mem_lo;
     A.zcol_n = slab.zcol ? (int32_t)slab.mem_n : 0;
     A.accumulate = accumulate;
+    A.vw = p->views ? 1 : 0;
     return A;
 }
 
 }  // namespace
+
+// CT_VIEWS_ADJ_DIRECT=1 sends the exact adjoint of vertical views to the per-view kernel (tests
+// compare the two).
+bool direct_views_adjoint() {
+    const char *e = std::getenv("CT_VIEWS_ADJ_DIRECT");
+    return e && e[0] == '1';
+}
 
 // rows of the padded copy whose parameter steps fit the column kernel's LDS table (64 KiB)
 constexpr int64_t ADJ_MAX_ROWS = 16384;
@@ -1172,7 +1272,10 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
     if (s != CT_OK) return s;
     const int64_t nzown = slab.own_hi - slab.own_lo;
     if (nzown <= 0) return CT_OK;
-    if (p->views) return launch_backproject_views(p, kind, proj, pt, vol, vt, accumulate, a0, a1, slab, tab, st);
+    // plans of views: the per-view kernels, except the exact adjoint of vertical views (circular and
+    // helical scans), which the column kernel serves
+    const bool vw_col = p->views && kind == CT_BP_ADJOINT && p->vertical && !slab.zcol && !direct_views_adjoint();
+    if (p->views && !vw_col) return launch_backproject_views(p, kind, proj, pt, vol, vt, accumulate, a0, a1, slab, tab, st);
     if (slab.zcol && (kind != CT_BP_ADJOINT || !adj_col_ok(p)))
         return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's column kernel");
     BpArgs A = make_bp_args(p, tab, a0, a1, slab, accumulate);
@@ -1221,7 +1324,9 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         // voxel lanes over a transposed, pre-scaled copy of the projections, made in angle
         // sub-chunks that fit the scratch (the caller's, else stream-ordered scratch of the whole
         // range when the launch may allocate); accumulators pass between sub-chunks in FP32
-        const int nr = p->g.nDetector[1] + 2 > ADJ_MAX_ROWS ? 5 : std::min<int>(adj_rows(p->g), (int)p->g.nDetector[1] + 2);
+        const int nr = p->g.nDetector[1] + 2 > ADJ_MAX_ROWS
+                           ? 5
+                           : std::min<int>(p->views ? adj_rows_views(p) : adj_rows(p->g), (int)p->g.nDetector[1] + 2);
         const size_t per_angle = adj_chunk_bytes_per_angle(p->g);
         void *yq = adj_scratch, *own = nullptr;
         size_t qcap = adj_scratch ? adj_bytes : 0;
@@ -1251,9 +1356,10 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
 #ifdef CT_ADJ_R
             R = CT_ADJ_R;
 #endif
-            // no voxel of the launch straddles the source plane (the kernel's own FP32 faces)
-            bool ord = true;
-            {
+            // no voxel of the launch straddles the source plane (the kernel's own FP32 faces); views
+            // take the general order
+            bool ord = !p->views;
+            if (ord) {
                 const float dzf = A.dz, zf0 = (float)(A.dz0 - 0.5 * A.ddz);
                 for (int64_t k = slab.own_lo; k < slab.own_hi && ord; ++k)
                     ord = !(std::fma((float)k, dzf, zf0) < 0.0f && std::fma((float)(k + 1), dzf, zf0) > 0.0f);
@@ -1274,13 +1380,16 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
 #define CT_ADJ_L(RR, NN, Z, O)                                                                                  \
     hipLaunchKernelGGL((k_adj_col<TV, RR, NN, Z, O>), ag, block, rsbytes, st, (const float *)yq, (TV *)vol, Ac, \
                        zgroups, xblocks)
-#define CT_ADJ(RR, NN)                                  \
-    CT_DISPATCH1(vt, TV, if (slab.zcol) {               \
-        if (ord) CT_ADJ_L(RR, NN, true, true);          \
-        else CT_ADJ_L(RR, NN, true, false);             \
-    } else {                                            \
-        if (ord) CT_ADJ_L(RR, NN, false, true);         \
-        else CT_ADJ_L(RR, NN, false, false);            \
+#define CT_ADJ(RR, NN)                                                                                        \
+    CT_DISPATCH1(vt, TV, if (p->views) {                                                                      \
+        hipLaunchKernelGGL((k_adj_col<TV, RR, NN, false, false, true>), ag, block, rsbytes, st, (const float *)yq, \
+                           (TV *)vol, Ac, zgroups, xblocks);                                                  \
+    } else if (slab.zcol) {                                                                                   \
+        if (ord) CT_ADJ_L(RR, NN, true, true);                                                                \
+        else CT_ADJ_L(RR, NN, true, false);                                                                   \
+    } else {                                                                                                  \
+        if (ord) CT_ADJ_L(RR, NN, false, true);                                                               \
+        else CT_ADJ_L(RR, NN, false, false);                                                                  \
     })
 #define CT_ADJ_R(NN)        \
     switch (R) {            \
@@ -1318,6 +1427,7 @@ ct_status launch_backproject(ct_plan *p, ct_backprojector kind, const void *proj
         if (own) CT_HIP(hipFreeAsync(own, st));
         if (slab.zcol) return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's scratch");
 #endif
+        if (p->views) return launch_backproject_views(p, kind, proj, pt, vol, vt, accumulate, a0, a1, slab, tab, st);
         if (slab.zcol) return fail(CT_ERR_STATE, "a column-major slab needs the exact adjoint's column kernel");
         CT_DISPATCH2(pt, TP, vt, TV,
                      hipLaunchKernelGGL((k_bp_adjoint<TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));

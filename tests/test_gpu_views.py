@@ -156,21 +156,24 @@ def test_views_cgls_and_os_sart(orc):
     assert e <= 1e-4
 
 
-def test_views_noalloc_equals_backproject(ragged, orc):
+@pytest.mark.parametrize("kind", ["carm", "helical"])
+def test_views_noalloc_equals_backproject(ragged, orc, kind):
+    """The allocation-free entry point on plans of views; a helical plan's exact adjoint runs the
+    column kernel on the static scratch, a C-arm plan's the per-view kernel."""
     w, vol, y, og = ragged
-    plan = Plan(w.geometry_dict(), _views("carm", w))
+    plan = Plan(w.geometry_dict(), _views(kind, w))
     yd = torch.from_numpy(y).to(DEV)
     from paper_1905_03748_amd import _abi as A
     kinds = {"fdk": A.CT_BP_FDK, "pm": A.CT_BP_PSEUDO_MATCHED, "adjoint": A.CT_BP_ADJOINT}
-    for kind in ("fdk", "pm", "adjoint"):
-        say(f"[views] no-alloc {kind}")
-        ref = plan.backproject(yd, kind)   # also puts the plan's table on the device
+    for bp in ("fdk", "pm", "adjoint"):
+        say(f"[views] {kind} no-alloc {bp}")
+        ref = plan.backproject(yd, bp)   # also puts the plan's table on the device
         out = torch.full_like(ref, -3.0)
         torch.cuda.synchronize()
-        A.ct_backproject_noalloc(plan.handle, kinds[kind], yd.data_ptr(), A.CT_F32, out.data_ptr(), A.CT_F32, 0, 0,
+        A.ct_backproject_noalloc(plan.handle, kinds[bp], yd.data_ptr(), A.CT_F32, out.data_ptr(), A.CT_F32, 0, 0,
                                  plan.n_angles, torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
-        assert torch.equal(out, ref), kind
+        assert torch.equal(out, ref), bp
 
 
 def test_views_volume_off_the_detector_gives_zeros(orc):
@@ -261,3 +264,56 @@ def test_views_full_size_carm_backprojection_sampled(orc):
         e = rel_l2(v[vidx], orc.bp_voxels(og, views, y, vidx, wk))
         say(f"   sampled voxels rel L2 {e:.3e}")
         assert e <= TOL_BP
+
+
+@pytest.mark.parametrize("kind", ["helical", "circular"])
+def test_vertical_views_adjoint_column_kernel_equals_per_view(ragged, orc, kind, monkeypatch):
+    """The exact adjoint of vertical views (detector columns vertical, the detector centre at the
+    source's height) runs the column kernel with each view's source and axes; with
+    CT_VIEWS_ADJ_DIRECT=1 the per-view kernel.  Both give the exact chords of every ray, formed in
+    different FP32 steps: within 2e-6, and both within the oracle's bar.  Angle ranges with
+    accumulation add up to the whole call."""
+    w, vol, y, og = ragged
+    views = orc.circular_views(og, w.angles) if kind == "circular" else _views(kind, w)
+    plan = Plan(w.geometry_dict(), views)
+    yd = torch.from_numpy(y).to(DEV)
+    say(f"[views] {kind} adjoint: column kernel vs per-view kernel")
+    monkeypatch.delenv("CT_VIEWS_ADJ_DIRECT", raising=False)
+    a = plan.backproject(yd, "adjoint")
+    part = plan.backproject(yd[:4].contiguous(), "adjoint", angle_begin=0, angle_end=4)
+    plan.backproject(yd[4:].contiguous(), "adjoint", out=part, accumulate=True, angle_begin=4, angle_end=13)
+    monkeypatch.setenv("CT_VIEWS_ADJ_DIRECT", "1")
+    b = plan.backproject(yd, "adjoint")
+    monkeypatch.delenv("CT_VIEWS_ADJ_DIRECT")
+    assert not torch.equal(a, b), "the column kernel did not run"
+    e = rel_l2(a.cpu().numpy(), b.cpu().numpy())
+    say(f"   rel L2 {e:.3e}")
+    assert e <= 2e-6
+    assert rel_l2(part.cpu().numpy(), a.cpu().numpy()) <= 1e-6
+    ref = orc.siddon_adj(og, views, y.astype(np.float64))
+    assert rel_l2(a.cpu().numpy(), ref) <= TOL_BP
+
+
+def test_helical_views_column_adjoint_dot_product(orc):
+    """A helical scan whose source passes through the volume's slices (so voxels lie above and
+    below the source plane within one launch), 40 views over two turns: <A u, v> = <u, A^T v> with
+    the Siddon column walk and the exact adjoint's column kernel, and sampled voxels against the
+    oracle."""
+    w = inputs.Workload("helix_dot", (48, 44, 40), (1.0, 1.0, 1.0), (64, 24), (1.5, 1.5), 40, 10, 41)
+    th = 4.0 * np.pi * np.arange(40) / 40
+    views = inputs.helical_views(w.DSO, w.DSD, th, pitch=20.0, z0=-20.0)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    plan = Plan(w.geometry_dict(), views)
+    rng = np.random.default_rng(8)
+    u = torch.from_numpy(rng.uniform(0, 1, plan.vol_shape).astype(np.float32)).to(DEV)
+    v = torch.from_numpy(rng.uniform(0, 1, plan.proj_shape).astype(np.float32)).to(DEV)
+    say("[views] helical through the volume: dot product")
+    lhs = float((plan.forward(u).double() * v.double()).sum())
+    at = plan.backproject(v, "adjoint")
+    rhs = float((u.double() * at.double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+    vidx = inputs.sample_indices(int(np.prod(plan.vol_shape)), 300, 42)
+    ref = orc.siddon_adj_voxels(og, views, v.cpu().numpy().astype(np.float64), vidx)
+    e = rel_l2(at.cpu().numpy().ravel()[vidx], ref)
+    say(f"   sampled voxels rel L2 {e:.3e}")
+    assert e <= TOL_BP
