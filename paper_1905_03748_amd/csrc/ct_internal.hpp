@@ -70,6 +70,7 @@ struct ct_plan {
     std::vector<ct::AngleGeo> tab;
     std::mutex mu;
     int vl_ww = -1, vl_hw = -1;  // LDS window of the per-view backprojection (-1: not computed yet)
+    int va_ww = -1, va_hw = -1;  // LDS window of the per-view exact adjoint (-1: not computed yet)
     struct DevTab {
         ct::AngleGeo *ptr;
         hipEvent_t ready;  // recorded after the upload on the stream that first used the plan

@@ -59,6 +59,8 @@ struct BpArgs {
     double dau0, dbv0;      // au0, bv0 in FP64
     double idu, idv;        // 1 / du, 1 / dv in FP64
     int32_t vw;             // a plan of vertical views: the exact adjoint takes each view's S, C - S, e_u
+    int32_t zrow;           // the detector row at the source's height (v_b = 0, rays parallel to the
+                            // slices), or -1
 };
 
 // 1 / d in FP64 without a division: the FP32 reciprocal (about 1 ulp) refined by one Newton step,
@@ -524,20 +526,24 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
             const float fx = -dperp * uy, fy = dperp * ux;
             // slab clip of fx + s ux in [-hx, hx], fy + s uy in [-hy, hy]  (s in mm)
             float s0 = -FLT_MAX, s1 = FLT_MAX;
-            if (fabsf(ux) > 1e-7f) {
+            // a trace the projector takes as parallel to an axis (|D_c| < 1e-12 |D|, in FP64; here with
+            // the horizontal |D|) runs at the source's coordinate: the column must hold it in its
+            // half-open slab
+            const double lpar = 1e-24 * (Dx * Dx + Dy * Dy);
+            if (Dx * Dx >= lpar) {
                 const float r = __builtin_amdgcn_rcpf(ux);
                 const float qa = (-hx - fx) * r, qb = (hx - fx) * r;
                 s0 = fmaxf(s0, fminf(qa, qb));
                 s1 = fminf(s1, fmaxf(qa, qb));
-            } else if (fabsf(fx) > hx) {
+            } else if ((int)floor(G.S[0] + 0.5) != i) {
                 continue;
             }
-            if (fabsf(uy) > 1e-7f) {
+            if (Dy * Dy >= lpar) {
                 const float r = __builtin_amdgcn_rcpf(uy);
                 const float qa = (-hy - fy) * r, qb = (hy - fy) * r;
                 s0 = fmaxf(s0, fminf(qa, qb));
                 s1 = fminf(s1, fmaxf(qa, qb));
-            } else if (fabsf(fy) > hy) {
+            } else if ((int)floor(G.S[1] + 0.5) != j) {
                 continue;
             }
             if (!(s0 < s1)) continue;
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(const TP *__restrict__ proj,
 // Parameter step dz / v_b of row r = b + 1 of the padded copy (0 for the zero rows).
 __device__ __forceinline__ float adj_row_step(const BpArgs &A, int r) {
     const int b = r - 1;
-    if (b < 0 || b >= A.nv) return 0.0f;
+    if (b < 0 || b >= A.nv || b == A.zrow) return 0.0f;  // the row at the source's height: see k_adj_col
     const double vb = (b - A.cv) * A.dv + A.offv;
     return vb != 0.0 ? (float)(A.ddz / vb) : 1e30f;
 }
@@ -811,20 +817,24 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
             const float dperp = cross * iL;
             const float fx = -dperp * uy, fy = dperp * ux;
             float s0 = -FLT_MAX, s1 = FLT_MAX;
-            if (fabsf(ux) > 1e-7f) {
+            // a trace the projector takes as parallel to an axis (|D_c| < 1e-12 |D|, in FP64; here with
+            // the horizontal |D|) runs at the source's coordinate: the column must hold it in its
+            // half-open slab
+            const double lpar = 1e-24 * (Dx * Dx + Dy * Dy);
+            if (Dx * Dx >= lpar) {
                 const float rr = __builtin_amdgcn_rcpf(ux);
                 const float qa = (-hx - fx) * rr, qb = (hx - fx) * rr;
                 s0 = fmaxf(s0, fminf(qa, qb));
                 s1 = fminf(s1, fmaxf(qa, qb));
-            } else if (fabsf(fx) > hx) {
+            } else if ((int)floor(G.S[0] + 0.5) != i) {
                 continue;
             }
-            if (fabsf(uy) > 1e-7f) {
+            if (Dy * Dy >= lpar) {
                 const float rr = __builtin_amdgcn_rcpf(uy);
                 const float qa = (-hy - fy) * rr, qb = (hy - fy) * rr;
                 s0 = fmaxf(s0, fminf(qa, qb));
                 s1 = fminf(s1, fmaxf(qa, qb));
-            } else if (fabsf(fy) > hy) {
+            } else if ((int)floor(G.S[1] + 0.5) != j) {
                 continue;
             }
             if (!(s0 < s1)) continue;
@@ -848,6 +858,17 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
             const float Sr = (float)(Sd - (double)Sh);
             const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
             const float *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
+            if (A.zrow >= 0) {
+                // the row at the source's height stays in one slice, the one whose half-open slab
+                // holds that height; its step is 0 in the table, so the loop below adds nothing
+                const int ks = (int)floor(-zf0v) - (A.own_lo + zg * 64 * R);
+                if (ks >= 0 && ks < 64 * R && (ks & 63) == lane) {
+                    const float yz = col[A.zrow + 1];
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if ((ks >> 6) == r) acc[r] = fmaf(T, yz, acc[r]);
+                }
+            }
             float wv[R][NR];
             float bl[R], E[R];
 #pragma unroll
@@ -1188,6 +1209,13 @@ int adj_rows_views(const ct_plan *p) {
     return rows;
 }
 
+// The least source-detector distance over a plan's views.
+double min_dsd(const ct_plan *p) {
+    double m = HUGE_VAL;
+    for (const AngleGeo &t : p->tab) m = std::min(m, t.DSDv);
+    return m;
+}
+
 BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, const Slab &slab, int accumulate) {
     const ct_geometry &g = p->g;
     BpArgs A;
@@ -1236,16 +1264,26 @@ BpArgs make_bp_args(ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, con
     A.zcol_n = slab.zcol ? (int32_t)slab.mem_n : 0;
     A.accumulate = accumulate;
     A.vw = p->views ? 1 : 0;
+    // the row at the source's height, as the projector decides it (|v_b| < 1e-12 |P - S|)
+    A.zrow = -1;
+    {
+        const double b0 = A.cv - A.offv / A.dv;
+        const double bi = std::nearbyint(b0);
+        if (bi >= 0.0 && bi < (double)A.nv) {
+            const double vb = (bi - A.cv) * A.dv + A.offv;
+            if (std::fabs(vb) < 1e-12 * (p->views ? min_dsd(p) : g.DSD)) A.zrow = (int32_t)bi;
+        }
+    }
     return A;
 }
 
 }  // namespace
 
-// CT_VIEWS_ADJ_DIRECT=1 sends the exact adjoint of vertical views to the per-view kernel (tests
-// compare the two).
+// CT_VIEWS_ADJ_DIRECT=1 or 2 sends the exact adjoint of vertical views to a per-view kernel (tests
+// compare them).
 bool direct_views_adjoint() {
     const char *e = std::getenv("CT_VIEWS_ADJ_DIRECT");
-    return e && e[0] == '1';
+    return e && (e[0] == '1' || e[0] == '2');
 }
 
 // rows of the padded copy whose parameter steps fit the column kernel's LDS table (64 KiB)

@@ -41,6 +41,12 @@ constexpr int VB_G = 64;         // views per group of tile references
 
 enum { VM_FDK = 0, VM_PM = 1, VM_SART = 2, VM_ADJ = 3 };
 
+// The projector's FP64 constants that fix a pixel's ray: detector spacing, centre and offset, voxel
+// size (rays parallel to a grid plane are decided from them).
+struct RayConst {
+    double du, dv, cu, cv, offu, offv, dx, dy, dz;
+};
+
 struct VArgs {
     const AngleGeo *tab;
     int64_t a0;
@@ -53,6 +59,7 @@ struct VArgs {
     int32_t mem_lo;          // slice at the volume pointer
     int32_t accumulate;
     float lambda;            // SART relaxation
+    RayConst K;              // the projector's FP64 constants (rays parallel to a grid plane)
 };
 
 // FP32 factors of one (tile, view) pair
@@ -68,10 +75,25 @@ struct VRef {
 struct VPix {
     float cs[3];  // detector centre - source
     float eu[3], ev[3];
-    float pad;
+    int ks[3];    // voxel indices whose half-open slabs hold the source's coordinates
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// FP64 direction (mm per unit t) of the ray of pixel (a, b) of view G, as the projector forms it.
+__device__ __forceinline__ void ray_dir(const RayConst &K, const AngleGeo *G, int a, int b, double m[3]) {
+    const double ua = (a - K.cu) * K.du + K.offu;
+    const double vb = (b - K.cv) * K.dv + K.offv;
+    m[0] = fma(vb, G->ev[0], G->Dc[0] + ua * G->eu[0]) * K.dx;
+    m[1] = fma(vb, G->ev[1], G->Dc[1] + ua * G->eu[1]) * K.dy;
+    m[2] = fma(vb, G->ev[2], fma(ua, G->eu[2], G->Dc[2])) * K.dz;
+}
+
+// FP32 direction D (mm) with a component within rounding of zero: |D_c| <= 1e-5 |D|.
+__device__ __forceinline__ bool near_parallel(float D0, float D1, float D2) {
+    const float lim = 1e-10f * fmaf(D0, D0, fmaf(D1, D1, D2 * D2));
+    return D0 * D0 <= lim || D1 * D1 <= lim || D2 * D2 <= lim;
+}
 
 // Reference point of a tile: the centre of its columns in the grid and of its run of slices
 // clipped to the grid (independent of the slab, so slab splits do the same arithmetic).
@@ -464,7 +486,9 @@ __global__ __launch_bounds__(256) void k_adj_views(const TP *__restrict__ proj, 
             P.ev[0] = (float)(G.ev[0] * (double)A.dx);
             P.ev[1] = (float)(G.ev[1] * (double)A.dy);
             P.ev[2] = (float)(G.ev[2] * (double)A.dz);
-            P.pad = 0.0f;
+            P.ks[0] = (int)fmin(fmax(floor(G.S[0] + 0.5), -2.0), 1e9);
+            P.ks[1] = (int)fmin(fmax(floor(G.S[1] + 0.5), -2.0), 1e9);
+            P.ks[2] = (int)fmin(fmax(floor(G.S[2] + 0.5), -2.0), 1e9);
             pixg[threadIdx.x] = P;
         }
         __syncthreads();
@@ -514,11 +538,13 @@ __global__ __launch_bounds__(256) void k_adj_views(const TP *__restrict__ proj, 
                         float tlo = -FLT_MAX, thi = FLT_MAX;
                         bool in = true;
                         const float Dq[3] = {D0, D1, D2}, Qq[3] = {Q0, Q1, Q2}, Hq[3] = {hx, hy, hz};
+                        const int vq[3] = {i, j, kb + k};
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             if (Dq[c] == 0.0f) {
-                                // parallel to the planes of this axis: inside the half-open slab
-                                in = in && (-Hq[c] <= Qq[c]) && (Qq[c] < Hq[c]);
+                                // the ray runs in the plane of the source's coordinate: the voxel must
+                                // hold it in its half-open slab [k - 1/2, k + 1/2), as in the projector
+                                in = in && vq[c] == P.ks[c];
                             } else {
                                 const float inv = __builtin_amdgcn_rcpf(Dq[c]);
                                 const float t1 = (-Hq[c] - Qq[c]) * inv, t2 = (Hq[c] - Qq[c]) * inv;
@@ -542,6 +568,259 @@ __global__ __launch_bounds__(256) void k_adj_views(const TP *__restrict__ proj, 
         if (kk >= A.own_hi) break;
         const int64_t o = ((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i;
         vol[o] = from_f<TV>(acc[k]);
+    }
+}
+
+// The exact adjoint with each tile's rays staged in LDS.  The arithmetic per (voxel, pixel) is that
+// of k_adj_views, but what depends on the pixel alone is formed once per block and view: for every
+// pixel of the window holding the image of the tile's voxel boxes (corners projected as in
+// k_bp_views_lds, heights per view, windows packed at a row pitch of PITCH records), the
+// reciprocals of the ray direction's components and the pixel's value times |P - S|.  A candidate
+// pixel then costs one 16-byte LDS read and the slab test without reciprocals or a square root.  A
+// ray within FP32 rounding of a grid plane has its record formed from the FP64 direction, which
+// decides, as the projector does, whether it runs parallel to the plane; such an axis is NaN in the
+// record, and a view whose window holds one reads its records with the half-open slab rule for it.
+constexpr int VA_REC = 2048;  // pixel records (16 B) per block
+constexpr int VA_G = 32;      // views per group of tile references
+#ifndef CT_VA_K
+#define CT_VA_K 8
+#endif
+constexpr int VA_K = CT_VA_K;  // views per staging round, at most
+constexpr int VA_PN = 41, VA_PW = 65;
+
+template <typename TP, typename TV, int PITCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_views_lds(const TP *__restrict__ proj, TV *__restrict__ vol, VArgs A, int WW,
+                                                      int HW) {
+    __shared__ float4 rec[VA_REC];
+    __shared__ VRef ref[VA_G];
+    __shared__ float iref[VA_G][2];
+    __shared__ VPix pixg[VA_G];
+    __shared__ int org[VA_G][2];
+    __shared__ int hgt[VA_G];
+    __shared__ int zfl[VA_G];
+    const int i0 = blockIdx.x * VB_TX, j0 = blockIdx.y * VB_TY;
+    const int tid = threadIdx.x;
+    const int i = i0 + (tid % VB_TX);
+    const int j = j0 + (tid / VB_TX);
+    const int kb = run_base<>(A);
+    const bool live = i < A.nx && j < A.ny;
+    const double ir = tile_mid(i0, VB_TX, A.nx), jr = tile_mid(j0, VB_TY, A.ny), kr = tile_mid(kb, VB_NZ, A.nz);
+    const float di = (float)((double)i - ir), dj = (float)((double)j - jr);
+    const float hx = 0.5f * A.dx, hy = 0.5f * A.dy, hz = 0.5f * A.dz;
+    constexpr int ROWS = VA_REC / PITCH;
+    // this thread's corner of the tile's voxel boxes (offsets from the reference point, clipped to the grid)
+    const int cn = tid & 7;
+    const float cx = (float)(((cn & 1) ? (double)min(i0 + VB_TX, A.nx) - 0.5 : (double)i0 - 0.5) - ir);
+    const float cy = (float)(((cn & 2) ? (double)min(j0 + VB_TY, A.ny) - 0.5 : (double)j0 - 0.5) - jr);
+    const float cz = (float)(((cn & 4) ? (double)min(kb + VB_NZ, A.nz) - 0.5 : (double)kb - 0.5) - kr);
+    float acc[VB_NZ];
+#pragma unroll
+    for (int k = 0; k < VB_NZ; ++k) {
+        const int kk = kb + k;
+        acc[k] = (live && A.accumulate && kk >= A.own_lo && kk < A.own_hi)
+                     ? to_f(vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i])
+                     : 0.0f;
+    }
+    const int64_t psz = (int64_t)A.nu * A.nv;
+    constexpr int ES = (int)sizeof(TP);
+    for (int g0 = 0; g0 < A.nang; g0 += VA_G) {
+        const int ng = min(VA_G, A.nang - g0);
+        __syncthreads();  // the last group's references and records have been read
+        if (tid < ng) {
+            const AngleGeo &G = A.tab[A.a0 + g0 + tid];
+            VRef R;
+            float fa, fb;
+            view_ref<VM_ADJ>(A, G, ir, jr, kr, R, fa, fb);
+            ref[tid] = R;
+            iref[tid][0] = fa;
+            iref[tid][1] = fb;
+            VPix P;
+            P.cs[0] = (float)(G.Dc[0] * (double)A.dx);
+            P.cs[1] = (float)(G.Dc[1] * (double)A.dy);
+            P.cs[2] = (float)(G.Dc[2] * (double)A.dz);
+            P.eu[0] = (float)(G.eu[0] * (double)A.dx);
+            P.eu[1] = (float)(G.eu[1] * (double)A.dy);
+            P.eu[2] = (float)(G.eu[2] * (double)A.dz);
+            P.ev[0] = (float)(G.ev[0] * (double)A.dx);
+            P.ev[1] = (float)(G.ev[1] * (double)A.dy);
+            P.ev[2] = (float)(G.ev[2] * (double)A.dz);
+            P.ks[0] = (int)fmin(fmax(floor(G.S[0] + 0.5), -2.0), 1e9);
+            P.ks[1] = (int)fmin(fmax(floor(G.S[1] + 0.5), -2.0), 1e9);
+            P.ks[2] = (int)fmin(fmax(floor(G.S[2] + 0.5), -2.0), 1e9);
+            pixg[tid] = P;
+            zfl[tid] = 0;
+        }
+        __syncthreads();
+        {
+            // lanes 8q .. 8q + 7: the corners of the tile's voxel boxes under view q (FP32, relative to
+            // the view's integer origin), reduced to the window's origin and height
+            const int q = tid >> 3;
+            float as = 0.0f, bs = 0.0f;
+            if (q < ng) {
+                const VRef &R = ref[q];
+                const float w = fmaf(R.mw[0], cx, fmaf(R.mw[1], cy, fmaf(R.mw[2], cz, R.wr)));
+                const float iw = __builtin_amdgcn_rcpf(w);
+                as = __builtin_amdgcn_fmed3f(fmaf(fmaf(R.ga[0], cx, fmaf(R.ga[1], cy, R.ga[2] * cz)), iw, R.Aloc),
+                                             -16777216.0f, 16777216.0f);
+                bs = __builtin_amdgcn_fmed3f(fmaf(fmaf(R.gb[0], cx, fmaf(R.gb[1], cy, R.gb[2] * cz)), iw, R.Bloc),
+                                             -16777216.0f, 16777216.0f);
+            }
+            float amin = as, bmin = bs, bmax = bs;
+#pragma unroll
+            for (int off = 1; off < 8; off <<= 1) {
+                amin = fminf(amin, __shfl_xor(amin, off, 64));
+                bmin = fminf(bmin, __shfl_xor(bmin, off, 64));
+                bmax = fmaxf(bmax, __shfl_xor(bmax, off, 64));
+            }
+            if (cn == 0 && q < ng) {
+                // pixels whose centres can fall in the image: columns from ceil(min a*), rows from
+                // ceil(min b*) to floor(max b*), with a pixel of margin each side
+                const int wa = (int)floorf(amin) - 1, wb = (int)floorf(bmin) - 1;
+                org[q][0] = (int)iref[q][0] + wa;
+                org[q][1] = (int)iref[q][1] + wb;
+                hgt[q] = min((int)floorf(bmax) - wb + 2, HW);
+            }
+        }
+        __syncthreads();
+        for (int t0 = 0; t0 < ng;) {
+            // the views t0 .. t1 - 1 whose windows fit the buffer together (at least one: HW <= ROWS)
+            int t1 = t0, rows = 0;
+            while (t1 < ng && t1 - t0 < VA_K && rows + hgt[t1] <= ROWS) rows += hgt[t1++];
+            __syncthreads();  // the last round's records have been read
+            // records of the round's windows, one thread per pixel
+            for (int pix = tid; pix < rows * PITCH; pix += 256) {
+                int r = pix / PITCH, q = t0;
+                const int c = pix - r * PITCH;
+                while (r >= hgt[q]) r -= hgt[q++];
+                const int a = org[q][0] + c, b = org[q][1] + r;
+                float4 R4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (c < WW && (unsigned)a < (unsigned)A.nu && (unsigned)b < (unsigned)A.nv) {
+                    const VPix &P = pixg[q];
+                    const float y = to_f(proj[(int64_t)(g0 + q) * psz + (int64_t)b * A.nu + a]);
+                    // the ray direction as k_adj_views forms it
+                    const float vb = fmaf((float)b - A.cv, A.dv, A.offv);
+                    const float ua = fmaf((float)a - A.cu, A.du, A.offu);
+                    const float D0 = fmaf(ua, P.eu[0], fmaf(vb, P.ev[0], P.cs[0]));
+                    const float D1 = fmaf(ua, P.eu[1], fmaf(vb, P.ev[1], P.cs[1]));
+                    const float D2 = fmaf(ua, P.eu[2], fmaf(vb, P.ev[2], P.cs[2]));
+                    R4 = make_float4(__builtin_amdgcn_rcpf(D0), __builtin_amdgcn_rcpf(D1), __builtin_amdgcn_rcpf(D2),
+                                     y * __builtin_amdgcn_sqrtf(fmaf(D0, D0, fmaf(D1, D1, D2 * D2))));
+                    if (near_parallel(D0, D1, D2)) {
+                        // within FP32 rounding of a grid plane: the FP64 direction decides, as the
+                        // projector decides, which axes the ray runs parallel to (NaN in the record, and
+                        // the view takes the form that reads it); the others take FP64 reciprocals
+                        double m[3];
+                        ray_dir(A.K, A.tab + A.a0 + g0 + q, a, b, m);
+                        const double L = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+                        float rr[3];
+                        bool par = false;
+#pragma unroll
+                        for (int c2 = 0; c2 < 3; ++c2) {
+                            const bool pc = fabs(m[c2]) < 1e-12 * L;
+                            par = par || pc;
+                            rr[c2] = pc ? __builtin_nanf("") : (float)(1.0 / m[c2]);
+                        }
+                        R4 = make_float4(rr[0], rr[1], rr[2], (float)(y * L));
+                        if (par) atomicOr(&zfl[q], 1);
+                    }
+                }
+                rec[pix] = R4;
+            }
+            __syncthreads();
+            if (live) {
+                int rb = 0;
+                for (int q = t0; q < t1; ++q) {
+                    const VRef R = ref[q];
+                    const VPix P = pixg[q];
+                    const float oa = iref[q][0], ob = iref[q][1];
+                    const int wa0 = org[q][0], wb0 = org[q][1], h = hgt[q];
+                    const bool slow = zfl[q] != 0;
+                    const int rbase = rb * PITCH - wa0;  // record of pixel (a, b): rbase + (b - wb0) PITCH + a
+                    rb += h;
+                    const float wxy = fmaf(R.mw[0], di, fmaf(R.mw[1], dj, R.wr));
+                    const float axy = fmaf(R.ga[0], di, R.ga[1] * dj), bxy = fmaf(R.gb[0], di, R.gb[1] * dj);
+#pragma unroll
+                    for (int k = 0; k < VB_NZ; ++k) {
+                        const float dkk = (float)((double)(kb + k) - kr);
+                        const float w = fmaf(R.mw[2], dkk, wxy);
+                        const float iw = __builtin_amdgcn_rcpf(w);
+                        const float al = fmaf(R.ga[2], dkk, axy) * iw, be = fmaf(R.gb[2], dkk, bxy) * iw;
+                        const float ha = 0.5f * (fabsf(fmaf(-al, R.mw[0], R.ga[0])) + fabsf(fmaf(-al, R.mw[1], R.ga[1])) +
+                                                 fabsf(fmaf(-al, R.mw[2], R.ga[2]))) * iw;
+                        const float hb = 0.5f * (fabsf(fmaf(-be, R.mw[0], R.gb[0])) + fabsf(fmaf(-be, R.mw[1], R.gb[1])) +
+                                                 fabsf(fmaf(-be, R.mw[2], R.gb[2]))) * iw;
+                        const float as = al + R.Aloc, bs = be + R.Bloc;
+                        const float ma = fmaf(ha, 0.02f, 1e-3f), mb = fmaf(hb, 0.02f, 1e-3f);
+                        const float fnu = (float)A.nu, fnv = (float)A.nv;
+                        // candidate pixels, clamped to the detector and to the view's window
+                        const int alo = max((int)fmaxf(oa + ceilf(as - ha - ma), 0.0f), wa0);
+                        const int ahi = min((int)fminf(oa + floorf(as + ha + ma), fnu - 1.0f), wa0 + WW - 1);
+                        const int blo = max((int)fmaxf(ob + ceilf(bs - hb - mb), 0.0f), wb0);
+                        const int bhi = min((int)fminf(ob + floorf(bs + hb + mb), fnv - 1.0f), wb0 + h - 1);
+                        const float sc = w * R.w0;
+                        const float qa0 = sc * A.du * P.eu[0], qa1 = sc * A.du * P.eu[1], qa2 = sc * A.du * P.eu[2];
+                        const float qb0 = sc * A.dv * P.ev[0], qb1 = sc * A.dv * P.ev[1], qb2 = sc * A.dv * P.ev[2];
+                        float s = 0.0f;
+                        if (!slow) {
+                            for (int b = blo; b <= bhi; ++b) {
+                                const float db = ((float)b - ob) - bs;
+                                const float pb0 = db * qb0, pb1 = db * qb1, pb2 = db * qb2;
+                                const float4 *rrow = rec + (rbase + (b - wb0) * PITCH);
+                                for (int a = alo; a <= ahi; ++a) {
+                                    const float da = ((float)a - oa) - as;
+                                    const float Q0 = fmaf(da, qa0, pb0), Q1 = fmaf(da, qa1, pb1), Q2 = fmaf(da, qa2, pb2);
+                                    const float4 ry = rrow[a];
+                                    // slab of each axis: t in -Q / D -+ h / |D|
+                                    const float m0 = -Q0 * ry.x, m1 = -Q1 * ry.y, m2 = -Q2 * ry.z;
+                                    const float e0 = hx * fabsf(ry.x), e1 = hy * fabsf(ry.y), e2 = hz * fabsf(ry.z);
+                                    const float tlo = fmaxf(fmaxf(m0 - e0, m1 - e1), m2 - e2);
+                                    const float thi = fminf(fminf(m0 + e0, m1 + e1), m2 + e2);
+                                    s = fmaf(fmaxf(thi - tlo, 0.0f), ry.w, s);
+                                }
+                            }
+                        } else {
+                            // records of rays parallel to a grid plane carry NaN for that axis: the voxel
+                            // must then hold the source's coordinate in its half-open slab
+                            for (int b = blo; b <= bhi; ++b) {
+                                const float db = ((float)b - ob) - bs;
+                                const float pb0 = db * qb0, pb1 = db * qb1, pb2 = db * qb2;
+                                const float4 *rrow = rec + (rbase + (b - wb0) * PITCH);
+                                for (int a = alo; a <= ahi; ++a) {
+                                    const float da = ((float)a - oa) - as;
+                                    const float Q0 = fmaf(da, qa0, pb0), Q1 = fmaf(da, qa1, pb1), Q2 = fmaf(da, qa2, pb2);
+                                    const float4 ry = rrow[a];
+                                    const float rq[3] = {ry.x, ry.y, ry.z}, Qq[3] = {Q0, Q1, Q2}, Hq[3] = {hx, hy, hz};
+                                    const int vq[3] = {i, j, kb + k};
+                                    float tlo = -FLT_MAX, thi = FLT_MAX;
+                                    bool in = true;
+#pragma unroll
+                                    for (int c = 0; c < 3; ++c) {
+                                        if (rq[c] != rq[c]) {
+                                            in = in && vq[c] == P.ks[c];
+                                        } else {
+                                            const float m = -Qq[c] * rq[c], e = Hq[c] * fabsf(rq[c]);
+                                            tlo = fmaxf(tlo, m - e);
+                                            thi = fminf(thi, m + e);
+                                        }
+                                    }
+                                    if (in) s = fmaf(fmaxf(thi - tlo, 0.0f), ry.w, s);
+                                }
+                            }
+                        }
+                        acc[k] += s;
+                    }
+                }
+            }
+            t0 = t1;
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < VB_NZ; ++k) {
+        const int kk = kb + k;
+        if (kk < A.own_lo) continue;
+        if (kk >= A.own_hi) break;
+        vol[((int64_t)(kk - A.mem_lo) * A.ny + j) * A.nx + i] = from_f<TV>(acc[k]);
     }
 }
 
@@ -570,6 +849,8 @@ VArgs make_vargs(const ct_plan *p, const AngleGeo *tab, int64_t a0, int64_t a1, 
     A.mem_lo = (int32_t)slab.mem_lo;
     A.accumulate = accumulate;
     A.lambda = 0.0f;
+    A.K = RayConst{g.dDetector[0], g.dDetector[1], (g.nDetector[0] - 1) / 2.0, (g.nDetector[1] - 1) / 2.0,
+                   g.offDetector[0], g.offDetector[1], g.dVoxel[0], g.dVoxel[1], g.dVoxel[2]};
     return A;
 }
 
@@ -585,30 +866,28 @@ dim3 vgrid(const VArgs &A, const Slab &slab, int nz = VB_NZ) {
     return dim3((unsigned)((A.nx + VB_TX - 1) / VB_TX), (unsigned)((A.ny + VB_TY - 1) / VB_TY), runs);
 }
 
-// Detector window (columns WW, rows HW) holding the taps of any 16 x 16 x VL_NZ tile, clipped to
-// the grid, under any view of the plan; 0 x 0 when some view's is too large for the staging buffer.
+// Detector window (columns WW, rows HW) holding the image of any 16 x 16 x TZ tile of voxel centres
+// (box = false: the backprojectors' bilinear taps) or of voxel boxes (box = true: the pixels whose
+// rays can cross the tile), clipped to the grid, under any view of the plan; the staging buffer's
+// limits (rows, pitch) are checked by the caller.
 // With L = n.(S - X) the depth, p = e_u.(X - S) and a* = const + DSD_v p / (L du), two points of a
 // tile differ in a* by at most DSD_v (E_p / L_min + |p|_max E_L / L_min^2) / du, where E_p and E_L
 // bound the change of p and L over the tile's extent (the sums of |e_u| and |n| times the extent
 // along each axis), and L_min and |p|_max are taken over the corners of a box holding the tile (both
 // are affine in X).  The grid is cut into VL_NS^3 boxes, each grown by a tile's extent so that every
 // tile lies in one, and the largest bound is kept; likewise for b* with e_v.  Margins: one pixel
-// each side plus the second tap.  Computed once per plan.
+// each side plus the second tap.  0 x 0 when a view's depth is not positive or the window is
+// implausibly large.
 constexpr int VL_NS = 4;
-void vl_window(ct_plan *p, int &WW, int &HW) {
-    std::lock_guard<std::mutex> lk(p->mu);
-    if (p->vl_ww >= 0) {
-        WW = p->vl_ww;
-        HW = p->vl_hw;
-        return;
-    }
+void window_bound(const ct_plan *p, int64_t tz, bool box, int &WW, int &HW) {
     const ct_geometry &g = p->g;
     double x0[3], x1[3], ext[3];
-    const int64_t tn[3] = {VB_TX, VB_TY, VL_NZ};
+    const int64_t tn[3] = {VB_TX, VB_TY, tz};
+    const double grow = box ? 0.5 : 0.0;  // voxel boxes reach half a voxel past the centres
     for (int a = 0; a < 3; ++a) {
-        x0[a] = g.offOrigin[a] - (g.nVoxel[a] - 1) / 2.0 * g.dVoxel[a];
-        x1[a] = x0[a] + (g.nVoxel[a] - 1) * g.dVoxel[a];
-        ext[a] = (double)(std::min(tn[a], g.nVoxel[a]) - 1) * g.dVoxel[a];
+        x0[a] = g.offOrigin[a] - ((g.nVoxel[a] - 1) / 2.0 + grow) * g.dVoxel[a];
+        x1[a] = g.offOrigin[a] + ((g.nVoxel[a] - 1) / 2.0 + grow) * g.dVoxel[a];
+        ext[a] = ((double)(std::min(tn[a], g.nVoxel[a]) - 1) + 2.0 * grow) * g.dVoxel[a];
     }
     double eu_max = 0.0, ev_max = 0.0;
     bool ok = true;
@@ -654,11 +933,42 @@ void vl_window(ct_plan *p, int &WW, int &HW) {
     if (ok) {
         WW = (int)std::ceil(eu_max) + 4;
         HW = (int)std::ceil(ev_max) + 4;
-        // one lane per window column when staging
-        if (WW > 64 || HW > VL_FLOATS / (WW <= VL_PN ? VL_PN : VL_PW)) WW = HW = 0;
     }
-    p->vl_ww = WW;
-    p->vl_hw = HW;
+}
+
+// The exact adjoint's window (16 x 16 x VB_NZ tiles of voxel boxes), once per plan; 0 x 0 when it
+// does not fit the records (VA_REC, at a pitch of at most VA_PW).
+void va_window(ct_plan *p, int &WW, int &HW) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->va_ww < 0) {
+        window_bound(p, VB_NZ, true, WW, HW);
+        if (WW > VA_PW || HW > VA_REC / (WW <= VA_PN ? VA_PN : VA_PW)) WW = HW = 0;
+        p->va_ww = WW;
+        p->va_hw = HW;
+    }
+    WW = p->va_ww;
+    HW = p->va_hw;
+}
+
+// CT_VIEWS_ADJ_DIRECT=1 sends the exact adjoint of plans of views to k_adj_views (no staging), =2 to
+// the staged per-view kernel even for vertical views (tests compare them).
+int views_adjoint_mode() {
+    const char *e = std::getenv("CT_VIEWS_ADJ_DIRECT");
+    return e && (e[0] == '1' || e[0] == '2') ? e[0] - '0' : 0;
+}
+
+// The backprojectors' window (16 x 16 x VL_NZ tiles of voxel centres), once per plan; 0 x 0 when it
+// does not fit the staging buffer (one lane per window column, VL_FLOATS floats).
+void vl_window(ct_plan *p, int &WW, int &HW) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->vl_ww < 0) {
+        window_bound(p, VL_NZ, false, WW, HW);
+        if (WW > 64 || HW > VL_FLOATS / (WW <= VL_PN ? VL_PN : VL_PW)) WW = HW = 0;
+        p->vl_ww = WW;
+        p->vl_hw = HW;
+    }
+    WW = p->vl_ww;
+    HW = p->vl_hw;
 }
 }  // namespace
 
@@ -702,8 +1012,22 @@ ct_status launch_backproject_views(ct_plan *p, ct_backprojector kind, const void
         CT_DISPATCH2(pt, TP, vt, TV,
                      hipLaunchKernelGGL((k_bp_views<VM_PM, TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));
     } else {
-        CT_DISPATCH2(pt, TP, vt, TV,
-                     hipLaunchKernelGGL((k_adj_views<TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));
+        int AW = 0, AH = 0;
+        va_window(p, AW, AH);
+        if (AW > 0 && views_adjoint_mode() != 1) {
+            if (AW <= VA_PN) {
+                CT_DISPATCH2(pt, TP, vt, TV,
+                             hipLaunchKernelGGL((k_adj_views_lds<TP, TV, VA_PN>), grid, block, 0, st, (const TP *)proj,
+                                                (TV *)vol, A, AW, AH));
+            } else {
+                CT_DISPATCH2(pt, TP, vt, TV,
+                             hipLaunchKernelGGL((k_adj_views_lds<TP, TV, VA_PW>), grid, block, 0, st, (const TP *)proj,
+                                                (TV *)vol, A, AW, AH));
+            }
+        } else {
+            CT_DISPATCH2(pt, TP, vt, TV,
+                         hipLaunchKernelGGL((k_adj_views<TP, TV>), grid, block, 0, st, (const TP *)proj, (TV *)vol, A));
+        }
     }
     CT_HIP(hipGetLastError());
     return CT_OK;

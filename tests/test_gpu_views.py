@@ -250,7 +250,8 @@ def test_views_staged_backprojection_equals_direct(ragged, orc, kind, monkeypatc
 def test_views_full_size_carm_backprojection_sampled(orc):
     """The C-arm scan of the 512^3 workload (360 views, 512^2 detector; detectors turned by up to 10
     degrees, sources and detectors displaced by up to 5 mm, orbit tilted by 5 degrees), backprojected
-    in the launch configuration of a resident call: sampled voxels against the oracle."""
+    (FDK, pseudo-matched, exact adjoint) in the launch configuration of a resident call: sampled
+    voxels against the oracle."""
     w = inputs.workload("medium")
     views = inputs.carm_views(w.DSO, w.DSD, w.angles, 7, tilt_deg=10.0, jitter_mm=5.0, orbit_tilt_deg=5.0)
     og = orc.Geometry.from_dict(w.geometry_dict())
@@ -258,10 +259,11 @@ def test_views_full_size_carm_backprojection_sampled(orc):
     y = inputs.random_array(plan.proj_shape, 38, kind="uniform")
     yd = torch.from_numpy(y).to(DEV)
     vidx = inputs.sample_indices(int(np.prod(plan.vol_shape)), 300, 39)
-    for bp, wk in (("fdk", orc.W_FDK), ("pm", orc.W_PM)):
+    for bp, wk in (("fdk", orc.W_FDK), ("pm", orc.W_PM), ("adjoint", None)):
         say(f"[views] C-arm 512^3 x 360 backprojection {bp}")
         v = plan.backproject(yd, bp).cpu().numpy().ravel()
-        e = rel_l2(v[vidx], orc.bp_voxels(og, views, y, vidx, wk))
+        ref = orc.siddon_adj_voxels(og, views, y, vidx) if wk is None else orc.bp_voxels(og, views, y, vidx, wk)
+        e = rel_l2(v[vidx], ref)
         say(f"   sampled voxels rel L2 {e:.3e}")
         assert e <= TOL_BP
 
@@ -317,3 +319,72 @@ def test_helical_views_column_adjoint_dot_product(orc):
     e = rel_l2(at.cpu().numpy().ravel()[vidx], ref)
     say(f"   sampled voxels rel L2 {e:.3e}")
     assert e <= TOL_BP
+
+
+@pytest.mark.parametrize("kind", ["carm", "helical"])
+def test_views_staged_adjoint_equals_direct(ragged, orc, kind, monkeypatch):
+    """The exact adjoint of plans of views stages each tile's rays in LDS (the reciprocals of their
+    directions and the pixel value times |P - S|); CT_VIEWS_ADJ_DIRECT=1 selects the kernel that
+    forms them per voxel and pixel, =2 the staged kernel even for vertical views.  Within 2e-6 of
+    each other and within the oracle's bar; angle ranges with accumulation add up."""
+    w, vol, y, og = ragged
+    views = _views(kind, w)
+    plan = Plan(w.geometry_dict(), views)
+    yd = torch.from_numpy(y).to(DEV)
+    say(f"[views] {kind} adjoint: staged vs direct")
+    monkeypatch.setenv("CT_VIEWS_ADJ_DIRECT", "2")
+    a = plan.backproject(yd, "adjoint")
+    part = plan.backproject(yd[:6].contiguous(), "adjoint", angle_begin=0, angle_end=6)
+    plan.backproject(yd[6:].contiguous(), "adjoint", out=part, accumulate=True, angle_begin=6, angle_end=13)
+    monkeypatch.setenv("CT_VIEWS_ADJ_DIRECT", "1")
+    b = plan.backproject(yd, "adjoint")
+    monkeypatch.delenv("CT_VIEWS_ADJ_DIRECT")
+    assert not torch.equal(a, b), "the staged kernel did not run"
+    e = rel_l2(a.cpu().numpy(), b.cpu().numpy())
+    say(f"   rel L2 {e:.3e}")
+    assert e <= 2e-6
+    assert rel_l2(part.cpu().numpy(), a.cpu().numpy()) <= 1e-6
+    assert rel_l2(a.cpu().numpy(), orc.siddon_adj(og, views, y.astype(np.float64))) <= TOL_BP
+
+
+def test_views_staged_adjoint_rays_in_grid_planes(orc, monkeypatch):
+    """A circular orbit written as views with odd detector sizes, no offsets and even grid sizes:
+    the central row's rays (and at 0 degrees the central column's) have exactly zero components and
+    run along voxel faces, where the half-open slab rule decides.  The other angles stay away from
+    quarter turns, whose FP64 cosines leave components of 1e-13 mm: a ray there crosses the face
+    inside the grid, and which side it takes is a tie at FP64 rounding.  The forward projectors and
+    the column kernels (circular plan, and the plan of views) against the oracle; each per-view
+    kernel (staged, CT_VIEWS_ADJ_DIRECT=2; per pixel, =1) against the oracle, the circular column
+    kernel and the dot product with the forward projector."""
+    th = np.array([0.0, 0.35, 1.1, 2.0, 2.6, 3.5, 4.4, 5.3])
+    w = inputs.Workload("views_planes", (20, 18, 16), (1.0, 1.0, 1.0), (31, 25), (1.5, 1.5), 8, 10, 43, angles=th)
+    og = orc.Geometry.from_dict(w.geometry_dict())
+    views = orc.circular_views(og, w.angles)
+    plan, pc = Plan(w.geometry_dict(), views), Plan(w.geometry_dict(), w.angles)
+    rng = np.random.default_rng(9)
+    u = torch.from_numpy(rng.uniform(0, 1, plan.vol_shape).astype(np.float32)).to(DEV)
+    v = torch.from_numpy(rng.uniform(0, 1, plan.proj_shape).astype(np.float32)).to(DEV)
+    ref = orc.siddon_adj(og, views, v.cpu().numpy().astype(np.float64))
+    fref = orc.siddon_fwd(og, views, u.cpu().numpy().astype(np.float64))
+    for name, p in (("circular", pc), ("views", plan)):
+        e = rel_l2(p.forward(u).cpu().numpy(), fref)
+        say(f"[views] rays in grid planes: {name} forward rel L2 {e:.3e}")
+        assert e <= TOL_PROJ, name
+    col = pc.backproject(v, "adjoint").cpu().numpy()
+    say(f"   circular column adjoint rel L2 {rel_l2(col, ref):.3e}")
+    assert rel_l2(col, ref) <= TOL_BP
+    say(f"   views column adjoint rel L2 {rel_l2(plan.backproject(v, 'adjoint').cpu().numpy(), ref):.3e}")
+    assert rel_l2(plan.backproject(v, "adjoint").cpu().numpy(), ref) <= TOL_BP
+    lhs = float((plan.forward(u).double() * v.double()).sum())
+    for mode in ("2", "1"):
+        monkeypatch.setenv("CT_VIEWS_ADJ_DIRECT", mode)
+        at = plan.backproject(v, "adjoint")
+        monkeypatch.delenv("CT_VIEWS_ADJ_DIRECT")
+        e = rel_l2(at.cpu().numpy(), ref)
+        say(f"   CT_VIEWS_ADJ_DIRECT={mode}: rel L2 {e:.3e}")
+        assert e <= TOL_BP
+        # the per-view kernels form each chord from FP32 detector offsets (8e-6 of the oracle's sums
+        # here, the column kernels 1.6e-6)
+        assert rel_l2(at.cpu().numpy(), col) <= 2e-5
+        rhs = float((u.double() * at.double()).sum())
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (mode, lhs, rhs)
