@@ -750,12 +750,18 @@ __global__ __launch_bounds__(256) void k_pcols2(const TV *__restrict__ src, TV *
     }
 }
 
-#ifndef CT_IC_BATCH
-#define CT_IC_BATCH 4
+// Samples per trip (IC_B): a lane issues the loads of IC_B samples before using them.  One sample
+// per trip suits detector columns whose rows share a vertical plane (circular and helical scans: a
+// wave's lanes change cells together, 101 ms at 512^3 / 360 against 104 with two and 135 with four);
+// four suit tilted columns, whose rows drift apart (168 ms for a C-arm scan against 183 with one).
+#ifndef CT_IC_BATCH_V
+#define CT_IC_BATCH_V 1
 #endif
-constexpr int IC_B = CT_IC_BATCH;  // samples per trip
+#ifndef CT_IC_BATCH_T
+#define CT_IC_BATCH_T 4
+#endif
 
-template <typename TV, typename TP, int ROWS, bool XP>
+template <typename TV, typename TP, int ROWS, bool XP, int IC_B>
 __global__ __launch_bounds__(64 * ZC_COLS) void k_interp_col(const TV *__restrict__ vp, TP *__restrict__ proj,
                                                              FwdArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1244,7 +1250,11 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
 #ifdef CT_ZC_ROWS
             const int rows = CT_ZC_ROWS;
 #else
+#ifndef CT_IC_ROWS
             const int rows = cblocks * (a1 - a0) * ((nv + 127) / 128) >= 4096 ? 2 : 1;
+#else
+            const int rows = CT_IC_ROWS;
+#endif
 #endif
             const int64_t rgroups = (nv + 64 * rows - 1) / (64 * rows);
             const int64_t max_ang = angles_per_launch(cblocks * rgroups, 64 * ZC_COLS);
@@ -1313,9 +1323,16 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
                 A.rgroups = (int32_t)rgroups;
                 char *pp = (char *)proj + (size_t)(c0 - a0) * proj_angle;
                 const dim3 grid((unsigned)(cblocks * (c1 - c0) * rgroups)), block(64 * ZC_COLS);
-#define CT_ICOL(R, X)                                                                                          \
+#define CT_ICOL2(R, X, B)                                                                                      \
     CT_DISPATCH2(vt, TV, pt, TP,                                                                               \
-                 hipLaunchKernelGGL((k_interp_col<TV, TP, R, X>), grid, block, 0, st, (const TV *)vpad, (TP *)pp, A))
+                 hipLaunchKernelGGL((k_interp_col<TV, TP, R, X, B>), grid, block, 0, st, (const TV *)vpad, (TP *)pp, \
+                                    A))
+#define CT_ICOL(R, X)                          \
+    if (p->views && !p->vertical) {            \
+        CT_ICOL2(R, X, CT_IC_BATCH_T);         \
+    } else {                                   \
+        CT_ICOL2(R, X, CT_IC_BATCH_V);         \
+    }
                 if (rows == 2) {
                     if (xp) {
                         CT_ICOL(2, true);
@@ -1330,6 +1347,7 @@ ct_status launch_forward(ct_plan *p, ct_projector kind, const void *vol, ct_dtyp
                     }
                 }
 #undef CT_ICOL
+#undef CT_ICOL2
                 CT_HIP(hipGetLastError());
             }
             CT_HIP(hipFreeAsync(vpad, st));

@@ -268,7 +268,9 @@ static_assert(VL_NZ * 256 <= VL_FLOATS, "the staging window parks the sums");
 #define CT_VL_WAVES 6
 #endif
 
-template <int MODE, int PITCH, typename TP, typename TV>
+// VERT: every view vertical (e_v = +z, e_u horizontal, the detector centre at the source's height),
+// where the depth and a* are constant along a voxel column.
+template <int MODE, int PITCH, bool VERT, typename TP, typename TV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT_VL_WAVES))) void k_bp_views_lds(
     const TP *__restrict__ proj, TV *__restrict__ vol, VArgs A, int WW, int HW) {
     __shared__ float win[VL_FLOATS];
@@ -397,6 +399,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CT_VL_WAVES
                     const float axy = fmaf(R.ga[0], di, R.ga[1] * dj), bxy = fmaf(R.gb[0], di, R.gb[1] * dj);
                     const float sx = fmaf(di, A.dx, R.sx), sy = fmaf(dj, A.dy, R.sy);
                     const float sxy2 = fmaf(sx, sx, sy * sy);
+                    if constexpr (VERT) {
+                        // vertical views: the depth and a* do not change along the column, so the
+                        // column's tap column, fraction and FDK weight are formed once; b* is affine in k
+                        const float iw = __builtin_amdgcn_rcpf(wxy);
+                        const float as = fmaf(axy, iw, R.Aloc);
+                        const float af = floorf(as);
+                        const float fa = as - af;
+                        const float cb = fmaf(__builtin_amdgcn_fmed3f(af, 0.0f, lamax), 4.0f, qb);
+                        const float b0 = fmaf(bxy, iw, R.Bloc), db = R.gb[2] * iw;
+                        const float iw2 = iw * iw, iw3 = iw2 * iw;
+#pragma unroll
+                        for (int k = 0; k < VL_NZ; ++k) {
+                            const float dk = dk0 + (float)k;
+                            const float bs = fmaf(dk, db, b0);
+                            const float bf = floorf(bs);
+                            const float fb = bs - bf;
+                            const float lb = __builtin_amdgcn_fmed3f(bf, 0.0f, lbmax);
+                            const float *t = (const float *)((const char *)win + (int)fmaf(lb, (float)(4 * PITCH), cb));
+                            const float v0 = fmaf(fa, t[1] - t[0], t[0]);
+                            const float v1 = fmaf(fa, t[PITCH + 1] - t[PITCH], t[PITCH]);
+                            const float v = fmaf(fb, v1 - v0, v0);
+                            float wt;
+                            if (MODE == VM_PM) {
+                                const float sz = fmaf(dk, A.dz, R.sz);
+                                wt = __builtin_amdgcn_sqrtf(fmaf(sz, sz, sxy2)) * iw3;
+                            } else {
+                                wt = iw2;
+                            }
+                            acc[k] = fmaf(wt, v, acc[k]);
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int k = 0; k < VL_NZ; ++k) {
                         const float dk = dk0 + (float)k;
@@ -984,10 +1018,16 @@ ct_status launch_backproject_views(ct_plan *p, ct_backprojector kind, const void
     if (WW > 0 && !direct_views_bp()) {
         const bool narrow = WW <= VL_PN;
         const dim3 lgrid = vgrid(A, slab, VL_NZ);
-#define CT_VL(MODE, PITCH)                                                                                      \
+#define CT_VL2(MODE, PITCH, VERT)                                                                               \
     CT_DISPATCH2(pt, TP, vt, TV,                                                                                \
-                 hipLaunchKernelGGL((k_bp_views_lds<MODE, PITCH, TP, TV>), lgrid, block, 0, st, (const TP *)proj, \
-                                    (TV *)vol, A, WW, HW))
+                 hipLaunchKernelGGL((k_bp_views_lds<MODE, PITCH, VERT, TP, TV>), lgrid, block, 0, st,           \
+                                    (const TP *)proj, (TV *)vol, A, WW, HW))
+#define CT_VL(MODE, PITCH)              \
+    if (p->vertical) {                  \
+        CT_VL2(MODE, PITCH, true);      \
+    } else {                            \
+        CT_VL2(MODE, PITCH, false);     \
+    }
         if (kind == CT_BP_FDK) {
             if (narrow) {
                 CT_VL(VM_FDK, VL_PN);
@@ -1002,6 +1042,7 @@ ct_status launch_backproject_views(ct_plan *p, ct_backprojector kind, const void
             }
         }
 #undef CT_VL
+#undef CT_VL2
         CT_HIP(hipGetLastError());
         return CT_OK;
     }
