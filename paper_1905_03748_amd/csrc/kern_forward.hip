@@ -86,8 +86,20 @@ __device__ __forceinline__ bool ray_clip(const AngleGeo &G, const FwdArgs &A, in
     return hit && t0 < t1;
 }
 
+#ifndef CT_FWD_XCD_W
+#define CT_FWD_XCD_W 32
+#endif
 __device__ __forceinline__ void pixel_of(const FwdArgs &A, int &ai, int &a, int &b) {
-    const int bid = blockIdx.x;
+    int bid = blockIdx.x;
+#if CT_FWD_XCD_W > 1
+    {
+        // workgroups are dealt to the 8 XCDs in turn: give each XCD CT_FWD_XCD_W consecutive blocks
+        // (neighbouring pixels and angles, whose rays cross the same voxels) out of every 8 * CT_FWD_XCD_W
+        constexpr int W = CT_FWD_XCD_W, C = 8 * W;
+        const int full = (int)(gridDim.x / C) * C;
+        if (bid < full) bid = (bid / C) * C + (bid % 8) * W + (bid % C) / 8;
+    }
+#endif
     const int ub = bid % A.ublocks;
     const int rest = bid / A.ublocks;
     ai = rest % A.nang;
