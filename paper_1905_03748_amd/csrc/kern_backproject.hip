@@ -910,8 +910,10 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
                         // both parameters below 0, which clamp to the same value
                         len = __builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T);
                     } else {
-                        const float lo = fmaxf(fminf(tA, tB), 0.0f), hi = fminf(fmaxf(tA, tB), T);
-                        len = fmaxf(hi - lo, 0.0f);
+                        // either order: clamping to [0, T] is monotonic, so the clamped pair's distance
+                        // is the overlap of [min, max] with [0, T] (0 when they miss), bit for bit the
+                        // max(min(max, T) - max(min, 0), 0) it replaces; the |.| folds into the FMA
+                        len = fabsf(__builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T));
                     }
                     acc[r] = fmaf(len, w.x, acc[r]);
                 }
