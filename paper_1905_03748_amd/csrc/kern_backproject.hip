@@ -70,6 +70,14 @@ __device__ __forceinline__ double rcp_f64(double d) {
     return r * fma(-d, r, 2.0);
 }
 
+// LDS written by some lanes of a wave and read by others: the wave's LDS accesses complete in
+// order, so this only keeps the compiler from moving accesses across it
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Detector coordinates of the voxels of a tile, relative to a reference point of the tile.
 //
 // At a detector of more than 2048 pixels an FP32 coordinate a* ~ 3000 is only resolved to
@@ -681,6 +689,8 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
                                                  int zgroups, int xblocks) {
     static_assert(!VW || (!ORD && !ZC), "vertical views take the general face order and [z][y][x] volumes");
     extern __shared__ float rstep[];  // nv + 2 parameter steps, one per row of the padded copy
+    __shared__ float4 chdr[4][64][3];  // per wave: the set-up of up to 64 (angle, column) pairs
+    __shared__ int cslot[4][3][64];    // per wave and angle of a batch: first column, pairs before, through
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     for (int r = threadIdx.x; r < A.nv + 2; r += 256) rstep[r] = adj_row_step(A, r);
@@ -750,174 +760,235 @@ __global__ __launch_bounds__(256) CT_ADJ_OCC void k_adj_col(const float *__restr
     const float bmax = (float)(A.nv + 1 - NR);
     const float aum = (float)(A.cu - A.offu / A.du), iau = (float)(1.0 / A.du);
     const int nvp = A.nv + 2;
-    for (int t = 0; t < A.nang; ++t) {
-        const AngleGeo &G = A.tab[A.a0 + t];
-        const double c = G.c, s = G.s;
-        double Wx, Wy;  // source -> column centre
-        double zf0v = zf0dz;  // lower face of voxel 0 above the source plane, voxel units
-        float umin = FLT_MAX, umax = -FLT_MAX;
-        float szf = 0.0f;  // VW: the source's height
-        if (VW) {
-            Wx = xc - G.Smm[0];
-            Wy = yc - G.Smm[1];
-            zf0v = zf0dz - G.Smm[2] / A.ddz;
-            szf = (float)G.Smm[2];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                // a voxel below the source plane is met by falling rows first at its upper face
-                const bool below = zb[r] - szf <= 0.0f;
-                kA[r] = below ? (float)(A.own_lo + zg * 64 * R + 64 * r + lane + 1) : (float)(A.own_lo + zg * 64 * R + 64 * r + lane);
-                sg[r] = below ? -1.0f : 1.0f;
-            }
-            // detector coordinate u of the ray through each corner of the column's square: with
-            // X - S = Xr and C - S + u e_u parallel to it, u = (Xr x (C - S)) / (e_u x Xr)
-            const float dcx = (float)(G.Dc[0] * A.ddx), dcy = (float)(G.Dc[1] * A.ddy);
-            const float eux = (float)(G.eu[0] * A.ddx), euy = (float)(G.eu[1] * A.ddy);
-            const float fwx = (float)Wx, fwy = (float)Wy;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float X = fwx + ((q & 1) ? hx : -hx), Y = fwy + ((q & 2) ? hy : -hy);
-                const float u = (X * dcy - Y * dcx) * __builtin_amdgcn_rcpf(eux * Y - euy * X);
-                umin = fminf(umin, u);
-                umax = fmaxf(umax, u);
-            }
-        } else {
-            Wx = xc - A.dDSO * c;
-            Wy = yc - A.dDSO * s;
-            const float fc = (float)c, fs = (float)s;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float X = fxc + ((q & 1) ? hx : -hx), Y = fyc + ((q & 2) ? hy : -hy);
-                const float u = A.DSD * (Y * fc - X * fs) * __builtin_amdgcn_rcpf(A.DSO - (X * fc + Y * fs));
-                umin = fminf(umin, u);
-                umax = fmaxf(umax, u);
-            }
-        }
-        // (a wider margin for views: their corner coordinates are formed from source-relative
-        // vectors of about a metre; a column too many is clipped away below)
-        const float um = VW ? 1e-2f : 1e-3f;
-        const int alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - um), 0.0f);
-        const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + um), (float)(A.nu - 1));
-        for (int a = alo; a <= ahi; ++a) {
-            const double ua = (a - A.cu) * A.du + A.offu;
-            double Dx, Dy;
+    // The set-up of a candidate detector column (its trace through the column's square in FP64, the
+    // entry parameter, the heights below) is the same for every lane of the wave, which holds one
+    // voxel column.  So the lanes share it out: each lane takes one angle of a batch of 64 and finds
+    // that angle's candidate columns, a prefix sum over the wave lays the (angle, column) pairs out
+    // in angle order, each lane forms the set-up of one pair into LDS, and the voxel loop reads the
+    // pairs back in that order (the same sums in the same order as one pair after another).
+    const int kw0 = A.own_lo + zg * 64 * R;  // first voxel of the wave's lanes
+    float4(*hdr)[3] = chdr[wave];
+    int(*slot)[64] = cslot[wave];
+    int tprev = -1;
+    for (int tb = 0; tb < A.nang; tb += 64) {
+        int alo = 0, cnt = 0;
+        if (tb + lane < A.nang) {
+            const AngleGeo &G = A.tab[A.a0 + tb + lane];
+            float umin = FLT_MAX, umax = -FLT_MAX;
             if (VW) {
-                Dx = fma(ua, G.eu[0], G.Dc[0]) * A.ddx;
-                Dy = fma(ua, G.eu[1], G.Dc[1]) * A.ddy;
+                // detector coordinate u of the ray through each corner of the column's square: with
+                // X - S = Xr and C - S + u e_u parallel to it, u = (Xr x (C - S)) / (e_u x Xr)
+                const double Wx = xc - G.Smm[0], Wy = yc - G.Smm[1];
+                const float dcx = (float)(G.Dc[0] * A.ddx), dcy = (float)(G.Dc[1] * A.ddy);
+                const float eux = (float)(G.eu[0] * A.ddx), euy = (float)(G.eu[1] * A.ddy);
+                const float fwx = (float)Wx, fwy = (float)Wy;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float X = fwx + ((q & 1) ? hx : -hx), Y = fwy + ((q & 2) ? hy : -hy);
+                    const float u = (X * dcy - Y * dcx) * __builtin_amdgcn_rcpf(eux * Y - euy * X);
+                    umin = fminf(umin, u);
+                    umax = fmaxf(umax, u);
+                }
             } else {
-                Dx = -A.dDSD * c - ua * s;
-                Dy = -A.dDSD * s + ua * c;
-            }
-            const float cross = (float)(Wx * Dy - Wy * Dx);
-            const double dotd = Wx * Dx + Wy * Dy;
-            const float fDx = (float)Dx, fDy = (float)Dy;
-            const float L2 = fmaf(fDx, fDx, fDy * fDy);
-            const float iL = __builtin_amdgcn_rsqf(L2);
-            const float ux = fDx * iL, uy = fDy * iL;
-            const float dperp = cross * iL;
-            const float fx = -dperp * uy, fy = dperp * ux;
-            float s0 = -FLT_MAX, s1 = FLT_MAX;
-            // a trace the projector takes as parallel to an axis (|D_c| < 1e-12 |D|, in FP64; here with
-            // the horizontal |D|) runs at the source's coordinate: the column must hold it in its
-            // half-open slab
-            const double lpar = 1e-24 * (Dx * Dx + Dy * Dy);
-            if (Dx * Dx >= lpar) {
-                const float rr = __builtin_amdgcn_rcpf(ux);
-                const float qa = (-hx - fx) * rr, qb = (hx - fx) * rr;
-                s0 = fmaxf(s0, fminf(qa, qb));
-                s1 = fminf(s1, fmaxf(qa, qb));
-            } else if ((int)floor(G.S[0] + 0.5) != i) {
-                continue;
-            }
-            if (Dy * Dy >= lpar) {
-                const float rr = __builtin_amdgcn_rcpf(uy);
-                const float qa = (-hy - fy) * rr, qb = (hy - fy) * rr;
-                s0 = fmaxf(s0, fminf(qa, qb));
-                s1 = fminf(s1, fmaxf(qa, qb));
-            } else if ((int)floor(G.S[1] + 0.5) != j) {
-                continue;
-            }
-            if (!(s0 < s1)) continue;
-            const float T = (s1 - s0) * iL;
-            // t where the trace enters the square, in FP64: the foot point's parameter W.D / |D|^2
-            // (one Newton step on the FP32 reciprocal) plus the small FP32 clip offset
-            const double L2d = Dx * Dx + Dy * Dy;
-            const double rl = (double)__builtin_amdgcn_rcpf((float)L2d);
-            const double t0d = fma(dotd, rl * fma(-L2d, rl, 2.0), (double)(s0 * iL));
-            const float t0 = (float)t0d;
-            // H0 = H0h + H0l with H0h on a grid of 2^-7 (adding and removing 1.5 * 2^16 rounds to
-            // it for |H0| < 2^15), S = Sh + Sr with Sh holding 10 significant bits: then for face
-            // index kA (an integer) and row b (|b| < 2^14) kA - H0h and b Sh are exact FP32 values
-            // and so is their difference, which is a few voxels for the candidate rows; only the
-            // small terms b Sr + H0l are rounded
-            const double H0d = fma(t0d, v0dz, -zf0v), Sd = t0d * dvdz;
-            const float H0h = ((float)H0d + 98304.0f) - 98304.0f;
-            const float H0l = (float)(H0d - (double)H0h);
-            const float Sf = (float)Sd;
-            const float Sh = __uint_as_float(__float_as_uint(Sf) & 0xFFFFC000u);
-            const float Sr = (float)(Sd - (double)Sh);
-            const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
-            const float *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
-            if (A.zrow >= 0) {
-                // the row at the source's height stays in one slice, the one whose half-open slab
-                // holds that height; its step is 0 in the table, so the loop below adds nothing
-                const int ks = (int)floor(-zf0v) - (A.own_lo + zg * 64 * R);
-                if (ks >= 0 && ks < 64 * R && (ks & 63) == lane) {
-                    const float yz = col[A.zrow + 1];
+                const float fc = (float)G.c, fs = (float)G.s;
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if ((ks >> 6) == r) acc[r] = fmaf(T, yz, acc[r]);
+                for (int q = 0; q < 4; ++q) {
+                    const float X = fxc + ((q & 1) ? hx : -hx), Y = fyc + ((q & 2) ? hy : -hy);
+                    const float u = A.DSD * (Y * fc - X * fs) * __builtin_amdgcn_rcpf(A.DSO - (X * fc + Y * fs));
+                    umin = fminf(umin, u);
+                    umax = fmaxf(umax, u);
                 }
             }
-            float wv[R][NR];
-            float bl[R], E[R];
+            // (a wider margin for views: their corner coordinates are formed from source-relative
+            // vectors of about a metre; a column too many is clipped away below)
+            const float um = VW ? 1e-2f : 1e-3f;
+            alo = (int)fmaxf(ceilf(fmaf(umin, iau, aum) - um), 0.0f);
+            const int ahi = (int)fminf(floorf(fmaf(umax, iau, aum) + um), (float)(A.nu - 1));
+            cnt = max(ahi - alo + 1, 0);
+        }
+        int incl = cnt;  // inclusive prefix sum of the counts over the lanes
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]: the lowest
-                // v = z / t over the lower face and t in [t0, t1] (with ORD, za * it1 for voxels
-                // above the plane and zb * it0 for voxels below)
-                const float zlo = VW ? za[r] - szf : za[r];
-                const float vlo = ORD ? fminf(za[r] * it1, zb[r] * it0) : fminf(zlo * it0, zlo * it1);
-                bl[r] = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
-                // the height of face A above row bl where the row enters the square, in voxel
-                // units (kA - H0 - bl S: a difference of heights of up to the volume's height,
-                // formed exactly up to the small terms)
-                const float d = (kA[r] - H0h) - bl[r] * Sh;
-                E[r] = d - fmaf(bl[r], Sr, H0l);
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
+        }
+        const int total = __builtin_amdgcn_readlane(incl, 63);
+        slot[0][lane] = alo;
+        slot[1][lane] = incl - cnt;
+        slot[2][lane] = incl;
+        wave_lds_sync();
+        for (int e0 = 0; e0 < total; e0 += 64) {
+            const int e = e0 + lane;
+            if (e < total) {
+                // the angle of pair e: the first lane whose inclusive sum exceeds e (at most lane 63)
+                int sl = 0;
+#pragma unroll
+                for (int st = 32; st > 0; st >>= 1)
+                    if (slot[2][sl + st - 1] <= e) sl += st;
+                const int t = tb + sl, a = slot[0][sl] + (e - slot[1][sl]);
+                hdr[lane][2] = make_float4(__int_as_float(-1), 0.0f, 0.0f, 0.0f);
+                const AngleGeo &G = A.tab[A.a0 + t];
+                double Wx, Wy;         // source -> column centre
+                double zf0v = zf0dz;   // lower face of voxel 0 above the source plane, voxel units
+                float szf = 0.0f;      // VW: the source's height
+                double Dx, Dy;
+                const double ua = (a - A.cu) * A.du + A.offu;
+                if (VW) {
+                    Wx = xc - G.Smm[0];
+                    Wy = yc - G.Smm[1];
+                    zf0v = zf0dz - G.Smm[2] / A.ddz;
+                    szf = (float)G.Smm[2];
+                    Dx = fma(ua, G.eu[0], G.Dc[0]) * A.ddx;
+                    Dy = fma(ua, G.eu[1], G.Dc[1]) * A.ddy;
+                } else {
+                    Wx = xc - A.dDSO * G.c;
+                    Wy = yc - A.dDSO * G.s;
+                    // (the per-angle product rounded first, as one FMA adds the column's term)
+                    Dx = fma(-ua, G.s, -A.dDSD * G.c);
+                    Dy = fma(ua, G.c, -A.dDSD * G.s);
+                }
+                const float cross = (float)(Wx * Dy - Wy * Dx);
+                const double dotd = Wx * Dx + Wy * Dy;
+                const float fDx = (float)Dx, fDy = (float)Dy;
+                const float L2 = fmaf(fDx, fDx, fDy * fDy);
+                const float iL = __builtin_amdgcn_rsqf(L2);
+                const float ux = fDx * iL, uy = fDy * iL;
+                const float dperp = cross * iL;
+                const float fx = -dperp * uy, fy = dperp * ux;
+                float s0 = -FLT_MAX, s1 = FLT_MAX;
+                // a trace the projector takes as parallel to an axis (|D_c| < 1e-12 |D|, in FP64; here
+                // with the horizontal |D|) runs at the source's coordinate: the column must hold it in
+                // its half-open slab
+                const double lpar = 1e-24 * (Dx * Dx + Dy * Dy);
+                bool hit = true;
+                if (Dx * Dx >= lpar) {
+                    const float rr = __builtin_amdgcn_rcpf(ux);
+                    const float qa = (-hx - fx) * rr, qb = (hx - fx) * rr;
+                    s0 = fmaxf(s0, fminf(qa, qb));
+                    s1 = fminf(s1, fmaxf(qa, qb));
+                } else {
+                    hit = (int)floor(G.S[0] + 0.5) == i;
+                }
+                if (Dy * Dy >= lpar) {
+                    const float rr = __builtin_amdgcn_rcpf(uy);
+                    const float qa = (-hy - fy) * rr, qb = (hy - fy) * rr;
+                    s0 = fmaxf(s0, fminf(qa, qb));
+                    s1 = fminf(s1, fmaxf(qa, qb));
+                } else {
+                    hit = hit && (int)floor(G.S[1] + 0.5) == j;
+                }
+                if (hit && s0 < s1) {
+                    const float T = (s1 - s0) * iL;
+                    // t where the trace enters the square, in FP64: the foot point's parameter
+                    // W.D / |D|^2 (one Newton step on the FP32 reciprocal) plus the small FP32 clip
+                    // offset
+                    const double L2d = Dx * Dx + Dy * Dy;
+                    const double rl = (double)__builtin_amdgcn_rcpf((float)L2d);
+                    const double t0d = fma(dotd, rl * fma(-L2d, rl, 2.0), (double)(s0 * iL));
+                    const float t0 = (float)t0d;
+                    // H0 = H0h + H0l with H0h on a grid of 2^-7 (adding and removing 1.5 * 2^16 rounds
+                    // to it for |H0| < 2^15), S = Sh + Sr with Sh holding 10 significant bits: then
+                    // for face index kA (an integer) and row b (|b| < 2^14) kA - H0h and b Sh are
+                    // exact FP32 values and so is their difference, which is a few voxels for the
+                    // candidate rows; only the small terms b Sr + H0l are rounded
+                    const double H0d = fma(t0d, v0dz, -zf0v), Sd = t0d * dvdz;
+                    const float H0h = ((float)H0d + 98304.0f) - 98304.0f;
+                    const float H0l = (float)(H0d - (double)H0h);
+                    const float Sf = (float)Sd;
+                    const float Sh = __uint_as_float(__float_as_uint(Sf) & 0xFFFFC000u);
+                    const float Sr = (float)(Sd - (double)Sh);
+                    const float it0 = __builtin_amdgcn_rcpf(t0), it1 = __builtin_amdgcn_rcpf(t0 + T);
+                    // the voxel (relative to kw0) whose half-open slab holds the source's height
+                    const int ks = (int)floor(-zf0v) - kw0;
+                    hdr[lane][0] = make_float4(T, H0h, H0l, Sf);
+                    hdr[lane][1] = make_float4(Sh, Sr, it0, it1);
+                    hdr[lane][2] = make_float4(__int_as_float(t), __int_as_float(a), szf, __int_as_float(ks));
+                }
             }
-            // the rows of all R voxels are loaded before any is used, so they are in flight together
+            wave_lds_sync();
+            const int ne = min(64, total - e0);
+            for (int p = 0; p < ne; ++p) {
+                const float4 h2 = hdr[p][2];
+                const int t = __builtin_amdgcn_readfirstlane(__float_as_int(h2.x));
+                if (t < 0) continue;  // the trace misses the column's square
+                const float4 h0 = hdr[p][0], h1 = hdr[p][1];
+                const int a = __builtin_amdgcn_readfirstlane(__float_as_int(h2.y));
+                const float T = h0.x, H0h = h0.y, H0l = h0.z, Sf = h0.w;
+                const float Sh = h1.x, Sr = h1.y, it0 = h1.z, it1 = h1.w;
+                const float szf = h2.z;
+                if (VW && t != tprev) {
+                    tprev = t;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                // uniform column base plus an unsigned 32-bit byte offset of row bl
-                const float *cb = (const float *)((const char *)col + (uint32_t)((int)bl[r] + 1) * 4u);
-#pragma unroll
-                for (int q = 0; q < NR; ++q) wv[r][q] = cb[q];
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const float *sb = rstep + ((int)bl[r] + 1);
-#pragma unroll
-                for (int q = 0; q < NR; ++q) {
-                    const float2 w = make_float2(wv[r][q], sb[q]);
-                    // parameters relative to t0 of the row's crossings of faces A and B (its
-                    // height below face A in voxels times dz / v_b, and one step dz / v_b more),
-                    // clipped to [0, T]: a row that stays inside the voxel gets exactly T
-                    const float Eq = q == 0 ? E[r] : fmaf(-(float)q, Sf, E[r]);
-                    const float tA = Eq * w.y, tB = fmaf(sg[r], w.y, tA);
-                    float len;
-                    if (ORD) {
-                        // tA <= tB for the rows that can meet the voxel; rows of the other sign have
-                        // both parameters below 0, which clamp to the same value
-                        len = __builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T);
-                    } else {
-                        // either order: clamping to [0, T] is monotonic, so the clamped pair's distance
-                        // is the overlap of [min, max] with [0, T] (0 when they miss), bit for bit the
-                        // max(min(max, T) - max(min, 0), 0) it replaces; the |.| folds into the FMA
-                        len = fabsf(__builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T));
+                    for (int r = 0; r < R; ++r) {
+                        // a voxel below the source plane is met by falling rows first at its upper face
+                        const bool below = zb[r] - szf <= 0.0f;
+                        kA[r] = below ? (float)(kw0 + 64 * r + lane + 1) : (float)(kw0 + 64 * r + lane);
+                        sg[r] = below ? -1.0f : 1.0f;
                     }
-                    acc[r] = fmaf(len, w.x, acc[r]);
+                }
+                const float *col = yq + ((int64_t)t * A.nu + a) * nvp;  // row b at col[b + 1]
+                if (A.zrow >= 0) {
+                    // the row at the source's height stays in one slice, the one whose half-open slab
+                    // holds that height; its step is 0 in the table, so the loop below adds nothing
+                    const int ks = __float_as_int(h2.w);
+                    if (ks >= 0 && ks < 64 * R && (ks & 63) == lane) {
+                        const float yz = col[A.zrow + 1];
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if ((ks >> 6) == r) acc[r] = fmaf(T, yz, acc[r]);
+                    }
+                }
+                float wv[R][NR];
+                float bl[R], E[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    // first row that can meet the voxel, kept inside [-1, nv + 1 - NR]: the lowest
+                    // v = z / t over the lower face and t in [t0, t1] (with ORD, za * it1 for voxels
+                    // above the plane and zb * it0 for voxels below)
+                    const float zlo = VW ? za[r] - szf : za[r];
+                    const float vlo = ORD ? fminf(za[r] * it1, zb[r] * it0) : fminf(zlo * it0, zlo * it1);
+                    bl[r] = __builtin_amdgcn_fmed3f(ceilf(fmaf(vlo, idv, nv0)), -1.0f, bmax);
+                    // the height of face A above row bl where the row enters the square, in voxel
+                    // units (kA - H0 - bl S: a difference of heights of up to the volume's height,
+                    // formed exactly up to the small terms)
+                    const float d = (kA[r] - H0h) - bl[r] * Sh;
+                    E[r] = d - fmaf(bl[r], Sr, H0l);
+                }
+                // the rows of all R voxels are loaded before any is used, so they are in flight together
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    // uniform column base plus an unsigned 32-bit byte offset of row bl
+                    const float *cb = (const float *)((const char *)col + (uint32_t)((int)bl[r] + 1) * 4u);
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) wv[r][q] = cb[q];
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float *sb = rstep + ((int)bl[r] + 1);
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        const float2 w = make_float2(wv[r][q], sb[q]);
+                        // parameters relative to t0 of the row's crossings of faces A and B (its
+                        // height below face A in voxels times dz / v_b, and one step dz / v_b more),
+                        // clipped to [0, T]: a row that stays inside the voxel gets exactly T
+                        const float Eq = q == 0 ? E[r] : fmaf(-(float)q, Sf, E[r]);
+                        const float tA = Eq * w.y, tB = fmaf(sg[r], w.y, tA);
+                        float len;
+                        if (ORD) {
+                            // tA <= tB for the rows that can meet the voxel; rows of the other sign have
+                            // both parameters below 0, which clamp to the same value
+                            len = __builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T);
+                        } else {
+                            // either order: clamping to [0, T] is monotonic, so the clamped pair's distance
+                            // is the overlap of [min, max] with [0, T] (0 when they miss), bit for bit the
+                            // max(min(max, T) - max(min, 0), 0) it replaces; the |.| folds into the FMA
+                            len = fabsf(__builtin_amdgcn_fmed3f(tB, 0.0f, T) - __builtin_amdgcn_fmed3f(tA, 0.0f, T));
+                        }
+                        acc[r] = fmaf(len, w.x, acc[r]);
+                    }
                 }
             }
+            wave_lds_sync();
         }
     }
 #pragma unroll
@@ -1288,8 +1359,9 @@ bool direct_views_adjoint() {
     return e && (e[0] == '1' || e[0] == '2');
 }
 
-// rows of the padded copy whose parameter steps fit the column kernel's LDS table (64 KiB)
-constexpr int64_t ADJ_MAX_ROWS = 16384;
+// rows of the padded copy whose parameter steps fit the column kernel's LDS table (48 KiB, beside
+// the 15 KiB of candidate set-ups: 63 KiB per workgroup)
+constexpr int64_t ADJ_MAX_ROWS = 12288;
 
 bool adj_col_ok(const ct_plan *p) {
 #ifdef CT_NO_ADJ_COL
