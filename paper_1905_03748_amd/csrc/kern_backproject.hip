@@ -422,22 +422,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W == CT_BP_
                 const float cbmax = fmaf(lbmax, (float)(4 * PITCH), cb);
                 // row coordinate of voxel k of the run: b0 + k db, with db a few pixels at most
                 const float b0 = fmaf(zl0, mv, bq), db = A.dz * mv;
+                // with the run climbing less than one row per voxel, a voxel's lower tap row is the
+                // previous voxel's lower or upper row: only its upper row is read (the same taps)
+                if (db < 0.999f) {
+                    float l0 = 0.0f, l1 = 0.0f, u0 = 0.0f, u1 = 0.0f, offp = 0.0f;
 #pragma unroll
-                for (int k = 0; k < BPL_NZ; ++k) {
-                    const float bs = fmaf((float)k, db, b0);
-                    const float bf = floorf(bs);
-                    const float fb = bs - bf;
-                    const float off = __builtin_amdgcn_fmed3f(fmaf(bf, (float)(4 * PITCH), cb), cb, cbmax);
-                    const float *t = (const float *)((const char *)win + (int)off);
-                    const float v0 = fmaf(wa1, t[1], wa0 * t[0]);
-                    const float v1 = fmaf(wa1, t[PITCH + 1], wa0 * t[PITCH]);
-                    const float v = fmaf(fb, v1 - v0, v0);
-                    float wk = w;
-                    if (W != CT_BP_FDK) {
-                        const float zk = fmaf((float)k, A.dz, zk0);
-                        wk = wpm * __builtin_amdgcn_sqrtf(fmaf(zk, zk, rxy2));
+                    for (int k = 0; k < BPL_NZ; ++k) {
+                        const float bs = fmaf((float)k, db, b0);
+                        const float bf = floorf(bs);
+                        const float fb = bs - bf;
+                        const float off = __builtin_amdgcn_fmed3f(fmaf(bf, (float)(4 * PITCH), cb), cb, cbmax);
+                        const float *t = (const float *)((const char *)win + (int)off);
+                        if (k == 0) {
+                            l0 = t[0];
+                            l1 = t[1];
+                        } else {
+                            const bool up = off != offp;  // one row up (4 PITCH bytes) or the same row
+                            l0 = up ? u0 : l0;
+                            l1 = up ? u1 : l1;
+                        }
+                        u0 = t[PITCH];
+                        u1 = t[PITCH + 1];
+                        offp = off;
+                        const float v0 = fmaf(wa1, l1, wa0 * l0);
+                        const float v1 = fmaf(wa1, u1, wa0 * u0);
+                        const float v = fmaf(fb, v1 - v0, v0);
+                        float wk = w;
+                        if (W != CT_BP_FDK) {
+                            const float zk = fmaf((float)k, A.dz, zk0);
+                            wk = wpm * __builtin_amdgcn_sqrtf(fmaf(zk, zk, rxy2));
+                        }
+                        acc[k] = fmaf(wk, v, acc[k]);
                     }
-                    acc[k] = fmaf(wk, v, acc[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < BPL_NZ; ++k) {
+                        const float bs = fmaf((float)k, db, b0);
+                        const float bf = floorf(bs);
+                        const float fb = bs - bf;
+                        const float off = __builtin_amdgcn_fmed3f(fmaf(bf, (float)(4 * PITCH), cb), cb, cbmax);
+                        const float *t = (const float *)((const char *)win + (int)off);
+                        const float v0 = fmaf(wa1, t[1], wa0 * t[0]);
+                        const float v1 = fmaf(wa1, t[PITCH + 1], wa0 * t[PITCH]);
+                        const float v = fmaf(fb, v1 - v0, v0);
+                        float wk = w;
+                        if (W != CT_BP_FDK) {
+                            const float zk = fmaf((float)k, A.dz, zk0);
+                            wk = wpm * __builtin_amdgcn_sqrtf(fmaf(zk, zk, rxy2));
+                        }
+                        acc[k] = fmaf(wk, v, acc[k]);
+                    }
                 }
             }
         }
