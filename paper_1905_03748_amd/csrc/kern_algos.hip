@@ -173,46 +173,83 @@ __global__ __launch_bounds__(256) void k_sart_resid_t(const TP *__restrict__ b, 
 }
 
 // TV_eps gradient with forward differences, unit spacing, zero difference at the last index.
-// Slice z = blockIdx.z + kg0 of the volume (nz slices in all); x holds slices from kx0 on (at
-// least z - 1 .. z + 1 where they exist) and g from kg0 on.  A whole resident volume has
-// kx0 = kg0 = 0.
+// Slices kg0 .. kg0 + nk - 1 of the volume (nz slices in all); x holds slices from kx0 on (at least
+// z - 1 .. z + 1 where they exist) and g from kg0 on.  A whole resident volume has kx0 = kg0 = 0.
+// Each thread walks TV_ZR slices of one (i, j) column: a voxel's gradient reads seven positions of
+// its own slice, three of the slice above and three of the one below, so the thread loads the
+// seven positions of each slice once and carries them up the column (7 loads per voxel, not 13).
+constexpr int TV_ZR = 8;
+struct TvPlane {
+    float c, e, n, w, wn, s, se;  // (i, j), (i + 1, j), (i, j + 1), (i - 1, j), (i - 1, j + 1), (i, j - 1), (i + 1, j - 1)
+};
 __global__ __launch_bounds__(256) void k_tv_grad(const float *__restrict__ x, float *__restrict__ g, int nx, int ny,
-                                                 int nz, float eps, int64_t kx0, int64_t kg0) {
+                                                 int nz, float eps, int64_t kx0, int64_t kg0, int64_t nk) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int64_t k = blockIdx.z + kg0;
     if (i >= nx || j >= ny) return;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const int64_t o = (k - kx0) * sz + (int64_t)j * sy + i;
-    auto X = [&](int di, int dj, int dk) { return x[o + dk * sz + dj * sy + di]; };
-    const float xc = X(0, 0, 0);
-    // differences at j
-    const float dxc = i < nx - 1 ? X(1, 0, 0) - xc : 0.0f;
-    const float dyc = j < ny - 1 ? X(0, 1, 0) - xc : 0.0f;
-    const float dzc = k < nz - 1 ? X(0, 0, 1) - xc : 0.0f;
-    float gv = -(dxc + dyc + dzc) / sqrtf(dxc * dxc + dyc * dyc + dzc * dzc + eps);
-    if (i > 0) {  // neighbour j - e_x
-        const float xm = X(-1, 0, 0);
-        const float a = xc - xm;
-        const float b = j < ny - 1 ? X(-1, 1, 0) - xm : 0.0f;
-        const float c = k < nz - 1 ? X(-1, 0, 1) - xm : 0.0f;
-        gv += a / sqrtf(a * a + b * b + c * c + eps);
+    const bool hx = i < nx - 1, hy = j < ny - 1, lx = i > 0, ly = j > 0;
+    auto plane = [&](int64_t k) {  // positions outside the volume's x-y extent read as 0 (unused)
+        const int64_t o = (k - kx0) * sz + (int64_t)j * sy + i;
+        TvPlane p;
+        p.c = x[o];
+        p.e = hx ? x[o + 1] : 0.0f;
+        p.n = hy ? x[o + sy] : 0.0f;
+        p.w = lx ? x[o - 1] : 0.0f;
+        p.wn = (lx && hy) ? x[o - 1 + sy] : 0.0f;
+        p.s = ly ? x[o - sy] : 0.0f;
+        p.se = (ly && hx) ? x[o - sy + 1] : 0.0f;
+        return p;
+    };
+    const int64_t r0 = (int64_t)blockIdx.z * TV_ZR, r1 = min(r0 + (int64_t)TV_ZR, nk);
+    int64_t k = kg0 + r0;
+    TvPlane pm = {}, pn = {};
+    if (k > 0) pm = plane(k - 1);
+    TvPlane pc = plane(k);
+    for (int64_t r = r0; r < r1; ++r, ++k) {
+        const bool hz = k < nz - 1;
+        if (hz) pn = plane(k + 1);
+        const float xc = pc.c;
+        // differences at the voxel
+        const float dxc = hx ? pc.e - xc : 0.0f;
+        const float dyc = hy ? pc.n - xc : 0.0f;
+        const float dzc = hz ? pn.c - xc : 0.0f;
+        float gv = -(dxc + dyc + dzc) / sqrtf(dxc * dxc + dyc * dyc + dzc * dzc + eps);
+        if (lx) {  // neighbour - e_x
+            const float xm = pc.w;
+            const float a = xc - xm;
+            const float b = hy ? pc.wn - xm : 0.0f;
+            const float c = hz ? pn.w - xm : 0.0f;
+            gv += a / sqrtf(a * a + b * b + c * c + eps);
+        }
+        if (ly) {
+            const float xm = pc.s;
+            const float a = hx ? pc.se - xm : 0.0f;
+            const float b = xc - xm;
+            const float c = hz ? pn.s - xm : 0.0f;
+            gv += b / sqrtf(a * a + b * b + c * c + eps);
+        }
+        if (k > 0) {
+            const float xm = pm.c;
+            const float a = hx ? pm.e - xm : 0.0f;
+            const float b = hy ? pm.n - xm : 0.0f;
+            const float c = xc - xm;
+            gv += c / sqrtf(a * a + b * b + c * c + eps);
+        }
+        g[(k - kg0) * sz + (int64_t)j * sy + i] = gv;
+        pm = pc;
+        pc = pn;
     }
-    if (j > 0) {
-        const float xm = X(0, -1, 0);
-        const float a = i < nx - 1 ? X(1, -1, 0) - xm : 0.0f;
-        const float b = xc - xm;
-        const float c = k < nz - 1 ? X(0, -1, 1) - xm : 0.0f;
-        gv += b / sqrtf(a * a + b * b + c * c + eps);
-    }
-    if (k > 0) {
-        const float xm = X(0, 0, -1);
-        const float a = i < nx - 1 ? X(1, 0, -1) - xm : 0.0f;
-        const float b = j < ny - 1 ? X(0, 1, -1) - xm : 0.0f;
-        const float c = xc - xm;
-        gv += c / sqrtf(a * a + b * b + c * c + eps);
-    }
-    g[(k - kg0) * sz + (int64_t)j * sy + i] = gv;
+}
+
+// gradient of slices kg0 .. kg0 + nk - 1 (see k_tv_grad)
+static ct_status launch_tv_grad(const float *x, float *g, int nx, int ny, int nz, float eps, int64_t kx0, int64_t kg0,
+                                int64_t nk, hipStream_t st) {
+    if (nk <= 0) return CT_OK;
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)((nk + TV_ZR - 1) / TV_ZR));
+    hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, st, x, g, nx, ny, nz, eps, kx0, kg0, nk);
+    CT_HIP(hipGetLastError());
+    return CT_OK;
 }
 
 // ROF model by Chambolle's projection.  The dual field p = (px, py, pz) holds one FP32 volume per
@@ -533,11 +570,8 @@ ct_status tv_run(const ct_geometry &g, void *xs, ct_dtype vt, int32_t nsteps, do
     CK(dot_f64(x, x, CT_F32, nv, scal + 0, parts, st));
     hipLaunchKernelGGL(k_tv_alpha, dim3(1), dim3(1), 0, st, scal, lambda);
     CT_HIP(hipGetLastError());
-    const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz);
     for (int32_t k = 0; k < nsteps; ++k) {
-        hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, st, (const float *)x, gbuf, nx, ny, nz, (float)eps,
-                           (int64_t)0, (int64_t)0);
-        CT_HIP(hipGetLastError());
+        CK(launch_tv_grad((const float *)x, gbuf, nx, ny, nz, (float)eps, 0, 0, nz, st));
         CK(dot_f64(gbuf, gbuf, CT_F32, nv, scal + 2, parts, st));
         hipLaunchKernelGGL(k_tv_update, dim3(ew_grid(nv)), dim3(EW_THREADS), 0, st, (float *)x, (const float *)gbuf, scal, nv);
         CT_HIP(hipGetLastError());
@@ -661,11 +695,7 @@ ct_status tv_host_run(const ct_geometry &g, float *hx, int32_t nsteps, double la
         m1 = std::min(nz, o1 + 1);
     };
     auto grad = [&](int64_t m0, int64_t o0, int64_t o1) -> ct_status {
-        const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)(o1 - o0));
-        hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, (const float *)xbuf, gbuf, nx, ny, (int)nz, (float)eps,
-                           m0, o0);
-        CT_HIP(hipGetLastError());
-        return CT_OK;
+        return launch_tv_grad((const float *)xbuf, gbuf, nx, ny, (int)nz, (float)eps, m0, o0, o1 - o0, s);
     };
     auto dot_host = [&](const float *a, int64_t n, double &out) -> ct_status {
         ct_status e = dot_f64(a, a, CT_F32, n, dscal + 3, (double *)parts.p, s);
@@ -803,10 +833,9 @@ ct_status tv_host_run_halo(const ct_geometry &g, float *hx, int32_t nsteps, doub
             const int64_t nown = (o1 - o0) * slice;
             for (int64_t i = 0; i < k; ++i) {
                 const int64_t r0 = m0 == 0 ? 0 : m0 + i + 1, r1 = m1 == nz ? nz : m1 - i - 1;
-                const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (unsigned)(r1 - r0));
-                hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, (const float *)xbuf, gbuf, nx, ny, (int)nz,
-                                   (float)eps, m0, r0);
-                CT_HIP(hipGetLastError());
+                if ((e = launch_tv_grad((const float *)xbuf, gbuf, nx, ny, (int)nz, (float)eps, m0, r0, r1 - r0, s)) !=
+                    CT_OK)
+                    return e;
                 if ((e = dot_f64(gbuf + (o0 - r0) * slice, gbuf + (o0 - r0) * slice, CT_F32, nown, dscal + 2,
                                  (double *)parts.p, s)) != CT_OK)
                     return e;
